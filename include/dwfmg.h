@@ -1,0 +1,214 @@
+/*
+ * dwfmg — domain-wall fermion multigrid hot path for MI355X (gfx950).
+ *
+ * C ABI of the library.  Every field is a device pointer to C-contiguous
+ * memory owned by the caller; the library never frees a caller buffer.
+ * Streams are HIP streams passed as `void*` (NULL = the default stream); all
+ * work is ordered on that stream.  Every entry point returns a status code
+ * (DWF_OK = 0, > 0 soft, < 0 hard) and never throws across the boundary.
+ *
+ * Physics follows Brower, Clark, Howarth, Weinberg, "Multigrid for Chiral
+ * Lattice Fermions: Domain Wall" (arXiv:2004.07732):
+ *   D_W(M)  : 2-d Wilson kernel with U(1) links                  (Sec. 2)
+ *   D_DW(m) : Shamir domain-wall operator                          (eq. DWoperator)
+ *   D_PV    : Pauli-Villars operator D_DW(1)                       (Sec. 2.2)
+ *   A       : D_PV^dagger D_DW, the approximate PV-preconditioned
+ *             operator the multigrid iterates on                   (eq. NormalExp, Sec. 2.3)
+ *   coarse  : Galerkin kernel P^dagger D_W P with wall-only transfer and a
+ *             reduced fifth extent on coarse levels                (Sec. 2.3, eq. coarsenDW,
+ *                                                                   eq. TruncProjectInterpolate)
+ *
+ * Conventions
+ *   - Lattice Lx x Ly, periodic; site index y*Lx + x.
+ *   - gamma_1 = sigma_1 (x), gamma_2 = sigma_2 (y), gamma_5 = sigma_3, so
+ *     spin component 0 is chirality +, component 1 is chirality -.
+ *   - Links U: complex [2][Ly][Lx], mu = 0 is the x direction.
+ *   - 5-d fermion fields: complex [nrhs][Ls][Ly][Lx][2]; slice s = 0..Ls-1
+ *     stands for the paper's s = 1..Ls.
+ *   - Complex numbers are interleaved (re, im): complex128 = two doubles,
+ *     complex64 = two floats.
+ *   - M5 is the paper's signed bulk mass (domain-wall regime -2 < M5 < 0;
+ *     the free-field optimum is -1).  A "domain-wall height" quoted as a
+ *     positive 1.0 is passed as M5 = -1.0.
+ */
+#ifndef DWFMG_H
+#define DWFMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define DWF_OK             0
+#define DWF_NOT_CONVERGED  1   /* soft: stats filled, x holds the best iterate      */
+#define DWF_EINVAL        -1   /* bad argument (sizes, null pointer, tolerance)      */
+#define DWF_EHIP          -2   /* a HIP runtime call failed                          */
+#define DWF_EBREAKDOWN    -3   /* Krylov breakdown (zero or non-finite norm)         */
+#define DWF_ENAN          -4   /* non-finite value in the input or the iteration     */
+#define DWF_ENOSETUP      -5   /* context missing or not set up                      */
+#define DWF_EUNSUPPORTED  -6   /* a size or option this build does not support       */
+
+/* ---------------------------------------------------------------- flags */
+#define DWF_DAGGER     1       /* apply the adjoint                                  */
+#define DWF_PREC_F32   2       /* fields (and U) are complex64 instead of complex128 */
+
+/* dwf_pv_apply modes */
+#define DWF_PV          0      /* out = D_PV psi                                     */
+#define DWF_PV_DAG      1      /* out = D_PV^dagger psi                              */
+#define DWF_PVDAG_DW    2      /* out = D_PV^dagger D_DW(m) psi   (operator A)       */
+#define DWF_PVDAG_DW_DAG 3     /* out = D_DW(m)^dagger D_PV psi   (A^dagger)         */
+
+/* precision of a multigrid level's storage / arithmetic */
+#define DWF_P_F64   0
+#define DWF_P_F32   1
+#define DWF_P_BF16  2          /* coarse links only: bfloat16 storage, FP32 arithmetic */
+#define DWF_P_F16   3          /* coarse links only: binary16 storage, FP32 arithmetic */
+
+#define DWF_MAX_LEVELS 3       /* coarse levels below the fine one                   */
+
+/* ---------------------------------------------------------------- operators */
+
+/* out = D_DW(m_f) psi (or D_DW(m_f)^dagger psi with DWF_DAGGER), eq. DWoperator.
+ * U [2][Ly][Lx], psi and out [nrhs][Ls][Ly][Lx][2]; complex128, or complex64
+ * with DWF_PREC_F32.  psi and out must not overlap.  Lx, Ly >= 1, Ls >= 1,
+ * nrhs >= 1.  Asynchronous on `stream`.  Returns DWF_EINVAL on bad sizes or
+ * null pointers, DWF_EHIP if the launch fails. */
+int dwf_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs,
+              double m_f, double M5, int flags, void* stream);
+
+/* Pauli-Villars forms (Sec. 2.2, eq. NormalExp): see the DWF_PV* modes.  The
+ * product modes use a library-owned intermediate field (allocated on first use
+ * and kept until dwf_release_scratch).  Same layout rules as dwf_apply. */
+int dwf_pv_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs,
+                 double m_f, double M5, int mode, int flags, void* stream);
+
+/* out = D_W(M) psi (or its adjoint) on 2-d fields [nrhs][Ly][Lx][2] (Sec. 2). */
+int dwf_wilson_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int nrhs,
+                     double M, int flags, void* stream);
+
+/* out = Gamma_5 psi with Gamma_5 = gamma_5 R, (R psi)_s = psi_{Ls+1-s} (Sec. 2.1).
+ * Bit-exact (sign flips and a permutation). complex128, or complex64 with DWF_PREC_F32. */
+int dwf_gamma5R(const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, int flags, void* stream);
+
+/* U(1) gauge transformation: Ug_mu(x) = (g(x) U_mu(x)) g(x+mu)^*, psig(x) = g(x) psi(x)
+ * for every slice, spin and rhs.  g [Ly][Lx] complex128.  Either output may be
+ * NULL to skip it.  Products are rounded one operation at a time (no fused
+ * multiply-add) so the result is reproducible bit for bit. */
+int dwf_gauge_transform(const void* U, const void* g, const void* psi, void* Ug, void* psig,
+                        int Lx, int Ly, int Ls, int nrhs, void* stream);
+
+/* Precision conversion of any complex array of n elements:
+ * dwf_pack:   complex128 -> complex64 (round to nearest);
+ * dwf_unpack: complex64  -> complex128 (exact). */
+int dwf_pack(const void* in_c128, void* out_c64, size_t n, void* stream);
+int dwf_unpack(const void* in_c64, void* out_c128, size_t n, void* stream);
+
+/* Fermion force for S = phi^dagger (D^dagger D)^{-1} phi, D = D_DW(m):
+ * with Y = D^{-dagger} phi and X = D^{-1} Y,
+ *   F_mu(x) = dS/dtheta_mu(x)
+ *           = 2 Re sum_{rhs,s} [ i U_mu(x) Y_s(x)^dag (1-gamma_mu)/2 X_s(x+mu)
+ *                               - i U_mu(x)^* Y_s(x+mu)^dag (1+gamma_mu)/2 X_s(x) ].
+ * U [2][Ly][Lx] complex128, X, Y [nrhs][Ls][Ly][Lx][2] complex128, F [2][Ly][Lx] double
+ * (overwritten). */
+int dwf_force(const void* U, const void* X, const void* Y, double* F, int Lx, int Ly, int Ls,
+              int nrhs, void* stream);
+
+/* ---------------------------------------------------------------- multigrid */
+typedef struct dwf_mg dwf_mg;
+
+/* Parameters of the K-cycle; dwf_mg_default_params fills the values of the
+ * paper's parameter table (Table kcycle) for `nlevels` coarse levels. */
+typedef struct {
+    int    nlevels;                       /* coarse levels, 1..DWF_MAX_LEVELS           */
+    int    nvec[DWF_MAX_LEVELS];          /* generated near-null vectors per level      */
+    int    block[DWF_MAX_LEVELS][2];      /* aggregate size (bx, by) per level          */
+    int    Ls_coarse[DWF_MAX_LEVELS];     /* fifth extent on each coarse level          */
+    int    link_prec[DWF_MAX_LEVELS];     /* DWF_P_* storage of each coarse kernel      */
+    int    vec_prec[DWF_MAX_LEVELS];      /* DWF_P_F64 / DWF_P_F32 Krylov vectors       */
+    int    fine_prec;                     /* DWF_P_F64 or DWF_P_F32 inner fine solve    */
+    double m_setup;                       /* mass of the setup Wilson kernel            */
+    int    setup_iters;                   /* CG iterations per null vector (max)        */
+    double setup_tol;                     /* |B v| <= setup_tol |B v0|                  */
+    int    outer_restart;                 /* fine flexible GCR restart length           */
+    int    smooth_iters;                  /* post-smoothing GCR steps (all levels)      */
+    int    inter_maxit;                   /* intermediate GCR max iterations            */
+    double inter_tol;                     /* intermediate GCR relative tolerance        */
+    int    inter_restart;
+    int    coarsest_maxit;                /* coarsest CGNR max iterations               */
+    double coarsest_tol;                  /* coarsest CGNR relative tolerance           */
+    double inner_tol;                     /* relative tolerance of one inner solve      */
+    int    max_iters;                     /* cap on fine GCR iterations per solve       */
+    int    max_outer;                     /* cap on defect-correction steps             */
+} dwf_mg_params;
+
+typedef struct {
+    int       status;                     /* same code as the return value              */
+    int       outer_steps;                /* defect-correction steps                    */
+    int       fine_iters;                 /* fine flexible-GCR iterations (max over rhs) */
+    long long fine_applies;               /* fine D_DW, D_DW^dag, D_PV, D_PV^dag applications */
+    long long level_iters[DWF_MAX_LEVELS];/* Krylov iterations summed over calls        */
+    long long level_calls[DWF_MAX_LEVELS];/* solves on each coarse level                */
+    double    true_rel_residual;          /* max over rhs of |b - D_DW x| / |b| (FP64)  */
+    double    solve_ms;                   /* wall time of the solve                     */
+} dwf_solve_stats;
+
+void dwf_mg_default_params(dwf_mg_params* p, int nlevels);
+
+/* Build the hierarchy for gauge field U (complex128 [2][Ly][Lx], device).
+ * null_starts[l] (device, complex128 [nvec_l][Ly_l][Lx_l][n_l]) are the
+ * starting vectors of level l's setup relaxation, with n_0 = 2 and
+ * n_l = 2*nvec_{l-1}; they are copied, not kept.  Per level: CG on
+ * D_W(m_setup) D_W(m_setup)^dagger v = 0 (Sec. 3.1), chiral doubling, block
+ * Gram-Schmidt, Galerkin kernel.  Allocates device memory owned by the
+ * context.  Errors: DWF_EINVAL (sizes not divisible by the blocks, nvec larger
+ * than the block dimension, Ls < 2), DWF_EUNSUPPORTED (2*nvec not in
+ * {4,8,12,16,24,32,48,64}), DWF_EBREAKDOWN (dependent null vectors), DWF_EHIP. */
+int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, double M5,
+             const dwf_mg_params* params, const void* const* null_starts, void* stream);
+
+/* Solve D_DW(m_f) x = b for nrhs right-hand sides b, x [nrhs][Ls][Ly][Lx][2]
+ * complex128 (device): flexible GCR on D_PV^dagger D_DW with the K-cycle as
+ * preconditioner (Sec. 2.3 summary) inside an FP64 defect correction, until
+ * |b - D_DW x| <= tol |b| for every rhs (FP64 true residual).  x is
+ * overwritten (zero initial guess).  Synchronises `stream` at the end.
+ * Returns DWF_NOT_CONVERGED when the caps are hit (x is the last iterate). */
+int mg_solve(dwf_mg* mg, const void* b, void* x, int nrhs, double tol, dwf_solve_stats* st,
+             void* stream);
+
+/* Level operators of a built hierarchy, for testing and diagnostics.  Fields
+ * are complex128 in the level's layout ([ncol][Ls_l][Ly_l][Lx_l][n_l]; 2-d
+ * fields have Ls_l = 1) and are converted to the level's working precision. */
+#define MG_OP_DW         0     /* D_DW(m)                                         */
+#define MG_OP_DW_DAG     1
+#define MG_OP_PV         2     /* D_PV                                            */
+#define MG_OP_PV_DAG     3
+#define MG_OP_A          4     /* D_PV^dag D_DW(m)                                */
+#define MG_OP_WILSON     5     /* 2-d kernel D_W(M) at M = the `mass` argument    */
+#define MG_OP_WILSON_DAG 6
+#define MG_OP_RESTRICT   7     /* level l -> l+1 wall restriction                 */
+#define MG_OP_PROLONG    8     /* level l+1 -> l wall prolongation                */
+#define MG_OP_KCYCLE     9     /* one application of level l's preconditioner    */
+int mg_level_op(dwf_mg* mg, int level, int op, const void* in, void* out, int ncol, double mass,
+                void* stream);
+
+/* Copy out level l's prolongator V[y][x][c][j][k] (complex128,
+ * Ly_l*Lx_l*2*nc*nvec) or coarse kernel (level l+1) in stencil form
+ * diag[Y][X][n][n] then hop[4][Y][X][n][n] (h = +x, -x, +y, -y), complex128. */
+int mg_export(dwf_mg* mg, int level, void* prolongator, void* coarse_kernel, void* stream);
+
+/* Geometry of level l: fills Lx, Ly, Ls, dof per site and nvec (0 on the coarsest). */
+int mg_level_info(const dwf_mg* mg, int level, int* Lx, int* Ly, int* Ls, int* n, int* nvec);
+
+int mg_destroy(dwf_mg* mg);
+
+/* Release the library-owned scratch field of dwf_pv_apply. */
+int dwf_release_scratch(void);
+
+const char* dwf_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DWFMG_H */

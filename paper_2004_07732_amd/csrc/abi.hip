@@ -1,0 +1,272 @@
+// C ABI of the library (declared in include/dwfmg.h): argument checks,
+// precision dispatch and status codes.  No exception crosses this boundary.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "mg.hpp"
+
+using namespace dwf;
+
+struct dwf_mg {
+    Hierarchy h;
+    bool ready = false;
+};
+
+namespace {
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+inline int hip_status(hipError_t e) { return e == hipSuccess ? DWF_OK : DWF_EHIP; }
+
+bool dims_ok(int Lx, int Ly, int Ls, int nrhs) {
+    return Lx >= 1 && Ly >= 1 && Ls >= 1 && nrhs >= 1 && (long long)Lx * Ly < (1LL << 30) &&
+           (long long)Lx * Ly * Ls * nrhs < (1LL << 40);
+}
+
+// library-owned intermediate field of the product modes of dwf_pv_apply
+std::mutex g_scratch_mu;
+void* g_scratch = nullptr;
+size_t g_scratch_bytes = 0;
+
+void* scratch(size_t bytes) {
+    if (bytes <= g_scratch_bytes) return g_scratch;
+    if (g_scratch) { hipDeviceSynchronize(); hipFree(g_scratch); }
+    g_scratch = nullptr;
+    g_scratch_bytes = 0;
+    if (hipMalloc(&g_scratch, bytes) != hipSuccess) return nullptr;
+    g_scratch_bytes = bytes;
+    return g_scratch;
+}
+
+template <typename R>
+int pv_apply_t(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, double m,
+               double M5, int mode, hipStream_t st) {
+    auto u = reinterpret_cast<const cpx<R>*>(U);
+    auto in = reinterpret_cast<const cpx<R>*>(psi);
+    auto o = reinterpret_cast<cpx<R>*>(out);
+    switch (mode) {
+        case DWF_PV: return hip_status(fine_dw<R>(u, in, o, nullptr, Lx, Ly, Ls, nrhs, 1.0, M5, false, nullptr, 1, st));
+        case DWF_PV_DAG: return hip_status(fine_dw<R>(u, in, o, nullptr, Lx, Ly, Ls, nrhs, 1.0, M5, true, nullptr, 1, st));
+        case DWF_PVDAG_DW:
+        case DWF_PVDAG_DW_DAG: {
+            std::lock_guard<std::mutex> lk(g_scratch_mu);
+            const size_t bytes = sizeof(cpx<R>) * 2 * (size_t)Lx * Ly * Ls * nrhs;
+            auto t = reinterpret_cast<cpx<R>*>(scratch(bytes));
+            if (!t) return DWF_EHIP;
+            if (mode == DWF_PVDAG_DW) {
+                if (fine_dw<R>(u, in, t, nullptr, Lx, Ly, Ls, nrhs, m, M5, false, nullptr, 1, st) != hipSuccess) return DWF_EHIP;
+                return hip_status(fine_dw<R>(u, t, o, nullptr, Lx, Ly, Ls, nrhs, 1.0, M5, true, nullptr, 1, st));
+            }
+            if (fine_dw<R>(u, in, t, nullptr, Lx, Ly, Ls, nrhs, 1.0, M5, false, nullptr, 1, st) != hipSuccess) return DWF_EHIP;
+            return hip_status(fine_dw<R>(u, t, o, nullptr, Lx, Ly, Ls, nrhs, m, M5, true, nullptr, 1, st));
+        }
+        default: return DWF_EINVAL;
+    }
+}
+
+bool valid_prec(int p, bool link) {
+    if (p == DWF_P_F64 || p == DWF_P_F32) return true;
+    return link && (p == DWF_P_BF16 || p == DWF_P_F16);
+}
+
+}  // namespace
+
+extern "C" {
+
+int dwf_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, double m_f,
+              double M5, int flags, void* stream) {
+    if (!U || !psi || !out || psi == out || !dims_ok(Lx, Ly, Ls, nrhs)) return DWF_EINVAL;
+    if (!std::isfinite(m_f) || !std::isfinite(M5)) return DWF_EINVAL;
+    const bool dag = flags & DWF_DAGGER;
+    if (flags & DWF_PREC_F32)
+        return hip_status(fine_dw<float>((const cpx<float>*)U, (const cpx<float>*)psi, (cpx<float>*)out, nullptr, Lx, Ly,
+                                         Ls, nrhs, m_f, M5, dag, nullptr, 1, S(stream)));
+    return hip_status(fine_dw<double>((const cpx<double>*)U, (const cpx<double>*)psi, (cpx<double>*)out, nullptr, Lx,
+                                      Ly, Ls, nrhs, m_f, M5, dag, nullptr, 1, S(stream)));
+}
+
+int dwf_pv_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, double m_f,
+                 double M5, int mode, int flags, void* stream) {
+    if (!U || !psi || !out || psi == out || !dims_ok(Lx, Ly, Ls, nrhs)) return DWF_EINVAL;
+    if (!std::isfinite(m_f) || !std::isfinite(M5) || mode < DWF_PV || mode > DWF_PVDAG_DW_DAG) return DWF_EINVAL;
+    if (flags & DWF_PREC_F32) return pv_apply_t<float>(U, psi, out, Lx, Ly, Ls, nrhs, m_f, M5, mode, S(stream));
+    return pv_apply_t<double>(U, psi, out, Lx, Ly, Ls, nrhs, m_f, M5, mode, S(stream));
+}
+
+int dwf_wilson_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int nrhs, double M, int flags,
+                     void* stream) {
+    if (!U || !psi || !out || psi == out || !dims_ok(Lx, Ly, 1, nrhs) || !std::isfinite(M)) return DWF_EINVAL;
+    const bool dag = flags & DWF_DAGGER;
+    if (flags & DWF_PREC_F32)
+        return hip_status(wilson2d<float>((const cpx<float>*)U, (const cpx<float>*)psi, (cpx<float>*)out, Lx, Ly, nrhs,
+                                          M, dag, S(stream)));
+    return hip_status(wilson2d<double>((const cpx<double>*)U, (const cpx<double>*)psi, (cpx<double>*)out, Lx, Ly, nrhs,
+                                       M, dag, S(stream)));
+}
+
+int dwf_gamma5R(const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, int flags, void* stream) {
+    if (!psi || !out || psi == out || !dims_ok(Lx, Ly, Ls, nrhs)) return DWF_EINVAL;
+    if (flags & DWF_PREC_F32)
+        return hip_status(gamma5R<float>((const cpx<float>*)psi, (cpx<float>*)out, Lx * Ly, Ls, nrhs, S(stream)));
+    return hip_status(gamma5R<double>((const cpx<double>*)psi, (cpx<double>*)out, Lx * Ly, Ls, nrhs, S(stream)));
+}
+
+int dwf_gauge_transform(const void* U, const void* g, const void* psi, void* Ug, void* psig, int Lx, int Ly, int Ls,
+                        int nrhs, void* stream) {
+    if (!g || !dims_ok(Lx, Ly, Ls, nrhs)) return DWF_EINVAL;
+    if (Ug && !U) return DWF_EINVAL;
+    if (psig && !psi) return DWF_EINVAL;
+    return hip_status(gauge_transform((const cpx<double>*)U, (const cpx<double>*)g, (const cpx<double>*)psi,
+                                      (cpx<double>*)Ug, (cpx<double>*)psig, Lx, Ly, Ls, nrhs, S(stream)));
+}
+
+int dwf_pack(const void* in_c128, void* out_c64, size_t n, void* stream) {
+    if (!in_c128 || !out_c64) return DWF_EINVAL;
+    if (n == 0) return DWF_OK;
+    return hip_status(vconvert<double, float>((const cpx<double>*)in_c128, (cpx<float>*)out_c64, n, S(stream)));
+}
+
+int dwf_unpack(const void* in_c64, void* out_c128, size_t n, void* stream) {
+    if (!in_c64 || !out_c128) return DWF_EINVAL;
+    if (n == 0) return DWF_OK;
+    return hip_status(vconvert<float, double>((const cpx<float>*)in_c64, (cpx<double>*)out_c128, n, S(stream)));
+}
+
+int dwf_force(const void* U, const void* X, const void* Y, double* F, int Lx, int Ly, int Ls, int nrhs, void* stream) {
+    if (!U || !X || !Y || !F || !dims_ok(Lx, Ly, Ls, nrhs)) return DWF_EINVAL;
+    return hip_status(force((const cpx<double>*)U, (const cpx<double>*)X, (const cpx<double>*)Y, F, Lx, Ly, Ls, nrhs,
+                            S(stream)));
+}
+
+void dwf_mg_default_params(dwf_mg_params* p, int nlevels) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    if (nlevels < 1) nlevels = 1;
+    if (nlevels > DWF_MAX_LEVELS) nlevels = DWF_MAX_LEVELS;
+    p->nlevels = nlevels;
+    for (int l = 0; l < DWF_MAX_LEVELS; ++l) {
+        p->nvec[l] = (l == 0) ? 8 : 12;           // Table kcycle
+        p->block[l][0] = p->block[l][1] = (l == 0) ? 4 : 2;
+        p->Ls_coarse[l] = 4;
+        p->link_prec[l] = DWF_P_F64;
+        p->vec_prec[l] = DWF_P_F64;
+    }
+    p->fine_prec = DWF_P_F64;
+    p->m_setup = 0.0;
+    p->setup_iters = 250;
+    p->setup_tol = 1e-4;
+    p->outer_restart = 16;
+    p->smooth_iters = 8;
+    p->inter_maxit = 16;
+    p->inter_tol = 0.25;
+    p->inter_restart = 16;
+    p->coarsest_maxit = 1024;
+    p->coarsest_tol = 0.05;
+    p->inner_tol = 0.0;
+    p->max_iters = 10000;
+    p->max_outer = 20;
+}
+
+int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, double M5, const dwf_mg_params* p,
+             const void* const* null_starts, void* stream) {
+    if (!out || !U || !p || !null_starts) return DWF_EINVAL;
+    *out = nullptr;
+    if (!dims_ok(Lx, Ly, Ls, 1) || Ls < 2 || !std::isfinite(m_f) || !std::isfinite(M5)) return DWF_EINVAL;
+    if (p->nlevels < 1 || p->nlevels > DWF_MAX_LEVELS) return DWF_EINVAL;
+    if (p->outer_restart < 1 || p->outer_restart > 16 || p->smooth_iters < 0 || p->smooth_iters > 16) return DWF_EINVAL;
+    if (p->nlevels > 1 && (p->inter_restart < 1 || p->inter_restart > 16)) return DWF_EINVAL;
+    if (!valid_prec(p->fine_prec, false)) return DWF_EINVAL;
+    int lx = Lx, ly = Ly, n = 2;
+    for (int l = 0; l < p->nlevels; ++l) {
+        const int bx = p->block[l][0], by = p->block[l][1], nv = p->nvec[l];
+        if (bx < 1 || by < 1 || lx % bx || ly % by || nv < 1) return DWF_EINVAL;
+        if (nv > bx * by * (n / 2)) return DWF_EINVAL;
+        if (p->Ls_coarse[l] < 2 || p->Ls_coarse[l] > 8) return DWF_EINVAL;
+        if (!valid_prec(p->link_prec[l], true) || !valid_prec(p->vec_prec[l], false)) return DWF_EINVAL;
+        if (!null_starts[l]) return DWF_EINVAL;
+        const int nn = 2 * nv;
+        if (nn != 4 && nn != 8 && nn != 12 && nn != 16 && nn != 24 && nn != 32 && nn != 48 && nn != 64)
+            return DWF_EUNSUPPORTED;
+        if ((long long)bx * by * (n / 2) * nv > 4096) return DWF_EUNSUPPORTED;
+        lx /= bx;
+        ly /= by;
+        n = nn;
+    }
+    dwf_mg* mg = new (std::nothrow) dwf_mg;
+    if (!mg) return DWF_EHIP;
+    int e = mg->h.setup((const cpx<double>*)U, Lx, Ly, Ls, m_f, M5, *p, null_starts, S(stream));
+    if (e != DWF_OK) {
+        delete mg;
+        return e;
+    }
+    mg->ready = true;
+    *out = mg;
+    return DWF_OK;
+}
+
+int mg_solve(dwf_mg* mg, const void* b, void* x, int nrhs, double tol, dwf_solve_stats* st, void* stream) {
+    if (!mg || !mg->ready) return DWF_ENOSETUP;
+    if (!b || !x || b == x || nrhs < 1 || !(tol > 0.0) || !std::isfinite(tol)) return DWF_EINVAL;
+    if (st) std::memset(st, 0, sizeof(*st));
+    int e = mg->h.solve((const cpx<double>*)b, (cpx<double>*)x, nrhs, tol, st, S(stream));
+    if (st) st->status = e;
+    return e;
+}
+
+int mg_level_op(dwf_mg* mg, int level, int op, const void* in, void* out, int ncol, double mass, void* stream) {
+    if (!mg || !mg->ready) return DWF_ENOSETUP;
+    if (!in || !out || in == out) return DWF_EINVAL;
+    return mg->h.level_op(level, op, (const cpx<double>*)in, (cpx<double>*)out, ncol, mass, S(stream));
+}
+
+int mg_export(dwf_mg* mg, int level, void* prolongator, void* coarse_kernel, void* stream) {
+    if (!mg || !mg->ready) return DWF_ENOSETUP;
+    return mg->h.export_level(level, (cpx<double>*)prolongator, (cpx<double>*)coarse_kernel, S(stream));
+}
+
+int mg_level_info(const dwf_mg* mg, int level, int* Lx, int* Ly, int* Ls, int* n, int* nvec) {
+    if (!mg || !mg->ready) return DWF_ENOSETUP;
+    if (level < 0 || level >= (int)mg->h.levels.size()) return DWF_EINVAL;
+    const Level& L = mg->h.levels[level];
+    if (Lx) *Lx = L.Lx;
+    if (Ly) *Ly = L.Ly;
+    if (Ls) *Ls = L.Ls;
+    if (n) *n = L.n;
+    if (nvec) *nvec = L.nvec_next;
+    return DWF_OK;
+}
+
+int mg_destroy(dwf_mg* mg) {
+    if (!mg) return DWF_EINVAL;
+    hipDeviceSynchronize();
+    delete mg;
+    return DWF_OK;
+}
+
+int dwf_release_scratch(void) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch) {
+        hipDeviceSynchronize();
+        hipFree(g_scratch);
+    }
+    g_scratch = nullptr;
+    g_scratch_bytes = 0;
+    return DWF_OK;
+}
+
+const char* dwf_strerror(int code) {
+    switch (code) {
+        case DWF_OK: return "ok";
+        case DWF_NOT_CONVERGED: return "not converged: iteration caps reached";
+        case DWF_EINVAL: return "invalid argument";
+        case DWF_EHIP: return "HIP runtime error";
+        case DWF_EBREAKDOWN: return "Krylov or Gram-Schmidt breakdown";
+        case DWF_ENAN: return "non-finite value";
+        case DWF_ENOSETUP: return "multigrid context missing or not set up";
+        case DWF_EUNSUPPORTED: return "unsupported size or option";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

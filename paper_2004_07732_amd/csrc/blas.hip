@@ -1,0 +1,544 @@
+// BLAS-1 kernels and the device-resident Krylov scalar algebra.
+//
+// Every reduction is deterministic: a block reduces with wavefront shuffles
+// (64 lanes) and a fixed-order sum over its four waves, writes one partial per
+// quantity, and the last block of the column (atomic ticket) sums the
+// partials in block order and runs the finaliser that turns sums into Krylov
+// coefficients.  The host never has to read a scalar back to continue: CG,
+// CGNR and GCR coefficients are computed on the device and consumed by the
+// next kernel, and a per-column `done` / `stop` flag turns later updates into
+// no-ops.  Accumulation is FP64 for both FP32 and FP64 vectors.
+#include "kernels.hpp"
+
+namespace dwf {
+
+namespace {
+
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxQ = 40;
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    return x;
+}
+
+// Reduce per-thread values v[0..nq) over the block; totals end in tot[0..nq)
+// (shared) and are visible to every thread of the block afterwards.
+template <int NQ>
+__device__ __forceinline__ void block_reduce(double (&v)[NQ], int nq, double* sh, double* tot) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (q < nq) {
+            double s = wave_sum(v[q]);
+            if (lane == 0) sh[q * kWaves + wid] = s;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nq) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s += sh[threadIdx.x * kWaves + w];
+        tot[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Block partials -> column totals.  Returns true in the last block of the
+// column, where tot[0..nq) then hold the full sums.
+template <int NQ>
+__device__ bool reduce_column(double (&v)[NQ], int nq, const RedWork& rw, int col, double* sh,
+                              double* tot) {
+    __shared__ bool last;
+    block_reduce<NQ>(v, nq, sh, tot);
+    double* part = rw.partial + (size_t)col * rw.max_q * rw.nblk;
+    if (threadIdx.x < nq) part[(size_t)threadIdx.x * rw.nblk + blockIdx.x] = tot[threadIdx.x];
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = atomicAdd(&rw.ticket[col], 1u);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double w[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        w[q] = 0.0;
+        if (q < nq) {
+            for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+                w[q] += __hip_atomic_load(&part[(size_t)q * rw.nblk + b], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    block_reduce<NQ>(w, nq, sh, tot);
+    if (threadIdx.x == 0) rw.ticket[col] = 0u;
+    return true;
+}
+
+inline dim3 red_grid(size_t n, int ncol, const RedWork& rw) {
+    long long nb = (long long)((n + kBlock - 1) / kBlock);
+    if (nb > rw.nblk) nb = rw.nblk;
+    if (nb < 1) nb = 1;
+    return dim3((unsigned)nb, (unsigned)ncol);
+}
+
+inline dim3 ew_grid(size_t n, int ncol) {
+    long long nb = (long long)((n + kBlock - 1) / kBlock);
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    return dim3((unsigned)nb, (unsigned)ncol);
+}
+
+#define GRID_STRIDE(i, n) \
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
+
+template <typename T>
+__device__ __forceinline__ cpx<double> up(cpx<T> a) { return {(double)a.re, (double)a.im}; }
+
+__device__ __forceinline__ bool finite(double x) { return !(isnan(x) || isinf(x)); }
+
+}  // namespace
+
+// ------------------------------------------------------------ elementwise
+template <typename T>
+__global__ void k_zero(cpx<T>* x, size_t n) {
+    GRID_STRIDE(i, n) x[i] = {T(0), T(0)};
+}
+template <typename Ti, typename To>
+__global__ void k_convert(const cpx<Ti>* in, cpx<To>* out, size_t n) {
+    GRID_STRIDE(i, n) out[i] = {(To)in[i].re, (To)in[i].im};
+}
+template <typename Tx, typename Ty>
+__global__ void k_add(const cpx<Tx>* x, cpx<Ty>* y, size_t n) {
+    GRID_STRIDE(i, n) {
+        cpx<Ty> a = y[i];
+        y[i] = {a.re + (Ty)x[i].re, a.im + (Ty)x[i].im};
+    }
+}
+template <typename T>
+__global__ void k_sub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n) {
+    GRID_STRIDE(i, n) out[i] = a[i] - b[i];
+}
+
+template <typename T> hipError_t vzero(cpx<T>* x, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero<T>, ew_grid(n, 1), dim3(kBlock), 0, st, x, n);
+    return hipGetLastError();
+}
+template <typename Ti, typename To>
+hipError_t vconvert(const cpx<Ti>* in, cpx<To>* out, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_convert<Ti, To>), ew_grid(n, 1), dim3(kBlock), 0, st, in, out, n);
+    return hipGetLastError();
+}
+template <typename Tx, typename Ty>
+hipError_t vadd(const cpx<Tx>* x, cpx<Ty>* y, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_add<Tx, Ty>), ew_grid(n, 1), dim3(kBlock), 0, st, x, y, n);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t vsub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_sub<T>, ew_grid(n, 1), dim3(kBlock), 0, st, a, b, out, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ plain reductions
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_norm2(const cpx<T>* x, size_t n, double* out, RedWork rw) {
+    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
+    const int col = blockIdx.y;
+    const cpx<T>* xc = x + (size_t)col * n;
+    double v[1] = {0.0};
+    GRID_STRIDE(i, n) {
+        cpx<double> a = up(xc[i]);
+        v[0] += a.re * a.re + a.im * a.im;
+    }
+    if (reduce_column<1>(v, 1, rw, col, sh, tot) && threadIdx.x == 0) out[col] = tot[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cdot(const cpx<T>* a, const cpx<T>* b, size_t n, double* out, RedWork rw) {
+    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
+    const int col = blockIdx.y;
+    const cpx<T>* ac = a + (size_t)col * n;
+    const cpx<T>* bc = b + (size_t)col * n;
+    double v[2] = {0.0, 0.0};
+    GRID_STRIDE(i, n) {
+        cpx<double> p = cjmul(up(ac[i]), up(bc[i]));
+        v[0] += p.re;
+        v[1] += p.im;
+    }
+    if (reduce_column<2>(v, 2, rw, col, sh, tot) && threadIdx.x == 0) {
+        out[2 * col] = tot[0];
+        out[2 * col + 1] = tot[1];
+    }
+}
+
+template <typename T>
+hipError_t norm2(const cpx<T>* x, size_t n, int ncol, double* out, const RedWork& rw, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm2<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, x, n, out, rw);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t cdot(const cpx<T>* a, const cpx<T>* b, size_t n, int ncol, double* out2, const RedWork& rw, hipStream_t st) {
+    hipLaunchKernelGGL(k_cdot<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, a, b, n, out2, rw);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ CG family
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_init(const cpx<T>* v, size_t n, CgScal* s, double tol2, RedWork rw) {
+    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
+    const int col = blockIdx.y;
+    const cpx<T>* vc = v + (size_t)col * n;
+    double q[1] = {0.0};
+    GRID_STRIDE(i, n) {
+        cpx<double> a = up(vc[i]);
+        q[0] += a.re * a.re + a.im * a.im;
+    }
+    if (reduce_column<1>(q, 1, rw, col, sh, tot) && threadIdx.x == 0) {
+        CgScal c;
+        c.zz = tot[0];
+        c.zz0 = tot[0];
+        c.alpha = 0.0;
+        c.beta = 0.0;
+        c.tol2 = tol2;
+        c.iters = 0;
+        c.done = (tot[0] == 0.0) ? 1 : (finite(tot[0]) ? 0 : 4);
+        s[col] = c;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_alpha(const cpx<T>* w, size_t n, CgScal* s, RedWork rw) {
+    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
+    const int col = blockIdx.y;
+    if (s[col].done) return;   // uniform per column: no block of this column reduces
+    const cpx<T>* wc = w + (size_t)col * n;
+    double q[1] = {0.0};
+    GRID_STRIDE(i, n) {
+        cpx<double> a = up(wc[i]);
+        q[0] += a.re * a.re + a.im * a.im;
+    }
+    if (reduce_column<1>(q, 1, rw, col, sh, tot) && threadIdx.x == 0) {
+        const double ww = tot[0];
+        if (!(ww > 0.0) || !finite(ww)) {
+            s[col].alpha = 0.0;
+            s[col].done = finite(ww) ? 2 : 4;   // breakdown / non-finite
+        } else {
+            s[col].alpha = s[col].zz / ww;
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_cg_update_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* w, size_t n, const CgScal* s) {
+    const int col = blockIdx.y;
+    if (s[col].done) return;
+    const T a = (T)s[col].alpha;
+    const size_t o = (size_t)col * n;
+    GRID_STRIDE(i, n) {
+        cpx<T> pi = p[o + i], wi = w[o + i], xi = x[o + i], ri = r[o + i];
+        x[o + i] = {xi.re + a * pi.re, xi.im + a * pi.im};
+        r[o + i] = {ri.re - a * wi.re, ri.im - a * wi.im};
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_beta(const cpx<T>* z, size_t n, CgScal* s, int maxit, RedWork rw) {
+    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
+    const int col = blockIdx.y;
+    if (s[col].done) return;
+    const cpx<T>* zc = z + (size_t)col * n;
+    double q[1] = {0.0};
+    GRID_STRIDE(i, n) {
+        cpx<double> a = up(zc[i]);
+        q[0] += a.re * a.re + a.im * a.im;
+    }
+    if (reduce_column<1>(q, 1, rw, col, sh, tot) && threadIdx.x == 0) {
+        CgScal c = s[col];
+        const double znew = tot[0];
+        c.iters += 1;
+        if (!finite(znew)) {
+            c.done = 4;
+        } else {
+            c.beta = znew / c.zz;
+            c.zz = znew;
+            if (znew <= c.tol2 * c.zz0) c.done = 1;
+            else if (c.iters >= maxit) c.done = 3;
+        }
+        s[col] = c;
+    }
+}
+
+template <typename T>
+__global__ void k_cg_update_p(cpx<T>* p, const cpx<T>* z, size_t n, const CgScal* s) {
+    const int col = blockIdx.y;
+    if (s[col].done) return;
+    const T b = (T)s[col].beta;
+    const size_t o = (size_t)col * n;
+    GRID_STRIDE(i, n) {
+        cpx<T> pi = p[o + i], zi = z[o + i];
+        p[o + i] = {zi.re + b * pi.re, zi.im + b * pi.im};
+    }
+}
+
+template <typename T>
+hipError_t cg_init(const cpx<T>* v, size_t n, int ncol, CgScal* s, double tol, const RedWork& rw, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_init<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, v, n, s, tol * tol, rw);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t cg_alpha(const cpx<T>* w, size_t n, int ncol, CgScal* s, const RedWork& rw, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_alpha<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, w, n, s, rw);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t cg_update_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* w, size_t n, int ncol,
+                        const CgScal* s, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_update_xr<T>, ew_grid(n, ncol), dim3(kBlock), 0, st, x, r, p, w, n, s);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t cg_beta(const cpx<T>* z, size_t n, int ncol, CgScal* s, int maxit, const RedWork& rw, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_beta<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, z, n, s, maxit, rw);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t cg_update_p(cpx<T>* p, const cpx<T>* z, size_t n, int ncol, const CgScal* s, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_update_p<T>, ew_grid(n, ncol), dim3(kBlock), 0, st, p, z, n, s);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ GCR
+namespace {
+__device__ __forceinline__ cpx<double> ld2(const double* p) { return {p[0], p[1]}; }
+__device__ __forceinline__ cpx<double> cdiv_real(cpx<double> a, double d) {
+    return d > 0.0 ? cpx<double>{a.re / d, a.im / d} : cpx<double>{0.0, 0.0};
+}
+}  // namespace
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_gcr_multidot(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w, size_t n, GcrDev g, RedWork rw) {
+    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
+    const int col = blockIdx.y;
+    const size_t o = (size_t)col * n;
+    const bool stop = g.stop[col] != 0;
+    double v[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) v[q] = 0.0;
+    if (!stop) GRID_STRIDE(e, n) {
+        const cpx<double> we = up(w[o + e]);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i < j) {
+                cpx<double> p = cjmul(up(W[(size_t)i * wstride + o + e]), we);
+                v[2 * i] += p.re;
+                v[2 * i + 1] += p.im;
+            }
+        }
+    }
+    if (reduce_column<32>(v, 2 * j, rw, col, sh, tot)) {
+        if (threadIdx.x < 2 * j) g.D[((size_t)col * g.kmax + j) * g.kmax * 2 + threadIdx.x] = tot[threadIdx.x];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_gcr_orth(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, const cpx<T>* r, size_t n, GcrDev g, RedWork rw) {
+    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
+    const int col = blockIdx.y;
+    const bool stop = g.stop[col] != 0;
+    const size_t o = (size_t)col * n;
+    cpx<T> c[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        c[i] = {T(0), T(0)};
+        if (i < j && !stop) {
+            cpx<double> d = ld2(&g.D[(((size_t)col * g.kmax + j) * g.kmax + i) * 2]);
+            cpx<double> ci = cdiv_real(d, g.nn[(size_t)col * g.kmax + i]);
+            c[i] = {(T)ci.re, (T)ci.im};
+        }
+    }
+    double v[3] = {0.0, 0.0, 0.0};
+    GRID_STRIDE(e, n) {
+        cpx<T> we = w[o + e];
+        if (!stop && j > 0) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i < j) {
+                    cpx<T> Wi = W[(size_t)i * wstride + o + e];
+                    we.re -= c[i].re * Wi.re - c[i].im * Wi.im;
+                    we.im -= c[i].re * Wi.im + c[i].im * Wi.re;
+                }
+            w[o + e] = we;
+        }
+        const cpx<double> wd = up(we), rd = up(r[o + e]);
+        v[0] += wd.re * wd.re + wd.im * wd.im;
+        cpx<double> p = cjmul(wd, rd);
+        v[1] += p.re;
+        v[2] += p.im;
+    }
+    if (reduce_column<3>(v, 3, rw, col, sh, tot) && threadIdx.x == 0) {
+        const size_t s = (size_t)col * g.kmax + j;
+        if (stop) {
+            g.nn[s] = 0.0;
+            g.wr[2 * s] = 0.0;
+            g.wr[2 * s + 1] = 0.0;
+        } else {
+            g.nn[s] = tot[0];
+            g.wr[2 * s] = tot[1];
+            g.wr[2 * s + 1] = tot[2];
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int want_norm, GcrDev g, RedWork rw) {
+    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
+    const int col = blockIdx.y;
+    const size_t s = (size_t)col * g.kmax + j;
+    const cpx<double> ad = cdiv_real(ld2(&g.wr[2 * s]), g.nn[s]);
+    const cpx<T> a = {(T)ad.re, (T)ad.im};
+    const size_t o = (size_t)col * n;
+    double v[1] = {0.0};
+    GRID_STRIDE(e, n) {
+        cpx<T> re = r[o + e];
+        const cpx<T> we = w[o + e];
+        re.re -= a.re * we.re - a.im * we.im;
+        re.im -= a.re * we.im + a.im * we.re;
+        r[o + e] = re;
+        if (copy) copy[o + e] = re;
+        const cpx<double> rd = up(re);
+        v[0] += rd.re * rd.re + rd.im * rd.im;
+    }
+    if (want_norm) {
+        if (reduce_column<1>(v, 1, rw, col, sh, tot) && threadIdx.x == 0) g.rr[col] = tot[0];
+    }
+}
+
+__global__ void k_gcr_solve(int k, int ncol, GcrDev g) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ncol) return;
+    const size_t b = (size_t)col * g.kmax;
+    for (int j = k - 1; j >= 0; --j) {
+        cpx<double> gj = cdiv_real(ld2(&g.wr[2 * (b + j)]), g.nn[b + j]);
+        for (int l = j + 1; l < k; ++l) {
+            // beta_{j l} = <w_j, A p_l> / |w_j|^2
+            cpx<double> bjl = cdiv_real(ld2(&g.D[((b + l) * g.kmax + j) * 2]), g.nn[b + j]);
+            cpx<double> gl = ld2(&g.gam[2 * (b + l)]);
+            cpx<double> t = cmul(bjl, gl);
+            gj.re -= t.re;
+            gj.im -= t.im;
+        }
+        g.gam[2 * (b + j)] = gj.re;
+        g.gam[2 * (b + j) + 1] = gj.im;
+    }
+}
+
+template <typename T, typename Tx>
+__global__ void k_gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int accumulate, GcrDev g) {
+    const int col = blockIdx.y;
+    const size_t o = (size_t)col * n;
+    cpx<double> c[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) c[i] = (i < k) ? ld2(&g.gam[2 * ((size_t)col * g.kmax + i)]) : cpx<double>{0.0, 0.0};
+    GRID_STRIDE(e, n) {
+        cpx<double> acc = {0.0, 0.0};
+        if (accumulate) acc = {(double)x[o + e].re, (double)x[o + e].im};
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < k) {
+                const cpx<double> p = up(P[(size_t)i * pstride + o + e]);
+                acc.re += c[i].re * p.re - c[i].im * p.im;
+                acc.im += c[i].re * p.im + c[i].im * p.re;
+            }
+        x[o + e] = {(Tx)acc.re, (Tx)acc.im};
+    }
+}
+
+template <typename T>
+hipError_t gcr_multidot(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w, size_t n, int ncol,
+                        const GcrDev& g, const RedWork& rw, hipStream_t st) {
+    if (j <= 0) return hipSuccess;
+    if (j > 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gcr_multidot<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, W, wstride, j, w, n, g, rw);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t gcr_orth(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, const cpx<T>* r, size_t n,
+                    int ncol, const GcrDev& g, const RedWork& rw, hipStream_t st) {
+    if (j > 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gcr_orth<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, W, wstride, j, w, r, n, g, rw);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int ncol,
+                       bool want_norm, const GcrDev& g, const RedWork& rw, hipStream_t st) {
+    dim3 grid = want_norm ? red_grid(n, ncol, rw) : ew_grid(n, ncol);
+    hipLaunchKernelGGL(k_gcr_rupdate<T>, grid, dim3(kBlock), 0, st, w, r, copy, j, n, want_norm ? 1 : 0, g, rw);
+    return hipGetLastError();
+}
+hipError_t gcr_solve(int k, int ncol, const GcrDev& g, hipStream_t st) {
+    hipLaunchKernelGGL(k_gcr_solve, dim3(grid_for(ncol, 64)), dim3(64), 0, st, k, ncol, g);
+    return hipGetLastError();
+}
+template <typename T, typename Tx>
+hipError_t gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int ncol,
+                       bool accumulate, const GcrDev& g, hipStream_t st) {
+    if (k > 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gcr_xupdate<T, Tx>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, pstride, k, x, n,
+                       accumulate ? 1 : 0, g);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ finiteness check
+template <typename T>
+__global__ void k_check_finite(const cpx<T>* x, size_t n, int* flag) {
+    bool bad = false;
+    GRID_STRIDE(i, n) {
+        cpx<T> a = x[i];
+        if (isnan(a.re) || isnan(a.im) || isinf(a.re) || isinf(a.im)) bad = true;
+    }
+    if (bad) flag[0] = 1;
+}
+template <typename T>
+hipError_t check_finite(const cpx<T>* x, size_t n, int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_finite<T>, ew_grid(n, 1), dim3(kBlock), 0, st, x, n, flag);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ instantiations
+#define INST_T(T)                                                                                       \
+    template hipError_t vzero<T>(cpx<T>*, size_t, hipStream_t);                                         \
+    template hipError_t vsub<T>(const cpx<T>*, const cpx<T>*, cpx<T>*, size_t, hipStream_t);            \
+    template hipError_t norm2<T>(const cpx<T>*, size_t, int, double*, const RedWork&, hipStream_t);     \
+    template hipError_t cdot<T>(const cpx<T>*, const cpx<T>*, size_t, int, double*, const RedWork&, hipStream_t); \
+    template hipError_t cg_init<T>(const cpx<T>*, size_t, int, CgScal*, double, const RedWork&, hipStream_t); \
+    template hipError_t cg_alpha<T>(const cpx<T>*, size_t, int, CgScal*, const RedWork&, hipStream_t); \
+    template hipError_t cg_update_xr<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const cpx<T>*, size_t, int, const CgScal*, hipStream_t); \
+    template hipError_t cg_beta<T>(const cpx<T>*, size_t, int, CgScal*, int, const RedWork&, hipStream_t); \
+    template hipError_t cg_update_p<T>(cpx<T>*, const cpx<T>*, size_t, int, const CgScal*, hipStream_t); \
+    template hipError_t gcr_multidot<T>(const cpx<T>*, size_t, int, const cpx<T>*, size_t, int, const GcrDev&, const RedWork&, hipStream_t); \
+    template hipError_t gcr_orth<T>(const cpx<T>*, size_t, int, cpx<T>*, const cpx<T>*, size_t, int, const GcrDev&, const RedWork&, hipStream_t); \
+    template hipError_t gcr_rupdate<T>(const cpx<T>*, cpx<T>*, cpx<T>*, int, size_t, int, bool, const GcrDev&, const RedWork&, hipStream_t); \
+    template hipError_t check_finite<T>(const cpx<T>*, size_t, int*, hipStream_t);
+
+INST_T(float)
+INST_T(double)
+
+template hipError_t vconvert<double, float>(const cpx<double>*, cpx<float>*, size_t, hipStream_t);
+template hipError_t vconvert<float, double>(const cpx<float>*, cpx<double>*, size_t, hipStream_t);
+template hipError_t vconvert<double, double>(const cpx<double>*, cpx<double>*, size_t, hipStream_t);
+template hipError_t vconvert<float, float>(const cpx<float>*, cpx<float>*, size_t, hipStream_t);
+template hipError_t vadd<float, double>(const cpx<float>*, cpx<double>*, size_t, hipStream_t);
+template hipError_t vadd<double, double>(const cpx<double>*, cpx<double>*, size_t, hipStream_t);
+template hipError_t vadd<float, float>(const cpx<float>*, cpx<float>*, size_t, hipStream_t);
+template hipError_t gcr_xupdate<float, float>(const cpx<float>*, size_t, int, cpx<float>*, size_t, int, bool, const GcrDev&, hipStream_t);
+template hipError_t gcr_xupdate<double, double>(const cpx<double>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
+template hipError_t gcr_xupdate<float, double>(const cpx<float>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
+
+}  // namespace dwf

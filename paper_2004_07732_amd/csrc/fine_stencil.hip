@@ -1,0 +1,174 @@
+// Fine-level operators: 2-d Wilson kernel with U(1) links (Sec. 2), the Shamir
+// domain-wall operator D_DW(m) of eq. DWoperator, the Pauli-Villars operator
+// D_PV = D_DW(1), and their adjoints.
+//
+// Layout: fields [ncol][Ls][Ly][Lx] of 2-spinors (one 16-byte load per site in
+// FP32, two in FP64); links [2][Ly][Lx].  One thread owns one 2-d site of one
+// column and walks a chunk of consecutive slices, keeping psi_{s-1}, psi_s and
+// psi_{s+1} in registers: the fifth-dimension hop never re-reads memory and the
+// two links of the site are loaded once per chunk.  The four spatial
+// neighbours are read through the L1/L2 caches (consecutive threads own
+// consecutive x, so a wavefront reads whole rows).
+//
+// In 2-d every Wilson hop goes through a rank-1 spin projector (1 -+ gamma_mu)/2,
+// so a hop is one complex projection, one complex link multiply and a
+// reconstruction of the second component (a fixed phase of the first).
+#include "kernels.hpp"
+
+namespace dwf {
+
+template <typename R, bool DAG>
+__device__ __forceinline__ void wilson_hops(const spinor<R>& fx, const spinor<R>& bx,
+                                            const spinor<R>& fy, const spinor<R>& by,
+                                            cpx<R> hu0, cpx<R> hu0m, cpx<R> hu1, cpx<R> hu1m,
+                                            cpx<R>& a0, cpx<R>& a1) {
+    // hu* hold U/2 (forward) and U/2 of the backward neighbour (conjugated here).
+    // Non-adjoint: forward x uses (1 - s1)/2, backward x (1 + s1)/2,
+    //              forward y (1 - s2)/2, backward y (1 + s2)/2.  The adjoint swaps.
+    cpx<R> h;
+    if (!DAG) {
+        h = cmul(hu0, fx.c0 - fx.c1);            a0 = a0 + h; a1 = a1 - h;
+        h = cjmul(hu0m, bx.c0 + bx.c1);          a0 = a0 + h; a1 = a1 + h;
+        h = cmul(hu1, fy.c0 + mul_i(fy.c1));     a0 = a0 + h; a1 = a1 - mul_i(h);
+        h = cjmul(hu1m, by.c0 - mul_i(by.c1));   a0 = a0 + h; a1 = a1 + mul_i(h);
+    } else {
+        h = cmul(hu0, fx.c0 + fx.c1);            a0 = a0 + h; a1 = a1 + h;
+        h = cjmul(hu0m, bx.c0 - bx.c1);          a0 = a0 + h; a1 = a1 - h;
+        h = cmul(hu1, fy.c0 - mul_i(fy.c1));     a0 = a0 + h; a1 = a1 + mul_i(h);
+        h = cjmul(hu1m, by.c0 + mul_i(by.c1));   a0 = a0 + h; a1 = a1 - mul_i(h);
+    }
+}
+
+// out = D psi  (RESID: out = b - D psi).  DW selects the domain-wall operator
+// (diagonal D_W(M5)+1 plus the fifth-dimension hop); otherwise a stack of
+// independent 2-d Wilson fields D_W(M).  `diag` = d + M5 + 1 or d + M,
+// `mwrap` = -m (the corner blocks of eq. DWoperator).
+template <typename R, bool DAG, bool DW, bool RESID>
+__global__ void __launch_bounds__(kBlock)
+fine_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in,
+            spinor<R>* __restrict__ out, const spinor<R>* __restrict__ b,
+            const int* __restrict__ skip, int skip_stride, int Lx, int Ly, int Ls, int nchunk, int cs,
+            long long total, R diag, R mwrap) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int V = Lx * Ly;
+    const int site = (int)(g % V);
+    const long long t = g / V;
+    const int chunk = (int)(t % nchunk);
+    const int col = (int)(t / nchunk);
+    if (skip && skip[(size_t)col * skip_stride]) return;
+    const int x = site % Lx, y = site / Lx;
+    const int xp = (x + 1 == Lx) ? 0 : x + 1, xm = (x == 0) ? Lx - 1 : x - 1;
+    const int yp = (y + 1 == Ly) ? 0 : y + 1, ym = (y == 0) ? Ly - 1 : y - 1;
+    const int sxp = y * Lx + xp, sxm = y * Lx + xm, syp = yp * Lx + x, sym = ym * Lx + x;
+    const R half = R(0.5);
+    const cpx<R> hu0 = half * U[site], hu0m = half * U[sxm];
+    const cpx<R> hu1 = half * U[V + site], hu1m = half * U[V + sym];
+
+    const size_t colbase = (size_t)col * Ls * V;
+    const spinor<R>* src = in + colbase;
+    const int s0 = chunk * cs;
+    const int s1 = min(s0 + cs, Ls);
+
+    spinor<R> cur, prv, nxt;
+    if (DW) {
+        cur = src[(size_t)s0 * V + site];
+        if (s0 == 0) {
+            prv = src[(size_t)(Ls - 1) * V + site];
+            prv.c0 = mwrap * prv.c0; prv.c1 = mwrap * prv.c1;
+        } else {
+            prv = src[(size_t)(s0 - 1) * V + site];
+        }
+    }
+    for (int s = s0; s < s1; ++s) {
+        const spinor<R>* sl = src + (size_t)s * V;
+        if (DW) {
+            if (s + 1 == Ls) {
+                nxt = src[site];
+                nxt.c0 = mwrap * nxt.c0; nxt.c1 = mwrap * nxt.c1;
+            } else {
+                nxt = src[(size_t)(s + 1) * V + site];
+            }
+        } else {
+            cur = sl[site];
+        }
+        const spinor<R> fx = sl[sxp], bx = sl[sxm], fy = sl[syp], by = sl[sym];
+        cpx<R> a0 = {R(0), R(0)}, a1 = {R(0), R(0)};
+        wilson_hops<R, DAG>(fx, bx, fy, by, hu0, hu0m, hu1, hu1m, a0, a1);
+        spinor<R> res;
+        res.c0 = diag * cur.c0 - a0;
+        res.c1 = diag * cur.c1 - a1;
+        if (DW) {
+            if (!DAG) {  // P_- psi_{s+1} + P_+ psi_{s-1}
+                res.c1 = res.c1 + nxt.c1;
+                res.c0 = res.c0 + prv.c0;
+            } else {     // P_+ psi_{s+1} + P_- psi_{s-1}
+                res.c0 = res.c0 + nxt.c0;
+                res.c1 = res.c1 + prv.c1;
+            }
+        }
+        const size_t o = colbase + (size_t)s * V + site;
+        if (RESID) {
+            const spinor<R> bb = b[o];
+            res.c0 = bb.c0 - res.c0;
+            res.c1 = bb.c1 - res.c1;
+        }
+        out[o] = res;
+        if (DW) { prv = cur; cur = nxt; }
+    }
+}
+
+static inline int pick_chunk(int Lx, int Ly, int Ls, int ncol) {
+    // enough threads to fill 256 CUs with several waves each, but long enough
+    // chunks that the fifth-dimension window amortises its two extra loads
+    const long long want = 256LL * 64 * 16;
+    long long sites = (long long)Lx * Ly * ncol;
+    int cs = Ls;
+    while (cs > 2 && sites * ((Ls + cs - 1) / cs) < want) cs = (cs + 1) / 2;
+    return cs;
+}
+
+template <typename R>
+hipError_t fine_dw(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b,
+                   int Lx, int Ly, int Ls, int ncol, double m, double M5, bool dagger,
+                   const int* skip, int skip_stride, hipStream_t st) {
+    const int cs = pick_chunk(Lx, Ly, Ls, ncol);
+    const int nchunk = (Ls + cs - 1) / cs;
+    const long long total = (long long)Lx * Ly * nchunk * ncol;
+    const R diag = R(2.0 + M5 + 1.0), mwrap = R(-m);
+    auto* si = reinterpret_cast<const spinor<R>*>(in);
+    auto* so = reinterpret_cast<spinor<R>*>(out);
+    auto* sb = reinterpret_cast<const spinor<R>*>(b);
+    dim3 grid(grid_for(total)), block(kBlock);
+    if (b) {
+        if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, true, true>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
+        else        hipLaunchKernelGGL((fine_kernel<R, false, true, true>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
+    } else {
+        if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, true, false>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
+        else        hipLaunchKernelGGL((fine_kernel<R, false, true, false>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t wilson2d(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int Ly, int ncol,
+                    double M, bool dagger, hipStream_t st) {
+    // each column is an independent 2-d field: treat columns as slices of one
+    // column with no fifth-dimension coupling
+    const int Ls = ncol, cs = 1, nchunk = ncol;
+    const long long total = (long long)Lx * Ly * nchunk;
+    const R diag = R(2.0 + M), mwrap = R(0);
+    auto* si = reinterpret_cast<const spinor<R>*>(in);
+    auto* so = reinterpret_cast<spinor<R>*>(out);
+    dim3 grid(grid_for(total)), block(kBlock);
+    if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, false, false>), grid, block, 0, st, U, si, so, nullptr, nullptr, 1, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
+    else        hipLaunchKernelGGL((fine_kernel<R, false, false, false>), grid, block, 0, st, U, si, so, nullptr, nullptr, 1, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
+    return hipGetLastError();
+}
+
+template hipError_t fine_dw<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, const cpx<float>*, int, int, int, int, double, double, bool, const int*, int, hipStream_t);
+template hipError_t fine_dw<double>(const cpx<double>*, const cpx<double>*, cpx<double>*, const cpx<double>*, int, int, int, int, double, double, bool, const int*, int, hipStream_t);
+template hipError_t wilson2d<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, int, int, int, double, bool, hipStream_t);
+template hipError_t wilson2d<double>(const cpx<double>*, const cpx<double>*, cpx<double>*, int, int, int, double, bool, hipStream_t);
+
+}  // namespace dwf

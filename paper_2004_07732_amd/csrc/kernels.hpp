@@ -1,0 +1,156 @@
+// Internal launch interface between the host orchestration and the HIP kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace dwf {
+
+// ------------------------------------------------------------ reductions
+// Deterministic two-level reduction: every block writes its partial sums to
+// `partial`, the last block of each column (atomic ticket in `ticket`, reset by
+// that block) adds them in block order and runs the finaliser.
+struct RedWork {
+    double* partial = nullptr;     // [ncol][nq][nblk]
+    unsigned* ticket = nullptr;    // [max_cols]
+    int nblk = 0;                  // blocks per column
+    int max_cols = 0;
+    int max_q = 0;
+};
+
+// Krylov scalars of one column, resident on the device
+struct CgScal {
+    double zz, zz0, alpha, beta, tol2;
+    int done, iters;
+};
+
+struct GcrScal;  // defined in blas.hip
+
+// ------------------------------------------------------------ fine operators
+template <typename R>
+hipError_t fine_dw(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b,
+                   int Lx, int Ly, int Ls, int ncol, double m, double M5, bool dagger,
+                   const int* skip, int skip_stride, hipStream_t st);
+template <typename R>
+hipError_t wilson2d(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int Ly, int ncol,
+                    double M, bool dagger, hipStream_t st);
+
+// ------------------------------------------------------------ coarse operator
+// Coarse links in "column" layout: per coarse site, five n x n blocks
+// (d = 0 site-diagonal, 1: +x, 2: -x, 3: +y, 4: -y), each stored as
+// blk[k][i] (row index i fastest).
+struct CoarseGeom {
+    int Lx, Ly, Ls, n;             // coarse extents and dof per site (n = 2 nvec)
+};
+template <typename T>
+hipError_t coarse_apply(const void* links, int link_prec, const cpx<T>* in, cpx<T>* out,
+                        const CoarseGeom& g, int ncol, double m, double M5, bool dagger,
+                        bool wilson_mode, double wilson_mass, const int* skip, int skip_stride,
+                        hipStream_t st);
+
+// ------------------------------------------------------------ BLAS-1 (T = float/double)
+template <typename T> hipError_t vzero(cpx<T>* x, size_t n, hipStream_t st);
+template <typename Ti, typename To> hipError_t vconvert(const cpx<Ti>* in, cpx<To>* out, size_t n, hipStream_t st);
+// y += x (mixed precision allowed: x in Tx, y in Ty)
+template <typename Tx, typename Ty> hipError_t vadd(const cpx<Tx>* x, cpx<Ty>* y, size_t n, hipStream_t st);
+template <typename T> hipError_t vsub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n, hipStream_t st);
+
+// per column: out[c] = |x_c|^2
+template <typename T>
+hipError_t norm2(const cpx<T>* x, size_t n, int ncol, double* out, const RedWork& rw, hipStream_t st);
+// per column: out[c] = <a_c, b_c>
+template <typename T>
+hipError_t cdot(const cpx<T>* a, const cpx<T>* b, size_t n, int ncol, double* out2, const RedWork& rw, hipStream_t st);
+
+// ---- CG family (homogeneous setup CG and CGNR), scalars in CgScal[ncol]
+// s.zz = |v|^2 ; s.zz0 = s.zz ; s.done = (zz == 0) ; s.iters = 0
+template <typename T>
+hipError_t cg_init(const cpx<T>* v, size_t n, int ncol, CgScal* s, double tol, const RedWork& rw, hipStream_t st);
+// s.alpha = s.zz / |w|^2  (0 when done)
+template <typename T>
+hipError_t cg_alpha(const cpx<T>* w, size_t n, int ncol, CgScal* s, const RedWork& rw, hipStream_t st);
+// x += alpha p ; r -= alpha w    (skipped when done)
+template <typename T>
+hipError_t cg_update_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* w, size_t n, int ncol,
+                        const CgScal* s, hipStream_t st);
+// znew = |z|^2; unless done: done = znew <= tol2 zz0, beta = znew / zz, zz = znew, iters++
+template <typename T>
+hipError_t cg_beta(const cpx<T>* z, size_t n, int ncol, CgScal* s, int maxit, const RedWork& rw, hipStream_t st);
+// p = z + beta p   (skipped when done)
+template <typename T>
+hipError_t cg_update_p(cpx<T>* p, const cpx<T>* z, size_t n, int ncol, const CgScal* s, hipStream_t st);
+
+// ---- GCR with classical Gram-Schmidt and a deferred solution update
+// Scalars per column (double): D[kmax][kmax] complex (D[j][i] = <w_i, w_j>),
+// nn[kmax] (|w_j|^2 after orthogonalisation), wr[kmax] complex (<w_j, r_j>),
+// gam[kmax] complex, rr (|r|^2), stop flag.
+struct GcrDev {
+    double* D;      // [ncol][kmax][kmax][2]
+    double* nn;     // [ncol][kmax]
+    double* wr;     // [ncol][kmax][2]
+    double* gam;    // [ncol][kmax][2]
+    double* rr;     // [ncol]
+    int* stop;      // [ncol]  1: column takes no update
+    int kmax;
+};
+// D[c][j][i] = <W_i, w>, i < j;  W_i = W + i*wstride
+template <typename T>
+hipError_t gcr_multidot(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w, size_t n, int ncol,
+                        const GcrDev& g, const RedWork& rw, hipStream_t st);
+// w -= sum_{i<j} D[j][i]/nn[i] W_i ; nn[j] = |w|^2 ; wr[j] = <w, r>
+template <typename T>
+hipError_t gcr_orth(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, const cpx<T>* r, size_t n,
+                    int ncol, const GcrDev& g, const RedWork& rw, hipStream_t st);
+// r -= (wr[j]/nn[j]) w ; rr = |r|^2 (when want_norm) ; copy of the new r to `copy` (may be null)
+template <typename T>
+hipError_t gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int ncol,
+                       bool want_norm, const GcrDev& g, const RedWork& rw, hipStream_t st);
+// back substitution for gam over directions 0..k-1
+hipError_t gcr_solve(int k, int ncol, const GcrDev& g, hipStream_t st);
+// x (+)= sum_{i<k} gam[i] P_i ; `accumulate` false overwrites x
+template <typename T, typename Tx>
+hipError_t gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int ncol,
+                       bool accumulate, const GcrDev& g, hipStream_t st);
+
+// ------------------------------------------------------------ transfer (Sec. 2.3)
+// Prolongator V[site][c][j][k] (nc internal dof per chirality, nvec coarse vectors).
+struct TransferGeom {
+    int Lx, Ly, Ls;        // fine level
+    int nc;                // internal dof per chirality on the fine level
+    int bx, by;            // aggregate
+    int Lsc, nvec;         // coarse fifth extent, coarse vectors per chirality
+};
+template <typename T>
+hipError_t restrict_wall(const cpx<T>* V, const cpx<T>* r, cpx<T>* rc, const TransferGeom& g, int ncol, hipStream_t st);
+template <typename T>
+hipError_t prolong_wall(const cpx<T>* V, const cpx<T>* ec, cpx<T>* e, const TransferGeom& g, int ncol, hipStream_t st);
+
+// ------------------------------------------------------------ setup
+// v[k][site][n] (n = 2 nc) -> V[site][c][j][k]
+hipError_t chiral_columns(const cpx<double>* v, cpx<double>* V, int nsites, int nc, int nvec, hipStream_t st);
+// block classical Gram-Schmidt, twice, per aggregate and chirality; bad[0] set on breakdown
+hipError_t block_orthonormalize(cpx<double>* V, int Lx, int Ly, int nc, int nvec, int bx, int by,
+                                int* bad, hipStream_t st);
+// coarse kernel P^dagger D_W(0) P from the fine links (level 0)
+hipError_t galerkin_fine(const cpx<double>* U, const cpx<double>* V, cpx<double>* links,
+                         int Lx, int Ly, int nvec, int bx, int by, hipStream_t st);
+// coarse kernel P^dagger S P from a coarse kernel S in column layout (level >= 1)
+hipError_t galerkin_coarse(const cpx<double>* S, const cpx<double>* V, cpx<double>* links,
+                           int Lx, int Ly, int nc, int nvec, int bx, int by, hipStream_t st);
+// convert FP64 links to the storage precision
+hipError_t convert_links(const cpx<double>* in, void* out, int prec, size_t n, hipStream_t st);
+// stencil form (diag, hop[4]) row-major [site][n][n] -> complex128 export
+hipError_t export_links(const cpx<double>* links, cpx<double>* out, int nsites, int n, hipStream_t st);
+
+// ------------------------------------------------------------ utilities
+template <typename R>
+hipError_t gamma5R(const cpx<R>* in, cpx<R>* out, int V, int Ls, int ncol, hipStream_t st);
+hipError_t gauge_transform(const cpx<double>* U, const cpx<double>* g, const cpx<double>* psi,
+                           cpx<double>* Ug, cpx<double>* psig, int Lx, int Ly, int Ls, int ncol,
+                           hipStream_t st);
+hipError_t force(const cpx<double>* U, const cpx<double>* X, const cpx<double>* Y, double* F,
+                 int Lx, int Ly, int Ls, int ncol, hipStream_t st);
+// scalar finiteness check: flag[0] = 1 if any entry of x is not finite
+template <typename T>
+hipError_t check_finite(const cpx<T>* x, size_t n, int* flag, hipStream_t st);
+
+}  // namespace dwf

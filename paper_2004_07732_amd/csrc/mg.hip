@@ -1,0 +1,698 @@
+// Host orchestration of the domain-wall multigrid (Sec. 2.3 summary, Sec. 3.1,
+// Table kcycle): setup of the hierarchy, the K-cycle, flexible GCR on
+// D_PV^dagger D_DW, CGNR on the coarsest level, and an FP64 defect correction
+// around a lower-precision inner solve.
+//
+// Krylov scalars never leave the device inside an iteration: reductions
+// finalise their own coefficients (see blas.hip).  The host reads scalars back
+// once per fine or intermediate GCR iteration (to decide convergence) and once
+// per chunk of coarsest CGNR iterations; within a chunk a per-column `done`
+// flag turns the remaining launches into no-ops, so the iteration count is
+// exactly that of a loop that tests convergence after every iteration.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "mg.hpp"
+
+namespace dwf {
+
+#define HIPCHK(...)                                 \
+    do {                                            \
+        hipError_t e_ = (__VA_ARGS__);              \
+        if (e_ != hipSuccess) return DWF_EHIP;      \
+    } while (0)
+
+namespace {
+template <typename T> inline cpx<T>* C(void* p) { return reinterpret_cast<cpx<T>*>(p); }
+template <typename T> inline const cpx<T>* C(const void* p) { return reinterpret_cast<const cpx<T>*>(p); }
+template <typename T> constexpr int prec_of() { return std::is_same<T, float>::value ? P_F32 : P_F64; }
+constexpr int kCgChunk = 16;
+const int kSkipStride = (int)(sizeof(CgScal) / sizeof(int));
+inline const int* cg_skip(const CgScal* s) { return s ? &s[0].done : nullptr; }
+}  // namespace
+
+Hierarchy::~Hierarchy() {
+    for (void* p : allocs_) hipFree(p);
+    if (h_scal_) hipHostFree(h_scal_);
+    if (h_int_) hipHostFree(h_int_);
+    if (h_cg_) hipHostFree(h_cg_);
+}
+
+void* Hierarchy::dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) return nullptr;
+    allocs_.push_back(p);
+    return p;
+}
+
+// ------------------------------------------------------------ level operators
+template <typename T>
+hipError_t Hierarchy::apply_dw(int l, const cpx<T>* in, cpx<T>* out, double mass, bool dag, int ncol,
+                               hipStream_t st, const int* skip) {
+    const Level& L = levels[l];
+    const int stride = skip ? kSkipStride : 1;
+    if (L.fine) {
+        const cpx<T>* U;
+        if constexpr (std::is_same<T, float>::value) U = L.U32; else U = L.U64;
+        return fine_dw<T>(U, in, out, nullptr, L.Lx, L.Ly, L.Ls, ncol, mass, M5, dag, skip, stride, st);
+    }
+    CoarseGeom g{L.Lx, L.Ly, L.Ls, L.n};
+    return coarse_apply<T>(L.links, L.link_prec, in, out, g, ncol, mass, M5, dag, false, 0.0, skip, stride, st);
+}
+
+template <typename T>
+hipError_t Hierarchy::apply_A(int l, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp, int ncol, hipStream_t st,
+                              const int* skip) {
+    hipError_t e = apply_dw<T>(l, in, tmp, m, false, ncol, st, skip);
+    if (e != hipSuccess) return e;
+    if (l == 0) cnt_.fine_applies += 2;
+    return apply_dw<T>(l, tmp, out, 1.0, true, ncol, st, skip);
+}
+
+template <typename T>
+hipError_t Hierarchy::apply_Adag(int l, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp, int ncol, hipStream_t st,
+                                 const int* skip) {
+    hipError_t e = apply_dw<T>(l, in, tmp, 1.0, false, ncol, st, skip);
+    if (e != hipSuccess) return e;
+    if (l == 0) cnt_.fine_applies += 2;
+    return apply_dw<T>(l, tmp, out, m, true, ncol, st, skip);
+}
+
+template <typename T>
+hipError_t Hierarchy::apply_wilson(int l, const cpx<T>* in, cpx<T>* out, double mass, bool dag, int ncol,
+                                   hipStream_t st) {
+    const Level& L = levels[l];
+    if (L.fine) {
+        const cpx<T>* U;
+        if constexpr (std::is_same<T, float>::value) U = L.U32; else U = L.U64;
+        return wilson2d<T>(U, in, out, L.Lx, L.Ly, ncol, mass, dag, st);
+    }
+    CoarseGeom g{L.Lx, L.Ly, 1, L.n};
+    if constexpr (std::is_same<T, double>::value)
+        return coarse_apply<T>(L.links64, P_F64, in, out, g, ncol, 0.0, M5, dag, true, mass, nullptr, 1, st);
+    else
+        return coarse_apply<T>(L.links, L.link_prec, in, out, g, ncol, 0.0, M5, dag, true, mass, nullptr, 1, st);
+}
+
+template <typename T>
+hipError_t Hierarchy::restrict_to(int l, const cpx<T>* r, void* rc_next, int ncol, hipStream_t st) {
+    const Level& L = levels[l];
+    const Level& N = levels[l + 1];
+    TransferGeom g{L.Lx, L.Ly, L.Ls, L.n / 2, L.bx, L.by, N.Ls, L.nvec_next};
+    const cpx<T>* V;
+    if constexpr (std::is_same<T, float>::value) V = L.V32; else V = L.V64;
+    if (N.vec_prec == prec_of<T>()) return restrict_wall<T>(V, r, C<T>(rc_next), g, ncol, st);
+    cpx<T>* loc = C<T>(work_[l].rc_local);
+    hipError_t e = restrict_wall<T>(V, r, loc, g, ncol, st);
+    if (e != hipSuccess) return e;
+    const size_t n = N.vec_elems() * ncol;
+    if constexpr (std::is_same<T, float>::value) return vconvert<float, double>(loc, C<double>(rc_next), n, st);
+    else return vconvert<double, float>(loc, C<float>(rc_next), n, st);
+}
+
+template <typename T>
+hipError_t Hierarchy::prolong_from(int l, const void* ec_next, cpx<T>* e, int ncol, hipStream_t st) {
+    const Level& L = levels[l];
+    const Level& N = levels[l + 1];
+    TransferGeom g{L.Lx, L.Ly, L.Ls, L.n / 2, L.bx, L.by, N.Ls, L.nvec_next};
+    const cpx<T>* V;
+    if constexpr (std::is_same<T, float>::value) V = L.V32; else V = L.V64;
+    if (N.vec_prec == prec_of<T>()) return prolong_wall<T>(V, C<T>(ec_next), e, g, ncol, st);
+    cpx<T>* loc = C<T>(work_[l].ec_local);
+    const size_t n = N.vec_elems() * ncol;
+    hipError_t err;
+    if constexpr (std::is_same<T, float>::value) err = vconvert<double, float>(C<double>(ec_next), loc, n, st);
+    else err = vconvert<float, double>(C<float>(ec_next), loc, n, st);
+    if (err != hipSuccess) return err;
+    return prolong_wall<T>(V, loc, e, g, ncol, st);
+}
+
+// ------------------------------------------------------------ work buffers
+int Hierarchy::alloc_level_work(int l, int ncol) {
+    const Level& L = levels[l];
+    LevelWork& w = work_[l];
+    w.ncol = ncol;
+    const size_t vb = L.vec_elems() * cplx_bytes(L.vec_prec) * ncol;
+    const bool coarsest = (l == (int)levels.size() - 1);
+    w.kmax = (l == 0) ? prm.outer_restart : (coarsest ? 0 : prm.inter_restart);
+    w.ksmooth = coarsest ? 0 : prm.smooth_iters;
+    auto A = [&](size_t bytes) { return dalloc(bytes); };
+    w.r = A(vb); w.x = A(vb); w.tmp = A(vb); w.tmp2 = A(vb); w.rhs = A(vb);
+    if (!w.r || !w.x || !w.tmp || !w.tmp2 || !w.rhs) return DWF_EHIP;
+    if (w.kmax > 0) {
+        w.P = A(vb * w.kmax);
+        w.W = A(vb * w.kmax);
+        if (!w.P || !w.W) return DWF_EHIP;
+    }
+    if (w.ksmooth > 0) {
+        w.Ps = A(vb * (w.ksmooth + 1));
+        w.Ws = A(vb * w.ksmooth);
+        w.rs = A(vb);
+        w.zt = A(vb);
+        if (!w.Ps || !w.Ws || !w.rs || !w.zt) return DWF_EHIP;
+    }
+    if (!coarsest) {
+        const Level& N = levels[l + 1];
+        const size_t cb = N.vec_elems() * cplx_bytes(L.vec_prec) * ncol;
+        w.rc_local = A(cb);
+        w.ec_local = A(cb);
+        if (!w.rc_local || !w.ec_local) return DWF_EHIP;
+    } else {
+        w.cp = A(vb); w.cw = A(vb); w.cz = A(vb);
+        w.cg = (CgScal*)A(sizeof(CgScal) * ncol);
+        if (!w.cp || !w.cw || !w.cz || !w.cg) return DWF_EHIP;
+    }
+    auto mk_gcr = [&](GcrDev& g, int kmax) -> int {
+        g.kmax = kmax;
+        g.D = (double*)A(sizeof(double) * 2 * kmax * kmax * ncol);
+        g.nn = (double*)A(sizeof(double) * kmax * ncol);
+        g.wr = (double*)A(sizeof(double) * 2 * kmax * ncol);
+        g.gam = (double*)A(sizeof(double) * 2 * kmax * ncol);
+        g.rr = (double*)A(sizeof(double) * ncol);
+        g.stop = (int*)A(sizeof(int) * ncol);
+        if (!g.D || !g.nn || !g.wr || !g.gam || !g.rr || !g.stop) return DWF_EHIP;
+        if (hipMemset(g.stop, 0, sizeof(int) * ncol) != hipSuccess) return DWF_EHIP;
+        return DWF_OK;
+    };
+    if (w.kmax > 0 && mk_gcr(w.gcr, w.kmax) != DWF_OK) return DWF_EHIP;
+    if (w.ksmooth > 0 && mk_gcr(w.gsm, w.ksmooth) != DWF_OK) return DWF_EHIP;
+    return DWF_OK;
+}
+
+int Hierarchy::ensure_scalars(int maxc) {
+    if (maxc <= scal_cols_) return DWF_OK;
+    rw_.nblk = 512;
+    rw_.max_q = 40;
+    rw_.max_cols = maxc;
+    rw_.partial = (double*)dalloc(sizeof(double) * (size_t)maxc * rw_.max_q * rw_.nblk);
+    rw_.ticket = (unsigned*)dalloc(sizeof(unsigned) * maxc);
+    if (!rw_.partial || !rw_.ticket) return DWF_EHIP;
+    HIPCHK(hipMemset(rw_.ticket, 0, sizeof(unsigned) * maxc));
+    if (h_scal_) hipHostFree(h_scal_);
+    if (h_int_) hipHostFree(h_int_);
+    if (h_cg_) hipHostFree(h_cg_);
+    HIPCHK(hipHostMalloc((void**)&h_scal_, sizeof(double) * 4 * maxc, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h_int_, sizeof(int) * 4 * maxc, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h_cg_, sizeof(CgScal) * maxc, hipHostMallocDefault));
+    if (!d_flag_) d_flag_ = (int*)dalloc(sizeof(int) * 4);
+    if (!d_flag_) return DWF_EHIP;
+    scal_cols_ = maxc;
+    return DWF_OK;
+}
+
+int Hierarchy::ensure_work(int ncol, hipStream_t st) {
+    if (ncol <= work_cols_) return DWF_OK;
+    HIPCHK(hipStreamSynchronize(st));
+    if (int e = ensure_scalars(std::max(ncol, 64))) return e;
+    work_.assign(levels.size(), LevelWork{});
+    for (int l = 0; l < (int)levels.size(); ++l)
+        if (int e = alloc_level_work(l, ncol)) return e;
+    work_cols_ = ncol;
+    return DWF_OK;
+}
+
+// ------------------------------------------------------------ CGNR (coarsest level)
+template <typename T>
+int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st) {
+    const Level& L = levels[l];
+    LevelWork& w = work_[l];
+    const size_t n = L.vec_elems();
+    const size_t nt = n * ncol;
+    cpx<T>* r = C<T>(w.r);
+    cpx<T>* p = C<T>(w.cp);
+    cpx<T>* q = C<T>(w.cw);
+    cpx<T>* z = C<T>(w.cz);
+    cpx<T>* t = C<T>(w.tmp);
+    CgScal* s = w.cg;
+    const int* skip = cg_skip(s);
+    HIPCHK(vzero<T>(x, nt, st));
+    HIPCHK(vconvert<T, T>(b, r, nt, st));
+    HIPCHK(apply_Adag<T>(l, r, z, t, ncol, st));
+    HIPCHK(cg_init<T>(z, n, ncol, s, prm.coarsest_tol, rw_, st));
+    HIPCHK(vconvert<T, T>(z, p, nt, st));
+    const int maxit = prm.coarsest_maxit;
+    int iters = 0;
+    for (int it0 = 0; it0 < maxit; it0 += kCgChunk) {
+        const int nchunk = std::min(kCgChunk, maxit - it0);
+        for (int c = 0; c < nchunk; ++c) {
+            HIPCHK(apply_A<T>(l, p, q, t, ncol, st, skip));
+            HIPCHK(cg_alpha<T>(q, n, ncol, s, rw_, st));
+            HIPCHK(cg_update_xr<T>(x, r, p, q, n, ncol, s, st));
+            HIPCHK(apply_Adag<T>(l, r, z, t, ncol, st, skip));
+            HIPCHK(cg_beta<T>(z, n, ncol, s, maxit, rw_, st));
+            HIPCHK(cg_update_p<T>(p, z, n, ncol, s, st));
+        }
+        HIPCHK(hipMemcpyAsync(h_cg_, s, sizeof(CgScal) * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool all = true;
+        for (int c = 0; c < ncol; ++c)
+            if (!h_cg_[c].done) all = false;
+        if (all) break;
+    }
+    for (int c = 0; c < ncol; ++c) iters = std::max(iters, h_cg_[c].iters);
+    if (maxit <= 0) iters = 0;
+    cnt_.level_iters[l - 1] += iters;
+    cnt_.level_calls[l - 1] += 1;
+    for (int c = 0; c < ncol; ++c)
+        if (h_cg_[c].done == 4) return DWF_ENAN;
+    return DWF_OK;
+}
+
+// ------------------------------------------------------------ GCR smoother
+template <typename T>
+int Hierarchy::smooth(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t st) {
+    const Level& L = levels[l];
+    LevelWork& w = work_[l];
+    const size_t n = L.vec_elems();
+    const size_t nt = n * ncol;
+    const int ns = w.ksmooth;
+    cpx<T>* Ps = C<T>(w.Ps);
+    cpx<T>* Ws = C<T>(w.Ws);
+    cpx<T>* rs = C<T>(w.rs);
+    cpx<T>* t = C<T>(w.tmp);
+    cpx<T>* Az = C<T>(w.tmp2);
+    HIPCHK(apply_A<T>(l, z, Az, t, ncol, st));
+    HIPCHK(vsub<T>(r, Az, rs, nt, st));
+    HIPCHK(vconvert<T, T>(rs, Ps, nt, st));
+    for (int j = 0; j < ns; ++j) {
+        cpx<T>* Pj = Ps + (size_t)j * nt;
+        cpx<T>* Wj = Ws + (size_t)j * nt;
+        HIPCHK(apply_A<T>(l, Pj, Wj, t, ncol, st));
+        HIPCHK(gcr_multidot<T>(Ws, nt, j, Wj, n, ncol, w.gsm, rw_, st));
+        HIPCHK(gcr_orth<T>(Ws, nt, j, Wj, rs, n, ncol, w.gsm, rw_, st));
+        HIPCHK(gcr_rupdate<T>(Wj, rs, (j + 1 < ns) ? Ps + (size_t)(j + 1) * nt : nullptr, j, n, ncol, false,
+                              w.gsm, rw_, st));
+    }
+    HIPCHK(gcr_solve(ns, ncol, w.gsm, st));
+    HIPCHK((gcr_xupdate<T, T>(Ps, nt, ns, z, n, ncol, true, w.gsm, st)));
+    return DWF_OK;
+}
+
+// ------------------------------------------------------------ K-cycle
+template <typename T>
+int Hierarchy::kcycle(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t st) {
+    LevelWork& wn = work_[l + 1];
+    HIPCHK(restrict_to<T>(l, r, wn.rhs, ncol, st));
+    int e;
+    if (levels[l + 1].vec_prec == P_F32) e = coarse_solve<float>(l + 1, wn.rhs, wn.x, ncol, st);
+    else e = coarse_solve<double>(l + 1, wn.rhs, wn.x, ncol, st);
+    if (e < 0) return e;
+    HIPCHK(prolong_from<T>(l, wn.x, z, ncol, st));
+    if (work_[l].ksmooth > 0) return smooth<T>(l, r, z, ncol, st);
+    return DWF_OK;
+}
+
+template <typename T>
+int Hierarchy::coarse_solve(int l, const void* rhs, void* x, int ncol, hipStream_t st) {
+    if (l == (int)levels.size() - 1) return cgnr<T>(l, C<T>(rhs), C<T>(x), ncol, st);
+    std::vector<double> tol(ncol, prm.inter_tol);
+    int it = 0;
+    int e = fgcr<T>(l, C<T>(rhs), C<T>(x), ncol, tol.data(), prm.inter_maxit, prm.inter_restart, &it, st);
+    cnt_.level_iters[l - 1] += it;
+    cnt_.level_calls[l - 1] += 1;
+    return e < 0 ? e : DWF_OK;
+}
+
+// ------------------------------------------------------------ flexible GCR with the K-cycle
+template <typename T>
+int Hierarchy::fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* rel_tol, int maxit, int restart,
+                    int* iters_out, hipStream_t st) {
+    const Level& L = levels[l];
+    LevelWork& w = work_[l];
+    const size_t n = L.vec_elems();
+    const size_t nt = n * ncol;
+    const int kmax = std::min(restart, w.kmax);
+    cpx<T>* r = C<T>(w.r);
+    cpx<T>* P = C<T>(w.P);
+    cpx<T>* W = C<T>(w.W);
+    cpx<T>* t = C<T>(w.tmp);
+    cpx<T>* t2 = C<T>(w.tmp2);
+    GcrDev& g = w.gcr;
+    HIPCHK(vzero<T>(x, nt, st));
+    HIPCHK(vconvert<T, T>(b, r, nt, st));
+    HIPCHK(norm2<T>(b, n, ncol, g.rr, rw_, st));
+    HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<double> bb(h_scal_, h_scal_ + ncol), rr(bb);
+    std::vector<int> stop(ncol, 0);
+    int it = 0, k = 0, status = DWF_OK;
+    auto push_stop = [&]() -> int {
+        for (int c = 0; c < ncol; ++c) h_int_[c] = stop[c];
+        HIPCHK(hipMemcpyAsync(g.stop, h_int_, sizeof(int) * ncol, hipMemcpyHostToDevice, st));
+        return DWF_OK;
+    };
+    auto flush = [&]() -> int {
+        if (k == 0) return DWF_OK;
+        HIPCHK(gcr_solve(k, ncol, g, st));
+        HIPCHK((gcr_xupdate<T, T>(P, nt, k, x, n, ncol, true, g, st)));
+        k = 0;
+        return DWF_OK;
+    };
+    while (true) {
+        bool all = true, changed = false;
+        for (int c = 0; c < ncol; ++c) {
+            if (!std::isfinite(rr[c])) { status = DWF_ENAN; stop[c] = 1; changed = true; }
+            if (!stop[c] && rr[c] <= rel_tol[c] * rel_tol[c] * bb[c]) { stop[c] = 1; changed = true; }
+            if (!stop[c]) all = false;
+        }
+        if (all || it >= maxit) break;
+        if (changed || it == 0) if (int e = push_stop()) return e;
+        cpx<T>* Pk = P + (size_t)k * nt;
+        cpx<T>* Wk = W + (size_t)k * nt;
+        if (int e = kcycle<T>(l, r, Pk, ncol, st)) if (e < 0) return e;
+        HIPCHK(apply_A<T>(l, Pk, Wk, t, ncol, st));
+        HIPCHK(gcr_multidot<T>(W, nt, k, Wk, n, ncol, g, rw_, st));
+        HIPCHK(gcr_orth<T>(W, nt, k, Wk, r, n, ncol, g, rw_, st));
+        HIPCHK(gcr_rupdate<T>(Wk, r, nullptr, k, n, ncol, true, g, rw_, st));
+        ++k;
+        ++it;
+        HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int c = 0; c < ncol; ++c) if (!stop[c]) rr[c] = h_scal_[c];
+        bool conv = true;
+        for (int c = 0; c < ncol; ++c)
+            if (!stop[c] && !(rr[c] <= rel_tol[c] * rel_tol[c] * bb[c])) conv = false;
+        if (k == kmax || conv || it >= maxit) {
+            if (int e = flush()) return e;
+            if (!conv && it < maxit) {
+                // true residual for the next cycle
+                HIPCHK(apply_A<T>(l, x, t2, t, ncol, st));
+                HIPCHK(vsub<T>(b, t2, r, nt, st));
+                HIPCHK(norm2<T>(r, n, ncol, g.rr, rw_, st));
+                HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                for (int c = 0; c < ncol; ++c) if (!stop[c]) rr[c] = h_scal_[c];
+            }
+        }
+    }
+    if (int e = flush()) return e;
+    // clear the stop mask for the next caller of this level's GCR scalars
+    std::fill(stop.begin(), stop.end(), 0);
+    if (int e = push_stop()) return e;
+    if (iters_out) *iters_out = it;
+    return status;
+}
+
+// ------------------------------------------------------------ setup
+int Hierarchy::null_vectors(int l, const cpx<double>* start, cpx<double>* v, hipStream_t st) {
+    const Level& L = levels[l];
+    const int nv = prm.nvec[l];
+    const size_t n = L.field2d_elems();
+    const size_t nt = n * nv;
+    cpx<double>* r = (cpx<double>*)dalloc(nt * sizeof(cpx<double>));
+    cpx<double>* p = (cpx<double>*)dalloc(nt * sizeof(cpx<double>));
+    cpx<double>* t = (cpx<double>*)dalloc(nt * sizeof(cpx<double>));
+    cpx<double>* q = (cpx<double>*)dalloc(nt * sizeof(cpx<double>));
+    CgScal* s = (CgScal*)dalloc(sizeof(CgScal) * nv);
+    if (!r || !p || !t || !q || !s) return DWF_EHIP;
+    const double ms = prm.m_setup;
+    HIPCHK(vconvert<double, double>(start, v, nt, st));
+    // r = -B v, B = D_W(ms) D_W(ms)^dagger
+    HIPCHK(apply_wilson<double>(l, v, t, ms, true, nv, st));
+    HIPCHK(apply_wilson<double>(l, t, q, ms, false, nv, st));
+    HIPCHK(vzero<double>(r, nt, st));
+    HIPCHK(vsub<double>(r, q, r, nt, st));
+    HIPCHK(cg_init<double>(r, n, nv, s, prm.setup_tol, rw_, st));
+    HIPCHK(vconvert<double, double>(r, p, nt, st));
+    const int maxit = prm.setup_iters;
+    for (int it0 = 0; it0 < maxit; it0 += kCgChunk) {
+        const int nchunk = std::min(kCgChunk, maxit - it0);
+        for (int c = 0; c < nchunk; ++c) {
+            HIPCHK(apply_wilson<double>(l, p, t, ms, true, nv, st));
+            HIPCHK(cg_alpha<double>(t, n, nv, s, rw_, st));
+            HIPCHK(apply_wilson<double>(l, t, q, ms, false, nv, st));
+            HIPCHK(cg_update_xr<double>(v, r, p, q, n, nv, s, st));
+            HIPCHK(cg_beta<double>(r, n, nv, s, maxit, rw_, st));
+            HIPCHK(cg_update_p<double>(p, r, n, nv, s, st));
+        }
+        HIPCHK(hipMemcpyAsync(h_cg_, s, sizeof(CgScal) * nv, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool all = true;
+        for (int c = 0; c < nv; ++c) if (!h_cg_[c].done) all = false;
+        if (all) break;
+    }
+    return DWF_OK;
+}
+
+int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, double M5_,
+                     const dwf_mg_params& p, const void* const* null_starts, hipStream_t st) {
+    prm = p;
+    m = m_;
+    M5 = M5_;
+    levels.clear();
+    Level f;
+    f.Lx = Lx; f.Ly = Ly; f.Ls = Ls; f.n = 2; f.nsites = Lx * Ly; f.fine = true;
+    f.vec_prec = p.fine_prec;
+    f.U64 = (cpx<double>*)dalloc(sizeof(cpx<double>) * 2 * f.nsites);
+    f.U32 = (cpx<float>*)dalloc(sizeof(cpx<float>) * 2 * f.nsites);
+    if (!f.U64 || !f.U32) return DWF_EHIP;
+    HIPCHK(hipMemcpyAsync(f.U64, U, sizeof(cpx<double>) * 2 * f.nsites, hipMemcpyDeviceToDevice, st));
+    HIPCHK((vconvert<double, float>(f.U64, f.U32, 2 * (size_t)f.nsites, st)));
+    levels.push_back(f);
+    // scalar scratch for the setup CG (nvec columns)
+    if (int e = ensure_scalars(64)) return e;
+    for (int l = 0; l < p.nlevels; ++l) {
+        Level& L = levels[l];
+        const int nv = p.nvec[l], bx = p.block[l][0], by = p.block[l][1];
+        L.nvec_next = nv; L.bx = bx; L.by = by;
+        const int nc = L.n / 2;
+        const size_t n2 = L.field2d_elems();
+        cpx<double>* v = (cpx<double>*)dalloc(sizeof(cpx<double>) * n2 * nv);
+        L.V64 = (cpx<double>*)dalloc(sizeof(cpx<double>) * n2 * nv);
+        L.V32 = (cpx<float>*)dalloc(sizeof(cpx<float>) * n2 * nv);
+        if (!v || !L.V64 || !L.V32) return DWF_EHIP;
+        if (int e = null_vectors(l, reinterpret_cast<const cpx<double>*>(null_starts[l]), v, st)) return e;
+        HIPCHK(chiral_columns(v, L.V64, L.nsites, nc, nv, st));
+        HIPCHK(hipMemsetAsync(d_flag_, 0, sizeof(int), st));
+        HIPCHK(block_orthonormalize(L.V64, L.Lx, L.Ly, nc, nv, bx, by, d_flag_, st));
+        int bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, d_flag_, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (bad) return DWF_EBREAKDOWN;
+        HIPCHK((vconvert<double, float>(L.V64, L.V32, n2 * nv, st)));
+        Level c;
+        c.Lx = L.Lx / bx; c.Ly = L.Ly / by; c.Ls = p.Ls_coarse[l]; c.n = 2 * nv;
+        c.nsites = c.Lx * c.Ly; c.fine = false;
+        c.vec_prec = p.vec_prec[l];
+        c.link_prec = p.link_prec[l];
+        const size_t nl = (size_t)c.nsites * 5 * c.n * c.n;
+        c.links64 = (cpx<double>*)dalloc(sizeof(cpx<double>) * nl);
+        if (!c.links64) return DWF_EHIP;
+        if (L.fine) HIPCHK(galerkin_fine(L.U64, L.V64, c.links64, L.Lx, L.Ly, nv, bx, by, st));
+        else HIPCHK(galerkin_coarse(L.links64, L.V64, c.links64, L.Lx, L.Ly, nc, nv, bx, by, st));
+        if (c.link_prec == P_F64) {
+            c.links = c.links64;
+        } else {
+            c.links = dalloc(cplx_bytes(c.link_prec) * nl);
+            if (!c.links) return DWF_EHIP;
+            HIPCHK(convert_links(c.links64, c.links, c.link_prec, nl, st));
+        }
+        levels.push_back(c);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return DWF_OK;
+}
+
+// ------------------------------------------------------------ solve
+int Hierarchy::solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol, dwf_solve_stats* stats,
+                     hipStream_t st) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (int e = ensure_work(ncol, st)) return e;
+    cnt_ = SolveCounters{};
+    const Level& L = levels[0];
+    LevelWork& w = work_[0];
+    const size_t n = L.vec_elems();
+    const size_t nt = n * ncol;
+    if (!r64_ || r64_cols_ < ncol) {
+        r64_ = (cpx<double>*)dalloc(sizeof(cpx<double>) * nt);
+        t64_ = (cpx<double>*)dalloc(sizeof(cpx<double>) * nt);
+        if (!r64_ || !t64_) return DWF_EHIP;
+        r64_cols_ = ncol;
+    }
+    double* d_s = work_[0].gcr.rr;   // scratch for column norms between inner solves
+    HIPCHK(norm2<double>(b, n, ncol, d_s, rw_, st));
+    HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<double> bb(h_scal_, h_scal_ + ncol);
+    for (int c = 0; c < ncol; ++c)
+        if (!std::isfinite(bb[c])) return DWF_ENAN;
+    HIPCHK(vzero<double>(x, nt, st));
+    const double floor_tol = (L.vec_prec == P_F32) ? 1e-5 : 1e-13;
+    const double inner_floor = prm.inner_tol > 0 ? prm.inner_tol : floor_tol;
+    int status = DWF_NOT_CONVERGED, outer = 0, total_it = 0;
+    double worst = 0.0;
+    std::vector<double> rel(ncol, 1.0);
+    while (true) {
+        HIPCHK(fine_dw<double>(L.U64, x, r64_, b, L.Lx, L.Ly, L.Ls, ncol, m, M5, false, nullptr, 1, st));
+        cnt_.fine_applies += 1;
+        HIPCHK(norm2<double>(r64_, n, ncol, d_s, rw_, st));
+        HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool all = true;
+        worst = 0.0;
+        for (int c = 0; c < ncol; ++c) {
+            const double rr = h_scal_[c];
+            if (!std::isfinite(rr)) { status = DWF_ENAN; all = true; worst = rr; break; }
+            rel[c] = bb[c] > 0 ? std::sqrt(rr / bb[c]) : 0.0;
+            worst = std::max(worst, rel[c]);
+            if (rel[c] > tol) all = false;
+        }
+        if (status == DWF_ENAN) break;
+        if (all) { status = DWF_OK; break; }
+        if (outer >= prm.max_outer || total_it >= prm.max_iters) { status = DWF_NOT_CONVERGED; break; }
+        // inner right-hand side D_PV^dagger r in the inner precision
+        HIPCHK(fine_dw<double>(L.U64, r64_, t64_, nullptr, L.Lx, L.Ly, L.Ls, ncol, 1.0, M5, true, nullptr, 1, st));
+        cnt_.fine_applies += 1;
+        HIPCHK(norm2<double>(t64_, n, ncol, d_s, rw_, st));
+        HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<double> itol(ncol);
+        for (int c = 0; c < ncol; ++c) {
+            const double ra = std::sqrt(h_scal_[c]);
+            if (rel[c] <= tol || ra == 0.0) { itol[c] = 2.0; continue; }   // column already converged
+            double want = 0.5 * tol * std::sqrt(bb[c]) / ra;
+            itol[c] = std::min(0.5, std::max(want, inner_floor));
+        }
+        int it = 0, e;
+        const int maxit = prm.max_iters - total_it;
+        if (L.vec_prec == P_F32) {
+            HIPCHK((vconvert<double, float>(t64_, C<float>(w.rhs), nt, st)));
+            e = fgcr<float>(0, C<float>(w.rhs), C<float>(w.x), ncol, itol.data(), maxit,
+                            prm.outer_restart, &it, st);
+            if (e < 0) { status = e; break; }
+            HIPCHK((vadd<float, double>(C<float>(w.x), x, nt, st)));
+        } else {
+            HIPCHK((vconvert<double, double>(t64_, C<double>(w.rhs), nt, st)));
+            e = fgcr<double>(0, C<double>(w.rhs), C<double>(w.x), ncol, itol.data(), maxit,
+                             prm.outer_restart, &it, st);
+            if (e < 0) { status = e; break; }
+            HIPCHK((vadd<double, double>(C<double>(w.x), x, nt, st)));
+        }
+        total_it += it;
+        ++outer;
+        if (it == 0) { status = DWF_NOT_CONVERGED; break; }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    auto t1 = std::chrono::steady_clock::now();
+    if (stats) {
+        stats->status = status;
+        stats->outer_steps = outer;
+        stats->fine_iters = total_it;
+        stats->fine_applies = cnt_.fine_applies;
+        for (int l = 0; l < DWF_MAX_LEVELS; ++l) {
+            stats->level_iters[l] = cnt_.level_iters[l];
+            stats->level_calls[l] = cnt_.level_calls[l];
+        }
+        stats->true_rel_residual = worst;
+        stats->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    return status;
+}
+
+// ------------------------------------------------------------ diagnostics
+namespace {
+template <typename T>
+hipError_t to_prec(const cpx<double>* in, void* out, size_t n, hipStream_t st) {
+    return vconvert<double, T>(in, C<T>(out), n, st);
+}
+template <typename T>
+hipError_t from_prec(const void* in, cpx<double>* out, size_t n, hipStream_t st) {
+    return vconvert<T, double>(C<T>(in), out, n, st);
+}
+}  // namespace
+
+int Hierarchy::level_op(int level, int op, const cpx<double>* in, cpx<double>* out, int ncol, double mass,
+                        hipStream_t st) {
+    if (level < 0 || level >= (int)levels.size() || ncol < 1) return DWF_EINVAL;
+    const bool transfer = (op == MG_OP_RESTRICT || op == MG_OP_PROLONG || op == MG_OP_KCYCLE);
+    if (transfer && level >= (int)levels.size() - 1) return DWF_EINVAL;
+    if (int e = ensure_work(ncol, st)) return e;
+    const Level& L = levels[level];
+    const size_t nl = L.vec_elems() * ncol;
+    const size_t n2 = L.field2d_elems() * ncol;
+    const bool is2d = (op == MG_OP_WILSON || op == MG_OP_WILSON_DAG);
+    const size_t nin_l = is2d ? n2 : nl;
+    const int T32 = (L.vec_prec == P_F32);
+    const size_t eb = cplx_bytes(L.vec_prec);
+    void* bin = nullptr; void* bout = nullptr; void* btmp = nullptr; void* bn = nullptr;
+    size_t nn = 0;
+    if (transfer) nn = levels[level + 1].vec_elems() * ncol;
+    const size_t nbig = std::max(nl, n2);
+    HIPCHK(hipMalloc(&bin, nbig * eb));
+    HIPCHK(hipMalloc(&bout, nbig * eb));
+    HIPCHK(hipMalloc(&btmp, nbig * eb));
+    if (transfer) HIPCHK(hipMalloc(&bn, nn * cplx_bytes(levels[level + 1].vec_prec)));
+    int status = DWF_OK;
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        cpx<T>* xi = C<T>(bin);
+        cpx<T>* xo = C<T>(bout);
+        cpx<T>* xt = C<T>(btmp);
+        const int nxt_prec = transfer ? levels[level + 1].vec_prec : 0;
+        switch (op) {
+            case MG_OP_DW: case MG_OP_DW_DAG: case MG_OP_PV: case MG_OP_PV_DAG: {
+                HIPCHK(to_prec<T>(in, bin, nl, st));
+                const double ms = (op == MG_OP_PV || op == MG_OP_PV_DAG) ? 1.0 : m;
+                const bool dg = (op == MG_OP_DW_DAG || op == MG_OP_PV_DAG);
+                HIPCHK(apply_dw<T>(level, xi, xo, ms, dg, ncol, st));
+                HIPCHK(from_prec<T>(bout, out, nl, st));
+                return DWF_OK;
+            }
+            case MG_OP_A:
+                HIPCHK(to_prec<T>(in, bin, nl, st));
+                HIPCHK(apply_A<T>(level, xi, xo, xt, ncol, st));
+                HIPCHK(from_prec<T>(bout, out, nl, st));
+                return DWF_OK;
+            case MG_OP_WILSON: case MG_OP_WILSON_DAG:
+                HIPCHK(to_prec<T>(in, bin, n2, st));
+                HIPCHK(apply_wilson<T>(level, xi, xo, mass, op == MG_OP_WILSON_DAG, ncol, st));
+                HIPCHK(from_prec<T>(bout, out, n2, st));
+                return DWF_OK;
+            case MG_OP_RESTRICT:
+                HIPCHK(to_prec<T>(in, bin, nl, st));
+                HIPCHK(restrict_to<T>(level, xi, bn, ncol, st));
+                if (nxt_prec == P_F32) HIPCHK(from_prec<float>(bn, out, nn, st));
+                else HIPCHK(from_prec<double>(bn, out, nn, st));
+                return DWF_OK;
+            case MG_OP_PROLONG:
+                if (nxt_prec == P_F32) HIPCHK(to_prec<float>(in, bn, nn, st));
+                else HIPCHK(to_prec<double>(in, bn, nn, st));
+                HIPCHK(prolong_from<T>(level, bn, xo, ncol, st));
+                HIPCHK(from_prec<T>(bout, out, nl, st));
+                return DWF_OK;
+            case MG_OP_KCYCLE: {
+                HIPCHK(to_prec<T>(in, bin, nl, st));
+                int e = kcycle<T>(level, xi, xo, ncol, st);
+                if (e < 0) return e;
+                HIPCHK(from_prec<T>(bout, out, nl, st));
+                return DWF_OK;
+            }
+            default:
+                return DWF_EINVAL;
+        }
+    };
+    (void)nin_l;
+    status = T32 ? run(float{}) : run(double{});
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(bin);
+    (void)hipFree(bout);
+    (void)hipFree(btmp);
+    if (bn) (void)hipFree(bn);
+    return status;
+}
+
+int Hierarchy::export_level(int level, cpx<double>* V, cpx<double>* kernel, hipStream_t st) {
+    if (level < 0 || level >= (int)levels.size() - 1) return DWF_EINVAL;
+    const Level& L = levels[level];
+    const Level& N = levels[level + 1];
+    if (V) HIPCHK(hipMemcpyAsync(V, L.V64, sizeof(cpx<double>) * L.field2d_elems() * L.nvec_next,
+                                 hipMemcpyDeviceToDevice, st));
+    if (kernel) HIPCHK(export_links(N.links64, kernel, N.nsites, N.n, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return DWF_OK;
+}
+
+}  // namespace dwf

@@ -1,0 +1,73 @@
+"""Host-side checks that need no GPU: the C-ABI library loads and exports every
+symbol that include/dwfmg.h declares, and the Python parameter mirror matches
+the paper's parameter table."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dwfmg.h")
+LIB = os.path.join(ROOT, "paper_2004_07732_amd", "libdwfmg.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^(?:int|void|size_t|const char\s*\*)\s+\**\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def libdwf():
+    if not os.path.exists(LIB):
+        from paper_2004_07732_amd import build
+        build.build(verbose=False)
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["dwf_apply", "dwf_pv_apply", "mg_setup", "mg_solve", "mg_destroy", "dwf_force",
+              "dwf_gauge_transform", "dwf_pack", "dwf_unpack", "dwf_gamma5R", "dwf_strerror"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(libdwf):
+    missing = [n for n in declared_functions() if not hasattr(libdwf, n)]
+    assert not missing, missing
+
+
+def test_strerror_and_defaults_without_gpu(libdwf):
+    libdwf.dwf_strerror.restype = ctypes.c_char_p
+    assert libdwf.dwf_strerror(0) == b"ok"
+    assert b"invalid" in libdwf.dwf_strerror(-1)
+    from paper_2004_07732_amd import dwfmg
+    c = dwfmg.MGParams().to_c()
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "kcycle_params.json")))
+    assert c.setup_iters == golden["setup"]["max_iterations"]
+    assert c.setup_tol == golden["setup"]["tolerance_per_null_vector"]
+    assert c.nvec[0] == golden["setup"]["nvec_level1"] and c.nvec[1] == golden["setup"]["nvec_coarser"]
+    assert tuple(c.block[0]) == tuple(golden["setup"]["block_level1"])
+    assert tuple(c.block[1]) == tuple(golden["setup"]["block_coarser"])
+    assert c.outer_restart == golden["level1"]["gcr_restart"]
+    assert c.smooth_iters == golden["level1"]["post_smooth"]
+    assert c.inter_maxit == golden["level2"]["max_iterations"]
+    assert c.inter_tol == golden["level2"]["tolerance"]
+    assert c.Ls_coarse[0] == golden["level2"]["Ls_coarse"]
+    assert c.coarsest_tol == golden["level3"]["tolerance"]
+    assert c.coarsest_maxit == golden["level3"]["max_iterations"]
+
+
+def test_argument_errors_are_reported_before_any_device_work(libdwf):
+    """Null pointers and impossible sizes are rejected on the host (no GPU touched)."""
+    vp = ctypes.c_void_p
+    libdwf.dwf_apply.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, vp]
+    assert libdwf.dwf_apply(None, None, None, 4, 4, 4, 1, 0.1, -1.0, 0, None) == -1
+    assert libdwf.dwf_apply(1, 2, 3, 0, 4, 4, 1, 0.1, -1.0, 0, None) == -1
+    assert libdwf.dwf_apply(1, 2, 3, 4, 4, 4, 1, float("nan"), -1.0, 0, None) == -1
+    libdwf.mg_solve.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_double, vp, vp]
+    assert libdwf.mg_solve(None, 1, 2, 1, 1e-10, None, None) == -5

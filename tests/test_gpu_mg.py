@@ -1,0 +1,260 @@
+"""GPU parity of the multigrid pieces (setup, coarse operator, wall transfer,
+K-cycle) and of the solves, against the FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dwf_oracle as O
+from paper_2004_07732_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+dwfmg = pytest.importorskip("paper_2004_07732_amd.dwfmg")
+DEV = "cuda"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def T(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def build_pair(L, Ls, m, M5, levels, seed, setup_iters=0, beta=6.0, sweeps=30, **kw):
+    """GPU hierarchy and oracle hierarchy from the same gauge field and null-vector starts.
+    levels: list of (nvec, (bx, by), Ls_coarse)."""
+    U = inputs.metropolis_u1(L, L, beta, sweeps, seed).U
+    starts = []
+    Lc, n = L, 2
+    for li, (nv, (bx, by), _) in enumerate(levels):
+        starts.append(inputs.gaussian_field((nv, Lc, Lc, n), seed + 10 + li))
+        Lc //= bx
+        n = 2 * nv
+    params = dwfmg.MGParams(nvec=[l[0] for l in levels], block=[l[1] for l in levels],
+                            Ls_coarse=[l[2] for l in levels], link_prec=[dwfmg.P_F64] * len(levels),
+                            vec_prec=[dwfmg.P_F64] * len(levels), setup_iters=setup_iters, **kw)
+    mg = dwfmg.MG(T(U), Ls, m, M5, params, [T(s) for s in starts])
+    oparams = O.MGParams(levels=[O.LevelParams(nvec=l[0], block=(l[1][1], l[1][0]), Ls=l[2], setup_iters=setup_iters)
+                                 for l in levels],
+                         smooth_iters=params.smooth_iters, coarsest_tol=params.coarsest_tol,
+                         coarsest_maxit=params.coarsest_maxit, inter_tol=params.inter_tol,
+                         inter_maxit=params.inter_maxit)
+    omg = O.MG(U, Ls, m, M5, oparams, starts)
+    return U, mg, omg
+
+
+LEVELS_2 = [(4, (4, 4), 4)]
+LEVELS_3 = [(4, (4, 4), 3), (2, (2, 2), 2)]
+
+
+@pytest.mark.parametrize("levels", [LEVELS_2, LEVELS_3])
+def test_setup_parity_without_relaxation(levels):
+    """With no setup iterations the prolongator and the Galerkin kernels are
+    plain functions of the start vectors: block Gram-Schmidt and P^dag D_W P."""
+    U, mg, omg = build_pair(16, 4, 0.05, -1.0, levels, 300)
+    for l in range(len(levels)):
+        V, diag, hop = mg.export(l)
+        P = omg.levels[l].P
+        S = omg.levels[l + 1].S
+        assert rel(V.cpu().numpy(), P.V) < 1e-13
+        assert rel(diag.cpu().numpy(), S.diag) < 1e-13
+        assert rel(hop.cpu().numpy(), S.hop) < 1e-13
+
+
+@pytest.mark.parametrize("L,block,nvec", [(4, (4, 4), 2), (8, (4, 4), 4), (12, (4, 4), 4), (8, (4, 2), 2)])
+def test_galerkin_coarse_extents(L, block, nvec):
+    """Coarse extents 1, 2 and 3 (periodic wrap inside one aggregate)."""
+    U, mg, omg = build_pair(L, 4, 0.05, -1.0, [(nvec, block, 4)], 310)
+    V, diag, hop = mg.export(0)
+    S = omg.levels[1].S
+    assert rel(diag.cpu().numpy(), S.diag) < 1e-13
+    assert rel(hop.cpu().numpy(), S.hop) < 1e-13
+
+
+@pytest.mark.parametrize("op", ["dw", "dw_dag", "pv", "pv_dag", "A", "wilson", "wilson_dag"])
+@pytest.mark.parametrize("level", [1, 2])
+def test_coarse_operators_fp64(op, level):
+    U, mg, omg = build_pair(16, 4, 0.05, -1.0, LEVELS_3, 320)
+    lev = omg.levels[level]
+    info = mg.info(level)
+    ncol = 2
+    if op.startswith("wilson"):
+        shape = (ncol, info["Ly"], info["Lx"], info["n"])
+    else:
+        shape = (ncol, info["Ls"], info["Ly"], info["Lx"], info["n"])
+    x = inputs.gaussian_field(shape, 321)
+    code = {"dw": dwfmg.MG_OP_DW, "dw_dag": dwfmg.MG_OP_DW_DAG, "pv": dwfmg.MG_OP_PV, "pv_dag": dwfmg.MG_OP_PV_DAG,
+            "A": dwfmg.MG_OP_A, "wilson": dwfmg.MG_OP_WILSON, "wilson_dag": dwfmg.MG_OP_WILSON_DAG}[op]
+    got = mg.level_op(level, code, T(x), ncol, mass=-0.2).cpu().numpy()
+    m, M5 = 0.05, -1.0
+    want = {"dw": lambda: lev.dw(x, m, M5), "dw_dag": lambda: lev.dw(x, m, M5, dagger=True),
+            "pv": lambda: lev.dw(x, 1.0, M5), "pv_dag": lambda: lev.dw(x, 1.0, M5, dagger=True),
+            "A": lambda: omg.A(level, x), "wilson": lambda: lev.wilson2d(x, -0.2),
+            "wilson_dag": lambda: lev.wilson2d(x, -0.2, dagger=True)}[op]()
+    assert rel(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_wall_transfer_parity(level):
+    U, mg, omg = build_pair(16, 6, 0.05, -1.0, LEVELS_3, 330)
+    f, c = mg.info(level), mg.info(level + 1)
+    r = inputs.gaussian_field((2, f["Ls"], f["Ly"], f["Lx"], f["n"]), 331)
+    e = inputs.gaussian_field((2, c["Ls"], c["Ly"], c["Lx"], c["n"]), 332)
+    got_r = mg.level_op(level, dwfmg.MG_OP_RESTRICT, T(r), 2, out_shape=e.shape).cpu().numpy()
+    got_e = mg.level_op(level, dwfmg.MG_OP_PROLONG, T(e), 2, out_shape=r.shape).cpu().numpy()
+    assert rel(got_r, omg.restrict(level, r)) < 1e-13
+    want_e = omg.prolong(level, e)
+    assert rel(got_e, want_e) < 1e-13
+    # the bulk of a prolonged field is exactly zero
+    assert np.all(got_e[:, 1:f["Ls"] - 1] == 0)
+
+
+def test_kcycle_with_exact_coarse_solve():
+    """No smoothing and a converged coarsest solve: M(r) = Prol hat-A^{-1} Restr r."""
+    U, mg, omg = build_pair(8, 4, 0.1, -1.0, [(2, (4, 4), 2)], 340, smooth_iters=0, coarsest_tol=1e-14,
+                            coarsest_maxit=4000)
+    r = inputs.gaussian_field((1, 4, 8, 8, 2), 341)
+    got = mg.level_op(0, dwfmg.MG_OP_KCYCLE, T(r), 1).cpu().numpy()
+    Ac = O.assemble(lambda v: omg.A(1, v), (2, 2, 2, 4))
+    rc = omg.restrict(0, r[0])
+    ec = np.linalg.solve(Ac, rc.reshape(-1)).reshape(rc.shape)
+    want = omg.prolong(0, ec)
+    assert rel(got[0], want) < 1e-10
+
+
+@pytest.mark.parametrize("levels", [LEVELS_2, LEVELS_3])
+def test_kcycle_matches_oracle(levels):
+    """Default K-cycle (8 post-smoothing GCR steps, CGNR to 0.05): the GPU and
+    the oracle run the same Krylov iterations; they differ only by rounding."""
+    U, mg, omg = build_pair(16, 4, 0.05, -1.0, levels, 350)
+    r = inputs.gaussian_field((1, 4, 16, 16, 2), 351)
+    got = mg.level_op(0, dwfmg.MG_OP_KCYCLE, T(r), 1).cpu().numpy()
+    want = omg.kcycle(0, r[0])
+    err = rel(got[0], want)
+    print(f"K-cycle GPU vs oracle relative difference: {err:.2e}")
+    assert err < 1e-8
+
+
+def test_setup_relaxation_parity():
+    """With the default 250-iteration setup the GPU and oracle null vectors come
+    from the same CG on the same starts."""
+    U, mg, omg = build_pair(16, 4, 0.05, -1.0, LEVELS_2, 360, setup_iters=250)
+    V, diag, hop = mg.export(0)
+    err = rel(V.cpu().numpy(), omg.levels[0].P.V)
+    print(f"relaxed prolongator GPU vs oracle: {err:.2e}")
+    assert err < 1e-6
+    Vn = V.cpu().numpy()
+    # P^dag P = 1 per aggregate and chirality
+    Vb = Vn.reshape(4, 4, 4, 4, 2, 1, 4).transpose(0, 2, 4, 1, 3, 5, 6).reshape(4, 4, 2, 16, 4)
+    G = np.einsum("...ik,...il->...kl", Vb.conj(), Vb)
+    assert np.max(np.abs(G - np.eye(4))) < 1e-13
+
+
+# ----------------------------------------------------------------------------- solves
+def oracle_residual(U, x, b, m, M5):
+    return max(np.linalg.norm(b[i] - O.dwf(U, x[i], m, M5)) / np.linalg.norm(b[i]) for i in range(b.shape[0]))
+
+
+def test_solve_plain_fp64_config1():
+    """32x32, Ls 8, M5 = -1, m = 0.01, beta 6 (200 sweeps), 2-level 4x4 / 8
+    null vectors, FP64 throughout, to 1e-10."""
+    L, Ls, m, M5 = 32, 8, 0.01, -1.0
+    g = inputs.metropolis_u1(L, L, 6.0, 200, inputs.gauge_seed(1, L))
+    b = inputs.gaussian_field((1, Ls, L, L, 2), inputs.rhs_seed(1, L, 0))
+    starts = [inputs.gaussian_field((8, L, L, 2), inputs.null_start_seed(1, 0))]
+    params = dwfmg.MGParams(nvec=[8], block=[(4, 4)], Ls_coarse=[4], link_prec=[dwfmg.P_F64],
+                            vec_prec=[dwfmg.P_F64])
+    mg = dwfmg.MG(T(g.U), Ls, m, M5, params, [T(s) for s in starts])
+    x, st = mg.solve(T(b), 1e-10)
+    xn = x.cpu().numpy()
+    res = oracle_residual(g.U, xn, b, m, M5)
+    print(f"config1 FP64: residual {res:.2e}, stats {st}")
+    assert res <= 1e-10
+    xo, _ = O.cgnr(lambda v: O.dwf(g.U, v, m, M5), lambda v: O.dwf(g.U, v, m, M5, dagger=True), b[0], 1e-13, 20000)
+    assert rel(xn[0], xo) < 1e-7
+
+
+def test_solve_mixed_precision_config2():
+    """128x128, Ls 16, FP32 fine, BF16 coarse links, FP64 defect correction to 1e-10."""
+    L, Ls, m, M5 = 128, 16, 0.01, -1.0
+    g = inputs.metropolis_u1(L, L, 6.0, 200, inputs.gauge_seed(2, L))
+    b = inputs.gaussian_field((1, Ls, L, L, 2), inputs.rhs_seed(2, L, 0))
+    starts = [inputs.gaussian_field((16, L, L, 2), inputs.null_start_seed(2, 0))]
+    params = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[4], link_prec=[dwfmg.P_BF16],
+                            vec_prec=[dwfmg.P_F64], fine_prec=dwfmg.P_F32)
+    mg = dwfmg.MG(T(g.U), Ls, m, M5, params, [T(s) for s in starts])
+    x, st = mg.solve(T(b), 1e-10)
+    res = oracle_residual(g.U, x.cpu().numpy(), b, m, M5)
+    print(f"config2 mixed: residual {res:.2e}, stats {st}")
+    assert res <= 1e-10
+
+
+def test_solve_batched_rhs_three_level():
+    L, Ls, m, M5 = 32, 8, 0.02, -1.0
+    g = inputs.metropolis_u1(L, L, 6.0, 100, 777)
+    b = inputs.gaussian_field((3, Ls, L, L, 2), 778)
+    starts = [inputs.gaussian_field((8, L, L, 2), 779), inputs.gaussian_field((12, 8, 8, 16), 780)]
+    params = dwfmg.MGParams(nvec=[8, 12], block=[(4, 4), (2, 2)], Ls_coarse=[4, 4],
+                            link_prec=[dwfmg.P_F32, dwfmg.P_F64], vec_prec=[dwfmg.P_F32, dwfmg.P_F64],
+                            fine_prec=dwfmg.P_F32)
+    mg = dwfmg.MG(T(g.U), Ls, m, M5, params, [T(s) for s in starts])
+    x, st = mg.solve(T(b), 1e-10)
+    res = oracle_residual(g.U, x.cpu().numpy(), b, m, M5)
+    print(f"3-level batched: residual {res:.2e}, stats {st}")
+    assert res <= 1e-10
+
+
+# ----------------------------------------------------------------------------- failure handling
+def small_mg(**kw):
+    L, Ls = 8, 4
+    U = inputs.metropolis_u1(L, L, 6.0, 10, 5).U
+    starts = [T(inputs.gaussian_field((2, L, L, 2), 6))]
+    params = dwfmg.MGParams(nvec=[2], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_F64],
+                            vec_prec=[dwfmg.P_F64], **kw)
+    return U, dwfmg.MG(T(U), Ls, 0.05, -1.0, params, starts)
+
+
+def test_nan_source_is_reported():
+    U, mg = small_mg()
+    b = inputs.gaussian_field((1, 4, 8, 8, 2), 1)
+    b[0, 1, 2, 3, 0] = np.nan
+    with pytest.raises(dwfmg.DwfError) as e:
+        mg.solve(T(b), 1e-10)
+    assert e.value.code == dwfmg.DWF_ENAN
+
+
+def test_iteration_cap_returns_not_converged():
+    U, mg = small_mg(max_iters=1, max_outer=1)
+    b = inputs.gaussian_field((1, 4, 8, 8, 2), 2)
+    x, st = mg.solve(T(b), 1e-14, check=False)
+    assert st.status == dwfmg.DWF_NOT_CONVERGED
+    assert st.true_rel_residual > 1e-14
+
+
+def test_singular_free_field_does_not_hang():
+    """U = 1, M5 = -1, m = 0 makes D_DW exactly singular (zero-momentum
+    eigenvalues m^{1/Ls} = 0): the solve must stop at its caps."""
+    L, Ls = 8, 4
+    U = np.ones((2, L, L), dtype=np.complex128)
+    starts = [T(inputs.gaussian_field((2, L, L, 2), 6))]
+    params = dwfmg.MGParams(nvec=[2], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_F64],
+                            vec_prec=[dwfmg.P_F64], max_iters=40, max_outer=2, coarsest_maxit=64)
+    mg = dwfmg.MG(T(U), Ls, 0.0, -1.0, params, starts)
+    b = inputs.gaussian_field((1, Ls, L, L, 2), 7)
+    x, st = mg.solve(T(b), 1e-12, check=False)
+    assert st.status in (dwfmg.DWF_NOT_CONVERGED, dwfmg.DWF_EBREAKDOWN, dwfmg.DWF_OK)
+    assert st.fine_iters <= 40
+
+
+def test_setup_argument_errors():
+    L = 8
+    U = T(np.ones((2, L, L), dtype=np.complex128))
+    starts = [T(inputs.gaussian_field((2, L, L, 2), 6))]
+    bad_block = dwfmg.MGParams(nvec=[2], block=[(3, 3)], Ls_coarse=[2])
+    with pytest.raises(dwfmg.DwfError) as e:
+        dwfmg.MG(U, 4, 0.1, -1.0, bad_block, starts)
+    assert e.value.code == dwfmg.DWF_EINVAL
+    too_many = dwfmg.MGParams(nvec=[40], block=[(4, 4)], Ls_coarse=[2])
+    with pytest.raises(dwfmg.DwfError):
+        dwfmg.MG(U, 4, 0.1, -1.0, too_many, [T(inputs.gaussian_field((40, L, L, 2), 6))])
