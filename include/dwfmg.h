@@ -193,6 +193,14 @@ int mg_solve(dwf_mg* mg, const void* b, void* x, int nrhs, double tol, dwf_solve
 int mg_level_op(dwf_mg* mg, int level, int op, const void* in, void* out, int ncol, double mass,
                 void* stream);
 
+/* Timing of one level operator (the kernels the solve runs, on the level's
+ * working precision and storage): `in` (complex128, as for mg_level_op) is
+ * converted once, then the operator runs `iters` times back to back on
+ * `stream`, bracketed by HIP events; *avg_ms receives the mean time per
+ * application.  Ops: MG_OP_DW, MG_OP_DW_DAG, MG_OP_PV, MG_OP_PV_DAG, MG_OP_A. */
+int mg_time_op(dwf_mg* mg, int level, int op, const void* in, int ncol, int iters, double* avg_ms,
+               void* stream);
+
 /* Copy out level l's prolongator V[y][x][c][j][k] (complex128,
  * Ly_l*Lx_l*2*nc*nvec) or coarse kernel (level l+1) in stencil form
  * diag[Y][X][n][n] then hop[4][Y][X][n][n] (h = +x, -x, +y, -y), complex128. */

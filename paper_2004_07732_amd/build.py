@@ -16,8 +16,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdwfmg.so")
 ARCH = os.environ.get("DWF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["fine_stencil.hip", "blas.hip", "coarse.hip", "transfer.hip", "setup.hip", "util.hip", "mg.hip",
-           "abi.hip"]
+SOURCES = ["fine_stencil.hip", "blas.hip", "coarse.hip", "coarse_mfma.hip", "transfer.hip", "setup.hip", "util.hip",
+           "mg.hip", "abi.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

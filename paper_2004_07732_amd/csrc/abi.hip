@@ -220,6 +220,12 @@ int mg_level_op(dwf_mg* mg, int level, int op, const void* in, void* out, int nc
     return mg->h.level_op(level, op, (const cpx<double>*)in, (cpx<double>*)out, ncol, mass, S(stream));
 }
 
+int mg_time_op(dwf_mg* mg, int level, int op, const void* in, int ncol, int iters, double* avg_ms, void* stream) {
+    if (!mg || !mg->ready) return DWF_ENOSETUP;
+    if (!in || !avg_ms) return DWF_EINVAL;
+    return mg->h.time_op(level, op, (const cpx<double>*)in, ncol, iters, avg_ms, S(stream));
+}
+
 int mg_export(dwf_mg* mg, int level, void* prolongator, void* coarse_kernel, void* stream) {
     if (!mg || !mg->ready) return DWF_ENOSETUP;
     return mg->h.export_level(level, (cpx<double>*)prolongator, (cpx<double>*)coarse_kernel, S(stream));

@@ -1,13 +1,15 @@
 // BLAS-1 kernels and the device-resident Krylov scalar algebra.
 //
-// Every reduction is deterministic: a block reduces with wavefront shuffles
-// (64 lanes) and a fixed-order sum over its four waves, writes one partial per
-// quantity, and the last block of the column (atomic ticket) sums the
-// partials in block order and runs the finaliser that turns sums into Krylov
-// coefficients.  The host never has to read a scalar back to continue: CG,
-// CGNR and GCR coefficients are computed on the device and consumed by the
-// next kernel, and a per-column `done` / `stop` flag turns later updates into
-// no-ops.  Accumulation is FP64 for both FP32 and FP64 vectors.
+// Reductions are deterministic and fence-free: the partial kernel reduces each
+// block with wavefront shuffles (64 lanes) and a fixed-order sum over its four
+// waves and writes one partial per quantity; a one-block-per-column finaliser
+// (the next launch, so the kernel boundary orders the two) adds the partials
+// in block order and turns the sums into Krylov coefficients.  No cross-block
+// fence is needed inside a kernel, which matters on a part whose L2 caches are
+// private to each XCD.  The host never has to read a scalar back to continue:
+// CG, CGNR and GCR coefficients live on the device and a per-column `done` /
+// `stop` flag turns later updates into no-ops.  Accumulation is FP64 for both
+// FP32 and FP64 vectors.
 #include "kernels.hpp"
 
 namespace dwf {
@@ -45,37 +47,26 @@ __device__ __forceinline__ void block_reduce(double (&v)[NQ], int nq, double* sh
     __syncthreads();
 }
 
-// Block partials -> column totals.  Returns true in the last block of the
-// column, where tot[0..nq) then hold the full sums.
 template <int NQ>
-__device__ bool reduce_column(double (&v)[NQ], int nq, const RedWork& rw, int col, double* sh,
-                              double* tot) {
-    __shared__ bool last;
+__device__ __forceinline__ void write_partials(double (&v)[NQ], int nq, const RedWork& rw, int col, double* sh,
+                                               double* tot) {
     block_reduce<NQ>(v, nq, sh, tot);
     double* part = rw.partial + (size_t)col * rw.max_q * rw.nblk;
     if (threadIdx.x < nq) part[(size_t)threadIdx.x * rw.nblk + blockIdx.x] = tot[threadIdx.x];
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(&rw.ticket[col], 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+}
+
+// finaliser side: column `col` (= blockIdx.x), nb partials per quantity
+template <int NQ>
+__device__ __forceinline__ void sum_partials(int nq, int nb, const RedWork& rw, int col, double* sh, double* tot) {
+    const double* part = rw.partial + (size_t)col * rw.max_q * rw.nblk;
     double w[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         w[q] = 0.0;
-        if (q < nq) {
-            for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
-                w[q] += __hip_atomic_load(&part[(size_t)q * rw.nblk + b], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (q < nq)
+            for (int b = threadIdx.x; b < nb; b += blockDim.x) w[q] += part[(size_t)q * rw.nblk + b];
     }
     block_reduce<NQ>(w, nq, sh, tot);
-    if (threadIdx.x == 0) rw.ticket[col] = 0u;
-    return true;
 }
 
 inline dim3 red_grid(size_t n, int ncol, const RedWork& rw) {
@@ -94,6 +85,8 @@ inline dim3 ew_grid(size_t n, int ncol) {
 
 #define GRID_STRIDE(i, n) \
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
+
+#define SHARED_RED __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ]
 
 template <typename T>
 __device__ __forceinline__ cpx<double> up(cpx<T> a) { return {(double)a.re, (double)a.im}; }
@@ -143,61 +136,20 @@ hipError_t vsub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n, hipStre
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------ plain reductions
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_norm2(const cpx<T>* x, size_t n, double* out, RedWork rw) {
-    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
-    const int col = blockIdx.y;
-    const cpx<T>* xc = x + (size_t)col * n;
-    double v[1] = {0.0};
-    GRID_STRIDE(i, n) {
-        cpx<double> a = up(xc[i]);
-        v[0] += a.re * a.re + a.im * a.im;
-    }
-    if (reduce_column<1>(v, 1, rw, col, sh, tot) && threadIdx.x == 0) out[col] = tot[0];
+// ------------------------------------------------------------ finalisers (one block per column)
+// out[col * stride + q] = total q
+__global__ void __launch_bounds__(kBlock) k_fin_store(RedWork rw, int nq, int nb, double* out, size_t stride) {
+    SHARED_RED;
+    const int col = blockIdx.x;
+    sum_partials<kMaxQ>(nq, nb, rw, col, sh, tot);
+    if (threadIdx.x < nq) out[(size_t)col * stride + threadIdx.x] = tot[threadIdx.x];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cdot(const cpx<T>* a, const cpx<T>* b, size_t n, double* out, RedWork rw) {
-    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
-    const int col = blockIdx.y;
-    const cpx<T>* ac = a + (size_t)col * n;
-    const cpx<T>* bc = b + (size_t)col * n;
-    double v[2] = {0.0, 0.0};
-    GRID_STRIDE(i, n) {
-        cpx<double> p = cjmul(up(ac[i]), up(bc[i]));
-        v[0] += p.re;
-        v[1] += p.im;
-    }
-    if (reduce_column<2>(v, 2, rw, col, sh, tot) && threadIdx.x == 0) {
-        out[2 * col] = tot[0];
-        out[2 * col + 1] = tot[1];
-    }
-}
-
-template <typename T>
-hipError_t norm2(const cpx<T>* x, size_t n, int ncol, double* out, const RedWork& rw, hipStream_t st) {
-    hipLaunchKernelGGL(k_norm2<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, x, n, out, rw);
-    return hipGetLastError();
-}
-template <typename T>
-hipError_t cdot(const cpx<T>* a, const cpx<T>* b, size_t n, int ncol, double* out2, const RedWork& rw, hipStream_t st) {
-    hipLaunchKernelGGL(k_cdot<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, a, b, n, out2, rw);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------ CG family
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cg_init(const cpx<T>* v, size_t n, CgScal* s, double tol2, RedWork rw) {
-    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
-    const int col = blockIdx.y;
-    const cpx<T>* vc = v + (size_t)col * n;
-    double q[1] = {0.0};
-    GRID_STRIDE(i, n) {
-        cpx<double> a = up(vc[i]);
-        q[0] += a.re * a.re + a.im * a.im;
-    }
-    if (reduce_column<1>(q, 1, rw, col, sh, tot) && threadIdx.x == 0) {
+__global__ void __launch_bounds__(kBlock) k_fin_cg_init(RedWork rw, int nb, CgScal* s, double tol2) {
+    SHARED_RED;
+    const int col = blockIdx.x;
+    sum_partials<1>(1, nb, rw, col, sh, tot);
+    if (threadIdx.x == 0) {
         CgScal c;
         c.zz = tot[0];
         c.zz0 = tot[0];
@@ -210,18 +162,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(const cpx<T>* v, size_t n, C
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cg_alpha(const cpx<T>* w, size_t n, CgScal* s, RedWork rw) {
-    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
-    const int col = blockIdx.y;
-    if (s[col].done) return;   // uniform per column: no block of this column reduces
-    const cpx<T>* wc = w + (size_t)col * n;
-    double q[1] = {0.0};
-    GRID_STRIDE(i, n) {
-        cpx<double> a = up(wc[i]);
-        q[0] += a.re * a.re + a.im * a.im;
-    }
-    if (reduce_column<1>(q, 1, rw, col, sh, tot) && threadIdx.x == 0) {
+__global__ void __launch_bounds__(kBlock) k_fin_cg_alpha(RedWork rw, int nb, CgScal* s) {
+    SHARED_RED;
+    const int col = blockIdx.x;
+    if (s[col].done) return;
+    sum_partials<1>(1, nb, rw, col, sh, tot);
+    if (threadIdx.x == 0) {
         const double ww = tot[0];
         if (!(ww > 0.0) || !finite(ww)) {
             s[col].alpha = 0.0;
@@ -230,6 +176,92 @@ __global__ void __launch_bounds__(kBlock) k_cg_alpha(const cpx<T>* w, size_t n, 
             s[col].alpha = s[col].zz / ww;
         }
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fin_cg_beta(RedWork rw, int nb, CgScal* s, int maxit) {
+    SHARED_RED;
+    const int col = blockIdx.x;
+    if (s[col].done) return;
+    sum_partials<1>(1, nb, rw, col, sh, tot);
+    if (threadIdx.x == 0) {
+        CgScal c = s[col];
+        const double znew = tot[0];
+        c.iters += 1;
+        if (!finite(znew)) {
+            c.done = 4;
+        } else {
+            c.beta = znew / c.zz;
+            c.zz = znew;
+            if (znew <= c.tol2 * c.zz0) c.done = 1;
+            else if (c.iters >= maxit) c.done = 3;
+        }
+        s[col] = c;
+    }
+}
+
+// ------------------------------------------------------------ reductions: partial kernels
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_norm2_part(const cpx<T>* x, size_t n, RedWork rw, const int* skip, int sks) {
+    SHARED_RED;
+    const int col = blockIdx.y;
+    if (skip && skip[(size_t)col * sks]) return;
+    const cpx<T>* xc = x + (size_t)col * n;
+    double v[1] = {0.0};
+    GRID_STRIDE(i, n) {
+        cpx<double> a = up(xc[i]);
+        v[0] += a.re * a.re + a.im * a.im;
+    }
+    write_partials<1>(v, 1, rw, col, sh, tot);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cdot_part(const cpx<T>* a, const cpx<T>* b, size_t n, RedWork rw) {
+    SHARED_RED;
+    const int col = blockIdx.y;
+    const cpx<T>* ac = a + (size_t)col * n;
+    const cpx<T>* bc = b + (size_t)col * n;
+    double v[2] = {0.0, 0.0};
+    GRID_STRIDE(i, n) {
+        cpx<double> p = cjmul(up(ac[i]), up(bc[i]));
+        v[0] += p.re;
+        v[1] += p.im;
+    }
+    write_partials<2>(v, 2, rw, col, sh, tot);
+}
+
+namespace {
+const int kCgSkipStride = (int)(sizeof(CgScal) / sizeof(int));
+}
+
+template <typename T>
+hipError_t norm2(const cpx<T>* x, size_t n, int ncol, double* out, const RedWork& rw, hipStream_t st) {
+    dim3 g = red_grid(n, ncol, rw);
+    hipLaunchKernelGGL(k_norm2_part<T>, g, dim3(kBlock), 0, st, x, n, rw, (const int*)nullptr, 1);
+    hipLaunchKernelGGL(k_fin_store, dim3(ncol), dim3(kBlock), 0, st, rw, 1, (int)g.x, out, (size_t)1);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t cdot(const cpx<T>* a, const cpx<T>* b, size_t n, int ncol, double* out2, const RedWork& rw, hipStream_t st) {
+    dim3 g = red_grid(n, ncol, rw);
+    hipLaunchKernelGGL(k_cdot_part<T>, g, dim3(kBlock), 0, st, a, b, n, rw);
+    hipLaunchKernelGGL(k_fin_store, dim3(ncol), dim3(kBlock), 0, st, rw, 2, (int)g.x, out2, (size_t)2);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ CG family
+template <typename T>
+hipError_t cg_init(const cpx<T>* v, size_t n, int ncol, CgScal* s, double tol, const RedWork& rw, hipStream_t st) {
+    dim3 g = red_grid(n, ncol, rw);
+    hipLaunchKernelGGL(k_norm2_part<T>, g, dim3(kBlock), 0, st, v, n, rw, (const int*)nullptr, 1);
+    hipLaunchKernelGGL(k_fin_cg_init, dim3(ncol), dim3(kBlock), 0, st, rw, (int)g.x, s, tol * tol);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t cg_alpha(const cpx<T>* w, size_t n, int ncol, CgScal* s, const RedWork& rw, hipStream_t st) {
+    dim3 g = red_grid(n, ncol, rw);
+    hipLaunchKernelGGL(k_norm2_part<T>, g, dim3(kBlock), 0, st, w, n, rw, &s[0].done, kCgSkipStride);
+    hipLaunchKernelGGL(k_fin_cg_alpha, dim3(ncol), dim3(kBlock), 0, st, rw, (int)g.x, s);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -246,33 +278,6 @@ __global__ void k_cg_update_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cg_beta(const cpx<T>* z, size_t n, CgScal* s, int maxit, RedWork rw) {
-    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
-    const int col = blockIdx.y;
-    if (s[col].done) return;
-    const cpx<T>* zc = z + (size_t)col * n;
-    double q[1] = {0.0};
-    GRID_STRIDE(i, n) {
-        cpx<double> a = up(zc[i]);
-        q[0] += a.re * a.re + a.im * a.im;
-    }
-    if (reduce_column<1>(q, 1, rw, col, sh, tot) && threadIdx.x == 0) {
-        CgScal c = s[col];
-        const double znew = tot[0];
-        c.iters += 1;
-        if (!finite(znew)) {
-            c.done = 4;
-        } else {
-            c.beta = znew / c.zz;
-            c.zz = znew;
-            if (znew <= c.tol2 * c.zz0) c.done = 1;
-            else if (c.iters >= maxit) c.done = 3;
-        }
-        s[col] = c;
-    }
-}
-
-template <typename T>
 __global__ void k_cg_update_p(cpx<T>* p, const cpx<T>* z, size_t n, const CgScal* s) {
     const int col = blockIdx.y;
     if (s[col].done) return;
@@ -285,16 +290,6 @@ __global__ void k_cg_update_p(cpx<T>* p, const cpx<T>* z, size_t n, const CgScal
 }
 
 template <typename T>
-hipError_t cg_init(const cpx<T>* v, size_t n, int ncol, CgScal* s, double tol, const RedWork& rw, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_init<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, v, n, s, tol * tol, rw);
-    return hipGetLastError();
-}
-template <typename T>
-hipError_t cg_alpha(const cpx<T>* w, size_t n, int ncol, CgScal* s, const RedWork& rw, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_alpha<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, w, n, s, rw);
-    return hipGetLastError();
-}
-template <typename T>
 hipError_t cg_update_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* w, size_t n, int ncol,
                         const CgScal* s, hipStream_t st) {
     hipLaunchKernelGGL(k_cg_update_xr<T>, ew_grid(n, ncol), dim3(kBlock), 0, st, x, r, p, w, n, s);
@@ -302,7 +297,9 @@ hipError_t cg_update_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* w, 
 }
 template <typename T>
 hipError_t cg_beta(const cpx<T>* z, size_t n, int ncol, CgScal* s, int maxit, const RedWork& rw, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_beta<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, z, n, s, maxit, rw);
+    dim3 g = red_grid(n, ncol, rw);
+    hipLaunchKernelGGL(k_norm2_part<T>, g, dim3(kBlock), 0, st, z, n, rw, &s[0].done, kCgSkipStride);
+    hipLaunchKernelGGL(k_fin_cg_beta, dim3(ncol), dim3(kBlock), 0, st, rw, (int)g.x, s, maxit);
     return hipGetLastError();
 }
 template <typename T>
@@ -322,7 +319,7 @@ __device__ __forceinline__ cpx<double> cdiv_real(cpx<double> a, double d) {
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_gcr_multidot(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w, size_t n, GcrDev g, RedWork rw) {
-    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
+    SHARED_RED;
     const int col = blockIdx.y;
     const size_t o = (size_t)col * n;
     const bool stop = g.stop[col] != 0;
@@ -340,15 +337,13 @@ k_gcr_multidot(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w, size_t n
             }
         }
     }
-    if (reduce_column<32>(v, 2 * j, rw, col, sh, tot)) {
-        if (threadIdx.x < 2 * j) g.D[((size_t)col * g.kmax + j) * g.kmax * 2 + threadIdx.x] = tot[threadIdx.x];
-    }
+    write_partials<32>(v, 2 * j, rw, col, sh, tot);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_gcr_orth(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, const cpx<T>* r, size_t n, GcrDev g, RedWork rw) {
-    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
+    SHARED_RED;
     const int col = blockIdx.y;
     const bool stop = g.stop[col] != 0;
     const size_t o = (size_t)col * n;
@@ -381,9 +376,16 @@ k_gcr_orth(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, const cpx<T>* r, s
         v[1] += p.re;
         v[2] += p.im;
     }
-    if (reduce_column<3>(v, 3, rw, col, sh, tot) && threadIdx.x == 0) {
+    write_partials<3>(v, 3, rw, col, sh, tot);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fin_gcr_orth(RedWork rw, int nb, GcrDev g, int j) {
+    SHARED_RED;
+    const int col = blockIdx.x;
+    sum_partials<3>(3, nb, rw, col, sh, tot);
+    if (threadIdx.x == 0) {
         const size_t s = (size_t)col * g.kmax + j;
-        if (stop) {
+        if (g.stop[col]) {
             g.nn[s] = 0.0;
             g.wr[2 * s] = 0.0;
             g.wr[2 * s + 1] = 0.0;
@@ -398,7 +400,7 @@ k_gcr_orth(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, const cpx<T>* r, s
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int want_norm, GcrDev g, RedWork rw) {
-    __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ];
+    SHARED_RED;
     const int col = blockIdx.y;
     const size_t s = (size_t)col * g.kmax + j;
     const cpx<double> ad = cdiv_real(ld2(&g.wr[2 * s]), g.nn[s]);
@@ -415,9 +417,7 @@ k_gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int wan
         const cpx<double> rd = up(re);
         v[0] += rd.re * rd.re + rd.im * rd.im;
     }
-    if (want_norm) {
-        if (reduce_column<1>(v, 1, rw, col, sh, tot) && threadIdx.x == 0) g.rr[col] = tot[0];
-    }
+    if (want_norm) write_partials<1>(v, 1, rw, col, sh, tot);
 }
 
 __global__ void k_gcr_solve(int k, int ncol, GcrDev g) {
@@ -465,14 +465,19 @@ hipError_t gcr_multidot(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w,
                         const GcrDev& g, const RedWork& rw, hipStream_t st) {
     if (j <= 0) return hipSuccess;
     if (j > 16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gcr_multidot<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, W, wstride, j, w, n, g, rw);
+    dim3 grid = red_grid(n, ncol, rw);
+    hipLaunchKernelGGL(k_gcr_multidot<T>, grid, dim3(kBlock), 0, st, W, wstride, j, w, n, g, rw);
+    hipLaunchKernelGGL(k_fin_store, dim3(ncol), dim3(kBlock), 0, st, rw, 2 * j, (int)grid.x,
+                       g.D + (size_t)j * g.kmax * 2, (size_t)g.kmax * g.kmax * 2);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t gcr_orth(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, const cpx<T>* r, size_t n,
                     int ncol, const GcrDev& g, const RedWork& rw, hipStream_t st) {
     if (j > 16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gcr_orth<T>, red_grid(n, ncol, rw), dim3(kBlock), 0, st, W, wstride, j, w, r, n, g, rw);
+    dim3 grid = red_grid(n, ncol, rw);
+    hipLaunchKernelGGL(k_gcr_orth<T>, grid, dim3(kBlock), 0, st, W, wstride, j, w, r, n, g, rw);
+    hipLaunchKernelGGL(k_fin_gcr_orth, dim3(ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g, j);
     return hipGetLastError();
 }
 template <typename T>
@@ -480,6 +485,8 @@ hipError_t gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n
                        bool want_norm, const GcrDev& g, const RedWork& rw, hipStream_t st) {
     dim3 grid = want_norm ? red_grid(n, ncol, rw) : ew_grid(n, ncol);
     hipLaunchKernelGGL(k_gcr_rupdate<T>, grid, dim3(kBlock), 0, st, w, r, copy, j, n, want_norm ? 1 : 0, g, rw);
+    if (want_norm)
+        hipLaunchKernelGGL(k_fin_store, dim3(ncol), dim3(kBlock), 0, st, rw, 1, (int)grid.x, g.rr, (size_t)1);
     return hipGetLastError();
 }
 hipError_t gcr_solve(int k, int ncol, const GcrDev& g, hipStream_t st) {

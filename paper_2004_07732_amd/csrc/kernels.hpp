@@ -6,12 +6,10 @@
 namespace dwf {
 
 // ------------------------------------------------------------ reductions
-// Deterministic two-level reduction: every block writes its partial sums to
-// `partial`, the last block of each column (atomic ticket in `ticket`, reset by
-// that block) adds them in block order and runs the finaliser.
+// Deterministic two-kernel reduction: every block writes its partial sums to
+// `partial`; a one-block-per-column finaliser adds them in block order.
 struct RedWork {
     double* partial = nullptr;     // [ncol][nq][nblk]
-    unsigned* ticket = nullptr;    // [max_cols]
     int nblk = 0;                  // blocks per column
     int max_cols = 0;
     int max_q = 0;
@@ -46,6 +44,14 @@ hipError_t coarse_apply(const void* links, int link_prec, const cpx<T>* in, cpx<
                         const CoarseGeom& g, int ncol, double m, double M5, bool dagger,
                         bool wilson_mode, double wilson_mass, const int* skip, int skip_stride,
                         hipStream_t st);
+
+// Matrix-core path (BF16 links stored row-major per site, n a multiple of 16);
+// coarse_apply dispatches to it by itself for such levels.
+bool coarse_mfma_supported(int n, int link_prec);
+template <typename T>
+hipError_t coarse_apply_mfma(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol,
+                             double m, double M5, bool dagger, const int* skip, int sks, hipStream_t st);
+hipError_t convert_links_rowmajor_bf16(const cpx<double>* in, void* out, int nsites, int n, hipStream_t st);
 
 // ------------------------------------------------------------ BLAS-1 (T = float/double)
 template <typename T> hipError_t vzero(cpx<T>* x, size_t n, hipStream_t st);

@@ -90,11 +90,9 @@ hipError_t Hierarchy::apply_wilson(int l, const cpx<T>* in, cpx<T>* out, double 
         if constexpr (std::is_same<T, float>::value) U = L.U32; else U = L.U64;
         return wilson2d<T>(U, in, out, L.Lx, L.Ly, ncol, mass, dag, st);
     }
+    // the 2-d kernel is only used by the setup and by diagnostics: FP64 links
     CoarseGeom g{L.Lx, L.Ly, 1, L.n};
-    if constexpr (std::is_same<T, double>::value)
-        return coarse_apply<T>(L.links64, P_F64, in, out, g, ncol, 0.0, M5, dag, true, mass, nullptr, 1, st);
-    else
-        return coarse_apply<T>(L.links, L.link_prec, in, out, g, ncol, 0.0, M5, dag, true, mass, nullptr, 1, st);
+    return coarse_apply<T>(L.links64, P_F64, in, out, g, ncol, 0.0, M5, dag, true, mass, nullptr, 1, st);
 }
 
 template <typename T>
@@ -188,9 +186,7 @@ int Hierarchy::ensure_scalars(int maxc) {
     rw_.max_q = 40;
     rw_.max_cols = maxc;
     rw_.partial = (double*)dalloc(sizeof(double) * (size_t)maxc * rw_.max_q * rw_.nblk);
-    rw_.ticket = (unsigned*)dalloc(sizeof(unsigned) * maxc);
-    if (!rw_.partial || !rw_.ticket) return DWF_EHIP;
-    HIPCHK(hipMemset(rw_.ticket, 0, sizeof(unsigned) * maxc));
+    if (!rw_.partial) return DWF_EHIP;
     if (h_scal_) hipHostFree(h_scal_);
     if (h_int_) hipHostFree(h_int_);
     if (h_cg_) hipHostFree(h_cg_);
@@ -488,7 +484,10 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
         } else {
             c.links = dalloc(cplx_bytes(c.link_prec) * nl);
             if (!c.links) return DWF_EHIP;
-            HIPCHK(convert_links(c.links64, c.links, c.link_prec, nl, st));
+            if (coarse_mfma_supported(c.n, c.link_prec))
+                HIPCHK(convert_links_rowmajor_bf16(c.links64, c.links, c.nsites, c.n, st));
+            else
+                HIPCHK(convert_links(c.links64, c.links, c.link_prec, nl, st));
         }
         levels.push_back(c);
     }
@@ -681,6 +680,46 @@ int Hierarchy::level_op(int level, int op, const cpx<double>* in, cpx<double>* o
     (void)hipFree(bout);
     (void)hipFree(btmp);
     if (bn) (void)hipFree(bn);
+    return status;
+}
+
+int Hierarchy::time_op(int level, int op, const cpx<double>* in, int ncol, int iters, double* avg_ms,
+                       hipStream_t st) {
+    if (level < 0 || level >= (int)levels.size() || ncol < 1 || iters < 1 || !avg_ms) return DWF_EINVAL;
+    if (op != MG_OP_DW && op != MG_OP_DW_DAG && op != MG_OP_PV && op != MG_OP_PV_DAG && op != MG_OP_A)
+        return DWF_EINVAL;
+    if (int e = ensure_work(ncol, st)) return e;
+    const Level& L = levels[level];
+    LevelWork& w = work_[level];
+    const size_t nl = L.vec_elems() * ncol;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        cpx<T>* xi = C<T>(w.rhs);
+        cpx<T>* xo = C<T>(w.tmp2);
+        cpx<T>* xt = C<T>(w.tmp);
+        HIPCHK(to_prec<T>(in, w.rhs, nl, st));
+        const double ms = (op == MG_OP_PV || op == MG_OP_PV_DAG) ? 1.0 : m;
+        const bool dg = (op == MG_OP_DW_DAG || op == MG_OP_PV_DAG);
+        auto once = [&]() -> hipError_t {
+            if (op == MG_OP_A) return apply_A<T>(level, xi, xo, xt, ncol, st);
+            return apply_dw<T>(level, xi, xo, ms, dg, ncol, st);
+        };
+        HIPCHK(once());   // warm-up
+        HIPCHK(hipEventRecord(e0, st));
+        for (int i = 0; i < iters; ++i) HIPCHK(once());
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, e0, e1));
+        *avg_ms = (double)t / iters;
+        return DWF_OK;
+    };
+    int status = (L.vec_prec == P_F32) ? run(float{}) : run(double{});
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return status;
 }
 

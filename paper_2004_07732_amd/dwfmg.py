@@ -69,6 +69,7 @@ def lib() -> ctypes.CDLL:
         L.mg_solve.argtypes = [vp, vp, vp, i, d, ctypes.POINTER(CStats), vp]
         L.mg_level_op.argtypes = [vp, i, i, vp, vp, i, d, vp]
         L.mg_export.argtypes = [vp, i, vp, vp, vp]
+        L.mg_time_op.argtypes = [vp, i, i, vp, i, i, ctypes.POINTER(d), vp]
         L.mg_level_info.argtypes = [vp, i] + [ctypes.POINTER(i)] * 5
         L.mg_destroy.argtypes = [vp]
         L.dwf_release_scratch.argtypes = []
@@ -76,6 +77,7 @@ def lib() -> ctypes.CDLL:
         L.dwf_strerror.restype = ctypes.c_char_p
         for name in ("dwf_apply", "dwf_pv_apply", "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
                      "dwf_pack", "dwf_unpack", "dwf_force", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
+                     "mg_time_op",
                      "mg_level_info", "mg_destroy", "dwf_release_scratch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -382,6 +384,14 @@ class MG:
         _check(lib().mg_level_op(self._h, level, op, _ptr(inp), _ptr(out), ncol, float(mass), _stream(stream)),
                "mg_level_op")
         return out
+
+    def time_op(self, level: int, op: int, inp: torch.Tensor, ncol: int, iters: int = 50, stream=None) -> float:
+        """Mean milliseconds of one application of a level operator (HIP events on `stream`)."""
+        _need(inp, "in", torch.complex128)
+        ms = ctypes.c_double()
+        _check(lib().mg_time_op(self._h, level, op, _ptr(inp), ncol, iters, ctypes.byref(ms), _stream(stream)),
+               "mg_time_op")
+        return ms.value
 
     def export(self, level: int, stream=None):
         """(V[y,x,c,j,k], diag[Y,X,n,n], hop[4,Y,X,n,n]) of level -> level+1, complex128."""

@@ -151,6 +151,58 @@ def test_setup_relaxation_parity():
     assert np.max(np.abs(G - np.eye(4))) < 1e-13
 
 
+def bf16_round(a):
+    """Round to bfloat16 (nearest even) through float32, as the library stores links."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_stencil(S):
+    r = lambda z: bf16_round(z.real) + 1j * bf16_round(z.imag)
+    return O.Stencil(diag=r(S.diag), hop=r(S.hop), chir=S.chir)
+
+
+@pytest.mark.parametrize("nvec,ncol,vec_prec,block", [(8, 1, "f64", (4, 4)), (16, 1, "f64", (4, 4)),
+                                                       (16, 3, "f32", (4, 4)), (8, 17, "f32", (4, 4)),
+                                                       (24, 2, "f64", (8, 4)), (32, 1, "f32", (8, 4)),
+                                                       (6, 2, "f64", (4, 4))])
+@pytest.mark.parametrize("op", ["dw", "dw_dag", "A"])
+def test_coarse_bf16_matrix_core_parity(nvec, ncol, vec_prec, block, op):
+    """The BF16 coarse operator (matrix cores when 2 nvec is a multiple of 16,
+    vector ALUs otherwise) against the oracle's coarse operator built on the
+    same links rounded to BF16."""
+    L, Ls, m, M5 = 16, 4, 0.05, -1.0
+    bx, by = block
+    U = inputs.metropolis_u1(L, L, 6.0, 30, 370).U
+    starts = [inputs.gaussian_field((nvec, L, L, 2), 371)]
+    vp = dwfmg.P_F64 if vec_prec == "f64" else dwfmg.P_F32
+    params = dwfmg.MGParams(nvec=[nvec], block=[block], Ls_coarse=[4], link_prec=[dwfmg.P_BF16],
+                            vec_prec=[vp], setup_iters=0)
+    mg = dwfmg.MG(T(U), Ls, m, M5, params, [T(s) for s in starts])
+    oparams = O.MGParams(levels=[O.LevelParams(nvec=nvec, block=(by, bx), Ls=4, setup_iters=0)])
+    omg = O.MG(U, Ls, m, M5, oparams, starts)
+    Sb = bf16_stencil(omg.levels[1].S)
+    x = inputs.gaussian_field((ncol, 4, L // by, L // bx, 2 * nvec), 372)
+    if vec_prec == "f32":
+        x = x.astype(np.complex64).astype(np.complex128)
+    code = {"dw": dwfmg.MG_OP_DW, "dw_dag": dwfmg.MG_OP_DW_DAG, "A": dwfmg.MG_OP_A}[op]
+    got = mg.level_op(1, code, T(x), ncol).cpu().numpy()
+    if op == "dw":
+        want = O.stencil_dwf(Sb, x, m, M5)
+    elif op == "dw_dag":
+        want = O.stencil_dwf(Sb, x, m, M5, dagger=True)
+    else:
+        want = O.stencil_dwf(Sb, O.stencil_dwf(Sb, x, m, M5), 1.0, M5, dagger=True)
+    err = rel(got, want)
+    full = rel(got, {"dw": lambda: omg.levels[1].dw(x, m, M5), "dw_dag": lambda: omg.levels[1].dw(x, m, M5, dagger=True),
+                     "A": lambda: omg.A(1, x)}[op]())
+    print(f"BF16 coarse {op} nvec={nvec} ncol={ncol}: vs BF16-link oracle {err:.2e}, vs FP64 oracle {full:.2e}")
+    assert err < (3e-5 if vec_prec == "f64" else 5e-5) * (1 if op == "dw" else 10)
+    assert full < 2e-2
+
+
 # ----------------------------------------------------------------------------- solves
 def oracle_residual(U, x, b, m, M5):
     return max(np.linalg.norm(b[i] - O.dwf(U, x[i], m, M5)) / np.linalg.norm(b[i]) for i in range(b.shape[0]))
