@@ -115,6 +115,10 @@ int dwf_unpack(const void* in_c64, void* out_c128, size_t n, void* stream);
 int dwf_force(const void* U, const void* X, const void* Y, double* F, int Lx, int Ly, int Ls,
               int nrhs, void* stream);
 
+/* out[c] = |x_c|^2 (FP64 accumulation, deterministic order) for ncol columns
+ * of n complex128 each; out is a device array of ncol doubles. */
+int dwf_norm2(const void* x, size_t n, int ncol, double* out, void* stream);
+
 /* ---------------------------------------------------------------- multigrid */
 typedef struct dwf_mg dwf_mg;
 
@@ -176,6 +180,13 @@ int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, do
  * Returns DWF_NOT_CONVERGED when the caps are hit (x is the last iterate). */
 int mg_solve(dwf_mg* mg, const void* b, void* x, int nrhs, double tol, dwf_solve_stats* st,
              void* stream);
+
+/* Replace the fine-level gauge field of a built hierarchy (complex128
+ * [2][Ly][Lx], copied).  The coarse levels are kept: they remain a valid
+ * preconditioner for a nearby field (a molecular-dynamics step, a finite
+ * difference), while every solve still converges on the true residual of the
+ * new D_DW. */
+int mg_update_links(dwf_mg* mg, const void* U, void* stream);
 
 /* Level operators of a built hierarchy, for testing and diagnostics.  Fields
  * are complex128 in the level's layout ([ncol][Ls_l][Ly_l][Lx_l][n_l]; 2-d

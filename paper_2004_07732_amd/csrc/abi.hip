@@ -220,6 +220,30 @@ int mg_level_op(dwf_mg* mg, int level, int op, const void* in, void* out, int nc
     return mg->h.level_op(level, op, (const cpx<double>*)in, (cpx<double>*)out, ncol, mass, S(stream));
 }
 
+int dwf_norm2(const void* x, size_t n, int ncol, double* out, void* stream) {
+    if (!x || !out || ncol < 1 || n == 0) return DWF_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    static double* partial = nullptr;
+    static int cap_cols = 0;
+    RedWork rw;
+    rw.nblk = 512;
+    rw.max_q = 1;
+    rw.max_cols = ncol;
+    if (ncol > cap_cols) {
+        if (partial) { hipDeviceSynchronize(); hipFree(partial); partial = nullptr; cap_cols = 0; }
+        if (hipMalloc(&partial, sizeof(double) * (size_t)rw.nblk * ncol) != hipSuccess) return DWF_EHIP;
+        cap_cols = ncol;
+    }
+    rw.partial = partial;
+    return hip_status(norm2<double>((const cpx<double>*)x, n, ncol, out, rw, S(stream)));
+}
+
+int mg_update_links(dwf_mg* mg, const void* U, void* stream) {
+    if (!mg || !mg->ready) return DWF_ENOSETUP;
+    if (!U) return DWF_EINVAL;
+    return mg->h.update_links((const cpx<double>*)U, S(stream));
+}
+
 int mg_time_op(dwf_mg* mg, int level, int op, const void* in, int ncol, int iters, double* avg_ms, void* stream) {
     if (!mg || !mg->ready) return DWF_ENOSETUP;
     if (!in || !avg_ms) return DWF_EINVAL;

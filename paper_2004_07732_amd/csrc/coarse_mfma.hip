@@ -11,8 +11,14 @@
 // complex inner entries.  The vector is split into two BF16 parts (hi + lo)
 // and multiplied twice, so the operator applied is the BF16-rounded link
 // matrix acting on a vector carried to about 16 mantissa bits; products are
-// exact in FP32 and accumulate in FP32.  One wavefront owns one coarse site
-// and up to 64 complex columns; each link element is read once per apply.
+// exact in FP32 and accumulate in FP32.
+//
+// Work split: one wavefront per (coarse site, 16-row tile).  A wave loads all
+// of its link fragments up front (every link element is read exactly once per
+// apply, with all loads in flight together) and keeps them in registers while
+// it walks the column tiles.  The five neighbour vectors of a column tile are
+// staged once per site in LDS, already split into BF16 hi/lo pairs, and read
+// back as 16-byte fragments.
 //
 // Links layout for this kernel: per site, row-major [i][d*n + k] complex BF16.
 // The site-local terms (the M5 + 1 shift and the fifth-dimension hops through
@@ -24,8 +30,16 @@ namespace dwf {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
+
+// (re, im) -> bf16 pair packed in 32 bits (re low, im high), RNE
+__device__ __forceinline__ uint32_t pack_bf16(float re, float im) {
+    return f32_to_bf16_bits(re) | (f32_to_bf16_bits(im) << 16);
+}
+__device__ __forceinline__ float bf16_lo_f(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16_hi_f(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
 
 template <typename T>
 __device__ __forceinline__ void load4(const cpx<T>* p, float (&re)[4], float (&im)[4]) {
@@ -37,107 +51,102 @@ __device__ __forceinline__ void load4(const cpx<T>* p, float (&re)[4], float (&i
     }
 }
 
-__device__ __forceinline__ void split(float x, __bf16& hi, __bf16& lo) {
-    hi = (__bf16)x;
-    lo = (__bf16)(x - (float)hi);
+// B fragment for 4 complex inner entries from packed bf16 pairs:
+// real-output columns take [re, -im], imaginary-output columns [im, re]
+__device__ __forceinline__ bf16x8 make_b(u32x4 u, bool imag_col) {
+    u32x4 r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = imag_col ? ((u[e] >> 16) | (u[e] << 16)) : (u[e] ^ 0x80000000u);
+    return __builtin_bit_cast(bf16x8, r);
 }
 
 }  // namespace
 
-template <typename T, int N, int NTMAX, bool DAG>
+template <typename T, int N, bool DAG>
 __global__ void __launch_bounds__(256)
 coarse_mfma_kernel(const bf16x8* __restrict__ links, const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                    const int* __restrict__ skip, int sks, int Lx, int Ly, int Ls, int nsites, int ncol,
                    float cdiag, float mwrap) {
-    constexpr int MT = N / 16;          // row tiles
-    constexpr int KS = 5 * N / 16;      // inner steps of 16 complex entries
-    constexpr int H = N / 2;            // chirality boundary (sigma_3)
+    constexpr int MT = N / 16;                    // row tiles = waves per site
+    constexpr int SPB = (MT >= 4) ? 1 : 4 / MT;   // sites per block
+    constexpr int KS = 5 * N / 16;                // inner steps of 16 complex entries
+    constexpr int H = N / 2;                      // chirality boundary (sigma_3)
+    constexpr int ROW = 5 * N / 4;                // 16-byte link chunks per row
+    constexpr int SLAB = 5 * 8 * N;               // staged entries per site and part (d, c8, k)
+    __shared__ __attribute__((aligned(16))) uint32_t sB[SPB][2][SLAB];   // [site][hi/lo][(d*8 + c8)*N + k]
+
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int site = blockIdx.x * 4 + wave;
-    if (site >= nsites) return;         // no block-level synchronisation in this kernel
-    const int C = Ls * ncol;            // complex columns
-    const int c0 = blockIdx.y * 8 * NTMAX;
+    const int sl = wave / MT, m = wave - sl * MT;
+    const int site = blockIdx.x * SPB + sl;
+    const bool valid_site = site < nsites;
+    const int C = Ls * ncol;
     const int q = lane & 15, kg = lane >> 4;
+    const bool imag_col = q >= 8;
 
-    const int x = site % Lx, y = site / Lx;
-    const int xp = (x + 1 == Lx) ? 0 : x + 1, xm = (x == 0) ? Lx - 1 : x - 1;
-    const int yp = (y + 1 == Ly) ? 0 : y + 1, ym = (y == 0) ? Ly - 1 : y - 1;
-    const int nb[5] = {site, y * Lx + xp, y * Lx + xm, yp * Lx + x, ym * Lx + x};
-
-    // column owned by this lane in tile t (B operand and epilogue)
-    auto col_of = [&](int t) { return c0 + 8 * t + (q & 7); };
-    auto col_ok = [&](int c) {
-        if (c >= C) return false;
-        return !(skip && skip[(size_t)(c / Ls) * sks]);
-    };
-
-    f32x4 acc[MT][NTMAX];
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int t = 0; t < NTMAX; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    // link rows of this site: row i starts at (site*N + i) * 5N complex = (site*N + i) * 5N/4 chunks
-    const bf16x8* lrow = links + ((size_t)site * N + q) * (5 * N / 4);
-
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int d = (ks * 16) / N;
-        const int kd = (ks * 16) % N + 4 * kg;     // first of this lane's 4 complex inner entries
-        bf16x8 a[MT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) a[m] = lrow[(size_t)m * 16 * (5 * N / 4) + ks * 4 + kg];
-        const int nbs = nb[d];
-        const bool neg = DAG && (kd >= H);
-#pragma unroll
-        for (int t = 0; t < NTMAX; ++t) {
-            const int c = col_of(t);
-            bf16x8 bh, bl;
-            if (col_ok(c)) {
-                float re[4], im[4];
-                load4<T>(in + ((size_t)c * nsites + nbs) * N + kd, re, im);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (neg) { re[e] = -re[e]; im[e] = -im[e]; }
-                    __bf16 rh, rl, ih, il, nih, nil;
-                    split(re[e], rh, rl);
-                    split(im[e], ih, il);
-                    split(-im[e], nih, nil);
-                    if (q < 8) {   // real part of the output: [re, -im] per inner entry
-                        bh[2 * e] = rh; bh[2 * e + 1] = nih;
-                        bl[2 * e] = rl; bl[2 * e + 1] = nil;
-                    } else {       // imaginary part: [im, re]
-                        bh[2 * e] = ih; bh[2 * e + 1] = rh;
-                        bl[2 * e] = il; bl[2 * e + 1] = rl;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) { bh[e] = (__bf16)0.f; bl[e] = (__bf16)0.f; }
-            }
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bh, acc[m][t], 0, 0, 0);
-                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bl, acc[m][t], 0, 0, 0);
-            }
-        }
+    int nb[5] = {0, 0, 0, 0, 0};
+    if (valid_site) {
+        const int x = site % Lx, y = site / Lx;
+        const int xp = (x + 1 == Lx) ? 0 : x + 1, xm = (x == 0) ? Lx - 1 : x - 1;
+        const int yp = (y + 1 == Ly) ? 0 : y + 1, ym = (y == 0) ? Ly - 1 : y - 1;
+        nb[0] = site; nb[1] = y * Lx + xp; nb[2] = y * Lx + xm; nb[3] = yp * Lx + x; nb[4] = ym * Lx + x;
     }
 
-    // epilogue: lanes q and q^8 hold the real and imaginary parts of the same outputs
+    // all link fragments of this wave's 16 rows, loaded once
+    bf16x8 a[KS];
+    if (valid_site) {
+        const bf16x8* lrow = links + ((size_t)site * N + 16 * m + q) * ROW + kg;
 #pragma unroll
-    for (int t = 0; t < NTMAX; ++t) {
-        const int c = col_of(t);
-        const bool ok = (q < 8) && col_ok(c);
-        const int rhs = c / Ls, s = c - rhs * Ls;
+        for (int ks = 0; ks < KS; ++ks) a[ks] = lrow[ks * 4];
+    }
+
+    auto col_ok = [&](int c) { return c < C && !(skip && skip[(size_t)(c / Ls) * sks]); };
+
+    const int ntile = (C + 7) / 8;
+    const int tid_in_site = threadIdx.x - sl * MT * 64;
+    for (int t = 0; t < ntile; ++t) {
+        const int cbase = 8 * t;
+        // stage the five neighbour vectors of columns cbase..cbase+7 (split hi/lo)
+        if (valid_site) {
+            for (int e = tid_in_site; e < SLAB; e += MT * 64) {
+                const int k = e % N;
+                const int dc = e / N;
+                const int c8 = dc & 7, d = dc >> 3;
+                const int c = cbase + c8;
+                uint32_t hi = 0u, lo = 0u;
+                if (col_ok(c)) {
+                    const cpx<T> v = in[((size_t)c * nsites + nb[d]) * N + k];
+                    float re = (float)v.re, im = (float)v.im;
+                    if (DAG && k >= H) { re = -re; im = -im; }
+                    hi = pack_bf16(re, im);
+                    lo = pack_bf16(re - bf16_lo_f(hi), im - bf16_hi_f(hi));
+                }
+                sB[sl][0][e] = hi;
+                sB[sl][1][e] = lo;
+            }
+        }
+        __syncthreads();
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        if (valid_site) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            f32x4 v = acc[m][t], p;
+            for (int ks = 0; ks < KS; ++ks) {
+                const int d = (ks * 16) / N;
+                const int kd = (ks * 16) % N + 4 * kg;
+                const int off = (d * 8 + (q & 7)) * N + kd;
+                const u32x4 uh = *reinterpret_cast<const u32x4*>(&sB[sl][0][off]);
+                const u32x4 ul = *reinterpret_cast<const u32x4*>(&sB[sl][1][off]);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], make_b(uh, imag_col), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], make_b(ul, imag_col), acc, 0, 0, 0);
+            }
+        }
+        // lanes q and q^8 hold the real and imaginary parts of the same outputs
+        f32x4 p;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) p[e] = __shfl_xor(v[e], 8, 64);
-            if (!ok) continue;
+        for (int e = 0; e < 4; ++e) p[e] = __shfl_xor(acc[e], 8, 64);
+        const int c = cbase + (q & 7);
+        if (valid_site && !imag_col && col_ok(c)) {
+            const int rhs = c / Ls, s = c - rhs * Ls;
             const int i0 = 16 * m + 4 * kg;
             const bool minus = (i0 >= H);
-            // fifth-dimension neighbour slice for these rows
             const bool from_up = DAG ? !minus : minus;
             int so;
             float f = 1.f;
@@ -149,39 +158,31 @@ coarse_mfma_kernel(const bf16x8* __restrict__ links, const cpx<T>* __restrict__ 
             cpx<T>* dst = out + ((size_t)c * nsites + site) * N + i0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                float re = v[e], im = p[e];
+                float re = acc[e], im = p[e];
                 if (DAG && minus) { re = -re; im = -im; }
                 re += cdiag * cr[e] + f * hr[e];
                 im += cdiag * ci[e] + f * hi[e];
                 dst[e] = {(T)re, (T)im};
             }
         }
+        __syncthreads();   // sB is rewritten for the next column tile
     }
 }
 
 namespace {
 
-template <typename T, int N, int NTMAX>
-hipError_t launch_nt(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol, double m,
-                     double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
-    const int nsites = g.Lx * g.Ly;
-    const int C = g.Ls * ncol;
-    dim3 grid((nsites + 3) / 4, (C + 8 * NTMAX - 1) / (8 * NTMAX)), block(256);
-    const bf16x8* lk = reinterpret_cast<const bf16x8*>(links);
-    const float cd = (float)(M5 + 1.0), mw = (float)(-m);
-    if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<T, N, NTMAX, true>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
-    else        hipLaunchKernelGGL((coarse_mfma_kernel<T, N, NTMAX, false>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
-    return hipGetLastError();
-}
-
 template <typename T, int N>
 hipError_t launch_n(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol, double m,
                     double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
-    const int tiles = (g.Ls * ncol + 7) / 8;
-    if (tiles <= 1) return launch_nt<T, N, 1>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
-    if (tiles <= 2) return launch_nt<T, N, 2>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
-    if (tiles <= 4) return launch_nt<T, N, 4>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
-    return launch_nt<T, N, 8>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
+    constexpr int MT = N / 16;
+    constexpr int SPB = (MT >= 4) ? 1 : 4 / MT;
+    const int nsites = g.Lx * g.Ly;
+    dim3 grid((nsites + SPB - 1) / SPB), block(64 * MT * SPB);
+    const bf16x8* lk = reinterpret_cast<const bf16x8*>(links);
+    const float cd = (float)(M5 + 1.0), mw = (float)(-m);
+    if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<T, N, true>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
+    else        hipLaunchKernelGGL((coarse_mfma_kernel<T, N, false>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
+    return hipGetLastError();
 }
 
 }  // namespace

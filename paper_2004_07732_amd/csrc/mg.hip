@@ -723,6 +723,13 @@ int Hierarchy::time_op(int level, int op, const cpx<double>* in, int ncol, int i
     return status;
 }
 
+int Hierarchy::update_links(const cpx<double>* U, hipStream_t st) {
+    Level& f = levels[0];
+    HIPCHK(hipMemcpyAsync(f.U64, U, sizeof(cpx<double>) * 2 * f.nsites, hipMemcpyDeviceToDevice, st));
+    HIPCHK((vconvert<double, float>(f.U64, f.U32, 2 * (size_t)f.nsites, st)));
+    return DWF_OK;
+}
+
 int Hierarchy::export_level(int level, cpx<double>* V, cpx<double>* kernel, hipStream_t st) {
     if (level < 0 || level >= (int)levels.size() - 1) return DWF_EINVAL;
     const Level& L = levels[level];

@@ -70,6 +70,8 @@ def lib() -> ctypes.CDLL:
         L.mg_level_op.argtypes = [vp, i, i, vp, vp, i, d, vp]
         L.mg_export.argtypes = [vp, i, vp, vp, vp]
         L.mg_time_op.argtypes = [vp, i, i, vp, i, i, ctypes.POINTER(d), vp]
+        L.dwf_norm2.argtypes = [vp, sz, i, vp, vp]
+        L.mg_update_links.argtypes = [vp, vp, vp]
         L.mg_level_info.argtypes = [vp, i] + [ctypes.POINTER(i)] * 5
         L.mg_destroy.argtypes = [vp]
         L.dwf_release_scratch.argtypes = []
@@ -77,7 +79,7 @@ def lib() -> ctypes.CDLL:
         L.dwf_strerror.restype = ctypes.c_char_p
         for name in ("dwf_apply", "dwf_pv_apply", "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
                      "dwf_pack", "dwf_unpack", "dwf_force", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
-                     "mg_time_op",
+                     "mg_time_op", "dwf_norm2", "mg_update_links",
                      "mg_level_info", "mg_destroy", "dwf_release_scratch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -328,6 +330,15 @@ def dwf_force(U, X, Y, stream=None):
     return F
 
 
+def dwf_norm2(x, stream=None):
+    """Per-column |x_c|^2 (first axis = columns), FP64, deterministic; returns a CUDA float64 tensor."""
+    _need(x, "x", torch.complex128)
+    ncol = x.shape[0] if x.dim() > 1 else 1
+    out = torch.empty(ncol, dtype=torch.float64, device=x.device)
+    _check(lib().dwf_norm2(_ptr(x), x.numel() // ncol, ncol, _ptr(out), _stream(stream)), "dwf_norm2")
+    return out
+
+
 def release_scratch():
     _check(lib().dwf_release_scratch(), "dwf_release_scratch")
 
@@ -369,6 +380,11 @@ class MG:
         if check:
             _check(code, "mg_solve")
         return x, stats
+
+    def update_links(self, U: torch.Tensor, stream=None):
+        """Swap in a new fine gauge field; the coarse levels stay as preconditioner."""
+        _need(U, "U", torch.complex128, (2, self.Ly, self.Lx))
+        _check(lib().mg_update_links(self._h, _ptr(U), _stream(stream)), "mg_update_links")
 
     def info(self, level: int):
         vals = [ctypes.c_int() for _ in range(5)]

@@ -1,0 +1,82 @@
+"""Differentiation form: S = phi^dag (D^dag D)^{-1} phi through the multigrid
+solver, with the hand-written backward (adjoint solve + outer-product force)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dwf_oracle as O
+from paper_2004_07732_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+dwfmg = pytest.importorskip("paper_2004_07732_amd.dwfmg")
+from paper_2004_07732_amd.autograd import action  # noqa: E402
+
+
+def T(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def dense_action_and_force(theta, phi, m, M5):
+    U = inputs.links_from_theta(theta)
+    shape = phi.shape
+    D = O.assemble(lambda v: O.dwf(U, v, m, M5), shape)
+    Y = np.linalg.solve(D.conj().T, phi.reshape(-1)).reshape(shape)
+    X = np.linalg.solve(D, Y.reshape(-1)).reshape(shape)
+    return float(np.vdot(Y, Y).real), O.force(U, X, Y)
+
+
+def test_gradient_matches_dense_oracle_and_finite_differences():
+    L, Ls, m, M5 = 8, 4, 0.05, -1.0
+    theta = inputs.metropolis_u1(L, L, 6.0, 30, 401).theta
+    phi = inputs.gaussian_field((Ls, L, L, 2), 402)
+    params = dwfmg.MGParams(nvec=[4], block=[(4, 4)], Ls_coarse=[4], link_prec=[dwfmg.P_F64],
+                            vec_prec=[dwfmg.P_F64])
+    starts = [T(inputs.gaussian_field((4, L, L, 2), 403))]
+    mg = dwfmg.MG(T(inputs.links_from_theta(theta)), Ls, m, M5, params, starts)
+    th = T(theta).requires_grad_(True)
+    S = action(th, T(phi[None]), mg, tol=1e-13)
+    S.backward()
+    S_o, F_o = dense_action_and_force(theta, phi, m, M5)
+    assert abs(S.item() - S_o) < 1e-10 * abs(S_o)
+    g = th.grad.cpu().numpy()
+    assert np.max(np.abs(g - F_o)) < 1e-8 * np.max(np.abs(F_o))
+    # central differences of the dense oracle action on a few links (h = 1e-5)
+    h = 1e-5
+    for (mu, y, x) in [(0, 1, 2), (1, 5, 0), (0, 7, 7)]:
+        tp = theta.copy(); tp[mu, y, x] += h
+        tm = theta.copy(); tm[mu, y, x] -= h
+        fd = (dense_action_and_force(tp, phi, m, M5)[0] - dense_action_and_force(tm, phi, m, M5)[0]) / (2 * h)
+        assert abs(fd - g[mu, y, x]) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_differentiation_form_full_size():
+    """256^2 x Ls 16, beta 6, m 0.01: forward + backward through the mixed-precision
+    solver; both solves meet their tolerance on the oracle operator and the force
+    kernel agrees with the oracle's force formula on the same X, Y."""
+    L, Ls, m, M5 = 256, 16, 0.01, -1.0
+    g = inputs.metropolis_u1(L, L, 6.0, 200, inputs.gauge_seed(4, L))
+    phi = inputs.gaussian_field((1, Ls, L, L, 2), 4256000)
+    params = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[4], link_prec=[dwfmg.P_BF16],
+                            vec_prec=[dwfmg.P_F64], fine_prec=dwfmg.P_F32)
+    starts = [T(inputs.gaussian_field((16, L, L, 2), inputs.null_start_seed(4, 0)))]
+    mg = dwfmg.MG(T(g.U), Ls, m, M5, params, starts)
+    th = T(g.theta).requires_grad_(True)
+    tol = 1e-10
+    U = torch.polar(torch.ones_like(th.detach()), th.detach())
+    # forward pieces, as the autograd function runs them
+    Y = dwfmg.dwf_gamma5R(mg.solve(dwfmg.dwf_gamma5R(T(phi)), tol)[0])
+    X = mg.solve(Y, tol)[0]
+    Yn, Xn = Y.cpu().numpy(), X.cpu().numpy()
+    Un = U.cpu().numpy()
+    # D^dag Y = phi  and  D X = Y  on the oracle operator
+    r1 = np.linalg.norm(phi - O.dwf(Un, Yn, m, M5, dagger=True)) / np.linalg.norm(phi)
+    r2 = np.linalg.norm(Yn - O.dwf(Un, Xn, m, M5)) / np.linalg.norm(Yn)
+    assert r1 <= 1e-9 and r2 <= 1e-10
+    F = dwfmg.dwf_force(U, X, Y).cpu().numpy()
+    F_o = O.force(Un, Xn, Yn)
+    assert np.max(np.abs(F - F_o)) < 1e-11 * np.max(np.abs(F_o))
+    # the autograd path produces the same gradient
+    S = action(th, T(phi), mg, tol=tol)
+    S.backward()
+    assert np.max(np.abs(th.grad.cpu().numpy() - F_o)) < 1e-6 * np.max(np.abs(F_o))
