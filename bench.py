@@ -134,6 +134,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stencil", action="store_true", help="skip the fine-stencil bandwidth run")
+    ap.add_argument("--counters", action="store_true",
+                    help="only run the dominant kernel (20 launches) next to a plain 256 MiB copy, for "
+                         "rocprofv3 --pmc runs; prints no benchmark line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -154,6 +157,19 @@ def main():
     U = torch.from_numpy(g.U).cuda()
     b = torch.from_numpy(inputs.gaussian_field((1, Ls, L, L, 2), inputs.rhs_seed(wl["cfg"], L, 0))).cuda()
     starts = null_starts(inputs, wl, torch)
+
+    if args.counters:
+        mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True), starts)
+        c = mg.info(1)
+        xin = torch.from_numpy(inputs.gaussian_field((1, c["Ls"], c["Ly"], c["Lx"], c["n"]), 5)).cuda()
+        mg.time_op(1, dwfmg.MG_OP_DW, xin, 1, iters=20)
+        a = torch.ones(256 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+        bcopy = torch.empty_like(a)
+        for _ in range(5):
+            bcopy.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] counters run done: 21 coarse launches, 5 copies of 256 MiB")
+        return
 
     # ---------------------------------------------------------------- mixed-precision solve
     torch.cuda.synchronize()
@@ -185,7 +201,7 @@ def main():
     vec_bytes = 16 if make_params(dwfmg, wl, True).vec_prec[0] == dwfmg.P_F64 else 8
     coarse_bytes = nsites * (5 * n * n * link_bytes + 2 * Lsc * n * vec_bytes)
     achieved = coarse_bytes / (t_coarse_ms * 1e-3) / 1e9
-    traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse.hip"))
+    traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse_mfma.hip"))
     log(f"[bench] coarse stencil {t_coarse_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
     mg.close()
 

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <type_traits>
 
@@ -35,10 +36,46 @@ inline const int* cg_skip(const CgScal* s) { return s ? &s[0].done : nullptr; }
 }  // namespace
 
 Hierarchy::~Hierarchy() {
-    for (void* p : allocs_) hipFree(p);
-    if (h_scal_) hipHostFree(h_scal_);
-    if (h_int_) hipHostFree(h_int_);
-    if (h_cg_) hipHostFree(h_cg_);
+    if (st_) (void)hipStreamSynchronize(st_);
+    clear_graphs();
+    for (void* p : allocs_) (void)hipFree(p);
+    if (h_scal_) (void)hipHostFree(h_scal_);
+    if (h_int_) (void)hipHostFree(h_int_);
+    if (h_cg_) (void)hipHostFree(h_cg_);
+    if (ev_in_) (void)hipEventDestroy(ev_in_);
+    if (st_) (void)hipStreamDestroy(st_);
+}
+
+void Hierarchy::clear_graphs() {
+    for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
+    graphs_.clear();
+}
+
+// Capture `enqueue` (a fixed sequence of launches on `st`) once per key as a
+// HIP graph, then replay it.  The captured sequence contains kernel launches
+// only (no memset or copy nodes).
+template <class F>
+int Hierarchy::run_graph(const GraphKey& key, hipStream_t st, F&& enqueue) {
+    auto it = graphs_.find(key);
+    if (it == graphs_.end()) {
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        capturing_ = true;
+        const int e = enqueue();
+        capturing_ = false;
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(st, &g);
+        if (e != DWF_OK || ee != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return e != DWF_OK ? e : DWF_EHIP;
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return DWF_EHIP;
+        it = graphs_.emplace(key, ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, st));
+    return DWF_OK;
 }
 
 void* Hierarchy::dalloc(size_t bytes) {
@@ -68,7 +105,7 @@ hipError_t Hierarchy::apply_A(int l, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp,
                               const int* skip) {
     hipError_t e = apply_dw<T>(l, in, tmp, m, false, ncol, st, skip);
     if (e != hipSuccess) return e;
-    if (l == 0) cnt_.fine_applies += 2;
+    if (l == 0 && !capturing_) cnt_.fine_applies += 2;
     return apply_dw<T>(l, tmp, out, 1.0, true, ncol, st, skip);
 }
 
@@ -77,7 +114,7 @@ hipError_t Hierarchy::apply_Adag(int l, const cpx<T>* in, cpx<T>* out, cpx<T>* t
                                  const int* skip) {
     hipError_t e = apply_dw<T>(l, in, tmp, 1.0, false, ncol, st, skip);
     if (e != hipSuccess) return e;
-    if (l == 0) cnt_.fine_applies += 2;
+    if (l == 0 && !capturing_) cnt_.fine_applies += 2;
     return apply_dw<T>(l, tmp, out, m, true, ncol, st, skip);
 }
 
@@ -202,6 +239,8 @@ int Hierarchy::ensure_scalars(int maxc) {
 int Hierarchy::ensure_work(int ncol, hipStream_t st) {
     if (ncol <= work_cols_) return DWF_OK;
     HIPCHK(hipStreamSynchronize(st));
+    if (st_) HIPCHK(hipStreamSynchronize(st_));
+    clear_graphs();   // captured launches refer to the buffers being replaced
     if (int e = ensure_scalars(std::max(ncol, 64))) return e;
     work_.assign(levels.size(), LevelWork{});
     for (int l = 0; l < (int)levels.size(); ++l)
@@ -231,15 +270,24 @@ int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st)
     HIPCHK(vconvert<T, T>(z, p, nt, st));
     const int maxit = prm.coarsest_maxit;
     int iters = 0;
-    for (int it0 = 0; it0 < maxit; it0 += kCgChunk) {
-        const int nchunk = std::min(kCgChunk, maxit - it0);
-        for (int c = 0; c < nchunk; ++c) {
+    // one chunk of CGNR iterations; iterations past convergence or maxit are
+    // no-ops on the device, so chunks always have the full length
+    auto chunk = [&](int len) -> int {
+        for (int c = 0; c < len; ++c) {
             HIPCHK(apply_A<T>(l, p, q, t, ncol, st, skip));
             HIPCHK(cg_alpha<T>(q, n, ncol, s, rw_, st));
             HIPCHK(cg_update_xr<T>(x, r, p, q, n, ncol, s, st));
             HIPCHK(apply_Adag<T>(l, r, z, t, ncol, st, skip));
             HIPCHK(cg_beta<T>(z, n, ncol, s, maxit, rw_, st));
             HIPCHK(cg_update_p<T>(p, z, n, ncol, s, st));
+        }
+        return DWF_OK;
+    };
+    for (int it0 = 0; it0 < maxit; it0 += kCgChunk) {
+        if (use_graphs_ && st == st_) {
+            if (int e = run_graph(GraphKey{0, l, ncol, b, x}, st, [&]() { return chunk(kCgChunk); })) return e;
+        } else {
+            if (int e = chunk(kCgChunk)) return e;
         }
         HIPCHK(hipMemcpyAsync(h_cg_, s, sizeof(CgScal) * ncol, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -270,21 +318,29 @@ int Hierarchy::smooth(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t s
     cpx<T>* rs = C<T>(w.rs);
     cpx<T>* t = C<T>(w.tmp);
     cpx<T>* Az = C<T>(w.tmp2);
-    HIPCHK(apply_A<T>(l, z, Az, t, ncol, st));
-    HIPCHK(vsub<T>(r, Az, rs, nt, st));
-    HIPCHK(vconvert<T, T>(rs, Ps, nt, st));
-    for (int j = 0; j < ns; ++j) {
-        cpx<T>* Pj = Ps + (size_t)j * nt;
-        cpx<T>* Wj = Ws + (size_t)j * nt;
-        HIPCHK(apply_A<T>(l, Pj, Wj, t, ncol, st));
-        HIPCHK(gcr_multidot<T>(Ws, nt, j, Wj, n, ncol, w.gsm, rw_, st));
-        HIPCHK(gcr_orth<T>(Ws, nt, j, Wj, rs, n, ncol, w.gsm, rw_, st));
-        HIPCHK(gcr_rupdate<T>(Wj, rs, (j + 1 < ns) ? Ps + (size_t)(j + 1) * nt : nullptr, j, n, ncol, false,
-                              w.gsm, rw_, st));
+    auto body = [&]() -> int {
+        HIPCHK(apply_A<T>(l, z, Az, t, ncol, st));
+        HIPCHK(vsub<T>(r, Az, rs, nt, st));
+        HIPCHK(vconvert<T, T>(rs, Ps, nt, st));
+        for (int j = 0; j < ns; ++j) {
+            cpx<T>* Pj = Ps + (size_t)j * nt;
+            cpx<T>* Wj = Ws + (size_t)j * nt;
+            HIPCHK(apply_A<T>(l, Pj, Wj, t, ncol, st));
+            HIPCHK(gcr_multidot<T>(Ws, nt, j, Wj, n, ncol, w.gsm, rw_, st));
+            HIPCHK(gcr_orth<T>(Ws, nt, j, Wj, rs, n, ncol, w.gsm, rw_, st));
+            HIPCHK(gcr_rupdate<T>(Wj, rs, (j + 1 < ns) ? Ps + (size_t)(j + 1) * nt : nullptr, j, n, ncol, false,
+                                  w.gsm, rw_, st));
+        }
+        HIPCHK(gcr_solve(ns, ncol, w.gsm, st));
+        HIPCHK((gcr_xupdate<T, T>(Ps, nt, ns, z, n, ncol, true, w.gsm, st)));
+        return DWF_OK;
+    };
+    if (use_graphs_ && st == st_) {
+        if (int e = run_graph(GraphKey{1, l, ncol, r, z}, st, body)) return e;
+        if (l == 0) cnt_.fine_applies += 2 * (ns + 1);
+        return DWF_OK;
     }
-    HIPCHK(gcr_solve(ns, ncol, w.gsm, st));
-    HIPCHK((gcr_xupdate<T, T>(Ps, nt, ns, z, n, ncol, true, w.gsm, st)));
-    return DWF_OK;
+    return body();
 }
 
 // ------------------------------------------------------------ K-cycle
@@ -439,6 +495,10 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
     m = m_;
     M5 = M5_;
     levels.clear();
+    if (!st_) HIPCHK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+    if (!ev_in_) HIPCHK(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
+    const char* ng = std::getenv("DWF_NO_GRAPHS");
+    use_graphs_ = !(ng && ng[0] == '1');
     Level f;
     f.Lx = Lx; f.Ly = Ly; f.Ls = Ls; f.n = 2; f.nsites = Lx * Ly; f.fine = true;
     f.vec_prec = p.fine_prec;
@@ -497,9 +557,13 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
 
 // ------------------------------------------------------------ solve
 int Hierarchy::solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol, dwf_solve_stats* stats,
-                     hipStream_t st) {
+                     hipStream_t caller) {
     auto t0 = std::chrono::steady_clock::now();
-    if (int e = ensure_work(ncol, st)) return e;
+    if (int e = ensure_work(ncol, caller)) return e;
+    // run on the context's stream, after everything already queued on the caller's
+    HIPCHK(hipEventRecord(ev_in_, caller));
+    HIPCHK(hipStreamWaitEvent(st_, ev_in_, 0));
+    hipStream_t st = st_;
     cnt_ = SolveCounters{};
     const Level& L = levels[0];
     LevelWork& w = work_[0];

@@ -1,6 +1,8 @@
 // Host-side multigrid hierarchy and Krylov drivers (internal).
 #pragma once
 
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "../../include/dwfmg.h"
@@ -99,6 +101,17 @@ private:
     cpx<double>* t64_ = nullptr;
     int r64_cols_ = 0;
     SolveCounters cnt_{};
+    // solves run on a stream of the context, so that fixed launch sequences
+    // (a chunk of coarsest CGNR iterations, a GCR smoother) can be captured
+    // once as HIP graphs and replayed
+    hipStream_t st_ = nullptr;
+    hipEvent_t ev_in_ = nullptr;
+    bool use_graphs_ = true;
+    bool capturing_ = false;
+    using GraphKey = std::tuple<int, int, int, const void*, const void*>;   // kind, level, ncol, ptrs
+    std::map<GraphKey, hipGraphExec_t> graphs_;
+    template <class F> int run_graph(const GraphKey& key, hipStream_t st, F&& enqueue);
+    void clear_graphs();
 
     void* dalloc(size_t bytes);
     int ensure_work(int ncol, hipStream_t st);

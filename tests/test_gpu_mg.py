@@ -257,6 +257,31 @@ def test_solve_batched_rhs_three_level():
     assert res <= 1e-10
 
 
+def test_graph_replays_match_eager_launches(monkeypatch):
+    """The coarsest CGNR chunks and the smoother run as captured HIP graphs;
+    several replays (with other eager work and synchronisations in between)
+    give bit-identical solutions to a context that launches eagerly."""
+    L, Ls, m, M5 = 32, 8, 0.02, -1.0
+    g = inputs.metropolis_u1(L, L, 6.0, 60, 901)
+    b = T(inputs.gaussian_field((2, Ls, L, L, 2), 902))
+    starts = [T(inputs.gaussian_field((8, L, L, 2), 903)), T(inputs.gaussian_field((12, 8, 8, 16), 904))]
+    params = dwfmg.MGParams(nvec=[8, 12], block=[(4, 4), (2, 2)], Ls_coarse=[4, 4],
+                            link_prec=[dwfmg.P_BF16, dwfmg.P_F64], vec_prec=[dwfmg.P_F32, dwfmg.P_F64],
+                            fine_prec=dwfmg.P_F32)
+    monkeypatch.setenv("DWF_NO_GRAPHS", "1")
+    eager = dwfmg.MG(T(g.U), Ls, m, M5, params, starts)
+    monkeypatch.delenv("DWF_NO_GRAPHS")
+    graphed = dwfmg.MG(T(g.U), Ls, m, M5, params, starts)
+    x_e, st_e = eager.solve(b, 1e-10)
+    for rep in range(3):
+        x_g, st_g = graphed.solve(b, 1e-10)
+        junk = dwfmg.dwf_apply(T(g.U), b, m, M5)      # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(x_g, x_e), f"replay {rep}"
+        assert st_g.level_iters == st_e.level_iters and st_g.fine_applies == st_e.fine_applies
+    del junk
+
+
 # ----------------------------------------------------------------------------- failure handling
 def small_mg(**kw):
     L, Ls = 8, 4
