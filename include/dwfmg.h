@@ -181,6 +181,17 @@ int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, do
 int mg_solve(dwf_mg* mg, const void* b, void* x, int nrhs, double tol, dwf_solve_stats* st,
              void* stream);
 
+/* Batched multi-lattice solve: solves ctx[i] for nrhs[i] right-hand sides
+ * b[i] -> x[i] (layouts as for mg_solve) for i < nctx, all at once.  Each
+ * context works on its own HIP stream from its own host thread, so lattices of
+ * different sizes proceed concurrently on the GPU; every context still
+ * converges on its own FP64 true residual.  stats may be NULL, else an array
+ * of nctx.  Waits for `stream` before starting and returns when all are done.
+ * Returns the worst status (hard errors before soft ones). Contexts must be
+ * distinct. */
+int mg_solve_batch(int nctx, dwf_mg* const* ctx, const void* const* b, void* const* x, const int* nrhs,
+                   double tol, dwf_solve_stats* stats, void* stream);
+
 /* Replace the fine-level gauge field of a built hierarchy (complex128
  * [2][Ly][Lx], copied).  The coarse levels are kept: they remain a valid
  * preconditioner for a nearby field (a molecular-dynamics step, a finite

@@ -4,6 +4,8 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <thread>
+#include <vector>
 
 #include "mg.hpp"
 
@@ -218,6 +220,40 @@ int mg_level_op(dwf_mg* mg, int level, int op, const void* in, void* out, int nc
     if (!mg || !mg->ready) return DWF_ENOSETUP;
     if (!in || !out || in == out) return DWF_EINVAL;
     return mg->h.level_op(level, op, (const cpx<double>*)in, (cpx<double>*)out, ncol, mass, S(stream));
+}
+
+int mg_solve_batch(int nctx, dwf_mg* const* ctx, const void* const* b, void* const* x, const int* nrhs, double tol,
+                   dwf_solve_stats* stats, void* stream) {
+    if (nctx < 1 || !ctx || !b || !x || !nrhs || !(tol > 0.0) || !std::isfinite(tol)) return DWF_EINVAL;
+    for (int i = 0; i < nctx; ++i) {
+        if (!ctx[i] || !ctx[i]->ready) return DWF_ENOSETUP;
+        if (!b[i] || !x[i] || b[i] == x[i] || nrhs[i] < 1) return DWF_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (ctx[j] == ctx[i]) return DWF_EINVAL;
+    }
+    // every context starts after the caller's queued work
+    if (hipStreamSynchronize(S(stream)) != hipSuccess) return DWF_EHIP;
+    std::vector<int> codes(nctx, DWF_OK);
+    std::vector<dwf_solve_stats> st(nctx);
+    std::vector<std::thread> workers;
+    workers.reserve(nctx);
+    for (int i = 0; i < nctx; ++i) {
+        workers.emplace_back([&, i]() {
+            std::memset(&st[i], 0, sizeof(st[i]));
+            codes[i] = ctx[i]->h.solve((const cpx<double>*)b[i], (cpx<double>*)x[i], nrhs[i], tol, &st[i],
+                                       ctx[i]->h.stream());
+            st[i].status = codes[i];
+        });
+    }
+    for (auto& t : workers) t.join();
+    int worst = DWF_OK;
+    for (int i = 0; i < nctx; ++i) {
+        if (stats) stats[i] = st[i];
+        const int c = codes[i];
+        if (c < 0 && (worst >= 0 || c < worst)) worst = c;
+        else if (c > 0 && worst == DWF_OK) worst = c;
+    }
+    return worst;
 }
 
 int dwf_norm2(const void* x, size_t n, int ncol, double* out, void* stream) {

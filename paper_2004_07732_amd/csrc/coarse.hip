@@ -164,7 +164,7 @@ hipError_t coarse_apply(const void* links, int link_prec, const cpx<T>* in, cpx<
                         bool wilson_mode, double wilson_mass, const int* skip, int sks, hipStream_t st) {
     if (g.Ls > 8) return hipErrorInvalidValue;
     if (!wilson_mode && coarse_mfma_supported(g.n, link_prec))
-        return coarse_apply_mfma<T>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
+        return coarse_apply_mfma<T>(links, link_prec, in, out, g, ncol, m, M5, dagger, skip, sks, st);
     switch (link_prec) {
         case P_F64: return launch_l<cpx<double>, T>(links, in, out, g, ncol, m, M5, dagger, wilson_mode, wilson_mass, skip, sks, st);
         case P_F32: return launch_l<cpx<float>, T>(links, in, out, g, ncol, m, M5, dagger, wilson_mode, wilson_mass, skip, sks, st);

@@ -1,4 +1,5 @@
-// Coarse domain-wall operator on the matrix cores (BF16 links, FP32 accumulation).
+// Coarse domain-wall operator on the matrix cores (BF16 or FP16 links, FP32
+// accumulation).
 //
 // Per coarse site the Galerkin stencil is a dense block contraction
 //   out[i][c] = sum_{d,k} Y_d[i][k] psi_d[k][c]        (d: site and 4 neighbours,
@@ -7,39 +8,59 @@
 // (k, re/im), the link rows are used as stored (interleaved complex) and the
 // vector side is rebuilt on the fly:
 //   [Re out | Im out] = [Yr Yi] . [[ psi_r, psi_i], [-psi_i, psi_r]],
-// so one v_mfma_f32_16x16x32_bf16 covers 16 rows x 8 complex columns x 16
-// complex inner entries.  The vector is split into two BF16 parts (hi + lo)
-// and multiplied twice, so the operator applied is the BF16-rounded link
-// matrix acting on a vector carried to about 16 mantissa bits; products are
-// exact in FP32 and accumulate in FP32.
+// so one 16x16x32 matrix instruction covers 16 rows x 8 complex columns x 16
+// complex inner entries.  The vector is split into two 16-bit parts (hi + lo)
+// and multiplied twice, so the operator applied is the rounded link matrix
+// acting on a vector carried to about twice the 16-bit mantissa; products are
+// exact in FP32 and accumulate in FP32.  With FP16 the staged vector of each
+// (site, column tile) is first scaled by a power of two that brings its
+// largest entry near 1 (exact, undone in the epilogue), which keeps FP16 in
+// range whatever the magnitude of the Krylov vectors.
 //
 // Work split: one wavefront per (coarse site, 16-row tile).  A wave loads all
 // of its link fragments up front (every link element is read exactly once per
 // apply, with all loads in flight together) and keeps them in registers while
 // it walks the column tiles.  The five neighbour vectors of a column tile are
-// staged once per site in LDS, already split into BF16 hi/lo pairs, and read
-// back as 16-byte fragments.
+// staged once per site in LDS, already split, and read back as 16-byte
+// fragments.
 //
-// Links layout for this kernel: per site, row-major [i][d*n + k] complex BF16.
-// The site-local terms (the M5 + 1 shift and the fifth-dimension hops through
-// hatP_pm with the -m corners, eq. coarsenDW) and sigma_3 for the adjoint
-// (hat-D_W^dagger = sigma_3 hat-D_W sigma_3) are applied in the epilogue.
+// Links layout for this kernel: per site, row-major [i][d*n + k] complex
+// 16-bit pairs (re low, im high).  The site-local terms (the M5 + 1 shift and
+// the fifth-dimension hops through hatP_pm with the -m corners, eq. coarsenDW)
+// and sigma_3 for the adjoint (hat-D_W^dagger = sigma_3 hat-D_W sigma_3) are
+// applied in the epilogue.
 #include "kernels.hpp"
 
 namespace dwf {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-// (re, im) -> bf16 pair packed in 32 bits (re low, im high), RNE
-__device__ __forceinline__ uint32_t pack_bf16(float re, float im) {
-    return f32_to_bf16_bits(re) | (f32_to_bf16_bits(im) << 16);
-}
-__device__ __forceinline__ float bf16_lo_f(uint32_t u) { return __uint_as_float(u << 16); }
-__device__ __forceinline__ float bf16_hi_f(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
+template <bool F16> struct Half;
+template <> struct Half<false> {   // bfloat16
+    static __device__ __forceinline__ uint32_t bits(float x) { return f32_to_bf16_bits(x); }
+    static __device__ __forceinline__ float value(uint32_t b) { return __uint_as_float(b << 16); }
+    static __device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                       0, 0, 0);
+    }
+};
+template <> struct Half<true> {    // binary16
+    static __device__ __forceinline__ uint32_t bits(float x) {
+        return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)x);
+    }
+    static __device__ __forceinline__ float value(uint32_t b) {
+        return (float)__builtin_bit_cast(_Float16, (unsigned short)(b & 0xffffu));
+    }
+    static __device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+    }
+};
 
 template <typename T>
 __device__ __forceinline__ void load4(const cpx<T>* p, float (&re)[4], float (&im)[4]) {
@@ -51,29 +72,33 @@ __device__ __forceinline__ void load4(const cpx<T>* p, float (&re)[4], float (&i
     }
 }
 
-// B fragment for 4 complex inner entries from packed bf16 pairs:
-// real-output columns take [re, -im], imaginary-output columns [im, re]
-__device__ __forceinline__ bf16x8 make_b(u32x4 u, bool imag_col) {
+// B fragment for 4 complex inner entries from packed 16-bit pairs (re low, im
+// high): real-output columns take [re, -im], imaginary-output columns [im, re]
+// (the sign bit of both formats is bit 15).
+__device__ __forceinline__ u32x4 make_b(u32x4 u, bool imag_col) {
     u32x4 r;
 #pragma unroll
     for (int e = 0; e < 4; ++e) r[e] = imag_col ? ((u[e] >> 16) | (u[e] << 16)) : (u[e] ^ 0x80000000u);
-    return __builtin_bit_cast(bf16x8, r);
+    return r;
 }
 
 }  // namespace
 
-template <typename T, int N, bool DAG>
+template <bool F16, typename T, int N, bool DAG>
 __global__ void __launch_bounds__(256)
-coarse_mfma_kernel(const bf16x8* __restrict__ links, const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                    const int* __restrict__ skip, int sks, int Lx, int Ly, int Ls, int nsites, int ncol,
                    float cdiag, float mwrap) {
+    using HF = Half<F16>;
     constexpr int MT = N / 16;                    // row tiles = waves per site
     constexpr int SPB = (MT >= 4) ? 1 : 4 / MT;   // sites per block
     constexpr int KS = 5 * N / 16;                // inner steps of 16 complex entries
     constexpr int H = N / 2;                      // chirality boundary (sigma_3)
     constexpr int ROW = 5 * N / 4;                // 16-byte link chunks per row
     constexpr int SLAB = 5 * 8 * N;               // staged entries per site and part (d, c8, k)
+    constexpr int PER = SLAB / (MT * 64);         // staged entries per thread (= 10)
     __shared__ __attribute__((aligned(16))) uint32_t sB[SPB][2][SLAB];   // [site][hi/lo][(d*8 + c8)*N + k]
+    __shared__ float smax[SPB][MT];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int sl = wave / MT, m = wave - sl * MT;
@@ -92,9 +117,9 @@ coarse_mfma_kernel(const bf16x8* __restrict__ links, const cpx<T>* __restrict__ 
     }
 
     // all link fragments of this wave's 16 rows, loaded once
-    bf16x8 a[KS];
+    u32x4 a[KS];
     if (valid_site) {
-        const bf16x8* lrow = links + ((size_t)site * N + 16 * m + q) * ROW + kg;
+        const u32x4* lrow = links + ((size_t)site * N + 16 * m + q) * ROW + kg;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) a[ks] = lrow[ks * 4];
     }
@@ -105,23 +130,51 @@ coarse_mfma_kernel(const bf16x8* __restrict__ links, const cpx<T>* __restrict__ 
     const int tid_in_site = threadIdx.x - sl * MT * 64;
     for (int t = 0; t < ntile; ++t) {
         const int cbase = 8 * t;
-        // stage the five neighbour vectors of columns cbase..cbase+7 (split hi/lo)
+        // stage the five neighbour vectors of columns cbase..cbase+7
+        float vr[PER], vi[PER];
+        float mx = 0.f;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            vr[p] = 0.f;
+            vi[p] = 0.f;
+            const int e = tid_in_site + p * MT * 64;
+            const int k = e % N;
+            const int dc = e / N;
+            const int c8 = dc & 7, d = dc >> 3;
+            const int c = cbase + c8;
+            if (valid_site && col_ok(c)) {
+                const cpx<T> v = in[((size_t)c * nsites + nb[d]) * N + k];
+                float re = (float)v.re, im = (float)v.im;
+                if (DAG && k >= H) { re = -re; im = -im; }
+                vr[p] = re;
+                vi[p] = im;
+                if (F16) mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+            }
+        }
+        float scale = 1.f, unscale = 1.f;
+        if (F16) {
+            for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+            if (lane == 0) smax[sl][m] = mx;
+            __syncthreads();
+            float smx = 0.f;
+#pragma unroll
+            for (int w = 0; w < MT; ++w) smx = fmaxf(smx, smax[sl][w]);
+            if (smx > 0.f) {
+                int ex;
+                frexpf(smx, &ex);            // smx in [2^(ex-1), 2^ex)
+                scale = ldexpf(1.f, -ex);    // scaled maximum in [1/2, 1)
+                unscale = ldexpf(1.f, ex);
+            }
+        }
         if (valid_site) {
-            for (int e = tid_in_site; e < SLAB; e += MT * 64) {
-                const int k = e % N;
-                const int dc = e / N;
-                const int c8 = dc & 7, d = dc >> 3;
-                const int c = cbase + c8;
-                uint32_t hi = 0u, lo = 0u;
-                if (col_ok(c)) {
-                    const cpx<T> v = in[((size_t)c * nsites + nb[d]) * N + k];
-                    float re = (float)v.re, im = (float)v.im;
-                    if (DAG && k >= H) { re = -re; im = -im; }
-                    hi = pack_bf16(re, im);
-                    lo = pack_bf16(re - bf16_lo_f(hi), im - bf16_hi_f(hi));
-                }
-                sB[sl][0][e] = hi;
-                sB[sl][1][e] = lo;
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int e = tid_in_site + p * MT * 64;
+                const float re = vr[p] * scale, im = vi[p] * scale;
+                const uint32_t hre = HF::bits(re), him = HF::bits(im);
+                const uint32_t lre = HF::bits(re - HF::value(hre)), lim = HF::bits(im - HF::value(him));
+                sB[sl][0][e] = hre | (him << 16);
+                sB[sl][1][e] = lre | (lim << 16);
             }
         }
         __syncthreads();
@@ -134,8 +187,8 @@ coarse_mfma_kernel(const bf16x8* __restrict__ links, const cpx<T>* __restrict__ 
                 const int off = (d * 8 + (q & 7)) * N + kd;
                 const u32x4 uh = *reinterpret_cast<const u32x4*>(&sB[sl][0][off]);
                 const u32x4 ul = *reinterpret_cast<const u32x4*>(&sB[sl][1][off]);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], make_b(uh, imag_col), acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], make_b(ul, imag_col), acc, 0, 0, 0);
+                acc = HF::mma(a[ks], make_b(uh, imag_col), acc);
+                acc = HF::mma(a[ks], make_b(ul, imag_col), acc);
             }
         }
         // lanes q and q^8 hold the real and imaginary parts of the same outputs
@@ -158,51 +211,60 @@ coarse_mfma_kernel(const bf16x8* __restrict__ links, const cpx<T>* __restrict__ 
             cpx<T>* dst = out + ((size_t)c * nsites + site) * N + i0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                float re = acc[e], im = p[e];
+                float re = acc[e] * unscale, im = p[e] * unscale;
                 if (DAG && minus) { re = -re; im = -im; }
                 re += cdiag * cr[e] + f * hr[e];
                 im += cdiag * ci[e] + f * hi[e];
                 dst[e] = {(T)re, (T)im};
             }
         }
-        __syncthreads();   // sB is rewritten for the next column tile
+        __syncthreads();   // sB and smax are rewritten for the next column tile
     }
 }
 
 namespace {
 
-template <typename T, int N>
+template <bool F16, typename T, int N>
 hipError_t launch_n(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol, double m,
                     double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
     constexpr int MT = N / 16;
     constexpr int SPB = (MT >= 4) ? 1 : 4 / MT;
     const int nsites = g.Lx * g.Ly;
     dim3 grid((nsites + SPB - 1) / SPB), block(64 * MT * SPB);
-    const bf16x8* lk = reinterpret_cast<const bf16x8*>(links);
+    const u32x4* lk = reinterpret_cast<const u32x4*>(links);
     const float cd = (float)(M5 + 1.0), mw = (float)(-m);
-    if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<T, N, true>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
-    else        hipLaunchKernelGGL((coarse_mfma_kernel<T, N, false>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
+    if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
+    else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, false>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
     return hipGetLastError();
 }
 
-}  // namespace
-
-bool coarse_mfma_supported(int n, int link_prec) { return link_prec == P_BF16 && (n % 16) == 0 && n <= 64; }
-
-template <typename T>
-hipError_t coarse_apply_mfma(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol,
-                             double m, double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
+template <bool F16, typename T>
+hipError_t launch_p(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol, double m,
+                    double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
     switch (g.n) {
-        case 16: return launch_n<T, 16>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
-        case 32: return launch_n<T, 32>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
-        case 48: return launch_n<T, 48>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
-        case 64: return launch_n<T, 64>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
+        case 16: return launch_n<F16, T, 16>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
+        case 32: return launch_n<F16, T, 32>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
+        case 48: return launch_n<F16, T, 48>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
+        case 64: return launch_n<F16, T, 64>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-// FP64 column layout blk[k][i] -> row-major [i][d*n + k] complex BF16 (round to nearest even)
-__global__ void k_links_rowmajor_bf16(const cpx<double>* in, cbf16* out, int nsites, int n) {
+}  // namespace
+
+bool coarse_mfma_supported(int n, int link_prec) {
+    return (link_prec == P_BF16 || link_prec == P_F16) && (n % 16) == 0 && n <= 64;
+}
+
+template <typename T>
+hipError_t coarse_apply_mfma(const void* links, int link_prec, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g,
+                             int ncol, double m, double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
+    if (link_prec == P_F16) return launch_p<true, T>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
+    return launch_p<false, T>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
+}
+
+// FP64 column layout blk[k][i] -> row-major [i][d*n + k] complex 16-bit pairs (round to nearest even)
+__global__ void k_links_rowmajor16(const cpx<double>* in, uint32_t* out, int nsites, int n, int f16) {
     const long long total = (long long)nsites * 5 * n * n;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
@@ -212,17 +274,25 @@ __global__ void k_links_rowmajor_bf16(const cpx<double>* in, cbf16* out, int nsi
     const int i = (int)((t / (5LL * n)) % n);
     const int site = (int)(t / (5LL * n * n));
     const cpx<double> v = in[(((size_t)site * 5 + d) * n + k) * n + i];
-    const uint32_t re = f32_to_bf16_bits((float)v.re), im = f32_to_bf16_bits((float)v.im);
-    out[t].v = re | (im << 16);
+    uint32_t re, im;
+    if (f16) {
+        re = (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)v.re);
+        im = (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)v.im);
+    } else {
+        re = f32_to_bf16_bits((float)v.re);
+        im = f32_to_bf16_bits((float)v.im);
+    }
+    out[t] = re | (im << 16);
 }
 
-hipError_t convert_links_rowmajor_bf16(const cpx<double>* in, void* out, int nsites, int n, hipStream_t st) {
+hipError_t convert_links_rowmajor16(const cpx<double>* in, void* out, int link_prec, int nsites, int n, hipStream_t st) {
     const long long total = (long long)nsites * 5 * n * n;
-    hipLaunchKernelGGL(k_links_rowmajor_bf16, dim3(grid_for(total)), dim3(kBlock), 0, st, in, (cbf16*)out, nsites, n);
+    hipLaunchKernelGGL(k_links_rowmajor16, dim3(grid_for(total)), dim3(kBlock), 0, st, in, (uint32_t*)out, nsites, n,
+                       link_prec == P_F16 ? 1 : 0);
     return hipGetLastError();
 }
 
-template hipError_t coarse_apply_mfma<float>(const void*, const cpx<float>*, cpx<float>*, const CoarseGeom&, int, double, double, bool, const int*, int, hipStream_t);
-template hipError_t coarse_apply_mfma<double>(const void*, const cpx<double>*, cpx<double>*, const CoarseGeom&, int, double, double, bool, const int*, int, hipStream_t);
+template hipError_t coarse_apply_mfma<float>(const void*, int, const cpx<float>*, cpx<float>*, const CoarseGeom&, int, double, double, bool, const int*, int, hipStream_t);
+template hipError_t coarse_apply_mfma<double>(const void*, int, const cpx<double>*, cpx<double>*, const CoarseGeom&, int, double, double, bool, const int*, int, hipStream_t);
 
 }  // namespace dwf

@@ -13,6 +13,15 @@
 // In 2-d every Wilson hop goes through a rank-1 spin projector (1 -+ gamma_mu)/2,
 // so a hop is one complex projection, one complex link multiply and a
 // reconstruction of the second component (a fixed phase of the first).
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "kernels.hpp"
 
 namespace dwf {
@@ -129,10 +138,80 @@ static inline int pick_chunk(int Lx, int Ly, int Ls, int ncol) {
 }
 
 template <typename R>
+static hipError_t launch_fine(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b, int Lx, int Ly,
+                              int Ls, int ncol, double m, double M5, bool dagger, const int* skip, int skip_stride,
+                              int cs, hipStream_t st);
+
+// Chunk length (slices per thread) of the fine stencil, chosen by timing the
+// candidates once per shape and precision (DWF_AUTOTUNE=0 disables it); the
+// choices persist in the file named by DWF_TUNE_CACHE when that is set.
+template <typename R>
+static int tuned_chunk(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int Ly, int Ls, int ncol,
+                       double m, double M5, bool dagger, hipStream_t st) {
+    static std::mutex mu;
+    static std::map<std::string, int> cache;
+    static bool loaded = false;
+    const int heuristic = pick_chunk(Lx, Ly, Ls, ncol);
+    const char* en = std::getenv("DWF_AUTOTUNE");
+    if (en && en[0] == '0') return heuristic;
+    char keyb[128];
+    std::snprintf(keyb, sizeof keyb, "fine_dw/%zu/%d/%d/%d/%d/%d", sizeof(R), Lx, Ly, Ls, ncol, dagger ? 1 : 0);
+    const std::string key(keyb);
+    std::lock_guard<std::mutex> lk(mu);
+    const char* path = std::getenv("DWF_TUNE_CACHE");
+    if (!loaded) {
+        loaded = true;
+        if (path) {
+            std::ifstream f(path);
+            std::string k;
+            int v;
+            while (f >> k >> v) cache[k] = v;
+        }
+    }
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return heuristic;
+    std::vector<int> cand;
+    for (int c : {Ls, (Ls + 1) / 2, (Ls + 3) / 4, 8, 4, 2})
+        if (c >= 1 && c <= Ls && std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return heuristic;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return heuristic; }
+    int best = heuristic;
+    float best_t = 1e30f;
+    for (int c : cand) {
+        (void)launch_fine<R>(U, in, out, nullptr, Lx, Ly, Ls, ncol, m, M5, dagger, nullptr, 1, c, st);
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < 5; ++r)
+            (void)launch_fine<R>(U, in, out, nullptr, Lx, Ly, Ls, ncol, m, M5, dagger, nullptr, 1, c, st);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, e0, e1) == hipSuccess && t < best_t) { best_t = t; best = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cache[key] = best;
+    if (path) {
+        std::ofstream f(path, std::ios::app);
+        f << key << " " << best << "\n";
+    }
+    return best;
+}
+
+template <typename R>
 hipError_t fine_dw(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b,
                    int Lx, int Ly, int Ls, int ncol, double m, double M5, bool dagger,
                    const int* skip, int skip_stride, hipStream_t st) {
-    const int cs = pick_chunk(Lx, Ly, Ls, ncol);
+    const int cs = tuned_chunk<R>(U, in, out, Lx, Ly, Ls, ncol, m, M5, dagger, st);
+    return launch_fine<R>(U, in, out, b, Lx, Ly, Ls, ncol, m, M5, dagger, skip, skip_stride, cs, st);
+}
+
+template <typename R>
+static hipError_t launch_fine(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b, int Lx, int Ly,
+                              int Ls, int ncol, double m, double M5, bool dagger, const int* skip, int skip_stride,
+                              int cs, hipStream_t st) {
     const int nchunk = (Ls + cs - 1) / cs;
     const long long total = (long long)Lx * Ly * nchunk * ncol;
     const R diag = R(2.0 + M5 + 1.0), mwrap = R(-m);

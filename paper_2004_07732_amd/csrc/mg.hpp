@@ -81,6 +81,7 @@ public:
     int export_level(int level, cpx<double>* V, cpx<double>* kernel, hipStream_t st);
     int time_op(int level, int op, const cpx<double>* in, int ncol, int iters, double* avg_ms, hipStream_t st);
     int update_links(const cpx<double>* U, hipStream_t st);
+    hipStream_t stream() const { return st_; }
 
     std::vector<Level> levels;
     dwf_mg_params prm{};

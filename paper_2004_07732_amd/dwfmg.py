@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
         L.mg_export.argtypes = [vp, i, vp, vp, vp]
         L.mg_time_op.argtypes = [vp, i, i, vp, i, i, ctypes.POINTER(d), vp]
         L.dwf_norm2.argtypes = [vp, sz, i, vp, vp]
+        L.mg_solve_batch.argtypes = [i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     ctypes.POINTER(i), d, ctypes.POINTER(CStats), vp]
         L.mg_update_links.argtypes = [vp, vp, vp]
         L.mg_level_info.argtypes = [vp, i] + [ctypes.POINTER(i)] * 5
         L.mg_destroy.argtypes = [vp]
@@ -79,7 +81,7 @@ def lib() -> ctypes.CDLL:
         L.dwf_strerror.restype = ctypes.c_char_p
         for name in ("dwf_apply", "dwf_pv_apply", "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
                      "dwf_pack", "dwf_unpack", "dwf_force", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
-                     "mg_time_op", "dwf_norm2", "mg_update_links",
+                     "mg_time_op", "dwf_norm2", "mg_update_links", "mg_solve_batch",
                      "mg_level_info", "mg_destroy", "dwf_release_scratch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -344,6 +346,35 @@ def release_scratch():
 
 
 # ----------------------------------------------------------------------------- multigrid
+def _stats(st: "CStats") -> "SolveStats":
+    return SolveStats(st.status, st.outer_steps, st.fine_iters, st.fine_applies, list(st.level_iters),
+                      list(st.level_calls), st.true_rel_residual, st.solve_ms)
+
+
+def solve_batch(mgs: Sequence["MG"], bs: Sequence[torch.Tensor], tol: float = 1e-10, stream=None,
+                check: bool = True):
+    """Solve several lattices at once (mg_solve_batch): returns ([x_i], [stats_i])."""
+    n = len(mgs)
+    if n != len(bs) or n == 0:
+        raise ValueError("one right-hand-side tensor per hierarchy is required")
+    xs, nr = [], []
+    for mg, b in zip(mgs, bs):
+        _need(b, "b", torch.complex128)
+        bb = b if b.dim() == 5 else b.unsqueeze(0)
+        if tuple(bb.shape[1:]) != (mg.Ls, mg.Ly, mg.Lx, 2):
+            raise ValueError("b has the wrong shape for its hierarchy")
+        xs.append(torch.empty_like(b))
+        nr.append(bb.shape[0])
+    VP = ctypes.c_void_p * n
+    st = (CStats * n)()
+    code = lib().mg_solve_batch(n, VP(*[m._h.value for m in mgs]), VP(*[b.data_ptr() for b in bs]),
+                                VP(*[x.data_ptr() for x in xs]), (ctypes.c_int * n)(*nr), float(tol), st,
+                                _stream(stream))
+    if check:
+        _check(code, "mg_solve_batch")
+    return xs, [_stats(s) for s in st]
+
+
 class MG:
     """Domain-wall multigrid hierarchy on one GPU (mg_setup / mg_solve)."""
 

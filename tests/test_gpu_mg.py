@@ -159,8 +159,11 @@ def bf16_round(a):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def bf16_stencil(S):
-    r = lambda z: bf16_round(z.real) + 1j * bf16_round(z.imag)
+def bf16_stencil(S, prec="bf16"):
+    if prec == "bf16":
+        r = lambda z: bf16_round(z.real) + 1j * bf16_round(z.imag)
+    else:
+        r = lambda z: z.real.astype(np.float16).astype(np.float64) + 1j * z.imag.astype(np.float16).astype(np.float64)
     return O.Stencil(diag=r(S.diag), hop=r(S.hop), chir=S.chir)
 
 
@@ -169,21 +172,23 @@ def bf16_stencil(S):
                                                        (24, 2, "f64", (8, 4)), (32, 1, "f32", (8, 4)),
                                                        (6, 2, "f64", (4, 4))])
 @pytest.mark.parametrize("op", ["dw", "dw_dag", "A"])
-def test_coarse_bf16_matrix_core_parity(nvec, ncol, vec_prec, block, op):
-    """The BF16 coarse operator (matrix cores when 2 nvec is a multiple of 16,
-    vector ALUs otherwise) against the oracle's coarse operator built on the
-    same links rounded to BF16."""
+@pytest.mark.parametrize("lprec", ["bf16", "f16"])
+def test_coarse_bf16_matrix_core_parity(nvec, ncol, vec_prec, block, op, lprec):
+    """The BF16 / FP16 coarse operator (matrix cores when 2 nvec is a multiple
+    of 16, vector ALUs otherwise) against the oracle's coarse operator built on
+    the same links rounded to the storage format."""
     L, Ls, m, M5 = 16, 4, 0.05, -1.0
     bx, by = block
     U = inputs.metropolis_u1(L, L, 6.0, 30, 370).U
     starts = [inputs.gaussian_field((nvec, L, L, 2), 371)]
     vp = dwfmg.P_F64 if vec_prec == "f64" else dwfmg.P_F32
-    params = dwfmg.MGParams(nvec=[nvec], block=[block], Ls_coarse=[4], link_prec=[dwfmg.P_BF16],
+    lp = dwfmg.P_BF16 if lprec == "bf16" else dwfmg.P_F16
+    params = dwfmg.MGParams(nvec=[nvec], block=[block], Ls_coarse=[4], link_prec=[lp],
                             vec_prec=[vp], setup_iters=0)
     mg = dwfmg.MG(T(U), Ls, m, M5, params, [T(s) for s in starts])
     oparams = O.MGParams(levels=[O.LevelParams(nvec=nvec, block=(by, bx), Ls=4, setup_iters=0)])
     omg = O.MG(U, Ls, m, M5, oparams, starts)
-    Sb = bf16_stencil(omg.levels[1].S)
+    Sb = bf16_stencil(omg.levels[1].S, lprec)
     x = inputs.gaussian_field((ncol, 4, L // by, L // bx, 2 * nvec), 372)
     if vec_prec == "f32":
         x = x.astype(np.complex64).astype(np.complex128)
@@ -198,9 +203,31 @@ def test_coarse_bf16_matrix_core_parity(nvec, ncol, vec_prec, block, op):
     err = rel(got, want)
     full = rel(got, {"dw": lambda: omg.levels[1].dw(x, m, M5), "dw_dag": lambda: omg.levels[1].dw(x, m, M5, dagger=True),
                      "A": lambda: omg.A(1, x)}[op]())
-    print(f"BF16 coarse {op} nvec={nvec} ncol={ncol}: vs BF16-link oracle {err:.2e}, vs FP64 oracle {full:.2e}")
+    print(f"{lprec} coarse {op} nvec={nvec} ncol={ncol}: vs rounded-link oracle {err:.2e}, vs FP64 oracle {full:.2e}")
     assert err < (3e-5 if vec_prec == "f64" else 5e-5) * (1 if op == "dw" else 10)
     assert full < 2e-2
+
+
+def test_batched_multi_lattice_solve_fp16():
+    """Several lattice sizes solved together (mg_solve_batch), FP16 coarse links
+    on the matrix cores, FP32 fine level, FP64 defect correction to 1e-10."""
+    Ls, m, M5 = 8, 0.005, -1.0
+    cases = [(16, 2), (32, 3), (24, 1)]
+    mgs, bs, raw = [], [], []
+    for k, (L, nr) in enumerate(cases):
+        g = inputs.metropolis_u1(L, L, 3.0, 100, 30000 + L)
+        starts = [T(inputs.gaussian_field((8, L, L, 2), inputs.null_start_seed(3, 0) + k))]
+        params = dwfmg.MGParams(nvec=[8], block=[(4, 4)], Ls_coarse=[4], link_prec=[dwfmg.P_F16],
+                                vec_prec=[dwfmg.P_F64], fine_prec=dwfmg.P_F32)
+        mgs.append(dwfmg.MG(T(g.U), Ls, m, M5, params, starts))
+        b = inputs.gaussian_field((nr, Ls, L, L, 2), 3_000_000 + 1000 * L)
+        bs.append(T(b))
+        raw.append((g.U, b))
+    xs, sts = dwfmg.solve_batch(mgs, bs, 1e-10)
+    for (U, b), x, st in zip(raw, xs, sts):
+        res = oracle_residual(U, x.cpu().numpy(), b, m, M5)
+        print(f"batched L={U.shape[1]} nrhs={b.shape[0]}: residual {res:.2e}, {st}")
+        assert res <= 1e-10 and st.status == 0
 
 
 # ----------------------------------------------------------------------------- solves
