@@ -43,7 +43,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_params(dwfmg, wl, mixed):
+def make_params(dwfmg, wl, mixed, nev=0, **eig):
     n = len(wl["nvec"])
     if mixed:
         link = [dwfmg.P_BF16] * n
@@ -54,7 +54,7 @@ def make_params(dwfmg, wl, mixed):
         vec = [dwfmg.P_F64] * n
         fine = dwfmg.P_F64
     return dwfmg.MGParams(nvec=list(wl["nvec"]), block=list(wl["block"]), Ls_coarse=list(wl["Ls_coarse"]),
-                          link_prec=link, vec_prec=vec, fine_prec=fine)
+                          link_prec=link, vec_prec=vec, fine_prec=fine, coarsest_nev=nev, **eig)
 
 
 def null_starts(inputs, wl, torch):
@@ -134,6 +134,15 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stencil", action="store_true", help="skip the fine-stencil bandwidth run")
+    ap.add_argument("--nev", type=int, default=0,
+                    help="deflate the coarsest solve with this many eigenvectors of its normal operator")
+    ap.add_argument("--eig-degree", type=int, default=None, help="Chebyshev filter degree of the eigensolver")
+    ap.add_argument("--eig-maxit", type=int, default=None)
+    ap.add_argument("--eig-tol", type=float, default=None)
+    ap.add_argument("--coarsest", choices=["cgnr", "gcr"], default="cgnr",
+                    help="coarsest-level solver: CGNR on A^dag A (as in the paper) or restarted GCR on A")
+    ap.add_argument("--coarsest-restart", type=int, default=16)
+    ap.add_argument("--coarsest-tol", type=float, default=None, help="coarsest relative tolerance (default 0.05)")
     ap.add_argument("--counters", action="store_true",
                     help="only run the dominant kernel (20 launches) next to a plain 256 MiB copy, for "
                          "rocprofv3 --pmc runs; prints no benchmark line")
@@ -174,10 +183,20 @@ def main():
     # ---------------------------------------------------------------- mixed-precision solve
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True), starts)
+    eig = {k: v for k, v in (("eig_degree", args.eig_degree), ("eig_maxit", args.eig_maxit),
+                             ("eig_tol", args.eig_tol)) if v is not None}
+    eig["coarsest_solver"] = dwfmg.COARSEST_GCR if args.coarsest == "gcr" else dwfmg.COARSEST_CGNR
+    eig["coarsest_restart"] = args.coarsest_restart
+    if args.coarsest_tol is not None:
+        eig["coarsest_tol"] = args.coarsest_tol
+    mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True, args.nev, **eig), starts)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"[bench] setup {setup_s:.2f} s")
+    if args.nev:
+        di = mg.deflation_info()
+        log(f"[bench] deflation: nev {di['nev']}, {di['iters']} filtered iterations, worst residual "
+            f"{di['worst_residual']:.1e}, lambda {di['lambdas'][0]:.3e} .. {di['lambdas'][-1]:.3e}")
     for i in range(args.warmup):
         x, st = mg.solve(b, 1e-10)
         log(f"[bench] warmup {i}: {st.solve_ms:.1f} ms, residual {st.true_rel_residual:.2e}, "
@@ -263,7 +282,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "lattice": f"{L}x{L}", "Ls": Ls, "nrhs": 1, "beta": wl["beta"],
                    "m_f": m, "M5": M5, "tol": 1e-10,
-                   "mg": {"nvec": wl["nvec"], "block": wl["block"], "Ls_coarse": wl["Ls_coarse"]},
+                   "mg": {"nvec": wl["nvec"], "block": wl["block"], "Ls_coarse": wl["Ls_coarse"],
+                          "coarsest_nev": args.nev, "coarsest_solver": args.coarsest},
                    "precision": "fine FP32, coarse links BF16 (FP32 arithmetic), coarse vectors FP64, "
                                 "outer defect correction FP64"},
         "roofline": {"bound": "hbm", "kernel": "coarse_kernel (coarse D_DW apply, level 1)",

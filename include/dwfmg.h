@@ -68,6 +68,10 @@ extern "C" {
 
 #define DWF_MAX_LEVELS 3       /* coarse levels below the fine one                   */
 
+/* coarsest-level solver */
+#define DWF_COARSEST_CGNR 0
+#define DWF_COARSEST_GCR  1
+
 /* ---------------------------------------------------------------- operators */
 
 /* out = D_DW(m_f) psi (or D_DW(m_f)^dagger psi with DWF_DAGGER), eq. DWoperator.
@@ -145,6 +149,18 @@ typedef struct {
     double inner_tol;                     /* relative tolerance of one inner solve      */
     int    max_iters;                     /* cap on fine GCR iterations per solve       */
     int    max_outer;                     /* cap on defect-correction steps             */
+    int    coarsest_nev;                  /* deflate the coarsest CGNR with this many
+                                             lowest eigenvectors of A^dag A (0: off;
+                                             needs FP64 coarsest vectors)               */
+    int    eig_degree;                    /* degree of the Chebyshev polynomial that
+                                             accelerates the Lanczos eigensolve
+                                             (0: chosen from the spectral bounds)       */
+    int    eig_maxit;                     /* thick-restart Lanczos cycles (max)         */
+    double eig_tol;                       /* |H v - lambda v| / lambda of the kept pairs */
+    int    coarsest_solver;               /* DWF_COARSEST_CGNR (Table 2) or
+                                             DWF_COARSEST_GCR: restarted GCR on A itself,
+                                             |r| <= coarsest_tol |b|                     */
+    int    coarsest_restart;              /* GCR restart length on the coarsest (<= 16) */
 } dwf_mg_params;
 
 typedef struct {
@@ -227,6 +243,16 @@ int mg_time_op(dwf_mg* mg, int level, int op, const void* in, int ncol, int iter
  * Ly_l*Lx_l*2*nc*nvec) or coarse kernel (level l+1) in stencil form
  * diag[Y][X][n][n] then hop[4][Y][X][n][n] (h = +x, -x, +y, -y), complex128. */
 int mg_export(dwf_mg* mg, int level, void* prolongator, void* coarse_kernel, void* stream);
+
+/* Deflation space of the coarsest level (Sec. 3, Table 1: the coarsest level
+ * deflated with its lowest eigenvectors).  H = A^dag A of the coarsest level;
+ * its lowest eigenpairs come from a thick-restart Lanczos process on a
+ * Chebyshev polynomial of H, finished by a Rayleigh-Ritz step on H itself.
+ * Fills the number of eigenpairs kept, the Lanczos steps taken and the worst
+ * relative residual |H v - lambda v| / lambda of the kept pairs; `lambdas`
+ * (host, may be NULL, nev entries) receives the eigenvalues in ascending
+ * order.  DWF_ENOSETUP without a set-up hierarchy. */
+int mg_deflation_info(const dwf_mg* mg, int* nev, int* iters, double* worst_residual, double* lambdas);
 
 /* Geometry of level l: fills Lx, Ly, Ls, dof per site and nvec (0 on the coarsest). */
 int mg_level_info(const dwf_mg* mg, int level, int* Lx, int* Ly, int* Ls, int* n, int* nvec);

@@ -17,7 +17,9 @@ LIB = os.path.join(HERE, "libdwfmg.so")
 ARCH = os.environ.get("DWF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["fine_stencil.hip", "blas.hip", "coarse.hip", "coarse_mfma.hip", "transfer.hip", "setup.hip", "util.hip",
-           "mg.hip", "abi.hip"]
+           "mg.hip", "deflate.hip", "abi.hip"]
+# dense block products of the coarsest-level eigensolver
+LIBS = ["-L/opt/rocm/lib", "-lrocblas", "-lrocsolver", "-Wl,-rpath,/opt/rocm/lib"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
@@ -54,7 +56,7 @@ def build(verbose: bool = True) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, *LIBS, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")

@@ -168,6 +168,22 @@ void dwf_mg_default_params(dwf_mg_params* p, int nlevels) {
     p->inner_tol = 0.0;
     p->max_iters = 10000;
     p->max_outer = 20;
+    p->coarsest_nev = 0;
+    p->eig_degree = 0;
+    p->eig_maxit = 40;
+    p->eig_tol = 1e-3;
+    p->coarsest_solver = DWF_COARSEST_CGNR;
+    p->coarsest_restart = 16;
+}
+
+int mg_deflation_info(const dwf_mg* mg, int* nev, int* iters, double* worst_residual, double* lambdas) {
+    if (!mg || !mg->ready) return DWF_ENOSETUP;
+    if (nev) *nev = mg->h.def_nev_;
+    if (iters) *iters = mg->h.eig_iters_;
+    if (worst_residual) *worst_residual = mg->h.eig_worst_;
+    if (lambdas)
+        for (int i = 0; i < mg->h.def_nev_; ++i) lambdas[i] = mg->h.def_lam_host_[i];
+    return DWF_OK;
 }
 
 int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, double M5, const dwf_mg_params* p,
@@ -179,6 +195,13 @@ int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, do
     if (p->outer_restart < 1 || p->outer_restart > 16 || p->smooth_iters < 0 || p->smooth_iters > 16) return DWF_EINVAL;
     if (p->nlevels > 1 && (p->inter_restart < 1 || p->inter_restart > 16)) return DWF_EINVAL;
     if (!valid_prec(p->fine_prec, false)) return DWF_EINVAL;
+    if (p->coarsest_nev < 0 || (p->coarsest_nev > 0 && (p->eig_maxit < 1 || p->eig_degree < 0 || !(p->eig_tol > 0.0))))
+        return DWF_EINVAL;
+    if (p->coarsest_nev > 0 && p->vec_prec[p->nlevels - 1] != DWF_P_F64) return DWF_EUNSUPPORTED;
+    if (p->coarsest_solver != DWF_COARSEST_CGNR && p->coarsest_solver != DWF_COARSEST_GCR) return DWF_EINVAL;
+    if (p->coarsest_solver == DWF_COARSEST_GCR && (p->coarsest_restart < 1 || p->coarsest_restart > 16))
+        return DWF_EINVAL;
+    if (p->coarsest_solver == DWF_COARSEST_GCR && p->coarsest_nev > 0) return DWF_EUNSUPPORTED;
     int lx = Lx, ly = Ly, n = 2;
     for (int l = 0; l < p->nlevels; ++l) {
         const int bx = p->block[l][0], by = p->block[l][1], nv = p->nvec[l];

@@ -420,6 +420,30 @@ k_gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int wan
     if (want_norm) write_partials<1>(v, 1, rw, col, sh, tot);
 }
 
+__global__ void k_gcr_dev_init(int ncol, GcrDev g) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    const double b = g.rr[c];
+    g.bb[c] = b;
+    g.it[c] = 0;
+    g.stop[c] = finite(b) ? (b == 0.0 ? 1 : 0) : 2;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fin_gcr_rr(RedWork rw, int nb, GcrDev g, double tol2) {
+    SHARED_RED;
+    const int col = blockIdx.x;
+    sum_partials<1>(1, nb, rw, col, sh, tot);
+    if (threadIdx.x == 0) {
+        const double rr = tot[0];
+        g.rr[col] = rr;
+        if (g.stop[col] == 0) {
+            g.it[col] += 1;
+            if (!finite(rr)) g.stop[col] = 2;
+            else if (rr <= tol2 * g.bb[col]) g.stop[col] = 1;
+        }
+    }
+}
+
 __global__ void k_gcr_solve(int k, int ncol, GcrDev g) {
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= ncol) return;
@@ -489,6 +513,18 @@ hipError_t gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n
         hipLaunchKernelGGL(k_fin_store, dim3(ncol), dim3(kBlock), 0, st, rw, 1, (int)grid.x, g.rr, (size_t)1);
     return hipGetLastError();
 }
+template <typename T>
+hipError_t gcr_rupdate_dev(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int ncol, double tol2,
+                           const GcrDev& g, const RedWork& rw, hipStream_t st) {
+    dim3 grid = red_grid(n, ncol, rw);
+    hipLaunchKernelGGL(k_gcr_rupdate<T>, grid, dim3(kBlock), 0, st, w, r, copy, j, n, 1, g, rw);
+    hipLaunchKernelGGL(k_fin_gcr_rr, dim3(ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g, tol2);
+    return hipGetLastError();
+}
+hipError_t gcr_dev_init(int ncol, const GcrDev& g, hipStream_t st) {
+    hipLaunchKernelGGL(k_gcr_dev_init, dim3(grid_for(ncol, 64)), dim3(64), 0, st, ncol, g);
+    return hipGetLastError();
+}
 hipError_t gcr_solve(int k, int ncol, const GcrDev& g, hipStream_t st) {
     hipLaunchKernelGGL(k_gcr_solve, dim3(grid_for(ncol, 64)), dim3(64), 0, st, k, ncol, g);
     return hipGetLastError();
@@ -532,6 +568,7 @@ hipError_t check_finite(const cpx<T>* x, size_t n, int* flag, hipStream_t st) {
     template hipError_t gcr_multidot<T>(const cpx<T>*, size_t, int, const cpx<T>*, size_t, int, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_orth<T>(const cpx<T>*, size_t, int, cpx<T>*, const cpx<T>*, size_t, int, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_rupdate<T>(const cpx<T>*, cpx<T>*, cpx<T>*, int, size_t, int, bool, const GcrDev&, const RedWork&, hipStream_t); \
+    template hipError_t gcr_rupdate_dev<T>(const cpx<T>*, cpx<T>*, cpx<T>*, int, size_t, int, double, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t check_finite<T>(const cpx<T>*, size_t, int*, hipStream_t);
 
 INST_T(float)

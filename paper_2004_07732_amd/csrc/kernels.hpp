@@ -82,6 +82,8 @@ hipError_t cg_update_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* w, 
 // znew = |z|^2; unless done: done = znew <= tol2 zz0, beta = znew / zz, zz = znew, iters++
 template <typename T>
 hipError_t cg_beta(const cpx<T>* z, size_t n, int ncol, CgScal* s, int maxit, const RedWork& rw, hipStream_t st);
+// s.zz0 = ref[c] (a reference norm other than the starting residual), done re-evaluated
+hipError_t cg_set_ref(CgScal* s, const double* ref, int ncol, hipStream_t st);
 // p = z + beta p   (skipped when done)
 template <typename T>
 hipError_t cg_update_p(cpx<T>* p, const cpx<T>* z, size_t n, int ncol, const CgScal* s, hipStream_t st);
@@ -96,7 +98,9 @@ struct GcrDev {
     double* wr;     // [ncol][kmax][2]
     double* gam;    // [ncol][kmax][2]
     double* rr;     // [ncol]
-    int* stop;      // [ncol]  1: column takes no update
+    int* stop;      // [ncol]  1: column takes no update (2: not finite)
+    double* bb;     // [ncol]  |b|^2 of the device-driven solve
+    int* it;        // [ncol]  iterations of the device-driven solve
     int kmax;
 };
 // D[c][j][i] = <W_i, w>, i < j;  W_i = W + i*wstride
@@ -111,6 +115,12 @@ hipError_t gcr_orth(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, const cpx
 template <typename T>
 hipError_t gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int ncol,
                        bool want_norm, const GcrDev& g, const RedWork& rw, hipStream_t st);
+// device-driven GCR: bb = rr (= |b|^2), it = 0, stop = 1 when bb == 0, 2 when not finite
+hipError_t gcr_dev_init(int ncol, const GcrDev& g, hipStream_t st);
+// gcr_rupdate with the norm, then on the device: it += 1 and stop = (rr <= tol2 bb) for live columns
+template <typename T>
+hipError_t gcr_rupdate_dev(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int ncol, double tol2,
+                           const GcrDev& g, const RedWork& rw, hipStream_t st);
 // back substitution for gam over directions 0..k-1
 hipError_t gcr_solve(int k, int ncol, const GcrDev& g, hipStream_t st);
 // x (+)= sum_{i<k} gam[i] P_i ; `accumulate` false overwrites x

@@ -38,6 +38,7 @@ inline const int* cg_skip(const CgScal* s) { return s ? &s[0].done : nullptr; }
 Hierarchy::~Hierarchy() {
     if (st_) (void)hipStreamSynchronize(st_);
     clear_graphs();
+    destroy_blas();
     for (void* p : allocs_) (void)hipFree(p);
     if (h_scal_) (void)hipHostFree(h_scal_);
     if (h_int_) (void)hipHostFree(h_int_);
@@ -172,7 +173,8 @@ int Hierarchy::alloc_level_work(int l, int ncol) {
     w.ncol = ncol;
     const size_t vb = L.vec_elems() * cplx_bytes(L.vec_prec) * ncol;
     const bool coarsest = (l == (int)levels.size() - 1);
-    w.kmax = (l == 0) ? prm.outer_restart : (coarsest ? 0 : prm.inter_restart);
+    const bool coarsest_gcr = coarsest && prm.coarsest_solver == DWF_COARSEST_GCR;
+    w.kmax = (l == 0) ? prm.outer_restart : (coarsest ? (coarsest_gcr ? prm.coarsest_restart : 0) : prm.inter_restart);
     w.ksmooth = coarsest ? 0 : prm.smooth_iters;
     auto A = [&](size_t bytes) { return dalloc(bytes); };
     w.r = A(vb); w.x = A(vb); w.tmp = A(vb); w.tmp2 = A(vb); w.rhs = A(vb);
@@ -208,7 +210,9 @@ int Hierarchy::alloc_level_work(int l, int ncol) {
         g.gam = (double*)A(sizeof(double) * 2 * kmax * ncol);
         g.rr = (double*)A(sizeof(double) * ncol);
         g.stop = (int*)A(sizeof(int) * ncol);
-        if (!g.D || !g.nn || !g.wr || !g.gam || !g.rr || !g.stop) return DWF_EHIP;
+        g.bb = (double*)A(sizeof(double) * ncol);
+        g.it = (int*)A(sizeof(int) * ncol);
+        if (!g.D || !g.nn || !g.wr || !g.gam || !g.rr || !g.stop || !g.bb || !g.it) return DWF_EHIP;
         if (hipMemset(g.stop, 0, sizeof(int) * ncol) != hipSuccess) return DWF_EHIP;
         return DWF_OK;
     };
@@ -266,7 +270,25 @@ int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st)
     HIPCHK(vzero<T>(x, nt, st));
     HIPCHK(vconvert<T, T>(b, r, nt, st));
     HIPCHK(apply_Adag<T>(l, r, z, t, ncol, st));
+    bool deflated = false;
+    if constexpr (std::is_same<T, double>::value) {
+        if (def_nev_ > 0 && l == (int)levels.size() - 1) {
+            // start from e0 = V Lambda^{-1} V^dag A^dag b; keep |A^dag b| as the reference
+            if (ncol > def_ref_cols_) {
+                def_ref_cols_ = std::max(ncol, 64);
+                def_ref_ = (double*)dalloc(sizeof(double) * def_ref_cols_);
+                if (!def_ref_) return DWF_EHIP;
+            }
+            HIPCHK(norm2<T>(z, n, ncol, def_ref_, rw_, st));
+            if (int e = deflate_guess(l, z, x, ncol, st)) return e;
+            HIPCHK(apply_A<T>(l, x, q, t, ncol, st));
+            HIPCHK(vsub<T>(b, q, r, nt, st));
+            HIPCHK(apply_Adag<T>(l, r, z, t, ncol, st));
+            deflated = true;
+        }
+    }
     HIPCHK(cg_init<T>(z, n, ncol, s, prm.coarsest_tol, rw_, st));
+    if (deflated) HIPCHK(cg_set_ref(s, def_ref_, ncol, st));
     HIPCHK(vconvert<T, T>(z, p, nt, st));
     const int maxit = prm.coarsest_maxit;
     int iters = 0;
@@ -303,6 +325,76 @@ int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st)
     for (int c = 0; c < ncol; ++c)
         if (h_cg_[c].done == 4) return DWF_ENAN;
     return DWF_OK;
+}
+
+// ------------------------------------------------------------ restarted GCR (coarsest level)
+// Unpreconditioned GCR(kmax) on A with every decision on the device (the
+// stop flags are reset by gcr_dev_init at the start of every solve): each
+// cycle runs kmax iterations whose kernels turn into no-ops for converged
+// columns, then updates x and recomputes the true residual.  The host reads
+// the stop flags once per cycle; a cycle is captured once as a HIP graph.
+template <typename T>
+int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol, int maxit, int restart,
+                         int* iters_out, hipStream_t st) {
+    const Level& L = levels[l];
+    LevelWork& w = work_[l];
+    const size_t n = L.vec_elems();
+    const size_t nt = n * ncol;
+    const int kmax = std::min(restart, w.kmax);
+    if (kmax < 1) return DWF_EINVAL;
+    cpx<T>* r = C<T>(w.r);
+    cpx<T>* P = C<T>(w.P);
+    cpx<T>* W = C<T>(w.W);
+    cpx<T>* t = C<T>(w.tmp);
+    cpx<T>* t2 = C<T>(w.tmp2);
+    GcrDev& g = w.gcr;
+    const double tol2 = tol * tol;
+    HIPCHK(vzero<T>(x, nt, st));
+    HIPCHK((vconvert<T, T>(b, r, nt, st)));
+    HIPCHK(norm2<T>(b, n, ncol, g.rr, rw_, st));
+    HIPCHK(gcr_dev_init(ncol, g, st));
+    auto cycle = [&]() -> int {
+        HIPCHK((vconvert<T, T>(r, P, nt, st)));
+        for (int k = 0; k < kmax; ++k) {
+            cpx<T>* Pk = P + (size_t)k * nt;
+            cpx<T>* Wk = W + (size_t)k * nt;
+            HIPCHK(apply_A<T>(l, Pk, Wk, t, ncol, st));
+            HIPCHK(gcr_multidot<T>(W, nt, k, Wk, n, ncol, g, rw_, st));
+            HIPCHK(gcr_orth<T>(W, nt, k, Wk, r, n, ncol, g, rw_, st));
+            // the updated residual is the next search direction
+            HIPCHK(gcr_rupdate_dev<T>(Wk, r, k + 1 < kmax ? P + (size_t)(k + 1) * nt : nullptr, k, n, ncol, tol2, g,
+                                      rw_, st));
+        }
+        HIPCHK(gcr_solve(kmax, ncol, g, st));
+        HIPCHK((gcr_xupdate<T, T>(P, nt, kmax, x, n, ncol, true, g, st)));
+        HIPCHK(apply_A<T>(l, x, t2, t, ncol, st));
+        HIPCHK(vsub<T>(b, t2, r, nt, st));
+        return DWF_OK;
+    };
+    const int max_cycles = std::max(1, (maxit + kmax - 1) / kmax);
+    for (int c = 0; c < max_cycles; ++c) {
+        if (use_graphs_ && st == st_) {
+            if (int e = run_graph(GraphKey{2, l, ncol, b, x}, st, cycle)) return e;
+        } else if (int e = cycle()) {
+            return e;
+        }
+        HIPCHK(hipMemcpyAsync(h_int_, g.stop, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool all = true;
+        for (int cc = 0; cc < ncol; ++cc)
+            if (h_int_[cc] == 0) all = false;
+        if (all) break;
+    }
+    HIPCHK(hipMemcpyAsync(h_int_, g.stop, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_int_ + ncol, g.it, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int it = 0, status = DWF_OK;
+    for (int cc = 0; cc < ncol; ++cc) {
+        it = std::max(it, h_int_[ncol + cc]);
+        if (h_int_[cc] == 2) status = DWF_ENAN;
+    }
+    if (iters_out) *iters_out = it;
+    return status;
 }
 
 // ------------------------------------------------------------ GCR smoother
@@ -359,10 +451,15 @@ int Hierarchy::kcycle(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t s
 
 template <typename T>
 int Hierarchy::coarse_solve(int l, const void* rhs, void* x, int ncol, hipStream_t st) {
-    if (l == (int)levels.size() - 1) return cgnr<T>(l, C<T>(rhs), C<T>(x), ncol, st);
-    std::vector<double> tol(ncol, prm.inter_tol);
-    int it = 0;
-    int e = fgcr<T>(l, C<T>(rhs), C<T>(x), ncol, tol.data(), prm.inter_maxit, prm.inter_restart, &it, st);
+    int it = 0, e;
+    if (l == (int)levels.size() - 1) {
+        if (prm.coarsest_solver == DWF_COARSEST_CGNR) return cgnr<T>(l, C<T>(rhs), C<T>(x), ncol, st);
+        e = gcr_plain<T>(l, C<T>(rhs), C<T>(x), ncol, prm.coarsest_tol, prm.coarsest_maxit, prm.coarsest_restart,
+                         &it, st);
+    } else {
+        std::vector<double> tol(ncol, prm.inter_tol);
+        e = fgcr<T>(l, C<T>(rhs), C<T>(x), ncol, tol.data(), prm.inter_maxit, prm.inter_restart, &it, st);
+    }
     cnt_.level_iters[l - 1] += it;
     cnt_.level_calls[l - 1] += 1;
     return e < 0 ? e : DWF_OK;
@@ -552,6 +649,7 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
         levels.push_back(c);
     }
     HIPCHK(hipStreamSynchronize(st));
+    if (int e = deflation_setup(st)) return e;
     return DWF_OK;
 }
 

@@ -1,6 +1,8 @@
 // Host-side multigrid hierarchy and Krylov drivers (internal).
 #pragma once
 
+#include <rocblas/rocblas.h>
+
 #include <map>
 #include <tuple>
 #include <vector>
@@ -114,6 +116,24 @@ private:
     template <class F> int run_graph(const GraphKey& key, hipStream_t st, F&& enqueue);
     void clear_graphs();
 
+public:
+    // coarsest-level deflation (lowest eigenpairs of A^dag A on the coarsest level)
+    int deflation_setup(hipStream_t st);
+    int def_nev_ = 0;
+    int eig_iters_ = 0;
+    double eig_worst_ = 0.0;
+    std::vector<double> def_lam_host_;
+
+private:
+    int deflate_guess(int l, const cpx<double>* z, cpx<double>* x, int ncol, hipStream_t st);
+    void destroy_blas();
+    rocblas_handle blas_ = nullptr;
+    cpx<double>* def_V_ = nullptr;
+    double* def_lam_ = nullptr;
+    cpx<double>* def_C_ = nullptr;
+    double* def_ref_ = nullptr;   // |A^dag b|^2 per column, the CGNR reference
+    int def_ref_cols_ = 0;
+
     void* dalloc(size_t bytes);
     int ensure_work(int ncol, hipStream_t st);
     int ensure_scalars(int maxc);
@@ -138,6 +158,8 @@ private:
     template <typename T> int cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st);
     template <typename T> int fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* rel_tol,
                                    int maxit, int restart, int* iters_out, hipStream_t st);
+    template <typename T> int gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol, int maxit,
+                                        int restart, int* iters_out, hipStream_t st);
     int null_vectors(int l, const cpx<double>* start, cpx<double>* v, hipStream_t st);
 };
 

@@ -35,6 +35,7 @@ MAX_LEVELS = 3
 
 MG_OP_DW, MG_OP_DW_DAG, MG_OP_PV, MG_OP_PV_DAG, MG_OP_A = 0, 1, 2, 3, 4
 MG_OP_WILSON, MG_OP_WILSON_DAG, MG_OP_RESTRICT, MG_OP_PROLONG, MG_OP_KCYCLE = 5, 6, 7, 8, 9
+COARSEST_CGNR, COARSEST_GCR = 0, 1
 
 
 class DwfError(RuntimeError):
@@ -75,6 +76,7 @@ def lib() -> ctypes.CDLL:
                                      ctypes.POINTER(i), d, ctypes.POINTER(CStats), vp]
         L.mg_update_links.argtypes = [vp, vp, vp]
         L.mg_level_info.argtypes = [vp, i] + [ctypes.POINTER(i)] * 5
+        L.mg_deflation_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(d), vp]
         L.mg_destroy.argtypes = [vp]
         L.dwf_release_scratch.argtypes = []
         L.dwf_strerror.argtypes = [i]
@@ -82,7 +84,7 @@ def lib() -> ctypes.CDLL:
         for name in ("dwf_apply", "dwf_pv_apply", "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
                      "dwf_pack", "dwf_unpack", "dwf_force", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
                      "mg_time_op", "dwf_norm2", "mg_update_links", "mg_solve_batch",
-                     "mg_level_info", "mg_destroy", "dwf_release_scratch"):
+                     "mg_level_info", "mg_deflation_info", "mg_destroy", "dwf_release_scratch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -123,6 +125,12 @@ class CParams(ctypes.Structure):
         ("inner_tol", ctypes.c_double),
         ("max_iters", ctypes.c_int),
         ("max_outer", ctypes.c_int),
+        ("coarsest_nev", ctypes.c_int),
+        ("eig_degree", ctypes.c_int),
+        ("eig_maxit", ctypes.c_int),
+        ("eig_tol", ctypes.c_double),
+        ("coarsest_solver", ctypes.c_int),
+        ("coarsest_restart", ctypes.c_int),
     ]
 
 
@@ -161,6 +169,12 @@ class MGParams:
     inner_tol: float = 0.0
     max_iters: int = 10000
     max_outer: int = 20
+    coarsest_nev: int = 0          # coarsest-level deflation (0: off, as in Table kcycle)
+    eig_degree: int = 0            # Chebyshev degree of the Lanczos acceleration (0: automatic)
+    eig_maxit: int = 40            # thick-restart cycles
+    eig_tol: float = 1e-3
+    coarsest_solver: int = COARSEST_CGNR   # CGNR on A^dag A (Table 2), or COARSEST_GCR: GCR on A
+    coarsest_restart: int = 16
 
     @property
     def nlevels(self) -> int:
@@ -178,7 +192,8 @@ class MGParams:
             c.vec_prec[l] = self.vec_prec[l]
         for name in ("fine_prec", "m_setup", "setup_iters", "setup_tol", "outer_restart", "smooth_iters",
                      "inter_maxit", "inter_tol", "inter_restart", "coarsest_maxit", "coarsest_tol", "inner_tol",
-                     "max_iters", "max_outer"):
+                     "max_iters", "max_outer", "coarsest_nev", "eig_degree", "eig_maxit", "eig_tol",
+                     "coarsest_solver", "coarsest_restart"):
             setattr(c, name, getattr(self, name))
         return c
 
@@ -422,6 +437,17 @@ class MG:
         _check(lib().mg_level_info(self._h, level, *[ctypes.byref(v) for v in vals]), "mg_level_info")
         Lx, Ly, Ls, n, nvec = (v.value for v in vals)
         return dict(Lx=Lx, Ly=Ly, Ls=Ls, n=n, nvec=nvec)
+
+    def deflation_info(self):
+        """Coarsest-level deflation space: dict(nev, iters, worst_residual, lambdas) with
+        the Ritz values of hat-A^dag hat-A in ascending order (empty when deflation is off)."""
+        nev, iters, worst = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().mg_deflation_info(self._h, ctypes.byref(nev), ctypes.byref(iters), ctypes.byref(worst), None),
+               "mg_deflation_info")
+        lam = (ctypes.c_double * max(nev.value, 1))()
+        _check(lib().mg_deflation_info(self._h, None, None, None, ctypes.cast(lam, ctypes.c_void_p)),
+               "mg_deflation_info")
+        return dict(nev=nev.value, iters=iters.value, worst_residual=worst.value, lambdas=list(lam)[:nev.value])
 
     def level_op(self, level: int, op: int, inp: torch.Tensor, ncol: int, mass: float = 0.0, out_shape=None,
                  stream=None) -> torch.Tensor:

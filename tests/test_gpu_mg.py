@@ -284,17 +284,19 @@ def test_solve_batched_rhs_three_level():
     assert res <= 1e-10
 
 
-def test_graph_replays_match_eager_launches(monkeypatch):
-    """The coarsest CGNR chunks and the smoother run as captured HIP graphs;
-    several replays (with other eager work and synchronisations in between)
-    give bit-identical solutions to a context that launches eagerly."""
+@pytest.mark.parametrize("coarsest", ["cgnr", "gcr"])
+def test_graph_replays_match_eager_launches(monkeypatch, coarsest):
+    """The coarsest CGNR chunks (or GCR cycles) and the smoother run as captured
+    HIP graphs; several replays (with other eager work and synchronisations in
+    between) give bit-identical solutions to a context that launches eagerly."""
     L, Ls, m, M5 = 32, 8, 0.02, -1.0
     g = inputs.metropolis_u1(L, L, 6.0, 60, 901)
     b = T(inputs.gaussian_field((2, Ls, L, L, 2), 902))
     starts = [T(inputs.gaussian_field((8, L, L, 2), 903)), T(inputs.gaussian_field((12, 8, 8, 16), 904))]
     params = dwfmg.MGParams(nvec=[8, 12], block=[(4, 4), (2, 2)], Ls_coarse=[4, 4],
                             link_prec=[dwfmg.P_BF16, dwfmg.P_F64], vec_prec=[dwfmg.P_F32, dwfmg.P_F64],
-                            fine_prec=dwfmg.P_F32)
+                            fine_prec=dwfmg.P_F32,
+                            coarsest_solver=dwfmg.COARSEST_GCR if coarsest == "gcr" else dwfmg.COARSEST_CGNR)
     monkeypatch.setenv("DWF_NO_GRAPHS", "1")
     eager = dwfmg.MG(T(g.U), Ls, m, M5, params, starts)
     monkeypatch.delenv("DWF_NO_GRAPHS")
