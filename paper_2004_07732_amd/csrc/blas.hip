@@ -145,6 +145,24 @@ __global__ void __launch_bounds__(kBlock) k_fin_store(RedWork rw, int nq, int nb
     if (threadIdx.x < nq) out[(size_t)col * stride + threadIdx.x] = tot[threadIdx.x];
 }
 
+// the same sums with one block per (quantity, column): for many quantities
+__global__ void __launch_bounds__(kBlock) k_fin_store_q(RedWork rw, int nb, double* out, size_t stride) {
+    __shared__ double sh[kWaves];
+    const int q = blockIdx.x, col = blockIdx.y;
+    const double* part = rw.partial + (size_t)col * rw.max_q * rw.nblk + (size_t)q * rw.nblk;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) t += sh[w];
+        out[(size_t)col * stride + q] = t;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_fin_cg_init(RedWork rw, int nb, CgScal* s, double tol2) {
     SHARED_RED;
     const int col = blockIdx.x;
@@ -491,7 +509,7 @@ hipError_t gcr_multidot(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w,
     if (j > 16) return hipErrorInvalidValue;
     dim3 grid = red_grid(n, ncol, rw);
     hipLaunchKernelGGL(k_gcr_multidot<T>, grid, dim3(kBlock), 0, st, W, wstride, j, w, n, g, rw);
-    hipLaunchKernelGGL(k_fin_store, dim3(ncol), dim3(kBlock), 0, st, rw, 2 * j, (int)grid.x,
+    hipLaunchKernelGGL(k_fin_store_q, dim3(2 * j, ncol), dim3(kBlock), 0, st, rw, (int)grid.x,
                        g.D + (size_t)j * g.kmax * 2, (size_t)g.kmax * g.kmax * 2);
     return hipGetLastError();
 }

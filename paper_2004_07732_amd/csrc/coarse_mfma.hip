@@ -20,15 +20,23 @@
 // Work split: one wavefront per (coarse site, 16-row tile).  A wave loads all
 // of its link fragments up front (every link element is read exactly once per
 // apply, with all loads in flight together) and keeps them in registers while
-// it walks the column tiles.  The five neighbour vectors of a column tile are
-// staged once per site in LDS, already split, and read back as 16-byte
-// fragments.
+// it walks the column tiles (8 columns, or 4 when there are at most 4).  The
+// five neighbour vectors of a column tile are staged once per site in LDS,
+// already split, and read back as 16-byte fragments; the staging loads are
+// branch-free (dead columns read a valid address and are zeroed) so that the
+// compiler keeps them all in flight.
 //
-// Links layout for this kernel: per site, row-major [i][d*n + k] complex
-// 16-bit pairs (re low, im high).  The site-local terms (the M5 + 1 shift and
+// Links layout for this kernel: in fragment order, so that every load of a
+// wave reads 1 KB contiguous: [site][row tile m][inner step ks][lane][4] with
+// lane = q + 16 kg holding row 16 m + q, inner entries j = 16 ks + 4 kg + e of
+// the row [d*n + k] (d: hop, k: column of that hop's block), each a complex
+// 16-bit pair (re low, im high).  The site-local terms (the M5 + 1 shift and
 // the fifth-dimension hops through hatP_pm with the -m corners, eq. coarsenDW)
 // and sigma_3 for the adjoint (hat-D_W^dagger = sigma_3 hat-D_W sigma_3) are
 // applied in the epilogue.
+#include <algorithm>
+#include <cstdlib>
+
 #include "kernels.hpp"
 
 namespace dwf {
@@ -84,7 +92,7 @@ __device__ __forceinline__ u32x4 make_b(u32x4 u, bool imag_col) {
 
 }  // namespace
 
-template <bool F16, typename T, int N, bool DAG>
+template <bool F16, typename T, int N, bool DAG, int TW>
 __global__ void __launch_bounds__(256)
 coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                    const int* __restrict__ skip, int sks, int Lx, int Ly, int Ls, int nsites, int ncol,
@@ -94,9 +102,8 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
     constexpr int SPB = (MT >= 4) ? 1 : 4 / MT;   // sites per block
     constexpr int KS = 5 * N / 16;                // inner steps of 16 complex entries
     constexpr int H = N / 2;                      // chirality boundary (sigma_3)
-    constexpr int ROW = 5 * N / 4;                // 16-byte link chunks per row
-    constexpr int SLAB = 5 * 8 * N;               // staged entries per site and part (d, c8, k)
-    constexpr int PER = SLAB / (MT * 64);         // staged entries per thread (= 10)
+    constexpr int SLAB = 5 * 8 * N;               // LDS entries per site and part (d, c8, k)
+    constexpr int PER = 5 * TW * N / (MT * 64);   // staged entries per thread (TW columns per tile)
     __shared__ __attribute__((aligned(16))) uint32_t sB[SPB][2][SLAB];   // [site][hi/lo][(d*8 + c8)*N + k]
     __shared__ float smax[SPB][MT];
 
@@ -119,37 +126,42 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
     // all link fragments of this wave's 16 rows, loaded once
     u32x4 a[KS];
     if (valid_site) {
-        const u32x4* lrow = links + ((size_t)site * N + 16 * m + q) * ROW + kg;
+        const u32x4* lf = links + ((size_t)site * MT + m) * KS * 64 + lane;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) a[ks] = lrow[ks * 4];
+        for (int ks = 0; ks < KS; ++ks) a[ks] = lf[ks * 64];
     }
 
-    auto col_ok = [&](int c) { return c < C && !(skip && skip[(size_t)(c / Ls) * sks]); };
-
-    const int ntile = (C + 7) / 8;
+    const int ntile = (C + TW - 1) / TW;
     const int tid_in_site = threadIdx.x - sl * MT * 64;
     for (int t = 0; t < ntile; ++t) {
-        const int cbase = 8 * t;
-        // stage the five neighbour vectors of columns cbase..cbase+7
+        const int cbase = TW * t;
+        // live columns of the tile as a bit mask, read once (no dependent loads in the staging loop)
+        unsigned live = 0;
+#pragma unroll
+        for (int c8 = 0; c8 < TW; ++c8) {
+            const int c = cbase + c8;
+            if (c < C && !(skip && skip[(size_t)(c / Ls) * sks])) live |= 1u << c8;
+        }
+        auto col_ok = [&](int c) { return ((live >> (c - cbase)) & 1u) != 0; };
+        // stage the five neighbour vectors of columns cbase..cbase+TW-1, entries
+        // e = (d * TW + c8) * N + k; branch-free loads (dead columns read column 0
+        // and are zeroed), so that all of them are in flight together
         float vr[PER], vi[PER];
         float mx = 0.f;
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
-            vr[p] = 0.f;
-            vi[p] = 0.f;
             const int e = tid_in_site + p * MT * 64;
             const int k = e % N;
             const int dc = e / N;
-            const int c8 = dc & 7, d = dc >> 3;
-            const int c = cbase + c8;
-            if (valid_site && col_ok(c)) {
-                const cpx<T> v = in[((size_t)c * nsites + nb[d]) * N + k];
-                float re = (float)v.re, im = (float)v.im;
-                if (DAG && k >= H) { re = -re; im = -im; }
-                vr[p] = re;
-                vi[p] = im;
-                if (F16) mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
-            }
+            const int c8 = dc % TW, d = dc / TW;
+            const bool use = valid_site && col_ok(cbase + c8);
+            const int c = use ? cbase + c8 : 0;
+            const cpx<T> v = in[((size_t)c * nsites + nb[d]) * N + k];
+            float re = use ? (float)v.re : 0.f, im = use ? (float)v.im : 0.f;
+            if (DAG && k >= H) { re = -re; im = -im; }
+            vr[p] = re;
+            vi[p] = im;
+            if (F16) mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
         float scale = 1.f, unscale = 1.f;
         if (F16) {
@@ -170,14 +182,17 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
                 const int e = tid_in_site + p * MT * 64;
+                const int k = e % N, dc = e / N;
+                const int o = ((dc / TW) * 8 + dc % TW) * N + k;   // LDS slot (d * 8 + c8) * N + k
                 const float re = vr[p] * scale, im = vi[p] * scale;
                 const uint32_t hre = HF::bits(re), him = HF::bits(im);
                 const uint32_t lre = HF::bits(re - HF::value(hre)), lim = HF::bits(im - HF::value(him));
-                sB[sl][0][e] = hre | (him << 16);
-                sB[sl][1][e] = lre | (lim << 16);
+                sB[sl][0][o] = hre | (him << 16);
+                sB[sl][1][o] = lre | (lim << 16);
             }
         }
         __syncthreads();
+        // (with TW = 4 the LDS columns 4..7 hold stale values that feed only unused outputs)
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         if (valid_site) {
 #pragma unroll
@@ -195,19 +210,21 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         f32x4 p;
 #pragma unroll
         for (int e = 0; e < 4; ++e) p[e] = __shfl_xor(acc[e], 8, 64);
-        const int c = cbase + (q & 7);
-        if (valid_site && !imag_col && col_ok(c)) {
-            const int rhs = c / Ls, s = c - rhs * Ls;
-            const int i0 = 16 * m + 4 * kg;
-            const bool minus = (i0 >= H);
-            const bool from_up = DAG ? !minus : minus;
-            int so;
-            float f = 1.f;
-            if (from_up) { so = s + 1; if (so == Ls) { so = 0; f = mwrap; } }
-            else         { so = s - 1; if (so < 0) { so = Ls - 1; f = mwrap; } }
-            float cr[4], ci[4], hr[4], hi[4];
-            load4<T>(in + ((size_t)c * nsites + site) * N + i0, cr, ci);
-            load4<T>(in + ((size_t)(rhs * Ls + so) * nsites + site) * N + i0, hr, hi);
+        const bool wr = valid_site && !imag_col && col_ok(cbase + (q & 7));
+        const int c = wr ? cbase + (q & 7) : 0;
+        const int rhs = c / Ls, s = c - rhs * Ls;
+        const int i0 = 16 * m + 4 * kg;
+        const bool minus = (i0 >= H);
+        const bool from_up = DAG ? !minus : minus;
+        int so;
+        float f = 1.f;
+        if (from_up) { so = s + 1; if (so == Ls) { so = 0; f = mwrap; } }
+        else         { so = s - 1; if (so < 0) { so = Ls - 1; f = mwrap; } }
+        float cr[4], ci[4], hr[4], hi[4];
+        const int sv = valid_site ? site : 0;
+        load4<T>(in + ((size_t)c * nsites + sv) * N + i0, cr, ci);
+        load4<T>(in + ((size_t)(rhs * Ls + so) * nsites + sv) * N + i0, hr, hi);
+        if (wr) {
             cpx<T>* dst = out + ((size_t)c * nsites + site) * N + i0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -233,8 +250,13 @@ hipError_t launch_n(const void* links, const cpx<T>* in, cpx<T>* out, const Coar
     dim3 grid((nsites + SPB - 1) / SPB), block(64 * MT * SPB);
     const u32x4* lk = reinterpret_cast<const u32x4*>(links);
     const float cd = (float)(M5 + 1.0), mw = (float)(-m);
-    if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
-    else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, false>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
+    if (g.Ls * ncol <= 4) {   // one tile of 4 columns (one right-hand side on 4 coarse slices)
+        if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true, 4>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
+        else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, false, 4>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
+    } else {
+        if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true, 8>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
+        else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, false, 8>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
+    }
     return hipGetLastError();
 }
 
@@ -263,16 +285,23 @@ hipError_t coarse_apply_mfma(const void* links, int link_prec, const cpx<T>* in,
     return launch_p<false, T>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
 }
 
-// FP64 column layout blk[k][i] -> row-major [i][d*n + k] complex 16-bit pairs (round to nearest even)
-__global__ void k_links_rowmajor16(const cpx<double>* in, uint32_t* out, int nsites, int n, int f16) {
+// FP64 column layout blk[k][i] -> fragment order [site][m][ks][lane][e] complex 16-bit pairs
+// (round to nearest even); see the layout note at the top of this file
+__global__ void k_links_fragment16(const cpx<double>* in, uint32_t* out, int nsites, int n, int f16) {
     const long long total = (long long)nsites * 5 * n * n;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    // output index t = ((site*n + i)*5 + d)*n + k
-    const int k = (int)(t % n);
-    const int d = (int)((t / n) % 5);
-    const int i = (int)((t / (5LL * n)) % n);
-    const int site = (int)(t / (5LL * n * n));
+    const int ks_n = 5 * n / 16;
+    const int e = (int)(t & 3);
+    const int lane = (int)((t >> 2) & 63);
+    const long long frag = t >> 8;                     // (site * (n/16) + m) * ks_n + ks
+    const int ks = (int)(frag % ks_n);
+    const long long sm = frag / ks_n;
+    const int m = (int)(sm % (n / 16));
+    const int site = (int)(sm / (n / 16));
+    const int i = 16 * m + (lane & 15);
+    const int j = 16 * ks + 4 * (lane >> 4) + e;
+    const int d = j / n, k = j - d * n;
     const cpx<double> v = in[(((size_t)site * 5 + d) * n + k) * n + i];
     uint32_t re, im;
     if (f16) {
@@ -285,9 +314,10 @@ __global__ void k_links_rowmajor16(const cpx<double>* in, uint32_t* out, int nsi
     out[t] = re | (im << 16);
 }
 
-hipError_t convert_links_rowmajor16(const cpx<double>* in, void* out, int link_prec, int nsites, int n, hipStream_t st) {
+hipError_t convert_links_fragment16(const cpx<double>* in, void* out, int link_prec, int nsites, int n, hipStream_t st) {
+    if (n % 16) return hipErrorInvalidValue;
     const long long total = (long long)nsites * 5 * n * n;
-    hipLaunchKernelGGL(k_links_rowmajor16, dim3(grid_for(total)), dim3(kBlock), 0, st, in, (uint32_t*)out, nsites, n,
+    hipLaunchKernelGGL(k_links_fragment16, dim3(grid_for(total)), dim3(kBlock), 0, st, in, (uint32_t*)out, nsites, n,
                        link_prec == P_F16 ? 1 : 0);
     return hipGetLastError();
 }

@@ -45,13 +45,13 @@ hipError_t coarse_apply(const void* links, int link_prec, const cpx<T>* in, cpx<
                         bool wilson_mode, double wilson_mass, const int* skip, int skip_stride,
                         hipStream_t st);
 
-// Matrix-core path (BF16 or FP16 links stored row-major per site, n a
-// multiple of 16); coarse_apply dispatches to it by itself for such levels.
+// Matrix-core path (BF16 or FP16 links stored in MFMA fragment order per
+// site, n a multiple of 16); coarse_apply dispatches to it by itself for such levels.
 bool coarse_mfma_supported(int n, int link_prec);
 template <typename T>
 hipError_t coarse_apply_mfma(const void* links, int link_prec, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g,
                              int ncol, double m, double M5, bool dagger, const int* skip, int sks, hipStream_t st);
-hipError_t convert_links_rowmajor16(const cpx<double>* in, void* out, int link_prec, int nsites, int n,
+hipError_t convert_links_fragment16(const cpx<double>* in, void* out, int link_prec, int nsites, int n,
                                     hipStream_t st);
 
 // ------------------------------------------------------------ BLAS-1 (T = float/double)

@@ -642,7 +642,7 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
             c.links = dalloc(cplx_bytes(c.link_prec) * nl);
             if (!c.links) return DWF_EHIP;
             if (coarse_mfma_supported(c.n, c.link_prec))
-                HIPCHK(convert_links_rowmajor16(c.links64, c.links, c.link_prec, c.nsites, c.n, st));
+                HIPCHK(convert_links_fragment16(c.links64, c.links, c.link_prec, c.nsites, c.n, st));
             else
                 HIPCHK(convert_links(c.links64, c.links, c.link_prec, nl, st));
         }
