@@ -3,14 +3,18 @@
 
 Metric: MG-preconditioned domain-wall solves per second to a true FP64
 relative residual of 1e-10 on a 256^2 x Ls 16 lattice (beta 6, m_f 0.01,
-M5 = -1), mixed precision (FP32 fine level, BF16 coarse links, FP64 outer
-defect correction and FP64 coarse Krylov vectors), next to the plain FP64
-solve and the fine-stencil HBM bandwidth.
+M5 = -1) with the 2-level hierarchy (4x4 aggregates, 16 null vectors, coarse
+Ls 4), mixed precision (FP32 fine level, BF16 coarse links on the matrix
+cores, FP64 outer defect correction and FP64 coarse Krylov vectors).  The
+coarsest level runs restarted GCR(8) on hat-A to 0.25 by default; the row
+`paper_coarsest_cgnr` runs the paper's CGNR to 0.05 on the same hierarchy.
 
 A step is one full solve (K-cycle preconditioned flexible GCR inside the FP64
 defect correction) of one right-hand side already resident in HBM.  The
-hierarchy setup is done once before timing and reported separately.  Prints
-one JSON line.
+hierarchy setup is done once before timing and reported separately.  Beside
+the headline: 16 right-hand sides in one solve, the three-level hierarchy,
+the plain FP64 solve of the same algorithm, the fine-stencil bandwidth rows
+and the oracle on the host.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -25,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+METRIC = "DWF solves/s to 1e-10 at 256\u00b2\u00d7Ls16, mixed vs FP64; D_dw stencil HBM GB/s"
 
 WORKLOADS = {
     # metric workload: 256^2 x 16, 2-level 4x4 aggregates with 16 null vectors
@@ -84,7 +89,7 @@ def stored_traffic(kernel_src):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, stats, U_np):
+def cpu_baseline(wl, stats, U_np, coarsest):
     """The oracle, untuned, on the host: unit costs of its operator applications
     on the same lattice and hierarchy shape, combined with the operation counts
     of one GPU solve (a lower bound on the oracle's solve time: the Krylov
@@ -113,10 +118,14 @@ def cpu_baseline(wl, stats, U_np):
         O.stencil_dwf(S, O.stencil_dwf(S, ec, m, M5), 1.0, M5, dagger=True)
         tAc = time.perf_counter() - t0
     fine_A = stats.fine_applies / 2.0
-    # one CGNR iteration applies A and A^dagger; each call adds one A^dagger
-    coarse_A = 2.0 * stats.level_iters[0] + stats.level_calls[0] if len(wl["nvec"]) == 1 else None
-    if coarse_A is None:
+    if len(wl["nvec"]) != 1:
         return None
+    if coarsest["coarsest_solver"] == 0:
+        # one CGNR iteration applies A and A^dagger; each call adds one A^dagger
+        coarse_A = 2.0 * stats.level_iters[0] + stats.level_calls[0]
+    else:
+        # one GCR iteration applies A; each restart cycle adds one for the true residual
+        coarse_A = stats.level_iters[0] * (1.0 + 1.0 / coarsest["coarsest_restart"]) + stats.level_calls[0]
     t_solve = fine_A * tA + coarse_A * tAc
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": (f"oracle unit costs on the host: D_PV^dag D_DW at {L}^2 x {Ls} = {tA:.3f} s, "
@@ -125,26 +134,95 @@ def cpu_baseline(wl, stats, U_np):
                        f"Krylov vector algebra not counted")}
 
 
+def timed(mg, b, steps, warmup, tol=1e-10):
+    """Mean seconds of `steps` solves after `warmup` untimed ones (the solve is
+    synchronous: it returns after the true residual is known)."""
+    import torch
+    st = None
+    for _ in range(warmup):
+        _, st = mg.solve(b, tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = mg.solve(b, tol)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / max(steps, 1), st
+
+
+def stats_dict(st):
+    return {"residual": st.true_rel_residual, "outer_steps": st.outer_steps, "fine_iters": st.fine_iters,
+            "fine_applies": st.fine_applies, "coarse_iters": st.level_iters, "coarse_calls": st.level_calls}
+
+
+def stencil_rows(dwfmg, inputs, torch, m, M5):
+    """Fine D_DW bandwidth: (ii) 512^2 x 32 x 4 rhs FP32 (about 1.08 GB per apply,
+    far above the 256 MB last-level cache) is the HBM figure; (i) 256^2 x 16
+    one rhs FP32 / FP64 and (iii) 256^2 x 16 x 16 rhs FP32 beside it; and the
+    bandwidth of a plain 2 GiB device copy as the measured peak."""
+    def one(L, Ls, nr, dtype, seed):
+        U = torch.from_numpy(inputs.links_from_theta(inputs.random_theta(L, L, seed))).cuda().to(dtype)
+        psi = torch.randn((nr, Ls, L, L, 2), dtype=dtype, device="cuda")
+        out = torch.empty_like(psi)
+        for _ in range(3):
+            dwfmg.dwf_apply(U, psi, m, M5, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 50
+        e0.record()
+        for _ in range(reps):
+            dwfmg.dwf_apply(U, psi, m, M5, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        t_ms = e0.elapsed_time(e1) / reps
+        esz = psi.element_size()
+        sbytes = 2 * psi.numel() * esz + U.numel() * esz
+        return {"shape": f"{L}^2 x {Ls} x {nr} rhs", "dtype": str(dtype).replace("torch.", ""), "us": t_ms * 1e3,
+                "bytes": sbytes, "GB_s": sbytes / (t_ms * 1e-3) / 1e9}
+    rows = {"ii_hbm": one(512, 32, 4, torch.complex64, 8_000_000),
+            "i_fp32": one(256, 16, 1, torch.complex64, 8_000_001),
+            "i_fp64": one(256, 16, 1, torch.complex128, 8_000_002),
+            "iii_fp32_16rhs": one(256, 16, 16, torch.complex64, 8_000_003)}
+    # measured peak: device-to-device copy of 2 GiB (read 2 GiB + write 2 GiB)
+    a = torch.ones(2 ** 31 // 4, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 2 ** 31 / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    del a, c
+    for r in rows.values():
+        r["frac_nominal"] = r["GB_s"] / PEAK_HBM_GBS
+        r["frac_measured_copy"] = r["GB_s"] / copy_gbs
+    rows["copy_2GiB_GB_s"] = copy_gbs
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dwf256_ls16_mg2", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 solve")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-stencil", action="store_true", help="skip the fine-stencil bandwidth run")
+    ap.add_argument("--coarsest", choices=["cgnr", "gcr"], default="gcr",
+                    help="coarsest-level solver: restarted GCR on A (default) or CGNR on A^dag A as in the paper")
+    ap.add_argument("--coarsest-restart", type=int, default=8)
+    ap.add_argument("--coarsest-tol", type=float, default=None,
+                    help="coarsest relative tolerance (default 0.25 with GCR, 0.05 with CGNR)")
     ap.add_argument("--nev", type=int, default=0,
-                    help="deflate the coarsest solve with this many eigenvectors of its normal operator")
-    ap.add_argument("--eig-degree", type=int, default=None, help="Chebyshev filter degree of the eigensolver")
+                    help="deflate the coarsest CGNR with this many eigenvectors of its normal operator")
+    ap.add_argument("--eig-degree", type=int, default=None, help="Chebyshev degree of the Lanczos acceleration")
     ap.add_argument("--eig-maxit", type=int, default=None)
     ap.add_argument("--eig-tol", type=float, default=None)
-    ap.add_argument("--coarsest", choices=["cgnr", "gcr"], default="cgnr",
-                    help="coarsest-level solver: CGNR on A^dag A (as in the paper) or restarted GCR on A")
-    ap.add_argument("--coarsest-restart", type=int, default=16)
-    ap.add_argument("--coarsest-tol", type=float, default=None, help="coarsest relative tolerance (default 0.05)")
+    ap.add_argument("--quick", action="store_true", help="only the headline solve and its roofline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 solve")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stencil", action="store_true", help="skip the fine-stencil bandwidth rows")
     ap.add_argument("--counters", action="store_true",
-                    help="only run the dominant kernel (20 launches) next to a plain 256 MiB copy, for "
+                    help="only run the dominant kernel (21 launches) next to a plain 256 MiB copy, for "
                          "rocprofv3 --pmc runs; prints no benchmark line")
     args = ap.parse_args()
 
@@ -167,8 +245,19 @@ def main():
     b = torch.from_numpy(inputs.gaussian_field((1, Ls, L, L, 2), inputs.rhs_seed(wl["cfg"], L, 0))).cuda()
     starts = null_starts(inputs, wl, torch)
 
+    def coarsest(kind, tol=None):
+        d = {"coarsest_solver": dwfmg.COARSEST_GCR if kind == "gcr" else dwfmg.COARSEST_CGNR,
+             "coarsest_restart": args.coarsest_restart}
+        d["coarsest_tol"] = tol if tol is not None else (0.25 if kind == "gcr" else 0.05)
+        return d
+
+    head = coarsest(args.coarsest, args.coarsest_tol)
+    for k, v in (("eig_degree", args.eig_degree), ("eig_maxit", args.eig_maxit), ("eig_tol", args.eig_tol)):
+        if v is not None:
+            head[k] = v
+
     if args.counters:
-        mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True), starts)
+        mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True, **head), starts)
         c = mg.info(1)
         xin = torch.from_numpy(inputs.gaussian_field((1, c["Ls"], c["Ly"], c["Lx"], c["n"]), 5)).cuda()
         mg.time_op(1, dwfmg.MG_OP_DW, xin, 1, iters=20)
@@ -180,36 +269,21 @@ def main():
         log("[bench] counters run done: 21 coarse launches, 5 copies of 256 MiB")
         return
 
-    # ---------------------------------------------------------------- mixed-precision solve
+    # ---------------------------------------------------------------- headline: mixed precision, 1 rhs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    eig = {k: v for k, v in (("eig_degree", args.eig_degree), ("eig_maxit", args.eig_maxit),
-                             ("eig_tol", args.eig_tol)) if v is not None}
-    eig["coarsest_solver"] = dwfmg.COARSEST_GCR if args.coarsest == "gcr" else dwfmg.COARSEST_CGNR
-    eig["coarsest_restart"] = args.coarsest_restart
-    if args.coarsest_tol is not None:
-        eig["coarsest_tol"] = args.coarsest_tol
-    mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True, args.nev, **eig), starts)
+    mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True, args.nev, **head), starts)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"[bench] setup {setup_s:.2f} s")
     if args.nev:
         di = mg.deflation_info()
-        log(f"[bench] deflation: nev {di['nev']}, {di['iters']} filtered iterations, worst residual "
+        log(f"[bench] deflation: nev {di['nev']}, {di['iters']} Lanczos steps, worst residual "
             f"{di['worst_residual']:.1e}, lambda {di['lambdas'][0]:.3e} .. {di['lambdas'][-1]:.3e}")
-    for i in range(args.warmup):
-        x, st = mg.solve(b, 1e-10)
-        log(f"[bench] warmup {i}: {st.solve_ms:.1f} ms, residual {st.true_rel_residual:.2e}, "
-            f"fine iters {st.fine_iters}, coarse iters {st.level_iters}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        x, st = mg.solve(b, 1e-10)
-        log(f"[bench] step {i}: {st.solve_ms:.1f} ms, residual {st.true_rel_residual:.2e}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    mixed_sps = args.steps / elapsed
-    stats = st
+    t_step, stats = timed(mg, b, args.steps, args.warmup)
+    mixed_sps = 1.0 / t_step
+    log(f"[bench] headline: {t_step * 1e3:.1f} ms/solve, residual {stats.true_rel_residual:.2e}, "
+        f"fine iters {stats.fine_iters}, coarse iters {stats.level_iters} calls {stats.level_calls}")
 
     # ---------------------------------------------------------------- dominant kernel: coarse stencil
     c = mg.info(1)
@@ -222,53 +296,57 @@ def main():
     achieved = coarse_bytes / (t_coarse_ms * 1e-3) / 1e9
     traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse_mfma.hip"))
     log(f"[bench] coarse stencil {t_coarse_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
+
+    rows = {}
+    if not args.quick:
+        # 16 right-hand sides in one solve on the same hierarchy
+        b16 = torch.from_numpy(np.stack([inputs.gaussian_field((Ls, L, L, 2), inputs.rhs_seed(wl["cfg"], L, j))
+                                         for j in range(16)])).cuda()
+        t16, st16 = timed(mg, b16, 1, 1)
+        rows["batched_16rhs"] = {"solves_per_s": 16.0 / t16, "ms_per_batch": t16 * 1e3, **stats_dict(st16)}
+        log(f"[bench] 16 rhs: {t16 * 1e3:.1f} ms per batch, {16.0 / t16:.3f} solves/s, "
+            f"residual {st16.true_rel_residual:.2e}")
+        del b16
     mg.close()
 
-    # ---------------------------------------------------------------- plain FP64 solve
+    if not args.quick:
+        # the paper's coarsest solver (CGNR on the normal equations to 0.05)
+        mgp = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True, **coarsest("cgnr")), starts)
+        tp, stp = timed(mgp, b, 1, 1)
+        rows["paper_coarsest_cgnr"] = {"solves_per_s": 1.0 / tp, **stats_dict(stp)}
+        log(f"[bench] coarsest CGNR (tol 0.05): {tp * 1e3:.1f} ms/solve")
+        mgp.close()
+        # three-level hierarchy of the paper's parameter table, same coarsest settings as the headline
+        wl3 = WORKLOADS["dwf256_ls16_mg3"]
+        mg3 = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl3, True, **head),
+                       null_starts(inputs, wl3, torch))
+        t3, st3 = timed(mg3, b, 1, 1)
+        rows["three_level"] = {"solves_per_s": 1.0 / t3, "mg": {"nvec": wl3["nvec"], "block": wl3["block"],
+                                                              "Ls_coarse": wl3["Ls_coarse"]}, **stats_dict(st3)}
+        log(f"[bench] three-level: {t3 * 1e3:.1f} ms/solve")
+        mg3.close()
+
+    # ---------------------------------------------------------------- plain FP64 solve (same algorithm)
     fp64 = None
-    if not args.no_fp64:
-        mg64 = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, False), starts)
-        x64, st64 = mg64.solve(b, 1e-10)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x64, st64 = mg64.solve(b, 1e-10)
-        torch.cuda.synchronize()
-        fp64 = {"solves_per_s": 1.0 / (time.perf_counter() - t0), "residual": st64.true_rel_residual,
-                "fine_iters": st64.fine_iters, "coarse_iters": st64.level_iters[0]}
-        log(f"[bench] fp64 solve {1e3 / fp64['solves_per_s']:.1f} ms")
+    if not args.no_fp64 and not args.quick:
+        mg64 = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, False, **head), starts)
+        t64, st64 = timed(mg64, b, 1, 1)
+        fp64 = {"solves_per_s": 1.0 / t64, **stats_dict(st64)}
+        log(f"[bench] fp64 solve {t64 * 1e3:.1f} ms")
         mg64.close()
 
-    # ---------------------------------------------------------------- fine stencil bandwidth
     stencil = None
-    if not args.no_stencil:
-        Ls2, L2, nr = 32, 512, 4
-        U2 = torch.from_numpy(inputs.links_from_theta(inputs.random_theta(L2, L2, 8_000_000))).cuda().to(torch.complex64)
-        psi = (torch.randn((nr, Ls2, L2, L2, 2), dtype=torch.complex64, device="cuda"))
-        out = torch.empty_like(psi)
-        for _ in range(3):
-            dwfmg.dwf_apply(U2, psi, m, M5, out=out)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 50
-        e0.record()
-        for _ in range(reps):
-            dwfmg.dwf_apply(U2, psi, m, M5, out=out)
-        e1.record()
-        torch.cuda.synchronize()
-        t_ms = e0.elapsed_time(e1) / reps
-        sbytes = 2 * psi.numel() * 8 + U2.numel() * 8
-        stencil = {"workload": f"{L2}^2 x {Ls2} x {nr} rhs FP32", "us": t_ms * 1e3,
-                   "GB_s": sbytes / (t_ms * 1e-3) / 1e9, "frac_of_peak": sbytes / (t_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
-        log(f"[bench] fine stencil {stencil}")
-        del psi, out
+    if not args.no_stencil and not args.quick:
+        stencil = stencil_rows(dwfmg, inputs, torch, m, M5)
+        log(f"[bench] fine stencil {json.dumps(stencil)}")
 
-    # ---------------------------------------------------------------- CPU baseline (oracle)
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.quick:
         log("[bench] timing the oracle on the host")
-        cpu = cpu_baseline(wl, stats, g.U)
+        cpu = cpu_baseline(wl, stats, g.U, head)
 
     res = {
-        "metric": "DWF solves/s to 1e-10 at 256^2xLs16, mixed vs FP64; D_dw stencil HBM GB/s",
+        "metric": METRIC,
         "value": mixed_sps,
         "unit": "solves/s",
         "n_gpus": 1,
@@ -283,20 +361,21 @@ def main():
         "config": {"workload": args.workload, "lattice": f"{L}x{L}", "Ls": Ls, "nrhs": 1, "beta": wl["beta"],
                    "m_f": m, "M5": M5, "tol": 1e-10,
                    "mg": {"nvec": wl["nvec"], "block": wl["block"], "Ls_coarse": wl["Ls_coarse"],
-                          "coarsest_nev": args.nev, "coarsest_solver": args.coarsest},
+                          "coarsest_solver": args.coarsest, "coarsest_tol": head["coarsest_tol"],
+                          "coarsest_restart": args.coarsest_restart if args.coarsest == "gcr" else None,
+                          "coarsest_nev": args.nev},
                    "precision": "fine FP32, coarse links BF16 (FP32 arithmetic), coarse vectors FP64, "
                                 "outer defect correction FP64"},
-        "roofline": {"bound": "hbm", "kernel": "coarse_kernel (coarse D_DW apply, level 1)",
+        "roofline": {"bound": "hbm", "kernel": "coarse_mfma_kernel (coarse D_DW apply, level 1)",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic, "algorithmic_bytes": coarse_bytes, "us_per_launch": t_coarse_ms * 1e3},
         "cpu_baseline": cpu,
         "fp64": fp64,
         "mixed_vs_fp64": (mixed_sps / fp64["solves_per_s"]) if fp64 else None,
+        "rows": rows,
         "fine_stencil": stencil,
         "setup_s": setup_s,
-        "solve": {"residual": stats.true_rel_residual, "outer_steps": stats.outer_steps,
-                  "fine_iters": stats.fine_iters, "fine_applies": stats.fine_applies,
-                  "coarse_iters": stats.level_iters, "coarse_calls": stats.level_calls},
+        "solve": stats_dict(stats),
     }
     print(json.dumps(res), flush=True)
 
