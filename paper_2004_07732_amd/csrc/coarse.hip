@@ -30,7 +30,7 @@ coarse_kernel(const L* __restrict__ links, const cpx<T>* __restrict__ in, cpx<T>
     extern __shared__ unsigned char smem_raw[];
     const int wpb = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int site = blockIdx.x * wpb + wave;
+    const int site = (int)xcd_block(blockIdx.x, gridDim.x) * wpb + wave;
     const int col = blockIdx.y;
     const int per_wave = ((5 * N > 64) ? 5 * N : 64) * Ls;
     cpx<A>* my = reinterpret_cast<cpx<A>*>(smem_raw) + (size_t)wave * per_wave;

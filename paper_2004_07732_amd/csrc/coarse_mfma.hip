@@ -109,7 +109,7 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int sl = wave / MT, m = wave - sl * MT;
-    const int site = blockIdx.x * SPB + sl;
+    const int site = (int)xcd_block(blockIdx.x, gridDim.x) * SPB + sl;
     const bool valid_site = site < nsites;
     const int C = Ls * ncol;
     const int q = lane & 15, kg = lane >> 4;

@@ -90,6 +90,17 @@ template <> struct acc_of<cpx<double>> { using type = double; };
 // ---------------------------------------------------------------- launch helpers
 constexpr int kBlock = 256;
 
+// Workgroups are dealt round-robin to the 8 XCDs (workgroup b runs on XCD
+// b % 8), each with its own L2.  Stencil kernels renumber their workgroups so
+// that every XCD owns one contiguous range of logical workgroups: lattice
+// neighbours (the next row, the next site) are then fetched into the same L2
+// instead of into three different ones.  Bijective for any grid size.
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+    const unsigned x = b % kXcds, k = b / kXcds, q = nb / kXcds, r = nb % kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
 inline unsigned grid_for(long long n, int block = kBlock) {
     long long g = (n + block - 1) / block;
     return (unsigned)(g < 1 ? 1 : g);

@@ -58,7 +58,7 @@ fine_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in,
             spinor<R>* __restrict__ out, const spinor<R>* __restrict__ b,
             const int* __restrict__ skip, int skip_stride, int Lx, int Ly, int Ls, int nchunk, int cs,
             long long total, R diag, R mwrap) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long g = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (g >= total) return;
     const int V = Lx * Ly;
     const int site = (int)(g % V);
