@@ -57,14 +57,18 @@ __global__ void __launch_bounds__(kBlock)
 fine_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in,
             spinor<R>* __restrict__ out, const spinor<R>* __restrict__ b,
             const int* __restrict__ skip, int skip_stride, int Lx, int Ly, int Ls, int nchunk, int cs,
-            long long total, R diag, R mwrap) {
-    const long long g = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (g >= total) return;
+            int nsb, R diag, R mwrap) {
+    // logical workgroup -> (column, block of 2-d sites, slice chunk), chunk fastest: the chunks of
+    // one block of sites share their boundary slices, and on one XCD (xcd_block) they run side by
+    // side, so those slices come from L2 rather than being fetched again
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int chunk = (int)(lb % (unsigned)nchunk);
+    const unsigned t = lb / (unsigned)nchunk;
+    const int sb = (int)(t % (unsigned)nsb);
+    const int col = (int)(t / (unsigned)nsb);
     const int V = Lx * Ly;
-    const int site = (int)(g % V);
-    const long long t = g / V;
-    const int chunk = (int)(t % nchunk);
-    const int col = (int)(t / nchunk);
+    const int site = sb * (int)blockDim.x + (int)threadIdx.x;
+    if (site >= V) return;
     if (skip && skip[(size_t)col * skip_stride]) return;
     const int x = site % Lx, y = site / Lx;
     const int xp = (x + 1 == Lx) ? 0 : x + 1, xm = (x == 0) ? Lx - 1 : x - 1;
@@ -213,18 +217,20 @@ static hipError_t launch_fine(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, co
                               int Ls, int ncol, double m, double M5, bool dagger, const int* skip, int skip_stride,
                               int cs, hipStream_t st) {
     const int nchunk = (Ls + cs - 1) / cs;
-    const long long total = (long long)Lx * Ly * nchunk * ncol;
+    const int nsb = (Lx * Ly + kBlock - 1) / kBlock;
+    const long long nblocks = (long long)nsb * nchunk * ncol;
     const R diag = R(2.0 + M5 + 1.0), mwrap = R(-m);
     auto* si = reinterpret_cast<const spinor<R>*>(in);
     auto* so = reinterpret_cast<spinor<R>*>(out);
     auto* sb = reinterpret_cast<const spinor<R>*>(b);
-    dim3 grid(grid_for(total)), block(kBlock);
+    if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nblocks), block(kBlock);
     if (b) {
-        if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, true, true>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
-        else        hipLaunchKernelGGL((fine_kernel<R, false, true, true>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
+        if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, true, true>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
+        else        hipLaunchKernelGGL((fine_kernel<R, false, true, true>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
     } else {
-        if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, true, false>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
-        else        hipLaunchKernelGGL((fine_kernel<R, false, true, false>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
+        if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, true, false>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
+        else        hipLaunchKernelGGL((fine_kernel<R, false, true, false>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
     }
     return hipGetLastError();
 }
@@ -235,13 +241,15 @@ hipError_t wilson2d(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int 
     // each column is an independent 2-d field: treat columns as slices of one
     // column with no fifth-dimension coupling
     const int Ls = ncol, cs = 1, nchunk = ncol;
-    const long long total = (long long)Lx * Ly * nchunk;
+    const int nsb = (Lx * Ly + kBlock - 1) / kBlock;
+    const long long nblocks = (long long)nsb * nchunk;
     const R diag = R(2.0 + M), mwrap = R(0);
     auto* si = reinterpret_cast<const spinor<R>*>(in);
     auto* so = reinterpret_cast<spinor<R>*>(out);
-    dim3 grid(grid_for(total)), block(kBlock);
-    if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, false, false>), grid, block, 0, st, U, si, so, nullptr, nullptr, 1, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
-    else        hipLaunchKernelGGL((fine_kernel<R, false, false, false>), grid, block, 0, st, U, si, so, nullptr, nullptr, 1, Lx, Ly, Ls, nchunk, cs, total, diag, mwrap);
+    if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nblocks), block(kBlock);
+    if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, false, false>), grid, block, 0, st, U, si, so, nullptr, nullptr, 1, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
+    else        hipLaunchKernelGGL((fine_kernel<R, false, false, false>), grid, block, 0, st, U, si, so, nullptr, nullptr, 1, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
     return hipGetLastError();
 }
 
