@@ -529,6 +529,100 @@ def cgnr(apply_A, apply_Adag, b, tol, maxit, x0=None):
     return x, it
 
 
+def cgnr_true(apply_A, apply_Adag, b, tol, maxit):
+    """CG on the normal equations A^dagger A x = A^dagger b without multigrid (Sec. 3,
+    Fig. iterationscompare: "CGNR on D_DW^dagger D_DW"), keeping the residual
+    r = b - A x of the original system.  READING: the figure's tolerance 1e-10 is
+    on |b - A x| / |b|, the stopping rule of the multigrid solve it is compared
+    with.  Returns (x, iterations, applications of A or A^dagger)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    bb = vdot(b, b).real
+    z = apply_Adag(r)
+    p = z.copy()
+    zz = vdot(z, z).real
+    it, applies = 0, 1
+    while it < maxit and vdot(r, r).real > tol * tol * bb:
+        w = apply_A(p)
+        alpha = zz / vdot(w, w).real
+        x = x + alpha * p
+        r = r - alpha * w
+        z = apply_Adag(r)
+        zz_new = vdot(z, z).real
+        p = z + (zz_new / zz) * p
+        zz = zz_new
+        it += 1
+        applies += 2
+    return x, it, applies
+
+
+def bicgstab_l(apply_A, b, ell, tol, maxit, x0=None):
+    """BiCGStab(ell) (Sleijpen & Fokkema, ETNA 1, 1993) on A x = b, as the paper
+    applies it to A = D_PV^dagger D_DW (Sec. 3, Fig. iterationscompare, ell = 6;
+    valid because that operator has its spectrum in the right half-plane,
+    appendix).  Each cycle runs ell BiCG steps, which build the Krylov
+    directions u_0..u_ell and residuals r_0..r_ell, then one minimal-residual
+    step that minimises |r_0 - sum_j gamma_j r_j| over gamma_1..gamma_ell by
+    modified Gram-Schmidt on r_1..r_ell.  Complex inner products are
+    (a, b) = a^H b; the shadow residual is the initial residual.  Stops when the
+    recursively updated |r| <= tol |b| (checked after every cycle) or after
+    maxit cycles.  Returns (x, cycles, applications of A)."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r0 = b - apply_A(x) if x0 is not None else b.copy()
+    applies = 1 if x0 is not None else 0
+    rt = r0.copy()                       # shadow residual
+    u = [np.zeros_like(b) for _ in range(ell + 1)]
+    r = [np.zeros_like(b) for _ in range(ell + 1)]
+    r[0] = r0
+    rho0, alpha, omega = 1.0 + 0j, 0.0 + 0j, 1.0 + 0j
+    bb = vdot(b, b).real
+    cycles = 0
+    while cycles < maxit and vdot(r[0], r[0]).real > tol * tol * bb:
+        rho0 = -omega * rho0
+        # BiCG part
+        for j in range(ell):
+            rho1 = vdot(rt, r[j])
+            beta = alpha * rho1 / rho0
+            rho0 = rho1
+            for i in range(j + 1):
+                u[i] = r[i] - beta * u[i]
+            u[j + 1] = apply_A(u[j])
+            gamma = vdot(rt, u[j + 1])
+            alpha = rho0 / gamma
+            for i in range(j + 1):
+                r[i] = r[i] - alpha * u[i + 1]
+            r[j + 1] = apply_A(r[j])
+            x = x + alpha * u[0]
+            applies += 2
+        # MR part: modified Gram-Schmidt on r_1..r_ell
+        tau = np.zeros((ell + 1, ell + 1), dtype=np.complex128)
+        sigma = np.zeros(ell + 1)
+        gp = np.zeros(ell + 1, dtype=np.complex128)      # gamma'
+        for j in range(1, ell + 1):
+            for i in range(1, j):
+                tau[i, j] = vdot(r[i], r[j]) / sigma[i]
+                r[j] = r[j] - tau[i, j] * r[i]
+            sigma[j] = vdot(r[j], r[j]).real
+            gp[j] = vdot(r[j], r[0]) / sigma[j]
+        g = np.zeros(ell + 1, dtype=np.complex128)       # gamma
+        g[ell] = gp[ell]
+        omega = g[ell]
+        for j in range(ell - 1, 0, -1):
+            g[j] = gp[j] - sum(tau[j, i] * g[i] for i in range(j + 1, ell + 1))
+        gpp = np.zeros(ell + 1, dtype=np.complex128)     # gamma''
+        for j in range(1, ell):
+            gpp[j] = g[j + 1] + sum(tau[j, i] * g[i + 1] for i in range(j + 1, ell))
+        x = x + g[1] * r[0]
+        r[0] = r[0] - gp[ell] * r[ell]
+        u[0] = u[0] - g[ell] * u[ell]
+        for j in range(1, ell):
+            u[0] = u[0] - g[j] * u[j]
+            x = x + gpp[j] * r[j]
+            r[0] = r[0] - gp[j] * r[j]
+        cycles += 1
+    return x, cycles, applies
+
+
 def gcr(apply_A, b, tol, maxit, restart, precond=None, x0=None):
     """Flexible GCR with restarts (Table kcycle): directions p_j = M(r_j),
     q_j = A p_j orthonormalised against the previous q's by modified

@@ -272,6 +272,125 @@ def test_dense_lu_vs_cgnr():
     assert np.linalg.norm(x_cg - x_lu) / np.linalg.norm(x_lu) < 1e-10
 
 
+def _textbook_bicgstab(A, b, iters):
+    """van der Vorst's BiCGStab (1992) written out independently, for the ell = 1 pin."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    rt = r.copy()
+    rho = alpha = omega = 1.0 + 0j
+    v = np.zeros_like(b)
+    p = np.zeros_like(b)
+    for _ in range(iters):
+        rho_new = np.vdot(rt, r)
+        beta = (rho_new / rho) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        v = A @ p
+        alpha = rho_new / np.vdot(rt, v)
+        s_ = r - alpha * v
+        t = A @ s_
+        omega = np.vdot(t, s_) / np.vdot(t, t)
+        x = x + alpha * p + omega * s_
+        r = s_ - omega * t
+        rho = rho_new
+    return x
+
+
+def _random_nonnormal(n, seed):
+    rng = np.random.default_rng(seed)
+    A = 3.0 * np.eye(n) + (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    return A, b
+
+
+@pytest.mark.parametrize("ell", [1, 2, 4, 6])
+def test_bicgstab_l_solves_and_keeps_its_residual(ell):
+    """BiCGStab(ell) solves a non-normal complex system (LAPACK solution), and its
+    recursively updated residual is the true residual b - A x (a wrong update of
+    x, r or u breaks the identity)."""
+    A, b = _random_nonnormal(80, 3)
+    x, cyc, ap = O.bicgstab_l(lambda v: A @ v, b, ell, 1e-12, 400)
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-10
+    assert ap == 2 * ell * cyc
+    # stop exactly when the true residual crosses the tolerance (within rounding)
+    res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert res <= 1.5e-12
+
+
+def test_bicgstab_1_is_textbook_bicgstab():
+    """ell = 1 is van der Vorst's BiCGStab: the iterates agree step by step."""
+    A, b = _random_nonnormal(50, 4)
+    for k in (1, 3, 6):
+        x1, _, _ = O.bicgstab_l(lambda v: A @ v, b, 1, 0.0, k)
+        xt = _textbook_bicgstab(A, b, k)
+        assert np.linalg.norm(x1 - xt) / np.linalg.norm(xt) < 1e-12
+
+
+def _bicgstab_l_lstsq(A, b, ell, cycles):
+    """BiCGStab(ell) with the minimal-residual step done as a dense least-squares
+    problem: gamma = argmin |r_0 - sum_j gamma_j r_j| over the BiCG residuals
+    r_j = A r_(j-1), then x += sum gamma_j r_(j-1), r_0 -= sum gamma_j r_j,
+    u_0 -= sum gamma_j u_j.  Independent of the recurrences the oracle uses."""
+    x = np.zeros_like(b)
+    rt = b.copy()
+    u = [np.zeros_like(b) for _ in range(ell + 1)]
+    r = [np.zeros_like(b) for _ in range(ell + 1)]
+    r[0] = b.copy()
+    rho0 = alpha = omega = 1.0 + 0j
+    for _ in range(cycles):
+        rho0 = -omega * rho0
+        for j in range(ell):
+            rho1 = np.vdot(rt, r[j])
+            beta = alpha * rho1 / rho0
+            rho0 = rho1
+            for i in range(j + 1):
+                u[i] = r[i] - beta * u[i]
+            u[j + 1] = A @ u[j]
+            alpha = rho0 / np.vdot(rt, u[j + 1])
+            for i in range(j + 1):
+                r[i] = r[i] - alpha * u[i + 1]
+            r[j + 1] = A @ r[j]
+            x = x + alpha * u[0]
+        R = np.stack(r[1:], axis=1)
+        gam = np.linalg.lstsq(R, r[0], rcond=None)[0]
+        omega = gam[-1]
+        x = x + sum(gam[j - 1] * r[j - 1] for j in range(1, ell + 1))
+        r[0] = r[0] - R @ gam
+        u[0] = u[0] - sum(gam[j - 1] * u[j] for j in range(1, ell + 1))
+    return x
+
+
+@pytest.mark.parametrize("ell", [2, 4])
+def test_bicgstab_l_minimal_residual_step(ell):
+    """The Gram-Schmidt recurrences of the minimal-residual step give the same
+    iterates as solving that least-squares problem directly."""
+    A, b = _random_nonnormal(50, 6)
+    for k in (1, 2, 3):
+        x1, _, _ = O.bicgstab_l(lambda v: A @ v, b, ell, 0.0, k)
+        x2 = _bicgstab_l_lstsq(A, b, ell, k)
+        assert np.linalg.norm(x1 - x2) / np.linalg.norm(x2) < 1e-10
+
+
+def test_fig1_baselines_solve_the_domain_wall_system():
+    """The two baselines of the paper's comparison reach the true residual of
+    D_DW x = b: CGNR on D_DW, and BiCGStab(6) on D_PV^dag D_DW x = D_PV^dag b
+    (same x, since D_PV is invertible); both against dense LU."""
+    L, Ls, m, M5 = 4, 4, 0.05, -1.0
+    U = metropolis_links(L, 3.0, 20, 8)
+    shape = (Ls, L, L, 2)
+    D = O.assemble(lambda v: O.dwf(U, v, m, M5), shape)
+    b = cgauss(shape, 45)
+    x_lu = np.linalg.solve(D, b.reshape(-1)).reshape(shape)
+    x1, it, ap = O.cgnr_true(lambda v: O.dwf(U, v, m, M5), lambda v: O.dwf(U, v, m, M5, dagger=True), b,
+                             1e-12, 5000)
+    assert ap == 2 * it + 1
+    assert np.linalg.norm(b - O.dwf(U, x1, m, M5)) / np.linalg.norm(b) <= 1e-12
+    assert np.linalg.norm(x1 - x_lu) / np.linalg.norm(x_lu) < 1e-8
+    bp = O.pv(U, b, M5, dagger=True)
+    x2, cyc, ap2 = O.bicgstab_l(lambda v: O.pv_dag_dw(U, v, m, M5), bp, 6, 1e-12, 500)
+    assert np.linalg.norm(x2 - x_lu) / np.linalg.norm(x_lu) < 1e-8
+
+
 # ----------------------------------------------------------------------------- coarse level
 def make_prolongator(L, block, nvec, nc, seed):
     """Orthonormalised random prolongator on an L x L lattice."""
