@@ -4,10 +4,11 @@
 Metric: MG-preconditioned domain-wall solves per second to a true FP64
 relative residual of 1e-10 on a 256^2 x Ls 16 lattice (beta 6, m_f 0.01,
 M5 = -1) with the 2-level hierarchy (4x4 aggregates, 16 null vectors, coarse
-Ls 4), mixed precision (FP32 fine level, BF16 coarse links on the matrix
+Ls 2), mixed precision (FP32 fine level, BF16 coarse links on the matrix
 cores, FP64 outer defect correction and FP64 coarse Krylov vectors).  The
-coarsest level runs restarted GCR(8) on hat-A to 0.25 by default; the row
-`paper_coarsest_cgnr` runs the paper's CGNR to 0.05 on the same hierarchy.
+coarsest level runs restarted GCR(8) on hat-A to 0.25 by default.  Rows beside
+the headline: the paper's parameter table throughout (coarse Ls 4, coarsest
+CGNR to 0.05), coarse Ls 4 with GCR, three levels, 8 null vectors.
 
 A step is one full solve (K-cycle preconditioned flexible GCR inside the FP64
 defect correction) of one right-hand side already resident in HBM.  The
@@ -32,12 +33,12 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "DWF solves/s to 1e-10 at 256\u00b2\u00d7Ls16, mixed vs FP64; D_dw stencil HBM GB/s"
 
 WORKLOADS = {
-    # metric workload: 256^2 x 16, 2-level 4x4 aggregates with 16 null vectors
+    # metric workload: 256^2 x 16, 2-level 4x4 aggregates with 16 null vectors, coarse Ls 2
     "dwf256_ls16_mg2": dict(L=256, Ls=16, beta=6.0, sweeps=200, m=0.01, M5=-1.0, cfg=6, gauge_cfg=4,
-                            nvec=[16], block=[(4, 4)], Ls_coarse=[4]),
-    # same lattice, the paper's three-level parameter table
+                            nvec=[16], block=[(4, 4)], Ls_coarse=[2]),
+    # same lattice, the three-level aggregation of the paper's parameter table, coarse Ls 2
     "dwf256_ls16_mg3": dict(L=256, Ls=16, beta=6.0, sweeps=200, m=0.01, M5=-1.0, cfg=6, gauge_cfg=4,
-                            nvec=[8, 12], block=[(4, 4), (2, 2)], Ls_coarse=[4, 4]),
+                            nvec=[8, 12], block=[(4, 4), (2, 2)], Ls_coarse=[2, 2]),
     # 128^2 x 16 precision form
     "dwf128_ls16_mg2": dict(L=128, Ls=16, beta=6.0, sweeps=200, m=0.01, M5=-1.0, cfg=2, gauge_cfg=2,
                             nvec=[16], block=[(4, 4)], Ls_coarse=[4]),
@@ -77,14 +78,15 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic(kernel_src):
+def stored_traffic(kernel_src, algorithmic_bytes):
     """HBM traffic of the dominant kernel from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+    summary, or None when the kernel source or the launch shape changed since
+    it was taken."""
     p = os.path.join(ROOT, "profiles", "coarse_stencil_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("source_sha256_16") != source_hash(kernel_src):
+    if d.get("source_sha256_16") != source_hash(kernel_src) or d.get("algorithmic_bytes") != algorithmic_bytes:
         return None
     return d.get("bytes_per_launch")
 
@@ -217,6 +219,8 @@ def main():
     ap.add_argument("--eig-degree", type=int, default=None, help="Chebyshev degree of the Lanczos acceleration")
     ap.add_argument("--eig-maxit", type=int, default=None)
     ap.add_argument("--eig-tol", type=float, default=None)
+    ap.add_argument("--nvec", type=int, nargs="+", default=None, help="override the workload's null vectors per level")
+    ap.add_argument("--ls-coarse", type=int, nargs="+", default=None, help="override the coarse Ls per level")
     ap.add_argument("--quick", action="store_true", help="only the headline solve and its roofline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -237,7 +241,11 @@ def main():
     from paper_2004_07732_amd import dwfmg, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    if args.nvec:
+        wl["nvec"] = list(args.nvec)
+    if args.ls_coarse:
+        wl["Ls_coarse"] = list(args.ls_coarse)
     L, Ls, m, M5 = wl["L"], wl["Ls"], wl["m"], wl["M5"]
     log(f"[bench] workload {args.workload}: generating gauge field {L}^2 beta {wl['beta']}")
     g = inputs.metropolis_u1(L, L, wl["beta"], wl["sweeps"], inputs.gauge_seed(wl["gauge_cfg"], L))
@@ -294,7 +302,7 @@ def main():
     vec_bytes = 16 if make_params(dwfmg, wl, True).vec_prec[0] == dwfmg.P_F64 else 8
     coarse_bytes = nsites * (5 * n * n * link_bytes + 2 * Lsc * n * vec_bytes)
     achieved = coarse_bytes / (t_coarse_ms * 1e-3) / 1e9
-    traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse_mfma.hip"))
+    traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse_mfma.hip"), coarse_bytes)
     log(f"[bench] coarse stencil {t_coarse_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
 
     rows = {}
@@ -310,21 +318,37 @@ def main():
     mg.close()
 
     if not args.quick:
-        # the paper's coarsest solver (CGNR on the normal equations to 0.05)
-        mgp = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True, **coarsest("cgnr")), starts)
-        tp, stp = timed(mgp, b, 1, 1)
-        rows["paper_coarsest_cgnr"] = {"solves_per_s": 1.0 / tp, **stats_dict(stp)}
-        log(f"[bench] coarsest CGNR (tol 0.05): {tp * 1e3:.1f} ms/solve")
-        mgp.close()
-        # three-level hierarchy of the paper's parameter table, same coarsest settings as the headline
-        wl3 = WORKLOADS["dwf256_ls16_mg3"]
-        mg3 = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl3, True, **head),
-                       null_starts(inputs, wl3, torch))
-        t3, st3 = timed(mg3, b, 1, 1)
-        rows["three_level"] = {"solves_per_s": 1.0 / t3, "mg": {"nvec": wl3["nvec"], "block": wl3["block"],
-                                                              "Ls_coarse": wl3["Ls_coarse"]}, **stats_dict(st3)}
-        log(f"[bench] three-level: {t3 * 1e3:.1f} ms/solve")
-        mg3.close()
+        def variant(name, wlv, **kw):
+            mgv = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wlv, True, **kw), null_starts(inputs, wlv, torch))
+            tv, stv = timed(mgv, b, 1, 1)
+            rows[name] = {"solves_per_s": 1.0 / tv, "mg": {"nvec": wlv["nvec"], "block": wlv["block"],
+                                                          "Ls_coarse": wlv["Ls_coarse"]},
+                          "coarsest": {k: v for k, v in kw.items() if k.startswith("coarsest")}, **stats_dict(stv)}
+            log(f"[bench] {name}: {tv * 1e3:.1f} ms/solve, fine applies {stv.fine_applies}")
+            mgv.close()
+        wl4 = dict(wl, Ls_coarse=[4] * len(wl["nvec"]))
+        # the paper's parameter table throughout: coarse Ls 4 and coarsest CGNR to 0.05
+        variant("paper_table_cgnr_Ls4", wl4, **coarsest("cgnr"))
+        # coarse Ls 4 with the headline's coarsest GCR
+        variant("gcr_Ls4", wl4, **head)
+        # three-level hierarchy (4x4 / 8 vectors, then 2x2 / 12 vectors), headline coarsest settings
+        variant("three_level", dict(WORKLOADS["dwf256_ls16_mg3"]), **head)
+        # the fastest shape measured: 8 null vectors, coarse Ls 2
+        variant("nvec8_Ls2", dict(wl, nvec=[8], Ls_coarse=[2]), **head)
+
+    if not args.quick:
+        # the paper's solver comparison: Krylov solves of the same system without multigrid (FP64)
+        bf = b[0].contiguous()
+        for name, meth, ell in (("krylov_cgnr", dwfmg.KRYLOV_CGNR, 0), ("krylov_bicgstab6", dwfmg.KRYLOV_BICGSTAB, 6)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, sk = dwfmg.dwf_krylov_solve(U, bf, m, M5, method=meth, ell=max(ell, 1), tol=1e-10, maxit=200000,
+                                           check=False)
+            tk = time.perf_counter() - t0
+            rows[name] = {"solves_per_s": 1.0 / tk, "iterations": sk.fine_iters, "fine_applies": sk.fine_applies,
+                          "residual": sk.true_rel_residual, "status": sk.status}
+            log(f"[bench] {name}: {tk * 1e3:.1f} ms, {sk.fine_iters} iterations, {sk.fine_applies} applications, "
+                f"residual {sk.true_rel_residual:.2e}")
 
     # ---------------------------------------------------------------- plain FP64 solve (same algorithm)
     fp64 = None

@@ -208,6 +208,30 @@ int mg_solve(dwf_mg* mg, const void* b, void* x, int nrhs, double tol, dwf_solve
 int mg_solve_batch(int nctx, dwf_mg* const* ctx, const void* const* b, void* const* x, const int* nrhs,
                    double tol, dwf_solve_stats* stats, void* stream);
 
+/* ---------------------------------------------------------------- Krylov baselines */
+#define DWF_KRYLOV_CGNR     0
+#define DWF_KRYLOV_BICGSTAB 1
+
+/* Solve D_DW(m_f) x = b without multigrid, by one of the two methods the paper
+ * compares its multigrid solver with (Sec. 3, Fig. iterationscompare):
+ *   DWF_KRYLOV_CGNR      CG on D_DW^dagger D_DW x = D_DW^dagger b, stopping on
+ *                        |b - D_DW x| <= tol |b| (residual kept by recursion);
+ *   DWF_KRYLOV_BICGSTAB  BiCGStab(ell) (ell = 1..16; the paper uses 6) on
+ *                        D_PV^dagger D_DW x = D_PV^dagger b, stopping on the
+ *                        residual of that system; if |b - D_DW x| is then
+ *                        above tol |b| it restarts from x with a tighter
+ *                        tolerance.
+ * FP64, one right-hand side: U [2][Ly][Lx], b and x [Ls][Ly][Lx][2]
+ * complex128 device arrays (x overwritten; it starts from zero).  maxit caps
+ * CG iterations or BiCGStab cycles.  stats (host, may be NULL): fine_iters =
+ * iterations or cycles, fine_applies = applications of D_DW, D_DW^dagger and
+ * D_PV^dagger (the paper's count), true_rel_residual, solve_ms.  Allocates its
+ * work vectors (about 2 ell + 5 fields) for the duration of the call and
+ * synchronises the stream.  DWF_NOT_CONVERGED (x = last iterate) when maxit
+ * is reached; DWF_EBREAKDOWN on a vanishing inner product. */
+int dwf_krylov_solve(const void* U, const void* b, void* x, int Lx, int Ly, int Ls, double m_f, double M5,
+                     int method, int ell, double tol, int maxit, dwf_solve_stats* stats, void* stream);
+
 /* Replace the fine-level gauge field of a built hierarchy (complex128
  * [2][Ly][Lx], copied).  The coarse levels are kept: they remain a valid
  * preconditioner for a nearby field (a molecular-dynamics step, a finite

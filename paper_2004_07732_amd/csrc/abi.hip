@@ -141,6 +141,16 @@ int dwf_force(const void* U, const void* X, const void* Y, double* F, int Lx, in
                             S(stream)));
 }
 
+int dwf_krylov_solve(const void* U, const void* b, void* x, int Lx, int Ly, int Ls, double m_f, double M5,
+                     int method, int ell, double tol, int maxit, dwf_solve_stats* stats, void* stream) {
+    if (!U || !b || !x || !dims_ok(Lx, Ly, Ls, 1) || Ls < 2) return DWF_EINVAL;
+    if (!std::isfinite(m_f) || !std::isfinite(M5) || !(tol > 0.0) || maxit < 1) return DWF_EINVAL;
+    if (method != DWF_KRYLOV_CGNR && method != DWF_KRYLOV_BICGSTAB) return DWF_EINVAL;
+    if (method == DWF_KRYLOV_BICGSTAB && (ell < 1 || ell > 16)) return DWF_EINVAL;
+    return krylov_solve((const cpx<double>*)U, (const cpx<double>*)b, (cpx<double>*)x, Lx, Ly, Ls, m_f, M5, method,
+                        ell, tol, maxit, stats, S(stream));
+}
+
 void dwf_mg_default_params(dwf_mg_params* p, int nlevels) {
     if (!p) return;
     std::memset(p, 0, sizeof(*p));

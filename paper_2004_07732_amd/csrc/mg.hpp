@@ -163,4 +163,8 @@ private:
     int null_vectors(int l, const cpx<double>* start, cpx<double>* v, hipStream_t st);
 };
 
+// ------------------------------------------------------------ Krylov baselines (krylov.hip)
+int krylov_solve(const cpx<double>* U, const cpx<double>* b, cpx<double>* x, int Lx, int Ly, int Ls, double m,
+                 double M5, int method, int ell, double tol, int maxit, dwf_solve_stats* stats, hipStream_t st);
+
 }  // namespace dwf

@@ -36,6 +36,7 @@ MAX_LEVELS = 3
 MG_OP_DW, MG_OP_DW_DAG, MG_OP_PV, MG_OP_PV_DAG, MG_OP_A = 0, 1, 2, 3, 4
 MG_OP_WILSON, MG_OP_WILSON_DAG, MG_OP_RESTRICT, MG_OP_PROLONG, MG_OP_KCYCLE = 5, 6, 7, 8, 9
 COARSEST_CGNR, COARSEST_GCR = 0, 1
+KRYLOV_CGNR, KRYLOV_BICGSTAB = 0, 1
 
 
 class DwfError(RuntimeError):
@@ -77,6 +78,7 @@ def lib() -> ctypes.CDLL:
         L.mg_update_links.argtypes = [vp, vp, vp]
         L.mg_level_info.argtypes = [vp, i] + [ctypes.POINTER(i)] * 5
         L.mg_deflation_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(d), vp]
+        L.dwf_krylov_solve.argtypes = [vp, vp, vp, i, i, i, d, d, i, i, d, i, ctypes.POINTER(CStats), vp]
         L.mg_destroy.argtypes = [vp]
         L.dwf_release_scratch.argtypes = []
         L.dwf_strerror.argtypes = [i]
@@ -84,7 +86,8 @@ def lib() -> ctypes.CDLL:
         for name in ("dwf_apply", "dwf_pv_apply", "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
                      "dwf_pack", "dwf_unpack", "dwf_force", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
                      "mg_time_op", "dwf_norm2", "mg_update_links", "mg_solve_batch",
-                     "mg_level_info", "mg_deflation_info", "mg_destroy", "dwf_release_scratch"):
+                     "mg_level_info", "mg_deflation_info", "mg_destroy", "dwf_release_scratch",
+                     "dwf_krylov_solve"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -364,6 +367,27 @@ def release_scratch():
 def _stats(st: "CStats") -> "SolveStats":
     return SolveStats(st.status, st.outer_steps, st.fine_iters, st.fine_applies, list(st.level_iters),
                       list(st.level_calls), st.true_rel_residual, st.solve_ms)
+
+
+def dwf_krylov_solve(U, b, m_f, M5, method=KRYLOV_BICGSTAB, ell=6, tol=1e-10, maxit=1_000_000, x=None,
+                     stream=None, check=True):
+    """Solve D_DW x = b without multigrid (CGNR on D_DW, or BiCGStab(ell) on
+    D_PV^dagger D_DW); U [2, Ly, Lx] and b [Ls, Ly, Lx, 2] complex128.
+    Returns (x, SolveStats) with fine_iters = iterations / cycles and
+    fine_applies = applications of D_DW, D_DW^dagger, D_PV^dagger."""
+    _need(U, "U", torch.complex128)
+    _need(b, "b", torch.complex128)
+    if b.dim() != 4 or b.shape[-1] != 2 or tuple(U.shape) != (2, b.shape[1], b.shape[2]):
+        raise ValueError("b must be [Ls, Ly, Lx, 2] matching U [2, Ly, Lx]")
+    x = torch.empty_like(b) if x is None else x
+    _need(x, "x", torch.complex128, b.shape)
+    st = CStats()
+    Ls, Ly, Lx = b.shape[0], b.shape[1], b.shape[2]
+    code = lib().dwf_krylov_solve(_ptr(U), _ptr(b), _ptr(x), Lx, Ly, Ls, float(m_f), float(M5), int(method), int(ell),
+                                  float(tol), int(maxit), ctypes.byref(st), _stream(stream))
+    if check:
+        _check(code, "dwf_krylov_solve", soft_ok=False)
+    return x, _stats(st)
 
 
 def solve_batch(mgs: Sequence["MG"], bs: Sequence[torch.Tensor], tol: float = 1e-10, stream=None,
