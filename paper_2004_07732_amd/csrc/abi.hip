@@ -33,6 +33,7 @@ size_t g_scratch_bytes = 0;
 
 void* scratch(size_t bytes) {
     if (bytes <= g_scratch_bytes) return g_scratch;
+    std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
     if (g_scratch) { hipDeviceSynchronize(); hipFree(g_scratch); }
     g_scratch = nullptr;
     g_scratch_bytes = 0;
@@ -299,6 +300,7 @@ int dwf_norm2(const void* x, size_t n, int ncol, double* out, void* stream) {
     rw.max_q = 1;
     rw.max_cols = ncol;
     if (ncol > cap_cols) {
+        std::lock_guard<std::recursive_mutex> rlk(runtime_mutex());
         if (partial) { hipDeviceSynchronize(); hipFree(partial); partial = nullptr; cap_cols = 0; }
         if (hipMalloc(&partial, sizeof(double) * (size_t)rw.nblk * ncol) != hipSuccess) return DWF_EHIP;
         cap_cols = ncol;
@@ -345,6 +347,7 @@ int mg_destroy(dwf_mg* mg) {
 
 int dwf_release_scratch(void) {
     std::lock_guard<std::mutex> lk(g_scratch_mu);
+    std::lock_guard<std::recursive_mutex> rlk(runtime_mutex());
     if (g_scratch) {
         hipDeviceSynchronize();
         hipFree(g_scratch);

@@ -438,6 +438,118 @@ k_gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int wan
     if (want_norm) write_partials<1>(v, 1, rw, col, sh, tot);
 }
 
+// ---- fused GCR iteration (see kernels.hpp)
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_gcr_dots(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w, const cpx<T>* r, size_t n, const int* stop,
+           RedWork rw) {
+    SHARED_RED;
+    const int col = blockIdx.y;
+    const size_t o = (size_t)col * n;
+    const bool stopped = stop[col] != 0;
+    // layout (static indices, so the accumulators stay in registers):
+    // [|w|^2, Re <w, r>, Im <w, r>, Re <W_0, w>, Im <W_0, w>, ...]
+    double v[35];
+#pragma unroll
+    for (int q = 0; q < 35; ++q) v[q] = 0.0;
+    if (!stopped) GRID_STRIDE(e, n) {
+        const cpx<double> we = up(w[o + e]), re = up(r[o + e]);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i < j) {
+                const cpx<double> p = cjmul(up(W[(size_t)i * wstride + o + e]), we);
+                v[3 + 2 * i] += p.re;
+                v[4 + 2 * i] += p.im;
+            }
+        }
+        v[0] += we.re * we.re + we.im * we.im;
+        const cpx<double> p = cjmul(we, re);
+        v[1] += p.re;
+        v[2] += p.im;
+    }
+    write_partials<35>(v, 2 * j + 3, rw, col, sh, tot);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_gcr_fused_update(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx<T>* r, cpx<T>* copy, size_t n,
+                   double tol2, const int* stop_in, int* stop_out, GcrDev g) {
+    const int col = blockIdx.y;
+    const bool stopped = stop_in[col] != 0;
+    const double* t = g.tot + (size_t)col * kGcrTot;
+    const size_t kb = (size_t)col * g.kmax;
+    cpx<double> c[16];
+    double nnj = t[0];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        c[i] = {0.0, 0.0};
+        if (i < j) {
+            const cpx<double> d = {t[3 + 2 * i], t[4 + 2 * i]};
+            const double nni = g.nn[kb + i];
+            if (nni > 0.0) {
+                c[i] = {d.re / nni, d.im / nni};
+                nnj -= (d.re * d.re + d.im * d.im) / nni;
+            }
+        }
+    }
+    const cpx<double> wr = {t[1], t[2]};
+    const bool live = !stopped && nnj > 0.0;
+    const cpx<double> a = live ? cpx<double>{wr.re / nnj, wr.im / nnj} : cpx<double>{0.0, 0.0};
+    const size_t o = (size_t)col * n;
+    if (!stopped) {
+        cpx<T> cc[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) cc[i] = {(T)c[i].re, (T)c[i].im};
+        const cpx<T> at = {(T)a.re, (T)a.im};
+        GRID_STRIDE(e, n) {
+            cpx<T> we = w[o + e];
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i < j) {
+                    const cpx<T> Wi = W[(size_t)i * wstride + o + e];
+                    we.re -= cc[i].re * Wi.re - cc[i].im * Wi.im;
+                    we.im -= cc[i].re * Wi.im + cc[i].im * Wi.re;
+                }
+            w[o + e] = we;
+            cpx<T> re = r[o + e];
+            re.re -= at.re * we.re - at.im * we.im;
+            re.im -= at.re * we.im + at.im * we.re;
+            r[o + e] = re;
+            if (copy) copy[o + e] = re;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const size_t s = kb + j;
+        g.nn[s] = live ? nnj : 0.0;
+        g.wr[2 * s] = live ? wr.re : 0.0;
+        g.wr[2 * s + 1] = live ? wr.im : 0.0;
+        for (int i = 0; i < j; ++i) {   // <W_i, w> for the back substitution
+            g.D[((kb + j) * g.kmax + i) * 2] = stopped ? 0.0 : t[3 + 2 * i];
+            g.D[((kb + j) * g.kmax + i) * 2 + 1] = stopped ? 0.0 : t[4 + 2 * i];
+        }
+        int sflag = stop_in[col];
+        if (!stopped) {
+            double rr = g.rr[col] - (live ? (wr.re * wr.re + wr.im * wr.im) / nnj : 0.0);
+            if (rr < 0.0) rr = 0.0;
+            g.rr[col] = rr;
+            g.it[col] += 1;
+            if (!finite(rr) || !finite(nnj)) sflag = 2;
+            else if (rr <= tol2 * g.bb[col]) sflag = 1;
+        }
+        stop_out[col] = sflag;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fin_gcr_cycle(RedWork rw, int nb, GcrDev g, const int* stop_src) {
+    SHARED_RED;
+    const int col = blockIdx.x;
+    sum_partials<1>(1, nb, rw, col, sh, tot);
+    if (threadIdx.x == 0) {
+        g.rr[col] = tot[0];
+        g.stop[col] = stop_src[col];
+    }
+}
+
 __global__ void k_gcr_dev_init(int ncol, GcrDev g) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncol) return;
@@ -539,6 +651,27 @@ hipError_t gcr_rupdate_dev(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size
     hipLaunchKernelGGL(k_fin_gcr_rr, dim3(ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g, tol2);
     return hipGetLastError();
 }
+template <typename T>
+hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx<T>* r, cpx<T>* copy, size_t n,
+                          int ncol, double tol2, const int* stop_in, int* stop_out, const GcrDev& g,
+                          const RedWork& rw, hipStream_t st) {
+    if (j < 0 || j > 15 || 2 * j + 3 > kGcrTot || 2 * j + 3 > rw.max_q) return hipErrorInvalidValue;
+    const dim3 grid = red_grid(n, ncol, rw);
+    hipLaunchKernelGGL(k_gcr_dots<T>, grid, dim3(kBlock), 0, st, W, wstride, j, w, r, n, stop_in, rw);
+    hipLaunchKernelGGL(k_fin_store_q, dim3(2 * j + 3, ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g.tot,
+                       (size_t)kGcrTot);
+    hipLaunchKernelGGL(k_gcr_fused_update<T>, ew_grid(n, ncol), dim3(kBlock), 0, st, W, wstride, j, w, r, copy, n,
+                       tol2, stop_in, stop_out, g);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t gcr_fused_cycle_end(const cpx<T>* r, size_t n, int ncol, const int* stop_src, const GcrDev& g,
+                               const RedWork& rw, hipStream_t st) {
+    const dim3 grid = red_grid(n, ncol, rw);
+    hipLaunchKernelGGL(k_norm2_part<T>, grid, dim3(kBlock), 0, st, r, n, rw, (const int*)nullptr, 1);
+    hipLaunchKernelGGL(k_fin_gcr_cycle, dim3(ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g, stop_src);
+    return hipGetLastError();
+}
 hipError_t gcr_dev_init(int ncol, const GcrDev& g, hipStream_t st) {
     hipLaunchKernelGGL(k_gcr_dev_init, dim3(grid_for(ncol, 64)), dim3(64), 0, st, ncol, g);
     return hipGetLastError();
@@ -587,6 +720,8 @@ hipError_t check_finite(const cpx<T>* x, size_t n, int* flag, hipStream_t st) {
     template hipError_t gcr_orth<T>(const cpx<T>*, size_t, int, cpx<T>*, const cpx<T>*, size_t, int, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_rupdate<T>(const cpx<T>*, cpx<T>*, cpx<T>*, int, size_t, int, bool, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_rupdate_dev<T>(const cpx<T>*, cpx<T>*, cpx<T>*, int, size_t, int, double, const GcrDev&, const RedWork&, hipStream_t); \
+    template hipError_t gcr_fused_step<T>(const cpx<T>*, size_t, int, cpx<T>*, cpx<T>*, cpx<T>*, size_t, int, double, const int*, int*, const GcrDev&, const RedWork&, hipStream_t); \
+    template hipError_t gcr_fused_cycle_end<T>(const cpx<T>*, size_t, int, const int*, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t check_finite<T>(const cpx<T>*, size_t, int*, hipStream_t);
 
 INST_T(float)

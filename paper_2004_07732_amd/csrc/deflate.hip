@@ -137,6 +137,7 @@ int Hierarchy::deflation_setup(hipStream_t st) {
     rocblas_int* info = nullptr;
     std::vector<void*> owned;
     auto get = [&](void** p, size_t bytes) {
+        std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
         if (hipMalloc(p, bytes) != hipSuccess) return false;
         owned.push_back(*p);
         return true;
@@ -152,6 +153,7 @@ int Hierarchy::deflation_setup(hipStream_t st) {
                     get((void**)&info, sizeof(rocblas_int));
     auto cleanup = [&]() {
         (void)hipStreamSynchronize(st);
+        std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
         for (void* p : owned) (void)hipFree(p);
     };
     if (!ok) { cleanup(); return DWF_EHIP; }

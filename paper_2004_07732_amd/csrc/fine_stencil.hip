@@ -161,6 +161,15 @@ static int tuned_chunk(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, i
     char keyb[128];
     std::snprintf(keyb, sizeof keyb, "fine_dw/%zu/%d/%d/%d/%d/%d", sizeof(R), Lx, Ly, Ls, ncol, dagger ? 1 : 0);
     const std::string key(keyb);
+    // inside a graph capture: use a choice already made, never time
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        return it != cache.end() ? it->second : heuristic;
+    }
+    // the timing runs synchronise: keep them apart from captures on other threads
+    std::lock_guard<std::recursive_mutex> rlk(runtime_mutex());
     std::lock_guard<std::mutex> lk(mu);
     const char* path = std::getenv("DWF_TUNE_CACHE");
     if (!loaded) {
@@ -174,8 +183,6 @@ static int tuned_chunk(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, i
     }
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return heuristic;
     std::vector<int> cand;
     for (int c : {Ls, (Ls + 1) / 2, (Ls + 3) / 4, 8, 4, 2})
         if (c >= 1 && c <= Ls && std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);

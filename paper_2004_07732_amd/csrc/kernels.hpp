@@ -1,9 +1,18 @@
 // Internal launch interface between the host orchestration and the HIP kernels.
 #pragma once
 
+#include <mutex>
+
 #include "common.hpp"
 
 namespace dwf {
+
+// One process-wide lock around HIP calls that must not overlap a graph capture
+// on another thread: capture itself, device and pinned-host allocation and
+// release, and the autotuner's timing runs.  Recursive, so a holder may call
+// into code that takes it again.
+std::recursive_mutex& runtime_mutex();
+
 
 // ------------------------------------------------------------ reductions
 // Deterministic two-kernel reduction: every block writes its partial sums to
@@ -101,8 +110,11 @@ struct GcrDev {
     int* stop;      // [ncol]  1: column takes no update (2: not finite)
     double* bb;     // [ncol]  |b|^2 of the device-driven solve
     int* it;        // [ncol]  iterations of the device-driven solve
+    int* stop2;     // [ncol]  second stop buffer of the fused iteration (written while `stop` is read)
+    double* tot;    // [ncol][kGcrTot]  inner products of the fused iteration
     int kmax;
 };
+constexpr int kGcrTot = 40;
 // D[c][j][i] = <W_i, w>, i < j;  W_i = W + i*wstride
 template <typename T>
 hipError_t gcr_multidot(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w, size_t n, int ncol,
@@ -121,6 +133,21 @@ hipError_t gcr_dev_init(int ncol, const GcrDev& g, hipStream_t st);
 template <typename T>
 hipError_t gcr_rupdate_dev(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int ncol, double tol2,
                            const GcrDev& g, const RedWork& rw, hipStream_t st);
+// Fused GCR iteration j (device-driven solve, no preconditioner), three launches:
+//   dots:   tot = [|w|^2, <w, r>, <W_i, w> (i < j)] in one pass;
+//   update: every block derives c_i = <W_i, w>/nn_i, |w'|^2 = |w|^2 - sum |<W_i, w>|^2/nn_i and
+//           a = <w, r>/|w'|^2 (r is orthogonal to every W_i, so <w', r> = <w, r>), then in one pass
+//           w' = w - sum c_i W_i, r -= a w', copy = r; block 0 stores nn_j, wr_j, D[j][.], the new
+//           |r|^2 = |r|^2 - |<w, r>|^2/|w'|^2 and the stop flag into `stop_out` (while `stop_in`
+//           is only read).
+template <typename T>
+hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx<T>* r, cpx<T>* copy, size_t n,
+                          int ncol, double tol2, const int* stop_in, int* stop_out, const GcrDev& g,
+                          const RedWork& rw, hipStream_t st);
+// end of a fused cycle: rr = |r|^2 exactly, stop = stop_src
+template <typename T>
+hipError_t gcr_fused_cycle_end(const cpx<T>* r, size_t n, int ncol, const int* stop_src, const GcrDev& g,
+                               const RedWork& rw, hipStream_t st);
 // back substitution for gam over directions 0..k-1
 hipError_t gcr_solve(int k, int ncol, const GcrDev& g, hipStream_t st);
 // x (+)= sum_{i<k} gam[i] P_i ; `accumulate` false overwrites x

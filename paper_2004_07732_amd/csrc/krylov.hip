@@ -59,10 +59,12 @@ struct Work {
     std::vector<void*> bufs;
     double* hres = nullptr;
     ~Work() {
+        std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
         for (void* p : bufs) (void)hipFree(p);
         if (hres) (void)hipHostFree(hres);
     }
     template <typename P> bool get(P** p, size_t bytes) {
+        std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
         void* q = nullptr;
         if (hipMalloc(&q, bytes) != hipSuccess) return false;
         bufs.push_back(q);
@@ -89,7 +91,10 @@ int krylov_solve(const cpx<double>* U, const cpx<double>* b, cpx<double>* x, int
         return DWF_EHIP;
     for (auto& p : v)
         if (!w.get(&p, sizeof(cpx<double>) * n)) return DWF_EHIP;
-    if (hipHostMalloc((void**)&w.hres, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) return DWF_EHIP;
+    {
+        std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
+        if (hipHostMalloc((void**)&w.hres, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) return DWF_EHIP;
+    }
 
     int status = DWF_OK;
     long long applies = 0;

@@ -16,14 +16,25 @@
 #include <cstring>
 #include <type_traits>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "mg.hpp"
 
 namespace dwf {
 
+// with DWF_VERBOSE set, a failing HIP call is reported with its place
+static void report_hip(hipError_t e, int line) {
+    static const bool on = std::getenv("DWF_VERBOSE") != nullptr;
+    if (on) std::fprintf(stderr, "[dwfmg] HIP error '%s' at mg.hip:%d\n", hipGetErrorString(e), line);
+}
 #define HIPCHK(...)                                 \
     do {                                            \
         hipError_t e_ = (__VA_ARGS__);              \
-        if (e_ != hipSuccess) return DWF_EHIP;      \
+        if (e_ != hipSuccess) {                     \
+            report_hip(e_, __LINE__);               \
+            return DWF_EHIP;                        \
+        }                                           \
     } while (0)
 
 namespace {
@@ -39,12 +50,18 @@ Hierarchy::~Hierarchy() {
     if (st_) (void)hipStreamSynchronize(st_);
     clear_graphs();
     destroy_blas();
+    std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
     for (void* p : allocs_) (void)hipFree(p);
     if (h_scal_) (void)hipHostFree(h_scal_);
     if (h_int_) (void)hipHostFree(h_int_);
     if (h_cg_) (void)hipHostFree(h_cg_);
     if (ev_in_) (void)hipEventDestroy(ev_in_);
     if (st_) (void)hipStreamDestroy(st_);
+}
+
+std::recursive_mutex& runtime_mutex() {
+    static std::recursive_mutex m;
+    return m;
 }
 
 void Hierarchy::clear_graphs() {
@@ -59,6 +76,7 @@ template <class F>
 int Hierarchy::run_graph(const GraphKey& key, hipStream_t st, F&& enqueue) {
     auto it = graphs_.find(key);
     if (it == graphs_.end()) {
+        std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         capturing_ = true;
         const int e = enqueue();
@@ -80,6 +98,7 @@ int Hierarchy::run_graph(const GraphKey& key, hipStream_t st, F&& enqueue) {
 }
 
 void* Hierarchy::dalloc(size_t bytes) {
+    std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
     void* p = nullptr;
     if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) return nullptr;
     allocs_.push_back(p);
@@ -212,7 +231,10 @@ int Hierarchy::alloc_level_work(int l, int ncol) {
         g.stop = (int*)A(sizeof(int) * ncol);
         g.bb = (double*)A(sizeof(double) * ncol);
         g.it = (int*)A(sizeof(int) * ncol);
-        if (!g.D || !g.nn || !g.wr || !g.gam || !g.rr || !g.stop || !g.bb || !g.it) return DWF_EHIP;
+        g.stop2 = (int*)A(sizeof(int) * ncol);
+        g.tot = (double*)A(sizeof(double) * kGcrTot * ncol);
+        if (!g.D || !g.nn || !g.wr || !g.gam || !g.rr || !g.stop || !g.bb || !g.it || !g.stop2 || !g.tot)
+            return DWF_EHIP;
         if (hipMemset(g.stop, 0, sizeof(int) * ncol) != hipSuccess) return DWF_EHIP;
         return DWF_OK;
     };
@@ -228,6 +250,7 @@ int Hierarchy::ensure_scalars(int maxc) {
     rw_.max_cols = maxc;
     rw_.partial = (double*)dalloc(sizeof(double) * (size_t)maxc * rw_.max_q * rw_.nblk);
     if (!rw_.partial) return DWF_EHIP;
+    std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
     if (h_scal_) hipHostFree(h_scal_);
     if (h_int_) hipHostFree(h_int_);
     if (h_cg_) hipHostFree(h_cg_);
@@ -330,8 +353,9 @@ int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st)
 // ------------------------------------------------------------ restarted GCR (coarsest level)
 // Unpreconditioned GCR(kmax) on A with every decision on the device (the
 // stop flags are reset by gcr_dev_init at the start of every solve): each
-// cycle runs kmax iterations whose kernels turn into no-ops for converged
-// columns, then updates x and recomputes the true residual.  The host reads
+// cycle runs kmax fused iterations whose kernels turn into no-ops for
+// converged columns, then updates x and recomputes the true residual and its
+// norm exactly.  The host reads
 // the stop flags once per cycle; a cycle is captured once as a HIP graph.
 template <typename T>
 int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol, int maxit, int restart,
@@ -353,22 +377,26 @@ int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol
     HIPCHK((vconvert<T, T>(b, r, nt, st)));
     HIPCHK(norm2<T>(b, n, ncol, g.rr, rw_, st));
     HIPCHK(gcr_dev_init(ncol, g, st));
+    // one restart cycle: kmax fused iterations (inner products, then one pass that orthogonalises
+    // the new direction and updates the residual; the stop flags alternate between two buffers so
+    // that no kernel writes the flags it reads), the solution update, and the true residual
     auto cycle = [&]() -> int {
         HIPCHK((vconvert<T, T>(r, P, nt, st)));
         for (int k = 0; k < kmax; ++k) {
             cpx<T>* Pk = P + (size_t)k * nt;
             cpx<T>* Wk = W + (size_t)k * nt;
+            const int* s_in = (k % 2 == 0) ? g.stop : g.stop2;
+            int* s_out = (k % 2 == 0) ? g.stop2 : g.stop;
             HIPCHK(apply_A<T>(l, Pk, Wk, t, ncol, st));
-            HIPCHK(gcr_multidot<T>(W, nt, k, Wk, n, ncol, g, rw_, st));
-            HIPCHK(gcr_orth<T>(W, nt, k, Wk, r, n, ncol, g, rw_, st));
             // the updated residual is the next search direction
-            HIPCHK(gcr_rupdate_dev<T>(Wk, r, k + 1 < kmax ? P + (size_t)(k + 1) * nt : nullptr, k, n, ncol, tol2, g,
-                                      rw_, st));
+            HIPCHK(gcr_fused_step<T>(W, nt, k, Wk, r, k + 1 < kmax ? P + (size_t)(k + 1) * nt : nullptr, n, ncol,
+                                     tol2, s_in, s_out, g, rw_, st));
         }
         HIPCHK(gcr_solve(kmax, ncol, g, st));
         HIPCHK((gcr_xupdate<T, T>(P, nt, kmax, x, n, ncol, true, g, st)));
         HIPCHK(apply_A<T>(l, x, t2, t, ncol, st));
         HIPCHK(vsub<T>(b, t2, r, nt, st));
+        HIPCHK(gcr_fused_cycle_end<T>(r, n, ncol, (kmax % 2 == 0) ? g.stop : g.stop2, g, rw_, st));
         return DWF_OK;
     };
     const int max_cycles = std::max(1, (maxit + kmax - 1) / kmax);
@@ -782,6 +810,7 @@ int Hierarchy::level_op(int level, int op, const cpx<double>* in, cpx<double>* o
     size_t nn = 0;
     if (transfer) nn = levels[level + 1].vec_elems() * ncol;
     const size_t nbig = std::max(nl, n2);
+    std::unique_lock<std::recursive_mutex> lk(runtime_mutex());
     HIPCHK(hipMalloc(&bin, nbig * eb));
     HIPCHK(hipMalloc(&bout, nbig * eb));
     HIPCHK(hipMalloc(&btmp, nbig * eb));
