@@ -87,3 +87,29 @@ def test_batched_form_64_rhs_three_lattices():
         bj = b[j].cpu().numpy()
         res = np.linalg.norm(bj - O.dwf(U, x[j].cpu().numpy(), m, M5)) / np.linalg.norm(bj)
         assert res <= 1e-10
+
+
+@pytest.mark.parametrize("nrhs", [1, 16])
+def test_headline_configuration(nrhs):
+    """The benchmark's own configuration at full size: 256^2 x Ls 16, beta 6,
+    m_f 0.01, 2 levels (4x4 aggregates, 16 null vectors, coarse Ls 2), FP32 fine
+    level, BF16 matrix-core coarse links, FP64 coarse vectors, coarsest GCR(8) to
+    0.25, FP64 defect correction to 1e-10; the oracle recomputes the residual of
+    sampled right-hand sides."""
+    L, Ls, m, M5, cfg = 256, 16, 0.01, -1.0, 6
+    g = inputs.metropolis_u1(L, L, 6.0, 200, inputs.gauge_seed(4, L))
+    b = torch.empty((nrhs, Ls, L, L, 2), dtype=torch.complex128, device="cuda")
+    for j in range(nrhs):
+        b[j] = torch.from_numpy(inputs.gaussian_field((Ls, L, L, 2), inputs.rhs_seed(cfg, L, j)))
+    starts = [torch.from_numpy(inputs.gaussian_field((16, L, L, 2), inputs.null_start_seed(cfg, 0))).cuda()]
+    p = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[dwfmg.P_F64],
+                       fine_prec=dwfmg.P_F32, coarsest_solver=dwfmg.COARSEST_GCR, coarsest_restart=8,
+                       coarsest_tol=0.25)
+    mg = dwfmg.MG(torch.from_numpy(g.U).cuda(), Ls, m, M5, p, starts)
+    x, st = mg.solve(b, 1e-10)
+    say(f"[headline] nrhs {nrhs}: {st.solve_ms:.0f} ms, fine iters {st.fine_iters}, residual {st.true_rel_residual:.2e}")
+    assert st.status == dwfmg.DWF_OK and st.true_rel_residual <= 1e-10
+    for j in sorted({0, nrhs - 1}):
+        bj = b[j].cpu().numpy()
+        res = np.linalg.norm(bj - O.dwf(g.U, x[j].cpu().numpy(), m, M5)) / np.linalg.norm(bj)
+        assert res <= 1e-10
