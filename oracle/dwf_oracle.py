@@ -370,6 +370,17 @@ def restrict2d(P: Prolongator, r: np.ndarray) -> np.ndarray:
     return out.reshape(lead + out.shape[nl:nl + 2] + (2 * nv,))
 
 
+def restrict_bulk(P: Prolongator, r: np.ndarray) -> np.ndarray:
+    """Sec. 4.1's alternative to the boundary-only transfer: the 2-d restriction
+    repeated on every slice, coarse slice s from fine slice s (L^_s = L_s)."""
+    return restrict2d(P, r)
+
+
+def prolong_bulk(P: Prolongator, ec: np.ndarray) -> np.ndarray:
+    """Adjoint of restrict_bulk: the 2-d prolongation on every slice."""
+    return prolong2d(P, ec)
+
+
 def chirality(n_per_chir: int) -> np.ndarray:
     """sigma_3 on a site with chirality-major dof ordering."""
     return np.concatenate([np.ones(n_per_chir), -np.ones(n_per_chir)])
@@ -682,6 +693,7 @@ class MGParams:
     inter_restart: int = 16
     coarsest_tol: float = 0.05
     coarsest_maxit: int = 1024
+    transfer: str = "wall"         # "wall": eq. TruncProjectInterpolate; "bulk": Sec. 4.1's alternative
 
 
 @dataclass
@@ -746,11 +758,24 @@ class MG:
 
     def restrict(self, l, r):
         lev = self.levels[l]
+        if self.params.transfer == "bulk":
+            return restrict_bulk(lev.P, r)
         return restrict_wall(lev.P, r, lev.chir, self.levels[l + 1].Ls)
 
     def prolong(self, l, e):
         lev = self.levels[l]
+        if self.params.transfer == "bulk":
+            return prolong_bulk(lev.P, e)
         return prolong_wall(lev.P, e, lev.chir, lev.Ls)
+
+    def local_colinearity(self, v):
+        """Sec. 4.1: |(1 - P R) v| for the level-0 transfer (wall or bulk)."""
+        return norm(v - self.prolong(0, self.restrict(0, v)))
+
+    def oblique_projector(self, v, coarse_inverse):
+        """Sec. 4.1: |(1 - P hat-A^{-1} R A) v| with A = D_PV^dag D_DW on level 0 and
+        hat-A its coarse counterpart; `coarse_inverse` applies hat-A^{-1} exactly."""
+        return norm(v - self.prolong(0, coarse_inverse(self.restrict(0, self.A(0, v)))))
 
     def coarse_solve(self, l, rc):
         """Approximate solve of level l's A (l >= 1) for the K-cycle."""

@@ -492,6 +492,56 @@ def test_wall_transfer_adjoint_and_identity():
     assert np.max(np.abs(back - ew)) < 1e-14
 
 
+def test_bulk_transfer_adjoint_identity_and_range():
+    """The bulk transfer of Sec. 4.1: R P = 1 (P^dag P = 1 per slice), P is the
+    adjoint of R, and a field in the range of P has zero local colinearity."""
+    L, nc, nvec, Ls = 8, 1, 3, 4
+    P = make_prolongator(L, (4, 4), nvec, nc, 60)
+    ec = cgauss((Ls, 2, 2, 2 * nvec), 61)
+    r = cgauss((Ls, L, L, 2 * nc), 62)
+    assert np.allclose(O.restrict_bulk(P, O.prolong_bulk(P, ec)), ec, atol=1e-13)
+    lhs = np.vdot(O.prolong_bulk(P, ec), r)
+    rhs = np.vdot(ec, O.restrict_bulk(P, r))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    v = O.prolong_bulk(P, ec)
+    assert np.linalg.norm(v - O.prolong_bulk(P, O.restrict_bulk(P, v))) < 1e-12 * np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("transfer", ["wall", "bulk"])
+def test_mg_solve_with_either_transfer(transfer):
+    """Both transfers give a working preconditioner: the MG solve reaches the
+    tolerance and agrees with LU (L^_s = L_s for the bulk transfer)."""
+    L, Ls, m, M5 = 8, 4, 0.05, -1.0
+    U = metropolis_links(L, 3.0, 20, 9)
+    shape = (Ls, L, L, 2)
+    b = cgauss(shape, 63)
+    starts = [cgauss((4, L, L, 2), 64)]
+    params = O.MGParams(levels=[O.LevelParams(nvec=4, block=(4, 4), Ls=Ls, setup_iters=20)], transfer=transfer)
+    mg = O.MG(U, Ls, m, M5, params, starts)
+    x, it = mg.solve(b, 1e-10)
+    D = O.assemble(lambda v: O.dwf(U, v, m, M5), shape)
+    x_lu = np.linalg.solve(D, b.reshape(-1)).reshape(shape)
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) < 1e-8
+
+
+def test_oblique_projector_annihilates_galerkin_range():
+    """With the bulk transfer and the exact Galerkin product R A P as hat-A, the
+    oblique projector 1 - P (R A P)^{-1} R A vanishes on the range of P: a check
+    of the composition order in the diagnostic."""
+    L, Ls, m, M5 = 8, 4, 0.05, -1.0
+    U = metropolis_links(L, 3.0, 20, 10)
+    starts = [cgauss((2, L, L, 2), 65)]
+    params = O.MGParams(levels=[O.LevelParams(nvec=2, block=(4, 4), Ls=Ls, setup_iters=10)], transfer="bulk")
+    mg = O.MG(U, Ls, m, M5, params, starts)
+    cshape = (Ls, 2, 2, 4)
+    RAP = O.assemble(lambda e: mg.restrict(0, mg.A(0, mg.prolong(0, e))), cshape)
+    inv = lambda rc: np.linalg.solve(RAP, rc.reshape(-1)).reshape(cshape)
+    v = mg.prolong(0, cgauss(cshape, 66))
+    assert mg.oblique_projector(v, inv) < 1e-10 * np.linalg.norm(v)
+    w = cgauss((Ls, L, L, 2), 67)
+    assert mg.oblique_projector(w, inv) > 1e-3 * np.linalg.norm(w)
+
+
 def test_kcycle_with_exact_coarse_solve():
     """With no smoothing and an (essentially) exact coarsest solve the K-cycle
     preconditioner is Prol . hat-A^{-1} . Restr (Sec. 2.3 summary)."""
