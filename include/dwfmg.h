@@ -68,6 +68,10 @@ extern "C" {
 
 #define DWF_MAX_LEVELS 3       /* coarse levels below the fine one                   */
 
+/* transfer between levels */
+#define DWF_TRANSFER_WALL 0
+#define DWF_TRANSFER_BULK 1
+
 /* coarsest-level solver */
 #define DWF_COARSEST_CGNR 0
 #define DWF_COARSEST_GCR  1
@@ -161,6 +165,12 @@ typedef struct {
                                              DWF_COARSEST_GCR: restarted GCR on A itself,
                                              |r| <= coarsest_tol |b|                     */
     int    coarsest_restart;              /* GCR restart length on the coarsest (<= 16) */
+    int    transfer;                      /* DWF_TRANSFER_WALL: restrict / prolong the
+                                             walls only (eq. TruncProjectInterpolate, the
+                                             paper's method); DWF_TRANSFER_BULK: the 2-d
+                                             prolongator on every slice (Sec. 4.1's
+                                             alternative; needs Ls_coarse equal to the
+                                             finer level's Ls on every level)          */
 } dwf_mg_params;
 
 typedef struct {

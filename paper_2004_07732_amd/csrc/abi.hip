@@ -185,6 +185,7 @@ void dwf_mg_default_params(dwf_mg_params* p, int nlevels) {
     p->eig_tol = 1e-3;
     p->coarsest_solver = DWF_COARSEST_CGNR;
     p->coarsest_restart = 16;
+    p->transfer = DWF_TRANSFER_WALL;
 }
 
 int mg_deflation_info(const dwf_mg* mg, int* nev, int* iters, double* worst_residual, double* lambdas) {
@@ -213,6 +214,10 @@ int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, do
     if (p->coarsest_solver == DWF_COARSEST_GCR && (p->coarsest_restart < 1 || p->coarsest_restart > 16))
         return DWF_EINVAL;
     if (p->coarsest_solver == DWF_COARSEST_GCR && p->coarsest_nev > 0) return DWF_EUNSUPPORTED;
+    if (p->transfer != DWF_TRANSFER_WALL && p->transfer != DWF_TRANSFER_BULK) return DWF_EINVAL;
+    if (p->transfer == DWF_TRANSFER_BULK)
+        for (int l = 0; l < p->nlevels; ++l)
+            if (p->Ls_coarse[l] != (l == 0 ? Ls : p->Ls_coarse[l - 1])) return DWF_EINVAL;
     int lx = Lx, ly = Ly, n = 2;
     for (int l = 0; l < p->nlevels; ++l) {
         const int bx = p->block[l][0], by = p->block[l][1], nv = p->nvec[l];

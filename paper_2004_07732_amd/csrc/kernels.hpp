@@ -165,6 +165,11 @@ struct TransferGeom {
 };
 template <typename T>
 hipError_t restrict_wall(const cpx<T>* V, const cpx<T>* r, cpx<T>* rc, const TransferGeom& g, int ncol, hipStream_t st);
+// bulk transfer: the 2-d prolongator on every slice (Lsc == Ls)
+template <typename T>
+hipError_t restrict_bulk(const cpx<T>* V, const cpx<T>* r, cpx<T>* rc, const TransferGeom& g, int ncol, hipStream_t st);
+template <typename T>
+hipError_t prolong_bulk(const cpx<T>* V, const cpx<T>* ec, cpx<T>* e, const TransferGeom& g, int ncol, hipStream_t st);
 template <typename T>
 hipError_t prolong_wall(const cpx<T>* V, const cpx<T>* ec, cpx<T>* e, const TransferGeom& g, int ncol, hipStream_t st);
 

@@ -159,9 +159,11 @@ hipError_t Hierarchy::restrict_to(int l, const cpx<T>* r, void* rc_next, int nco
     TransferGeom g{L.Lx, L.Ly, L.Ls, L.n / 2, L.bx, L.by, N.Ls, L.nvec_next};
     const cpx<T>* V;
     if constexpr (std::is_same<T, float>::value) V = L.V32; else V = L.V64;
-    if (N.vec_prec == prec_of<T>()) return restrict_wall<T>(V, r, C<T>(rc_next), g, ncol, st);
+    const bool bulk = prm.transfer == DWF_TRANSFER_BULK;
+    auto R = [&](cpx<T>* dst) { return bulk ? restrict_bulk<T>(V, r, dst, g, ncol, st) : restrict_wall<T>(V, r, dst, g, ncol, st); };
+    if (N.vec_prec == prec_of<T>()) return R(C<T>(rc_next));
     cpx<T>* loc = C<T>(work_[l].rc_local);
-    hipError_t e = restrict_wall<T>(V, r, loc, g, ncol, st);
+    hipError_t e = R(loc);
     if (e != hipSuccess) return e;
     const size_t n = N.vec_elems() * ncol;
     if constexpr (std::is_same<T, float>::value) return vconvert<float, double>(loc, C<double>(rc_next), n, st);
@@ -175,14 +177,16 @@ hipError_t Hierarchy::prolong_from(int l, const void* ec_next, cpx<T>* e, int nc
     TransferGeom g{L.Lx, L.Ly, L.Ls, L.n / 2, L.bx, L.by, N.Ls, L.nvec_next};
     const cpx<T>* V;
     if constexpr (std::is_same<T, float>::value) V = L.V32; else V = L.V64;
-    if (N.vec_prec == prec_of<T>()) return prolong_wall<T>(V, C<T>(ec_next), e, g, ncol, st);
+    const bool bulk = prm.transfer == DWF_TRANSFER_BULK;
+    auto P = [&](const cpx<T>* src) { return bulk ? prolong_bulk<T>(V, src, e, g, ncol, st) : prolong_wall<T>(V, src, e, g, ncol, st); };
+    if (N.vec_prec == prec_of<T>()) return P(C<T>(ec_next));
     cpx<T>* loc = C<T>(work_[l].ec_local);
     const size_t n = N.vec_elems() * ncol;
     hipError_t err;
     if constexpr (std::is_same<T, float>::value) err = vconvert<double, float>(C<double>(ec_next), loc, n, st);
     else err = vconvert<float, double>(C<float>(ec_next), loc, n, st);
     if (err != hipSuccess) return err;
-    return prolong_wall<T>(V, loc, e, g, ncol, st);
+    return P(loc);
 }
 
 // ------------------------------------------------------------ work buffers

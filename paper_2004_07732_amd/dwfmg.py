@@ -37,6 +37,7 @@ MG_OP_DW, MG_OP_DW_DAG, MG_OP_PV, MG_OP_PV_DAG, MG_OP_A = 0, 1, 2, 3, 4
 MG_OP_WILSON, MG_OP_WILSON_DAG, MG_OP_RESTRICT, MG_OP_PROLONG, MG_OP_KCYCLE = 5, 6, 7, 8, 9
 COARSEST_CGNR, COARSEST_GCR = 0, 1
 KRYLOV_CGNR, KRYLOV_BICGSTAB = 0, 1
+TRANSFER_WALL, TRANSFER_BULK = 0, 1
 
 
 class DwfError(RuntimeError):
@@ -134,6 +135,7 @@ class CParams(ctypes.Structure):
         ("eig_tol", ctypes.c_double),
         ("coarsest_solver", ctypes.c_int),
         ("coarsest_restart", ctypes.c_int),
+        ("transfer", ctypes.c_int),
     ]
 
 
@@ -178,6 +180,7 @@ class MGParams:
     eig_tol: float = 1e-3
     coarsest_solver: int = COARSEST_CGNR   # CGNR on A^dag A (Table 2), or COARSEST_GCR: GCR on A
     coarsest_restart: int = 16
+    transfer: int = 0              # TRANSFER_WALL (the paper's method) or TRANSFER_BULK (Sec. 4.1)
 
     @property
     def nlevels(self) -> int:
@@ -196,7 +199,7 @@ class MGParams:
         for name in ("fine_prec", "m_setup", "setup_iters", "setup_tol", "outer_restart", "smooth_iters",
                      "inter_maxit", "inter_tol", "inter_restart", "coarsest_maxit", "coarsest_tol", "inner_tol",
                      "max_iters", "max_outer", "coarsest_nev", "eig_degree", "eig_maxit", "eig_tol",
-                     "coarsest_solver", "coarsest_restart"):
+                     "coarsest_solver", "coarsest_restart", "transfer"):
             setattr(c, name, getattr(self, name))
         return c
 
