@@ -86,6 +86,24 @@ extern "C" {
 int dwf_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs,
               double m_f, double M5, int flags, void* stream);
 
+/* Launch configuration of the fine D_DW stencil (every operator above and every
+ * fine-level apply inside the solvers goes through it).  The results do not
+ * depend on it: all configurations evaluate each site with the same expression
+ * and agree bit for bit.  By default (DWF_FINE_AUTO) the library times the
+ * candidates once per lattice shape, column count, precision and adjoint flag
+ * and keeps the fastest.  dwf_fine_config pins one for all later calls in the
+ * process: shape DWF_FINE_ROW (any lattice) or one of the tiled shapes (used
+ * only where Lx and Ly divide into its tiles; elsewhere the automatic choice
+ * applies), chunk = slices walked per thread, 1 <= chunk <= 4095 (capped at
+ * Ls).  shape = DWF_FINE_AUTO restores the automatic choice (chunk ignored).
+ * Returns DWF_EINVAL for an unknown shape or a chunk out of range. */
+#define DWF_FINE_AUTO        -1
+#define DWF_FINE_ROW          0   /* one thread per site, neighbours through the caches */
+#define DWF_FINE_TILE_64x8    1   /* LDS tile of 64 x 8 sites per workgroup             */
+#define DWF_FINE_TILE_32x16   2
+#define DWF_FINE_TILE_128x4   3
+int dwf_fine_config(int shape, int chunk);
+
 /* Pauli-Villars forms (Sec. 2.2, eq. NormalExp): see the DWF_PV* modes.  The
  * product modes use a library-owned intermediate field (allocated on first use
  * and kept until dwf_release_scratch).  Same layout rules as dwf_apply. */

@@ -89,6 +89,8 @@ int dwf_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls,
                                       Ly, Ls, nrhs, m_f, M5, dag, nullptr, 1, S(stream)));
 }
 
+int dwf_fine_config(int shape, int chunk) { return set_fine_config(shape, chunk) ? DWF_OK : DWF_EINVAL; }
+
 int dwf_pv_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, double m_f,
                  double M5, int mode, int flags, void* stream) {
     if (!U || !psi || !out || psi == out || !dims_ok(Lx, Ly, Ls, nrhs)) return DWF_EINVAL;

@@ -6,14 +6,26 @@
 // FP32, two in FP64); links [2][Ly][Lx].  One thread owns one 2-d site of one
 // column and walks a chunk of consecutive slices, keeping psi_{s-1}, psi_s and
 // psi_{s+1} in registers: the fifth-dimension hop never re-reads memory and the
-// two links of the site are loaded once per chunk.  The four spatial
-// neighbours are read through the L1/L2 caches (consecutive threads own
-// consecutive x, so a wavefront reads whole rows).
+// two links of the site are loaded once per chunk.
+//
+// Two kernels share that walk and differ in how the four spatial neighbours
+// arrive.  The tiled kernel (the one used whenever the lattice divides into its
+// tiles) gives a workgroup a TX x TY tile of sites: at every slice each thread
+// puts its own psi_s, which it already holds, into an LDS tile, the halo ring
+// (one row above and below, one column left and right) is loaded one slice
+// ahead, and the neighbours are read back from LDS after one barrier; the LDS
+// tile is double-buffered so that barrier is the only one per slice.  Global
+// traffic is then psi once plus the ring, instead of four neighbour loads per
+// site through L1/L2, which measured about 40% slower.  The row kernel (any
+// lattice) reads the neighbours through the caches.  Results are written with
+// streaming (nontemporal) stores; both kernels evaluate each site with the same
+// expression, so they agree bit for bit.
 //
 // In 2-d every Wilson hop goes through a rank-1 spin projector (1 -+ gamma_mu)/2,
 // so a hop is one complex projection, one complex link multiply and a
 // reconstruction of the second component (a fixed phase of the first).
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -46,6 +58,60 @@ __device__ __forceinline__ void wilson_hops(const spinor<R>& fx, const spinor<R>
         h = cmul(hu1, fy.c0 - mul_i(fy.c1));     a0 = a0 + h; a1 = a1 + mul_i(h);
         h = cjmul(hu1m, by.c0 + mul_i(by.c1));   a0 = a0 + h; a1 = a1 - mul_i(h);
     }
+}
+
+// One site and slice of D_DW (or its adjoint): diagonal D_W(M5)+1 with the four
+// hops, plus the fifth-dimension terms through P_-+ (prv and nxt already carry
+// the -m of the wrap where it applies).
+template <typename R, bool DAG>
+__device__ __forceinline__ spinor<R> dw_site(const spinor<R>& fx, const spinor<R>& bx, const spinor<R>& fy,
+                                             const spinor<R>& by, const spinor<R>& cur, const spinor<R>& prv,
+                                             const spinor<R>& nxt, cpx<R> hu0, cpx<R> hu0m, cpx<R> hu1, cpx<R> hu1m,
+                                             R diag) {
+    cpx<R> a0 = {R(0), R(0)}, a1 = {R(0), R(0)};
+    wilson_hops<R, DAG>(fx, bx, fy, by, hu0, hu0m, hu1, hu1m, a0, a1);
+    spinor<R> res;
+    res.c0 = diag * cur.c0 - a0;
+    res.c1 = diag * cur.c1 - a1;
+    if (!DAG) {  // P_- psi_{s+1} + P_+ psi_{s-1}
+        res.c1 = res.c1 + nxt.c1;
+        res.c0 = res.c0 + prv.c0;
+    } else {     // P_+ psi_{s+1} + P_- psi_{s-1}
+        res.c0 = res.c0 + nxt.c0;
+        res.c1 = res.c1 + prv.c1;
+    }
+    return res;
+}
+
+// the four components of a spinor as one vector value: values that are loaded
+// conditionally and carried across loop iterations stay in registers in this
+// form (as a 32-byte FP64 struct they were kept in scratch memory)
+template <typename R> struct vec4_of;
+template <> struct vec4_of<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct vec4_of<double> { typedef double type __attribute__((ext_vector_type(4))); };
+template <typename R>
+__device__ __forceinline__ typename vec4_of<R>::type load4(const spinor<R>* p) {
+    return *reinterpret_cast<const typename vec4_of<R>::type*>(p);
+}
+template <typename R>
+__device__ __forceinline__ spinor<R> unpack4(const typename vec4_of<R>::type& v) {
+    spinor<R> r;
+    r.c0 = {v[0], v[1]};
+    r.c1 = {v[2], v[3]};
+    return r;
+}
+
+// write-once output: nontemporal stores keep it from displacing the input
+// slices that neighbouring workgroups are still reading from L2
+__device__ __forceinline__ void store_stream(spinor<float>* p, const spinor<float>& v) {
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(f32x4{v.c0.re, v.c0.im, v.c1.re, v.c1.im}, reinterpret_cast<f32x4*>(p));
+}
+__device__ __forceinline__ void store_stream(spinor<double>* p, const spinor<double>& v) {
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    f64x2* q = reinterpret_cast<f64x2*>(p);
+    __builtin_nontemporal_store(f64x2{v.c0.re, v.c0.im}, q);
+    __builtin_nontemporal_store(f64x2{v.c1.re, v.c1.im}, q + 1);
 }
 
 // out = D psi  (RESID: out = b - D psi).  DW selects the domain-wall operator
@@ -106,19 +172,14 @@ fine_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in,
             cur = sl[site];
         }
         const spinor<R> fx = sl[sxp], bx = sl[sxm], fy = sl[syp], by = sl[sym];
-        cpx<R> a0 = {R(0), R(0)}, a1 = {R(0), R(0)};
-        wilson_hops<R, DAG>(fx, bx, fy, by, hu0, hu0m, hu1, hu1m, a0, a1);
         spinor<R> res;
-        res.c0 = diag * cur.c0 - a0;
-        res.c1 = diag * cur.c1 - a1;
         if (DW) {
-            if (!DAG) {  // P_- psi_{s+1} + P_+ psi_{s-1}
-                res.c1 = res.c1 + nxt.c1;
-                res.c0 = res.c0 + prv.c0;
-            } else {     // P_+ psi_{s+1} + P_- psi_{s-1}
-                res.c0 = res.c0 + nxt.c0;
-                res.c1 = res.c1 + prv.c1;
-            }
+            res = dw_site<R, DAG>(fx, bx, fy, by, cur, prv, nxt, hu0, hu0m, hu1, hu1m, diag);
+        } else {
+            cpx<R> a0 = {R(0), R(0)}, a1 = {R(0), R(0)};
+            wilson_hops<R, DAG>(fx, bx, fy, by, hu0, hu0m, hu1, hu1m, a0, a1);
+            res.c0 = diag * cur.c0 - a0;
+            res.c1 = diag * cur.c1 - a1;
         }
         const size_t o = colbase + (size_t)s * V + site;
         if (RESID) {
@@ -126,40 +187,146 @@ fine_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in,
             res.c0 = bb.c0 - res.c0;
             res.c1 = bb.c1 - res.c1;
         }
-        out[o] = res;
+        store_stream(out + o, res);
         if (DW) { prv = cur; cur = nxt; }
     }
 }
 
-static inline int pick_chunk(int Lx, int Ly, int Ls, int ncol) {
-    // enough threads to fill 256 CUs with several waves each, but long enough
-    // chunks that the fifth-dimension window amortises its two extra loads
+// Tiled D_DW: a workgroup owns a TX x TY tile of 2-d sites of one column and one
+// chunk of slices (same logical-workgroup order as the row kernel).  LDS holds
+// the tile of the current slice with a one-site ring, double-buffered by slice
+// parity.  Per slice: write own psi_s and the prefetched ring into the buffer,
+// issue the loads for the next slice (ring) and the slice after it (own site),
+// barrier, read the four neighbours, evaluate, store.  The buffer written at
+// slice s was last read at slice s-2, before the barrier of slice s-1, so one
+// barrier per slice suffices.  Requires Lx % TX == 0 and Ly % TY == 0.
+template <typename R, bool DAG, bool RESID, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+fine_tile_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in, spinor<R>* __restrict__ out,
+                 const spinor<R>* __restrict__ b, const int* __restrict__ skip, int skip_stride, int Lx, int Ly,
+                 int Ls, int nchunk, int cs, int ntile, R diag, R mwrap) {
+    static_assert(TX >= 2 && TY >= 2, "the ring needs two distinct edges per direction");
+    __shared__ spinor<R> tile[2][TY + 2][TX + 2];
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int chunk = (int)(lb % (unsigned)nchunk);
+    const unsigned t = lb / (unsigned)nchunk;
+    const int tl = (int)(t % (unsigned)ntile);
+    const int col = (int)(t / (unsigned)ntile);
+    if (skip && skip[(size_t)col * skip_stride]) return;   // the same for the whole workgroup
+    const int V = Lx * Ly;
+    const int ntx = Lx / TX;
+    const int x0 = (tl % ntx) * TX, y0 = (tl / ntx) * TY;
+    const int lx = (int)threadIdx.x % TX, ly = (int)threadIdx.x / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const int site = y * Lx + x;
+    const int xm = (x == 0) ? Lx - 1 : x - 1, ym = (y == 0) ? Ly - 1 : y - 1;
+    const R half = R(0.5);
+    const cpx<R> hu0 = half * U[site], hu0m = half * U[y * Lx + xm];
+    const cpx<R> hu1 = half * U[V + site], hu1m = half * U[V + ym * Lx + x];
+    // the ring (row below, row above, left column, right column; 2 TX + 2 TY
+    // sites) is loaded by the first threads of the workgroup, one site each, in
+    // whole wavefronts; the spare lanes of the last of those wavefronts repeat
+    // its final site
+    constexpr int kRing = 2 * TX + 2 * TY;
+    constexpr int kRingThreads = (kRing + 63) / 64 * 64;
+    static_assert(kRingThreads <= TX * TY, "the ring needs enough threads");
+    const int tid = (int)threadIdx.x;
+    const bool ring = tid < kRingThreads;
+    int hsite = 0, hlds = 0;
+    {
+        const int r = min(tid, kRing - 1);
+        const int ybelow = (y0 == 0) ? Ly - 1 : y0 - 1, yabove = (y0 + TY == Ly) ? 0 : y0 + TY;
+        const int xleft = (x0 == 0) ? Lx - 1 : x0 - 1, xright = (x0 + TX == Lx) ? 0 : x0 + TX;
+        if (r < TX) { hsite = ybelow * Lx + x0 + r; hlds = r + 1; }
+        else if (r < 2 * TX) { hsite = yabove * Lx + x0 + (r - TX); hlds = (TY + 1) * (TX + 2) + (r - TX) + 1; }
+        else if (r < 2 * TX + TY) { hsite = (y0 + r - 2 * TX) * Lx + xleft; hlds = (r - 2 * TX + 1) * (TX + 2); }
+        else { hsite = (y0 + r - 2 * TX - TY) * Lx + xright; hlds = (r - 2 * TX - TY + 1) * (TX + 2) + TX + 1; }
+    }
+
+    const size_t colbase = (size_t)col * Ls * V;
+    const spinor<R>* src = in + colbase;
+    const int s0 = chunk * cs;
+    const int s1 = min(s0 + cs, Ls);
+    spinor<R> prv = src[(size_t)((s0 == 0) ? Ls - 1 : s0 - 1) * V + site];
+    if (s0 == 0) { prv.c0 = mwrap * prv.c0; prv.c1 = mwrap * prv.c1; }
+    spinor<R> cur = src[(size_t)s0 * V + site];
+    spinor<R> nxt = src[(size_t)((s0 + 1 == Ls) ? 0 : s0 + 1) * V + site];
+    typedef typename vec4_of<R>::type vec4;
+    vec4 hv = {};
+    if (ring) hv = load4(src + (size_t)s0 * V + hsite);
+    for (int s = s0; s < s1; ++s) {
+        spinor<R>(*bf)[TX + 2] = tile[s & 1];
+        bf[ly + 1][lx + 1] = cur;
+        if (ring) *reinterpret_cast<vec4*>(&bf[0][0] + hlds) = hv;
+        vec4 nn = {};
+        if (s + 1 < s1) {   // the same for the whole workgroup
+            const int sn = (s + 1 == Ls) ? 0 : s + 1;
+            const int s2 = (s + 2 >= Ls) ? s + 2 - Ls : s + 2;
+            nn = load4(src + (size_t)s2 * V + site);
+            if (ring) hv = load4(src + (size_t)sn * V + hsite);
+        }
+        __syncthreads();
+        const spinor<R> fx = bf[ly + 1][lx + 2], bx = bf[ly + 1][lx], fy = bf[ly + 2][lx + 1], by = bf[ly][lx + 1];
+        spinor<R> nx = nxt;
+        if (s + 1 == Ls) { nx.c0 = mwrap * nx.c0; nx.c1 = mwrap * nx.c1; }
+        spinor<R> res = dw_site<R, DAG>(fx, bx, fy, by, cur, prv, nx, hu0, hu0m, hu1, hu1m, diag);
+        const size_t o = colbase + (size_t)s * V + site;
+        if (RESID) {
+            const spinor<R> bb = b[o];
+            res.c0 = bb.c0 - res.c0;
+            res.c1 = bb.c1 - res.c1;
+        }
+        store_stream(out + o, res);
+        prv = cur;
+        cur = nxt;
+        nxt = unpack4<R>(nn);
+    }
+}
+
+// A launch configuration of D_DW: kernel shape (0: row kernel, k >= 1: tiled
+// kernel with kTiles[k-1]) and slice-chunk length, packed as shape * 4096 + cs.
+struct TileShape { int tx, ty; };
+static constexpr TileShape kTiles[] = {{64, 8}, {32, 16}, {128, 4}};
+static constexpr int kNumTiles = (int)(sizeof(kTiles) / sizeof(kTiles[0]));
+static constexpr int kCfgStride = 4096;
+
+static inline bool tile_fits(int shape, int Lx, int Ly) {
+    return shape >= 1 && shape <= kNumTiles && Lx % kTiles[shape - 1].tx == 0 && Ly % kTiles[shape - 1].ty == 0;
+}
+
+static inline int pick_cfg(int Lx, int Ly, int Ls, int ncol) {
+    // the first tile shape that divides the lattice, else the row kernel; chunks
+    // as long as possible while the grid still gives every CU several workgroups
     const long long want = 256LL * 64 * 16;
-    long long sites = (long long)Lx * Ly * ncol;
-    int cs = Ls;
+    const long long sites = (long long)Lx * Ly * ncol;
+    int shape = 0;
+    for (int k = 1; k <= kNumTiles && !shape; ++k)
+        if (tile_fits(k, Lx, Ly)) shape = k;
+    int cs = std::min(Ls, kCfgStride - 1);
     while (cs > 2 && sites * ((Ls + cs - 1) / cs) < want) cs = (cs + 1) / 2;
-    return cs;
+    return shape * kCfgStride + cs;
 }
 
 template <typename R>
 static hipError_t launch_fine(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b, int Lx, int Ly,
                               int Ls, int ncol, double m, double M5, bool dagger, const int* skip, int skip_stride,
-                              int cs, hipStream_t st);
+                              int cfg, hipStream_t st);
 
-// Chunk length (slices per thread) of the fine stencil, chosen by timing the
-// candidates once per shape and precision (DWF_AUTOTUNE=0 disables it); the
-// choices persist in the file named by DWF_TUNE_CACHE when that is set.
+// Launch configuration of the fine stencil (kernel shape and chunk length),
+// chosen by timing the candidates once per lattice shape, column count,
+// precision and adjoint flag (DWF_AUTOTUNE=0 disables it); the choices persist
+// in the file named by DWF_TUNE_CACHE when that is set.
 template <typename R>
-static int tuned_chunk(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int Ly, int Ls, int ncol,
-                       double m, double M5, bool dagger, hipStream_t st) {
+static int tuned_cfg(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int Ly, int Ls, int ncol,
+                     double m, double M5, bool dagger, hipStream_t st) {
     static std::mutex mu;
     static std::map<std::string, int> cache;
     static bool loaded = false;
-    const int heuristic = pick_chunk(Lx, Ly, Ls, ncol);
+    const int heuristic = pick_cfg(Lx, Ly, Ls, ncol);
     const char* en = std::getenv("DWF_AUTOTUNE");
     if (en && en[0] == '0') return heuristic;
     char keyb[128];
-    std::snprintf(keyb, sizeof keyb, "fine_dw/%zu/%d/%d/%d/%d/%d", sizeof(R), Lx, Ly, Ls, ncol, dagger ? 1 : 0);
+    std::snprintf(keyb, sizeof keyb, "fine_dw2/%zu/%d/%d/%d/%d/%d", sizeof(R), Lx, Ly, Ls, ncol, dagger ? 1 : 0);
     const std::string key(keyb);
     // inside a graph capture: use a choice already made, never time
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -183,16 +350,22 @@ static int tuned_chunk(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, i
     }
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
-    std::vector<int> cand;
+    std::vector<int> chunks;
     for (int c : {Ls, (Ls + 1) / 2, (Ls + 3) / 4, 8, 4, 2})
-        if (c >= 1 && c <= Ls && std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+        if (c >= 1 && c <= Ls && c < kCfgStride && std::find(chunks.begin(), chunks.end(), c) == chunks.end())
+            chunks.push_back(c);
+    std::vector<int> cand;
+    for (int shape = 0; shape <= kNumTiles; ++shape)
+        if (shape == 0 || tile_fits(shape, Lx, Ly))
+            for (int c : chunks) cand.push_back(shape * kCfgStride + c);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return heuristic;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return heuristic; }
     int best = heuristic;
     float best_t = 1e30f;
     for (int c : cand) {
-        (void)launch_fine<R>(U, in, out, nullptr, Lx, Ly, Ls, ncol, m, M5, dagger, nullptr, 1, c, st);
+        if (launch_fine<R>(U, in, out, nullptr, Lx, Ly, Ls, ncol, m, M5, dagger, nullptr, 1, c, st) != hipSuccess)
+            continue;
         (void)hipEventRecord(e0, st);
         for (int r = 0; r < 5; ++r)
             (void)launch_fine<R>(U, in, out, nullptr, Lx, Ly, Ls, ncol, m, M5, dagger, nullptr, 1, c, st);
@@ -211,25 +384,69 @@ static int tuned_chunk(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, i
     return best;
 }
 
+// configuration pinned by the caller (packed as above), or -1
+static std::atomic<int> g_fine_pin{-1};
+
+bool set_fine_config(int shape, int chunk) {
+    if (shape == -1) { g_fine_pin.store(-1); return true; }
+    if (shape < 0 || shape > kNumTiles || chunk < 1 || chunk >= kCfgStride) return false;
+    g_fine_pin.store(shape * kCfgStride + chunk);
+    return true;
+}
+
 template <typename R>
 hipError_t fine_dw(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b,
                    int Lx, int Ly, int Ls, int ncol, double m, double M5, bool dagger,
                    const int* skip, int skip_stride, hipStream_t st) {
-    const int cs = tuned_chunk<R>(U, in, out, Lx, Ly, Ls, ncol, m, M5, dagger, st);
-    return launch_fine<R>(U, in, out, b, Lx, Ly, Ls, ncol, m, M5, dagger, skip, skip_stride, cs, st);
+    const int pin = g_fine_pin.load(std::memory_order_relaxed);
+    int cfg;
+    if (pin >= 0 && (pin / kCfgStride == 0 || tile_fits(pin / kCfgStride, Lx, Ly)))
+        cfg = (pin / kCfgStride) * kCfgStride + std::min(pin % kCfgStride, Ls);
+    else
+        cfg = tuned_cfg<R>(U, in, out, Lx, Ly, Ls, ncol, m, M5, dagger, st);
+    return launch_fine<R>(U, in, out, b, Lx, Ly, Ls, ncol, m, M5, dagger, skip, skip_stride, cfg, st);
+}
+
+template <typename R, int TX, int TY>
+static hipError_t launch_tile(const cpx<R>* U, const spinor<R>* si, spinor<R>* so, const spinor<R>* sb, int Lx,
+                              int Ly, int Ls, int ncol, R diag, R mwrap, bool dagger, const int* skip,
+                              int skip_stride, int cs, hipStream_t st) {
+    if (Lx % TX || Ly % TY) return hipErrorInvalidValue;
+    const int nchunk = (Ls + cs - 1) / cs;
+    const int ntile = (Lx / TX) * (Ly / TY);
+    const long long nblocks = (long long)ntile * nchunk * ncol;
+    if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nblocks), block(TX * TY);
+    if (sb) {
+        if (dagger) hipLaunchKernelGGL((fine_tile_kernel<R, true, true, TX, TY>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, ntile, diag, mwrap);
+        else        hipLaunchKernelGGL((fine_tile_kernel<R, false, true, TX, TY>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, ntile, diag, mwrap);
+    } else {
+        if (dagger) hipLaunchKernelGGL((fine_tile_kernel<R, true, false, TX, TY>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, ntile, diag, mwrap);
+        else        hipLaunchKernelGGL((fine_tile_kernel<R, false, false, TX, TY>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, ntile, diag, mwrap);
+    }
+    return hipGetLastError();
 }
 
 template <typename R>
 static hipError_t launch_fine(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b, int Lx, int Ly,
                               int Ls, int ncol, double m, double M5, bool dagger, const int* skip, int skip_stride,
-                              int cs, hipStream_t st) {
-    const int nchunk = (Ls + cs - 1) / cs;
-    const int nsb = (Lx * Ly + kBlock - 1) / kBlock;
-    const long long nblocks = (long long)nsb * nchunk * ncol;
+                              int cfg, hipStream_t st) {
+    const int shape = cfg / kCfgStride, cs = cfg % kCfgStride;
+    if (cs < 1 || shape < 0 || shape > kNumTiles) return hipErrorInvalidValue;
     const R diag = R(2.0 + M5 + 1.0), mwrap = R(-m);
     auto* si = reinterpret_cast<const spinor<R>*>(in);
     auto* so = reinterpret_cast<spinor<R>*>(out);
     auto* sb = reinterpret_cast<const spinor<R>*>(b);
+    static_assert(kNumTiles == 3, "one case per tile shape");
+    switch (shape) {
+        case 1: return launch_tile<R, kTiles[0].tx, kTiles[0].ty>(U, si, so, sb, Lx, Ly, Ls, ncol, diag, mwrap, dagger, skip, skip_stride, cs, st);
+        case 2: return launch_tile<R, kTiles[1].tx, kTiles[1].ty>(U, si, so, sb, Lx, Ly, Ls, ncol, diag, mwrap, dagger, skip, skip_stride, cs, st);
+        case 3: return launch_tile<R, kTiles[2].tx, kTiles[2].ty>(U, si, so, sb, Lx, Ly, Ls, ncol, diag, mwrap, dagger, skip, skip_stride, cs, st);
+        default: break;
+    }
+    const int nchunk = (Ls + cs - 1) / cs;
+    const int nsb = (Lx * Ly + kBlock - 1) / kBlock;
+    const long long nblocks = (long long)nsb * nchunk * ncol;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
     dim3 grid((unsigned)nblocks), block(kBlock);
     if (b) {

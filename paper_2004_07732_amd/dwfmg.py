@@ -38,6 +38,7 @@ MG_OP_WILSON, MG_OP_WILSON_DAG, MG_OP_RESTRICT, MG_OP_PROLONG, MG_OP_KCYCLE = 5,
 COARSEST_CGNR, COARSEST_GCR = 0, 1
 KRYLOV_CGNR, KRYLOV_BICGSTAB = 0, 1
 TRANSFER_WALL, TRANSFER_BULK = 0, 1
+FINE_AUTO, FINE_ROW, FINE_TILE_64x8, FINE_TILE_32x16, FINE_TILE_128x4 = -1, 0, 1, 2, 3
 
 
 class DwfError(RuntimeError):
@@ -59,6 +60,7 @@ def lib() -> ctypes.CDLL:
         vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
         L.dwf_apply.argtypes = [vp, vp, vp, i, i, i, i, d, d, i, vp]
         L.dwf_pv_apply.argtypes = [vp, vp, vp, i, i, i, i, d, d, i, i, vp]
+        L.dwf_fine_config.argtypes = [i, i]
         L.dwf_wilson_apply.argtypes = [vp, vp, vp, i, i, i, d, i, vp]
         L.dwf_gamma5R.argtypes = [vp, vp, i, i, i, i, i, vp]
         L.dwf_gauge_transform.argtypes = [vp, vp, vp, vp, vp, i, i, i, i, vp]
@@ -84,7 +86,7 @@ def lib() -> ctypes.CDLL:
         L.dwf_release_scratch.argtypes = []
         L.dwf_strerror.argtypes = [i]
         L.dwf_strerror.restype = ctypes.c_char_p
-        for name in ("dwf_apply", "dwf_pv_apply", "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
+        for name in ("dwf_apply", "dwf_pv_apply", "dwf_fine_config", "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
                      "dwf_pack", "dwf_unpack", "dwf_force", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
                      "mg_time_op", "dwf_norm2", "mg_update_links", "mg_solve_batch",
                      "mg_level_info", "mg_deflation_info", "mg_destroy", "dwf_release_scratch",
@@ -267,6 +269,12 @@ def dwf_apply(U, psi, m_f, M5, dagger=False, out=None, stream=None):
     _check(lib().dwf_apply(_ptr(U), _ptr(psi), _ptr(out), Lx, Ly, Ls, nrhs, float(m_f), float(M5), flags,
                            _stream(stream)), "dwf_apply")
     return out
+
+
+def dwf_fine_config(shape, chunk=1):
+    """Pin the fine stencil's launch configuration for the process (FINE_ROW or a
+    FINE_TILE_* shape, `chunk` slices per thread); FINE_AUTO restores the tuned choice."""
+    _check(lib().dwf_fine_config(int(shape), int(chunk)), "dwf_fine_config")
 
 
 def dwf_pv_apply(U, psi, m_f, M5, mode=DWF_PVDAG_DW, out=None, stream=None):

@@ -41,6 +41,48 @@ def test_dwf_fp64_parity(Lx, Ly, Ls, nrhs, dagger):
     assert rel(got.cpu().numpy(), want) < 1e-13
 
 
+# lattices where every tile shape fits (128 x 16), where one tile is the whole
+# lattice so the halo ring wraps onto the tile itself (64 x 8, 128 x 4), and
+# chunks that leave ragged last chunks or a single slice per thread
+FINE_CFG_CASES = [((128, 16, 6, 2), (1, 2, 4, 6)), ((64, 8, 5, 1), (1, 2, 5)), ((128, 4, 3, 1), (1, 2, 3))]
+FINE_SHAPES = ["FINE_ROW", "FINE_TILE_64x8", "FINE_TILE_32x16", "FINE_TILE_128x4"]
+
+
+@pytest.mark.parametrize("case", range(len(FINE_CFG_CASES)))
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_fine_launch_configs_bitwise(case, dtype):
+    """Every launch configuration of the fine stencil (row kernel, LDS-tiled
+    shapes, chunk lengths) gives the same bits, and those match the oracle."""
+    (Lx, Ly, Ls, nrhs), chunks = FINE_CFG_CASES[case]
+    U = gauge(Lx, Ly, 300 + Lx + Ly)
+    psi = inputs.gaussian_field((nrhs, Ls, Ly, Lx, 2), 310 + Ls)
+    m, M5 = 0.02, -1.0
+    Ut, pt = torch.from_numpy(U).to(DEV).to(dtype), torch.from_numpy(psi).to(DEV).to(dtype)
+    try:
+        for dagger in (False, True):
+            want = O.dwf(U, psi, m, M5, dagger=dagger)
+            ref = None
+            for shape in FINE_SHAPES:
+                for c in chunks:
+                    dwfmg.dwf_fine_config(getattr(dwfmg, shape), c)
+                    got = dwfmg.dwf_apply(Ut, pt, m, M5, dagger=dagger)
+                    torch.cuda.synchronize()
+                    if ref is None:
+                        ref = got.clone()
+                        err = rel(got.cpu().numpy().astype(np.complex128), want)
+                        assert err < (1e-13 if dtype == torch.complex128 else 2e-6), err
+                    assert torch.equal(got, ref), (shape, c, dagger)
+    finally:
+        dwfmg.dwf_fine_config(dwfmg.FINE_AUTO)
+
+
+def test_fine_config_argument_errors():
+    for shape, chunk in ((7, 1), (-2, 1), (0, 0), (1, 4096)):
+        with pytest.raises(dwfmg.DwfError):
+            dwfmg.dwf_fine_config(shape, chunk)
+    dwfmg.dwf_fine_config(dwfmg.FINE_AUTO)
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_pv_modes_fp64_parity(mode):
     Lx, Ly, Ls, nrhs, m, M5 = 32, 24, 8, 2, 0.01, -1.0
