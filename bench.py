@@ -78,11 +78,11 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic(kernel_src, algorithmic_bytes):
-    """HBM traffic of the dominant kernel from the committed rocprofv3 counter
+def stored_traffic(kernel_src, algorithmic_bytes, summary="coarse_stencil_traffic.json"):
+    """HBM traffic per launch of a kernel from its committed rocprofv3 counter
     summary, or None when the kernel source or the launch shape changed since
     it was taken."""
-    p = os.path.join(ROOT, "profiles", "coarse_stencil_traffic.json")
+    p = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -156,30 +156,44 @@ def stats_dict(st):
             "fine_applies": st.fine_applies, "coarse_iters": st.level_iters, "coarse_calls": st.level_calls}
 
 
+# the HBM-bound fine stencil shape: 512^2 x Ls 32 x 4 rhs, FP32 (about 1.08 GB per apply)
+FINE_HBM_SHAPE = (512, 32, 4)
+
+
 def stencil_rows(dwfmg, inputs, torch, m, M5):
     """Fine D_DW bandwidth: (ii) 512^2 x 32 x 4 rhs FP32 (about 1.08 GB per apply,
     far above the 256 MB last-level cache) is the HBM figure; (i) 256^2 x 16
     one rhs FP32 / FP64 and (iii) 256^2 x 16 x 16 rhs FP32 beside it; and the
-    bandwidth of a plain 2 GiB device copy as the measured peak."""
+    bandwidth of a plain 2 GiB device copy as the measured peak.  Each figure is
+    50 back-to-back applies replayed from one HIP graph, timed with events."""
     def one(L, Ls, nr, dtype, seed):
         U = torch.from_numpy(inputs.links_from_theta(inputs.random_theta(L, L, seed))).cuda().to(dtype)
         psi = torch.randn((nr, Ls, L, L, 2), dtype=dtype, device="cuda")
         out = torch.empty_like(psi)
-        for _ in range(3):
+        for _ in range(3):   # the first call times the launch configurations
             dwfmg.dwf_apply(U, psi, m, M5, out=out)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        # the applies are replayed from a HIP graph, so that host launch overhead
+        # (larger than the kernel at the one-rhs 256^2 shape) is not timed
         reps = 50
+        graph, cap = torch.cuda.CUDAGraph(), torch.cuda.Stream()
+        with torch.cuda.graph(graph, stream=cap):
+            for _ in range(reps):
+                dwfmg.dwf_apply(U, psi, m, M5, out=out)
+        graph.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(reps):
-            dwfmg.dwf_apply(U, psi, m, M5, out=out)
+        graph.replay()
         e1.record()
         torch.cuda.synchronize()
         t_ms = e0.elapsed_time(e1) / reps
+        del graph
         esz = psi.element_size()
         sbytes = 2 * psi.numel() * esz + U.numel() * esz
         return {"shape": f"{L}^2 x {Ls} x {nr} rhs", "dtype": str(dtype).replace("torch.", ""), "us": t_ms * 1e3,
                 "bytes": sbytes, "GB_s": sbytes / (t_ms * 1e-3) / 1e9}
-    rows = {"ii_hbm": one(512, 32, 4, torch.complex64, 8_000_000),
+    rows = {"ii_hbm": one(*FINE_HBM_SHAPE, torch.complex64, 8_000_000),
             "i_fp32": one(256, 16, 1, torch.complex64, 8_000_001),
             "i_fp64": one(256, 16, 1, torch.complex128, 8_000_002),
             "iii_fp32_16rhs": one(256, 16, 16, torch.complex64, 8_000_003)}
@@ -200,6 +214,9 @@ def stencil_rows(dwfmg, inputs, torch, m, M5):
         r["frac_nominal"] = r["GB_s"] / PEAK_HBM_GBS
         r["frac_measured_copy"] = r["GB_s"] / copy_gbs
     rows["copy_2GiB_GB_s"] = copy_gbs
+    rows["ii_hbm"]["traffic"] = stored_traffic(
+        os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "fine_stencil.hip"), rows["ii_hbm"]["bytes"],
+        "fine_stencil_traffic.json")
     return rows
 
 
@@ -225,9 +242,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stencil", action="store_true", help="skip the fine-stencil bandwidth rows")
-    ap.add_argument("--counters", action="store_true",
-                    help="only run the dominant kernel (21 launches) next to a plain 256 MiB copy, for "
-                         "rocprofv3 --pmc runs; prints no benchmark line")
+    ap.add_argument("--counters", nargs="?", const="coarse", choices=["coarse", "fine"], default=None,
+                    help="only run one kernel (21 launches: the dominant coarse stencil, or with 'fine' the "
+                         "fine stencil at 512^2 x 32 x 4 rhs FP32 in a fixed launch configuration) "
+                         "next to a plain 256 MiB copy, for rocprofv3 --pmc runs; prints no benchmark line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -263,6 +281,28 @@ def main():
     for k, v in (("eig_degree", args.eig_degree), ("eig_maxit", args.eig_maxit), ("eig_tol", args.eig_tol)):
         if v is not None:
             head[k] = v
+
+    if args.counters == "fine":
+        Lf, Lsf, nrf = FINE_HBM_SHAPE
+        Uf = torch.from_numpy(inputs.links_from_theta(inputs.random_theta(Lf, Lf, 8_000_000))).cuda()
+        Uf = Uf.to(torch.complex64)
+        psi = torch.randn((nrf, Lsf, Lf, Lf, 2), dtype=torch.complex64, device="cuda")
+        out = torch.empty_like(psi)
+        # one fixed configuration (64 x 8 tiles, 8 slices per thread; among the tuner's
+        # equally fast choices at this shape) so that separate profiler runs see the same kernel
+        dwfmg.dwf_fine_config(dwfmg.FINE_TILE_64x8, 8)
+        dwfmg.dwf_apply(Uf, psi, m, M5, out=out)
+        torch.cuda.synchronize()
+        log("[bench] fine stencil: 21 launches follow")
+        for _ in range(21):
+            dwfmg.dwf_apply(Uf, psi, m, M5, out=out)
+        a = torch.ones(256 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+        bcopy = torch.empty_like(a)
+        for _ in range(5):
+            bcopy.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] counters run done: 21 fine stencil launches, 5 copies of 256 MiB")
+        return
 
     if args.counters:
         mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True, **head), starts)
