@@ -50,7 +50,10 @@ namespace {
 
 template <bool F16> struct Half;
 template <> struct Half<false> {   // bfloat16
-    static __device__ __forceinline__ uint32_t bits(float x) { return f32_to_bf16_bits(x); }
+    // round to nearest even by the hardware conversion (branch-free)
+    static __device__ __forceinline__ uint32_t bits(float x) {
+        return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)x);
+    }
     static __device__ __forceinline__ float value(uint32_t b) { return __uint_as_float(b << 16); }
     static __device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
@@ -82,11 +85,17 @@ __device__ __forceinline__ void load4(const cpx<T>* p, float (&re)[4], float (&i
 
 // B fragment for 4 complex inner entries from packed 16-bit pairs (re low, im
 // high): real-output columns take [re, -im], imaginary-output columns [im, re]
-// (the sign bit of both formats is bit 15).
-__device__ __forceinline__ u32x4 make_b(u32x4 u, bool imag_col) {
+// (the sign bit of both formats is bit 15).  `imag_mask` is all ones on lanes of
+// imaginary-output columns and zero elsewhere; the choice is made with bit
+// arithmetic, since a select on freshly loaded operands is compiled to branches.
+__device__ __forceinline__ u32x4 make_b(u32x4 u, uint32_t imag_mask) {
     u32x4 r;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) r[e] = imag_col ? ((u[e] >> 16) | (u[e] << 16)) : (u[e] ^ 0x80000000u);
+    for (int e = 0; e < 4; ++e) {
+        const uint32_t rot = (u[e] >> 16) | (u[e] << 16);
+        const uint32_t neg = u[e] ^ 0x80000000u;
+        r[e] = neg ^ ((neg ^ rot) & imag_mask);
+    }
     return r;
 }
 
@@ -114,6 +123,7 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
     const int C = Ls * ncol;
     const int q = lane & 15, kg = lane >> 4;
     const bool imag_col = q >= 8;
+    const uint32_t imag_mask = imag_col ? 0xffffffffu : 0u;
 
     int nb[5] = {0, 0, 0, 0, 0};
     if (valid_site) {
@@ -135,30 +145,41 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
     const int tid_in_site = threadIdx.x - sl * MT * 64;
     for (int t = 0; t < ntile; ++t) {
         const int cbase = TW * t;
-        // live columns of the tile as a bit mask, read once (no dependent loads in the staging loop)
-        unsigned live = 0;
-#pragma unroll
-        for (int c8 = 0; c8 < TW; ++c8) {
-            const int c = cbase + c8;
-            if (c < C && !(skip && skip[(size_t)(c / Ls) * sks])) live |= 1u << c8;
-        }
-        auto col_ok = [&](int c) { return ((live >> (c - cbase)) & 1u) != 0; };
         // stage the five neighbour vectors of columns cbase..cbase+TW-1, entries
-        // e = (d * TW + c8) * N + k; branch-free loads (dead columns read column 0
-        // and are zeroed), so that all of them are in flight together
+        // e = (d * TW + c8) * N + k.  The loads do not depend on the column flags
+        // (columns past the end read column 0), so all of them, and the flag load
+        // below, are in flight together; dead columns are zeroed afterwards.
+        cpx<T> v[PER];
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int e = tid_in_site + p * MT * 64;
+            const int k = e % N;
+            const int c8 = (e / N) % TW, d = (e / N) / TW;
+            const int c = (cbase + c8 < C) ? cbase + c8 : 0;
+            v[p] = in[((size_t)c * nsites + nb[d]) * N + k];
+        }
+        // live columns of the tile: lanes c8 < TW read one flag each, a ballot
+        // makes the mask (the same for the whole wavefront)
+        bool lane_live = false;
+        if (lane < TW) {
+            const int c = cbase + lane;
+            lane_live = c < C && !(skip && skip[(size_t)(c / Ls) * sks]);
+        }
+        const unsigned live = (unsigned)(__ballot(lane_live) & ((1ull << TW) - 1));
+        auto col_ok = [&](int c) { return ((live >> (c - cbase)) & 1u) != 0; };
         float vr[PER], vi[PER];
         float mx = 0.f;
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int e = tid_in_site + p * MT * 64;
             const int k = e % N;
-            const int dc = e / N;
-            const int c8 = dc % TW, d = dc / TW;
-            const bool use = valid_site && col_ok(cbase + c8);
-            const int c = use ? cbase + c8 : 0;
-            const cpx<T> v = in[((size_t)c * nsites + nb[d]) * N + k];
-            float re = use ? (float)v.re : 0.f, im = use ? (float)v.im : 0.f;
-            if (DAG && k >= H) { re = -re; im = -im; }
+            const int c8 = (e / N) % TW;
+            // dead columns zeroed and the sigma_3 sign of the adjoint applied on the bits
+            // (exact; selects on loaded values would again become branches)
+            const uint32_t keep = (valid_site && col_ok(cbase + c8)) ? 0xffffffffu : 0u;
+            const uint32_t sign = (DAG && k >= H) ? 0x80000000u : 0u;
+            const float re = __uint_as_float((__float_as_uint((float)v[p].re) & keep) ^ (sign & keep));
+            const float im = __uint_as_float((__float_as_uint((float)v[p].im) & keep) ^ (sign & keep));
             vr[p] = re;
             vi[p] = im;
             if (F16) mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
@@ -202,8 +223,8 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
                 const int off = (d * 8 + (q & 7)) * N + kd;
                 const u32x4 uh = *reinterpret_cast<const u32x4*>(&sB[sl][0][off]);
                 const u32x4 ul = *reinterpret_cast<const u32x4*>(&sB[sl][1][off]);
-                acc = HF::mma(a[ks], make_b(uh, imag_col), acc);
-                acc = HF::mma(a[ks], make_b(ul, imag_col), acc);
+                acc = HF::mma(a[ks], make_b(uh, imag_mask), acc);
+                acc = HF::mma(a[ks], make_b(ul, imag_mask), acc);
             }
         }
         // lanes q and q^8 hold the real and imaginary parts of the same outputs
