@@ -6,7 +6,7 @@
 //                                                       c: coarse slice x right-hand side)
 // with complex entries.  In real arithmetic, with the inner index split as
 // (k, re/im), the link rows are used as stored (interleaved complex) and the
-// vector side is rebuilt on the fly:
+// vector side takes the two forms
 //   [Re out | Im out] = [Yr Yi] . [[ psi_r, psi_i], [-psi_i, psi_r]],
 // so one 16x16x32 matrix instruction covers 16 rows x 8 complex columns x 16
 // complex inner entries.  The vector is split into two 16-bit parts (hi + lo)
@@ -22,9 +22,10 @@
 // apply, with all loads in flight together) and keeps them in registers while
 // it walks the column tiles (8 columns, or 4 when there are at most 4).  The
 // five neighbour vectors of a column tile are staged once per site in LDS,
-// already split, and read back as 16-byte fragments; the staging loads are
-// branch-free (dead columns read a valid address and are zeroed) so that the
-// compiler keeps them all in flight.
+// already split and in both forms above (each entry converted by one thread,
+// instead of every reading lane rearranging its fragments), and read back as
+// 16-byte fragments; the staging loads are branch-free (dead columns read a
+// valid address and are zeroed) so that the compiler keeps them all in flight.
 //
 // Links layout for this kernel: in fragment order, so that every load of a
 // wave reads 1 KB contiguous: [site][row tile m][inner step ks][lane][4] with
@@ -83,22 +84,6 @@ __device__ __forceinline__ void load4(const cpx<T>* p, float (&re)[4], float (&i
     }
 }
 
-// B fragment for 4 complex inner entries from packed 16-bit pairs (re low, im
-// high): real-output columns take [re, -im], imaginary-output columns [im, re]
-// (the sign bit of both formats is bit 15).  `imag_mask` is all ones on lanes of
-// imaginary-output columns and zero elsewhere; the choice is made with bit
-// arithmetic, since a select on freshly loaded operands is compiled to branches.
-__device__ __forceinline__ u32x4 make_b(u32x4 u, uint32_t imag_mask) {
-    u32x4 r;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const uint32_t rot = (u[e] >> 16) | (u[e] << 16);
-        const uint32_t neg = u[e] ^ 0x80000000u;
-        r[e] = neg ^ ((neg ^ rot) & imag_mask);
-    }
-    return r;
-}
-
 }  // namespace
 
 template <bool F16, typename T, int N, bool DAG, int TW>
@@ -111,9 +96,13 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
     constexpr int SPB = (MT >= 4) ? 1 : 4 / MT;   // sites per block
     constexpr int KS = 5 * N / 16;                // inner steps of 16 complex entries
     constexpr int H = N / 2;                      // chirality boundary (sigma_3)
-    constexpr int SLAB = 5 * 8 * N;               // LDS entries per site and part (d, c8, k)
+    constexpr int SLAB = 5 * 8 * N;               // LDS entries per site, part and form (d, c8, k)
     constexpr int PER = 5 * TW * N / (MT * 64);   // staged entries per thread (TW columns per tile)
-    __shared__ __attribute__((aligned(16))) uint32_t sB[SPB][2][SLAB];   // [site][hi/lo][(d*8 + c8)*N + k]
+    // staged vectors as B fragments, [site][hi/lo][form][(d*8 + c8)*N + k], each entry a
+    // complex 16-bit pair in the order the matrix instruction takes it: form 0 feeds the
+    // real-output columns ([re, -im]), form 1 the imaginary-output columns ([im, re]), so
+    // the lanes read their operands ready-made
+    __shared__ __attribute__((aligned(16))) uint32_t sB[SPB][2][2][SLAB];
     __shared__ float smax[SPB][MT];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -123,7 +112,7 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
     const int C = Ls * ncol;
     const int q = lane & 15, kg = lane >> 4;
     const bool imag_col = q >= 8;
-    const uint32_t imag_mask = imag_col ? 0xffffffffu : 0u;
+    const int form = imag_col ? 1 : 0;
 
     int nb[5] = {0, 0, 0, 0, 0};
     if (valid_site) {
@@ -208,8 +197,10 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
                 const float re = vr[p] * scale, im = vi[p] * scale;
                 const uint32_t hre = HF::bits(re), him = HF::bits(im);
                 const uint32_t lre = HF::bits(re - HF::value(hre)), lim = HF::bits(im - HF::value(him));
-                sB[sl][0][o] = hre | (him << 16);
-                sB[sl][1][o] = lre | (lim << 16);
+                sB[sl][0][0][o] = hre | ((him ^ 0x8000u) << 16);
+                sB[sl][0][1][o] = him | (hre << 16);
+                sB[sl][1][0][o] = lre | ((lim ^ 0x8000u) << 16);
+                sB[sl][1][1][o] = lim | (lre << 16);
             }
         }
         __syncthreads();
@@ -221,10 +212,10 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
                 const int d = (ks * 16) / N;
                 const int kd = (ks * 16) % N + 4 * kg;
                 const int off = (d * 8 + (q & 7)) * N + kd;
-                const u32x4 uh = *reinterpret_cast<const u32x4*>(&sB[sl][0][off]);
-                const u32x4 ul = *reinterpret_cast<const u32x4*>(&sB[sl][1][off]);
-                acc = HF::mma(a[ks], make_b(uh, imag_mask), acc);
-                acc = HF::mma(a[ks], make_b(ul, imag_mask), acc);
+                const u32x4 uh = *reinterpret_cast<const u32x4*>(&sB[sl][0][form][off]);
+                const u32x4 ul = *reinterpret_cast<const u32x4*>(&sB[sl][1][form][off]);
+                acc = HF::mma(a[ks], uh, acc);
+                acc = HF::mma(a[ks], ul, acc);
             }
         }
         // lanes q and q^8 hold the real and imaginary parts of the same outputs
