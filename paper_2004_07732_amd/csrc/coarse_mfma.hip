@@ -20,7 +20,8 @@
 // Work split: one wavefront per (coarse site, 16-row tile).  A wave loads all
 // of its link fragments up front (every link element is read exactly once per
 // apply, with all loads in flight together) and keeps them in registers while
-// it walks the column tiles (8 columns, or 4 when there are at most 4).  The
+// it walks the column tiles (8 columns, or 4 or 2 when there are at most that
+// many).  The
 // five neighbour vectors of a column tile are staged once per site in LDS,
 // already split and in both forms above (each entry converted by one thread,
 // instead of every reading lane rearranging its fragments), and read back as
@@ -96,9 +97,9 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
     constexpr int SPB = (MT >= 4) ? 1 : 4 / MT;   // sites per block
     constexpr int KS = 5 * N / 16;                // inner steps of 16 complex entries
     constexpr int H = N / 2;                      // chirality boundary (sigma_3)
-    constexpr int SLAB = 5 * 8 * N;               // LDS entries per site, part and form (d, c8, k)
-    constexpr int PER = 5 * TW * N / (MT * 64);   // staged entries per thread (TW columns per tile)
-    // staged vectors as B fragments, [site][hi/lo][form][(d*8 + c8)*N + k], each entry a
+    constexpr int SLAB = 5 * TW * N;              // LDS entries per site, part and form (d, c8, k)
+    constexpr int PER = (SLAB + MT * 64 - 1) / (MT * 64);   // staged entries per thread (the last may be partial)
+    // staged vectors as B fragments, [site][hi/lo][form][(d*TW + c8)*N + k], each entry a
     // complex 16-bit pair in the order the matrix instruction takes it: form 0 feeds the
     // real-output columns ([re, -im]), form 1 the imaginary-output columns ([im, re]), so
     // the lanes read their operands ready-made
@@ -122,12 +123,13 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         nb[0] = site; nb[1] = y * Lx + xp; nb[2] = y * Lx + xm; nb[3] = yp * Lx + x; nb[4] = ym * Lx + x;
     }
 
-    // all link fragments of this wave's 16 rows, loaded once
+    // all link fragments of this wave's 16 rows, loaded once (32-bit offsets from
+    // the uniform base pointers: the launcher keeps every array under 4 GiB)
     u32x4 a[KS];
     if (valid_site) {
-        const u32x4* lf = links + ((size_t)site * MT + m) * KS * 64 + lane;
+        const uint32_t lf = ((uint32_t)site * MT + m) * KS * 64 + lane;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) a[ks] = lf[ks * 64];
+        for (int ks = 0; ks < KS; ++ks) a[ks] = links[lf + ks * 64];
     }
 
     const int ntile = (C + TW - 1) / TW;
@@ -141,18 +143,18 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         cpx<T> v[PER];
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
-            const int e = tid_in_site + p * MT * 64;
+            const int e = min(tid_in_site + p * MT * 64, SLAB - 1);   // (past the end: a repeat, not stored)
             const int k = e % N;
             const int c8 = (e / N) % TW, d = (e / N) / TW;
             const int c = (cbase + c8 < C) ? cbase + c8 : 0;
-            v[p] = in[((size_t)c * nsites + nb[d]) * N + k];
+            v[p] = in[((uint32_t)c * nsites + nb[d]) * N + k];
         }
         // live columns of the tile: lanes c8 < TW read one flag each, a ballot
         // makes the mask (the same for the whole wavefront)
         bool lane_live = false;
         if (lane < TW) {
             const int c = cbase + lane;
-            lane_live = c < C && !(skip && skip[(size_t)(c / Ls) * sks]);
+            lane_live = c < C && !(skip && skip[(uint32_t)(c / Ls) * sks]);
         }
         const unsigned live = (unsigned)(__ballot(lane_live) & ((1ull << TW) - 1));
         auto col_ok = [&](int c) { return ((live >> (c - cbase)) & 1u) != 0; };
@@ -160,7 +162,7 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         float mx = 0.f;
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
-            const int e = tid_in_site + p * MT * 64;
+            const int e = min(tid_in_site + p * MT * 64, SLAB - 1);
             const int k = e % N;
             const int c8 = (e / N) % TW;
             // dead columns zeroed and the sigma_3 sign of the adjoint applied on the bits
@@ -191,27 +193,27 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         if (valid_site) {
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
-                const int e = tid_in_site + p * MT * 64;
-                const int k = e % N, dc = e / N;
-                const int o = ((dc / TW) * 8 + dc % TW) * N + k;   // LDS slot (d * 8 + c8) * N + k
+                const int e = tid_in_site + p * MT * 64;   // LDS slot (d * TW + c8) * N + k
                 const float re = vr[p] * scale, im = vi[p] * scale;
                 const uint32_t hre = HF::bits(re), him = HF::bits(im);
                 const uint32_t lre = HF::bits(re - HF::value(hre)), lim = HF::bits(im - HF::value(him));
-                sB[sl][0][0][o] = hre | ((him ^ 0x8000u) << 16);
-                sB[sl][0][1][o] = him | (hre << 16);
-                sB[sl][1][0][o] = lre | ((lim ^ 0x8000u) << 16);
-                sB[sl][1][1][o] = lim | (lre << 16);
+                if ((p + 1) * MT * 64 <= SLAB || e < SLAB) {
+                    sB[sl][0][0][e] = hre | ((him ^ 0x8000u) << 16);
+                    sB[sl][0][1][e] = him | (hre << 16);
+                    sB[sl][1][0][e] = lre | ((lim ^ 0x8000u) << 16);
+                    sB[sl][1][1][e] = lim | (lre << 16);
+                }
             }
         }
         __syncthreads();
-        // (with TW = 4 the LDS columns 4..7 hold stale values that feed only unused outputs)
+        // (with TW < 8 the B columns TW..7 repeat staged columns and feed only unused outputs)
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         if (valid_site) {
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 const int d = (ks * 16) / N;
                 const int kd = (ks * 16) % N + 4 * kg;
-                const int off = (d * 8 + (q & 7)) * N + kd;
+                const int off = (d * TW + (q & 7) % TW) * N + kd;
                 const u32x4 uh = *reinterpret_cast<const u32x4*>(&sB[sl][0][form][off]);
                 const u32x4 ul = *reinterpret_cast<const u32x4*>(&sB[sl][1][form][off]);
                 acc = HF::mma(a[ks], uh, acc);
@@ -232,12 +234,11 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         float f = 1.f;
         if (from_up) { so = s + 1; if (so == Ls) { so = 0; f = mwrap; } }
         else         { so = s - 1; if (so < 0) { so = Ls - 1; f = mwrap; } }
-        float cr[4], ci[4], hr[4], hi[4];
-        const int sv = valid_site ? site : 0;
-        load4<T>(in + ((size_t)c * nsites + sv) * N + i0, cr, ci);
-        load4<T>(in + ((size_t)(rhs * Ls + so) * nsites + sv) * N + i0, hr, hi);
-        if (wr) {
-            cpx<T>* dst = out + ((size_t)c * nsites + site) * N + i0;
+        if (wr) {   // (only the writing lanes load the site-local terms)
+            float cr[4], ci[4], hr[4], hi[4];
+            load4<T>(in + ((uint32_t)c * nsites + site) * N + i0, cr, ci);
+            load4<T>(in + ((uint32_t)(rhs * Ls + so) * nsites + site) * N + i0, hr, hi);
+            cpx<T>* dst = out + ((uint32_t)c * nsites + site) * N + i0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 float re = acc[e] * unscale, im = p[e] * unscale;
@@ -262,7 +263,14 @@ hipError_t launch_n(const void* links, const cpx<T>* in, cpx<T>* out, const Coar
     dim3 grid((nsites + SPB - 1) / SPB), block(64 * MT * SPB);
     const u32x4* lk = reinterpret_cast<const u32x4*>(links);
     const float cd = (float)(M5 + 1.0), mw = (float)(-m);
-    if (g.Ls * ncol <= 4) {   // one tile of 4 columns (one right-hand side on 4 coarse slices)
+    // the kernel indexes the vectors and links with 32-bit offsets
+    const double vec_bytes = (double)g.Ls * ncol * nsites * N * sizeof(cpx<T>);
+    const double link_bytes = (double)nsites * 5 * N * N * 4;
+    if (vec_bytes >= 4294967296.0 || link_bytes >= 4294967296.0) return hipErrorInvalidValue;
+    if (g.Ls * ncol <= 2) {   // one tile of 2 columns (one right-hand side on 2 coarse slices)
+        if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true, 2>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
+        else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, false, 2>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
+    } else if (g.Ls * ncol <= 4) {   // one tile of 4 columns
         if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true, 4>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
         else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, false, 4>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
     } else {
