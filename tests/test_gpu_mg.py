@@ -167,13 +167,17 @@ def bf16_stencil(S, prec="bf16"):
     return O.Stencil(diag=r(S.diag), hop=r(S.hop), chir=S.chir)
 
 
-@pytest.mark.parametrize("nvec,ncol,vec_prec,block", [(8, 1, "f64", (4, 4)), (16, 1, "f64", (4, 4)),
-                                                       (16, 3, "f32", (4, 4)), (8, 17, "f32", (4, 4)),
-                                                       (24, 2, "f64", (8, 4)), (32, 1, "f32", (8, 4)),
-                                                       (6, 2, "f64", (4, 4))])
+@pytest.mark.parametrize("nvec,ncol,vec_prec,block,Lsc", [(8, 1, "f64", (4, 4), 4), (16, 1, "f64", (4, 4), 4),
+                                                           (16, 3, "f32", (4, 4), 4), (8, 17, "f32", (4, 4), 4),
+                                                           (24, 2, "f64", (8, 4), 4), (32, 1, "f32", (8, 4), 4),
+                                                           (6, 2, "f64", (4, 4), 4),
+                                                           # one tile of at most 2 columns
+                                                           (16, 1, "f64", (4, 4), 2), (16, 1, "f32", (4, 4), 2),
+                                                           (24, 1, "f64", (8, 4), 2), (8, 1, "f64", (4, 4), 2),
+                                                           (16, 2, "f64", (4, 4), 2)])
 @pytest.mark.parametrize("op", ["dw", "dw_dag", "A"])
 @pytest.mark.parametrize("lprec", ["bf16", "f16"])
-def test_coarse_bf16_matrix_core_parity(nvec, ncol, vec_prec, block, op, lprec):
+def test_coarse_bf16_matrix_core_parity(nvec, ncol, vec_prec, block, Lsc, op, lprec):
     """The BF16 / FP16 coarse operator (matrix cores when 2 nvec is a multiple
     of 16, vector ALUs otherwise) against the oracle's coarse operator built on
     the same links rounded to the storage format."""
@@ -183,13 +187,13 @@ def test_coarse_bf16_matrix_core_parity(nvec, ncol, vec_prec, block, op, lprec):
     starts = [inputs.gaussian_field((nvec, L, L, 2), 371)]
     vp = dwfmg.P_F64 if vec_prec == "f64" else dwfmg.P_F32
     lp = dwfmg.P_BF16 if lprec == "bf16" else dwfmg.P_F16
-    params = dwfmg.MGParams(nvec=[nvec], block=[block], Ls_coarse=[4], link_prec=[lp],
+    params = dwfmg.MGParams(nvec=[nvec], block=[block], Ls_coarse=[Lsc], link_prec=[lp],
                             vec_prec=[vp], setup_iters=0)
     mg = dwfmg.MG(T(U), Ls, m, M5, params, [T(s) for s in starts])
-    oparams = O.MGParams(levels=[O.LevelParams(nvec=nvec, block=(by, bx), Ls=4, setup_iters=0)])
+    oparams = O.MGParams(levels=[O.LevelParams(nvec=nvec, block=(by, bx), Ls=Lsc, setup_iters=0)])
     omg = O.MG(U, Ls, m, M5, oparams, starts)
     Sb = bf16_stencil(omg.levels[1].S, lprec)
-    x = inputs.gaussian_field((ncol, 4, L // by, L // bx, 2 * nvec), 372)
+    x = inputs.gaussian_field((ncol, Lsc, L // by, L // bx, 2 * nvec), 372)
     if vec_prec == "f32":
         x = x.astype(np.complex64).astype(np.complex128)
     code = {"dw": dwfmg.MG_OP_DW, "dw_dag": dwfmg.MG_OP_DW_DAG, "A": dwfmg.MG_OP_A}[op]
