@@ -139,6 +139,60 @@ def pv_dag_dw_dagger(U: np.ndarray, psi: np.ndarray, m: float, M5: float) -> np.
     return dwf(U, pv(U, psi, M5), m, M5, dagger=True)
 
 
+def pv_normal(U: np.ndarray, psi: np.ndarray, M5: float) -> np.ndarray:
+    """X = D_PV D_PV^dagger, the operator whose inverse the PV preconditioning
+    of Sec. 2.3 truncates to 1 (eq. NormalExp)."""
+    return pv(U, pv(U, psi, M5, dagger=True), M5)
+
+
+def pv_poly_dw(U: np.ndarray, psi: np.ndarray, m: float, M5: float, c, dagger: bool = False) -> np.ndarray:
+    """Polynomial correction of the PV preconditioning (the remark after
+    eq. NormalExp and the expansion at the end of App. A): (D_PV D_PV^dag)^{-1}
+    is replaced by p(X) = sum_k c_k X^k instead of by 1, giving
+        A_p = D_PV^dagger p(X) D_DW(m),     c = (1): A of the paper;
+        A_p^dagger = D_DW(m)^dagger p(X) D_PV   (p(X) is Hermitian for real c).
+    The powers of X are summed term by term."""
+    w = pv(U, psi, M5) if dagger else dwf(U, psi, m, M5)
+    y = np.zeros_like(w)
+    Xk = w
+    for k, ck in enumerate(c):
+        if k > 0:
+            Xk = pv_normal(U, Xk, M5)
+        y = y + ck * Xk
+    return dwf(U, y, m, M5, dagger=True) if dagger else pv(U, y, M5, dagger=True)
+
+
+def pv_poly_neumann(order: int):
+    """c_k of the expansion of (1 + A_PV)^{-1}, A_PV = X - 1, truncated after
+    A_PV^order and rewritten in powers of X (App. A): order 0 gives (1), order 1
+    the paper's (2, -1)."""
+    c = np.zeros(order + 1)
+    for j in range(order + 1):          # (-1)^j (X - 1)^j
+        for k in range(j + 1):
+            c[k] += (-1) ** j * math.comb(j, k) * (-1) ** (j - k)
+    return c
+
+
+def pv_poly_chebyshev(order: int, lam_min: float, lam_max: float):
+    """c_k of the polynomial p of degree `order` that minimises max |1 - x p(x)|
+    over [lam_min, lam_max]: 1 - x p(x) = T_{n}(t(x)) / T_{n}(t(0)), n = order + 1,
+    t(x) = (lam_max + lam_min - 2 x) / (lam_max - lam_min).  READING: the paper
+    asks for the coefficients to be weighted over the whole spectrum (App. A)
+    without fixing a weighting; this minimax choice keeps x p(x) in (0, 2) on
+    the interval, so A_p stays in the right half plane where A is."""
+    from numpy.polynomial import chebyshev as npc
+    from numpy.polynomial import polynomial as npp
+    n = order + 1
+    a = (lam_max + lam_min) / (lam_max - lam_min)
+    b = -2.0 / (lam_max - lam_min)
+    tn = npc.cheb2poly([0.0] * n + [1.0])      # T_n(t) as a power series in t
+    r = np.zeros(1)
+    for coef in tn[::-1]:                       # Horner in t = a + b x
+        r = npp.polyadd(npp.polymul(r, [a, b]), [coef])
+    r = r / r[0]                                # r(x) = 1 - x p(x), r(0) = 1
+    return -np.asarray(r[1:], dtype=np.float64)
+
+
 def gamma5_field(psi: np.ndarray) -> np.ndarray:
     return spin_mul(GAMMA5, psi)
 

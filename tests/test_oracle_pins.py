@@ -631,3 +631,96 @@ def test_metropolis_plaquette_matches_exact_result():
     exact = scipy.special.i1(beta) / scipy.special.i0(beta)
     assert abs(mean - exact) < 0.01
     assert 0.2 < g.acceptance < 0.95
+
+
+# ----------------------------------------------------------------------------- polynomial PV correction
+def test_pv_poly_order_zero_is_the_paper_operator():
+    """c = (1): the polynomial-corrected operator is A = D_PV^dag D_DW (Sec. 2.3)."""
+    U = hot_links(6, 4, 41)
+    psi = cgauss((5, 4, 6, 2), 42)
+    assert np.array_equal(O.pv_poly_dw(U, psi, 0.05, -1.0, [1.0]), O.pv_dag_dw(U, psi, 0.05, -1.0))
+    assert np.array_equal(O.pv_poly_dw(U, psi, 0.05, -1.0, [1.0], dagger=True),
+                          O.pv_dag_dw_dagger(U, psi, 0.05, -1.0))
+
+
+def test_pv_poly_free_plane_waves():
+    """Free field: on chi e^{ip.x} the operator acts as the momentum-space product
+    M_PV^dag p(M_PV M_PV^dag) M_DW (and M_DW^dag p(.) M_PV for the adjoint), with
+    the 2 Ls x 2 Ls blocks of eq. DWoperator at momentum p."""
+    Lx, Ly, Ls, m, M5 = 4, 6, 4, 0.03, -1.0
+    U = np.ones((2, Ly, Lx), dtype=np.complex128)
+    c = [0.7, -0.2, 0.05]
+    for (kx, ky) in [(0, 0), (1, 2), (3, 5)]:
+        p = (2 * math.pi * kx / Lx, 2 * math.pi * ky / Ly)
+        Mdw = free_dw_block(p, Ls, m, M5)
+        Mpv = free_dw_block(p, Ls, 1.0, M5)
+        X = Mpv @ Mpv.conj().T
+        P = sum(ck * np.linalg.matrix_power(X, k) for k, ck in enumerate(c))
+        chi = cgauss((Ls, 2), 50 + kx * 10 + ky)
+        pw = plane_wave(Lx, Ly, p)
+        psi = pw[None, :, :, None] * chi[:, None, None, :]
+        for dag, M in ((False, Mpv.conj().T @ P @ Mdw), (True, Mdw.conj().T @ P @ Mpv)):
+            got = O.pv_poly_dw(U, psi, m, M5, c, dagger=dag)
+            want = pw[None, :, :, None] * (M @ chi.reshape(-1)).reshape(Ls, 2)[:, None, None, :]
+            assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_pv_poly_neumann_truncation_gains_two_powers_of_momentum():
+    """App. A: truncating the expansion of (1 + A_PV)^{-1}, A_PV = D_PV D_PV^dag - 1,
+    after one more term corrects D_PV^{-1} ~ D_PV^dag p(D_PV D_PV^dag) by another two
+    powers of p; the second-order coefficients are the printed (2, -1)."""
+    assert np.array_equal(O.pv_poly_neumann(0), [1.0])
+    assert np.array_equal(O.pv_poly_neumann(1), [2.0, -1.0])
+    Ls, M5 = 8, -1.0
+
+    def err(q, c):
+        Mpv = free_dw_block((q, 0.5 * q), Ls, 1.0, M5)
+        X = Mpv @ Mpv.conj().T
+        P = sum(ck * np.linalg.matrix_power(X, k) for k, ck in enumerate(c))
+        return np.linalg.norm(Mpv.conj().T @ P - np.linalg.inv(Mpv), 2)
+
+    for order in (0, 1, 2):
+        c = O.pv_poly_neumann(order)
+        slope = math.log2(err(0.1, c) / err(0.05, c))
+        assert abs(slope - 2 * (order + 1)) < 0.1, (order, slope)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_pv_poly_chebyshev_is_minimax_and_positive(order):
+    """The weighted coefficients: 1 - x p(x) equioscillates with the bound
+    1 / T_n((b + a)/(b - a)), n = order + 1, on [a, b] (the Chebyshev minimax
+    property), so x p(x) stays in (0, 2) there."""
+    lo, hi = 1.0, 25.0
+    c = O.pv_poly_chebyshev(order, lo, hi)
+    x = np.linspace(lo, hi, 200001)
+    xp = x * np.polynomial.polynomial.polyval(x, c)
+    bound = 1.0 / math.cosh((order + 1) * math.acosh((hi + lo) / (hi - lo)))
+    dev = np.abs(1.0 - xp)
+    assert dev.max() <= bound * (1 + 1e-9)
+    assert dev.max() >= bound * (1 - 1e-6)
+    assert np.all(xp > 0) and np.all(xp < 2)
+    # the extremes alternate in sign at order + 2 points
+    ext = np.linspace(0, 1, order + 2) * math.pi
+    xe = 0.5 * (hi + lo) - 0.5 * (hi - lo) * np.cos(ext)
+    re = 1.0 - xe * np.polynomial.polynomial.polyval(xe, c)
+    assert np.allclose(np.abs(re), bound, rtol=1e-9)
+    assert np.all(np.sign(re[1:]) == -np.sign(re[:-1]))
+
+
+def test_second_order_truncation_is_not_positive_on_the_free_spectrum():
+    """App. A warns that 2 - D_PV D_PV^dag is not positive definite: on the free
+    field (M5 = -1) the squared singular values of D_PV reach past 2 (towards 25),
+    while the minimax polynomial on [1, 25] keeps x p(x) > 0 over all of them."""
+    Lx, Ly, Ls = 8, 8, 8
+    sig2 = []
+    for kx in range(Lx):
+        for ky in range(Ly):
+            a = [2 * math.sin(math.pi * kx / Lx) ** 2, 2 * math.sin(math.pi * ky / Ly) ** 2]
+            for n in range(Ls):
+                p5 = math.pi * (2 * n + 1) / Ls
+                sig2.append(1 + sum(a) ** 2 - sum(v * v for v in a) + 2 * sum(a) * (1 + math.cos(p5)))
+    sig2 = np.array(sig2)
+    assert sig2.min() >= 1 - 1e-12 and sig2.max() < 25
+    assert np.any(2 - sig2 < 0)
+    c = O.pv_poly_chebyshev(1, 1.0, 25.0)
+    assert np.all(sig2 * np.polynomial.polynomial.polyval(sig2, c) > 0)
