@@ -67,6 +67,7 @@ extern "C" {
 #define DWF_P_F16   3          /* coarse links only: binary16 storage, FP32 arithmetic */
 
 #define DWF_MAX_LEVELS 3       /* coarse levels below the fine one                   */
+#define DWF_PV_POLY_MAX 3      /* highest power of D_PV D_PV^dag in the PV polynomial */
 
 /* transfer between levels */
 #define DWF_TRANSFER_WALL 0
@@ -109,6 +110,27 @@ int dwf_fine_config(int shape, int chunk);
  * and kept until dwf_release_scratch).  Same layout rules as dwf_apply. */
 int dwf_pv_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs,
                  double m_f, double M5, int mode, int flags, void* stream);
+
+/* Polynomial correction of the PV preconditioning (the remark after eq.
+ * NormalExp; App. A): out = D_PV^dag p(D_PV D_PV^dag) D_DW(m_f) psi with
+ * p(X) = sum_{k=0}^{order} c[k] X^k (host array of order + 1 real coefficients,
+ * 0 <= order <= DWF_PV_POLY_MAX); with DWF_DAGGER the adjoint
+ * D_DW(m_f)^dag p(D_PV D_PV^dag) D_PV psi.  order = 0 with c = {1} is
+ * DWF_PVDAG_DW.  2 order + 2 stencil applications (Horner's scheme); three
+ * library-owned intermediate fields as for dwf_pv_apply.  Same layout rules as
+ * dwf_apply; DWF_EINVAL for a bad order, null or non-finite coefficients. */
+int dwf_pv_poly_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs,
+                      double m_f, double M5, const double* c, int order, int flags, void* stream);
+
+/* Coefficients c[0..order] (host array) of the polynomial p of degree `order`
+ * that minimises max |1 - x p(x)| over [lam_min, lam_max] (1 - x p(x) is the
+ * scaled Chebyshev polynomial T_{order+1}), a weighting of the correction over
+ * the whole spectrum, as App. A asks for; x p(x) then lies in (0, 2) on the
+ * interval.  For D_PV D_PV^dag take lam_min = 1 (its spectrum starts there, App.
+ * A) and lam_max its largest eigenvalue (25 on the free field at M5 = -1).
+ * Host only.  DWF_EINVAL unless 0 <= order <= DWF_PV_POLY_MAX and
+ * 0 < lam_min < lam_max. */
+int dwf_pv_poly_chebyshev(int order, double lam_min, double lam_max, double* c);
 
 /* out = D_W(M) psi (or its adjoint) on 2-d fields [nrhs][Ly][Lx][2] (Sec. 2). */
 int dwf_wilson_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int nrhs,
@@ -189,6 +211,16 @@ typedef struct {
                                              prolongator on every slice (Sec. 4.1's
                                              alternative; needs Ls_coarse equal to the
                                              finer level's Ls on every level)          */
+    int    pv_poly_order;                 /* 0: the fine-level operator is the paper's
+                                             A = D_PV^dag D_DW; K = 1..DWF_PV_POLY_MAX:
+                                             A_p = D_PV^dag p(D_PV D_PV^dag) D_DW with
+                                             p(X) = sum_{k<=K} pv_poly[k] X^k (the
+                                             correction the paper leaves for future
+                                             work, Sec. 2.3 and App. A); the outer
+                                             solve, the smoother and the right-hand side
+                                             D_PV^dag p(.) r all use it; coarse levels
+                                             are unchanged                              */
+    double pv_poly[DWF_PV_POLY_MAX + 1];  /* c_0..c_K (see dwf_pv_poly_chebyshev)     */
 } dwf_mg_params;
 
 typedef struct {

@@ -68,6 +68,33 @@ int pv_apply_t(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls
     }
 }
 
+// out = D_PV^dag p(X) D_DW psi (or D_DW^dag p(X) D_PV psi), X = D_PV D_PV^dag,
+// p(X) w by Horner's scheme: y = c_K w, then y = c_k w + X y for k = K-1..0
+template <typename R>
+int pv_poly_apply_t(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, double m,
+                    double M5, const double* c, int order, bool dag, hipStream_t st) {
+    auto u = reinterpret_cast<const cpx<R>*>(U);
+    auto in = reinterpret_cast<const cpx<R>*>(psi);
+    auto o = reinterpret_cast<cpx<R>*>(out);
+    const size_t n = (size_t)2 * Lx * Ly * Ls * nrhs;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto t = reinterpret_cast<cpx<R>*>(scratch(sizeof(cpx<R>) * 3 * n));
+    if (!t) return DWF_EHIP;
+    cpx<R>* w = t;
+    cpx<R>* y = t + n;
+    cpx<R>* z = t + 2 * n;
+    auto D = [&](const cpx<R>* a, cpx<R>* b, double mass, bool adj) {
+        return fine_dw<R>(u, a, b, nullptr, Lx, Ly, Ls, nrhs, mass, M5, adj, nullptr, 1, st);
+    };
+    if ((dag ? D(in, w, 1.0, false) : D(in, w, m, false)) != hipSuccess) return DWF_EHIP;
+    if (vaxpby<R>(c[order], w, 0.0, y, n, st) != hipSuccess) return DWF_EHIP;
+    for (int k = order - 1; k >= 0; --k) {
+        if (D(y, z, 1.0, true) != hipSuccess || D(z, y, 1.0, false) != hipSuccess) return DWF_EHIP;
+        if (vaxpby<R>(c[k], w, 1.0, y, n, st) != hipSuccess) return DWF_EHIP;
+    }
+    return hip_status(dag ? D(y, o, m, true) : D(y, o, 1.0, true));
+}
+
 bool valid_prec(int p, bool link) {
     if (p == DWF_P_F64 || p == DWF_P_F32) return true;
     return link && (p == DWF_P_BF16 || p == DWF_P_F16);
@@ -87,6 +114,42 @@ int dwf_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls,
                                          Ls, nrhs, m_f, M5, dag, nullptr, 1, S(stream)));
     return hip_status(fine_dw<double>((const cpx<double>*)U, (const cpx<double>*)psi, (cpx<double>*)out, nullptr, Lx,
                                       Ly, Ls, nrhs, m_f, M5, dag, nullptr, 1, S(stream)));
+}
+
+int dwf_pv_poly_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, double m_f,
+                      double M5, const double* c, int order, int flags, void* stream) {
+    if (!U || !psi || !out || !c || psi == out || !dims_ok(Lx, Ly, Ls, nrhs)) return DWF_EINVAL;
+    if (!std::isfinite(m_f) || !std::isfinite(M5) || order < 0 || order > DWF_PV_POLY_MAX) return DWF_EINVAL;
+    for (int k = 0; k <= order; ++k)
+        if (!std::isfinite(c[k])) return DWF_EINVAL;
+    const bool dag = flags & DWF_DAGGER;
+    if (flags & DWF_PREC_F32)
+        return pv_poly_apply_t<float>(U, psi, out, Lx, Ly, Ls, nrhs, m_f, M5, c, order, dag, S(stream));
+    return pv_poly_apply_t<double>(U, psi, out, Lx, Ly, Ls, nrhs, m_f, M5, c, order, dag, S(stream));
+}
+
+int dwf_pv_poly_chebyshev(int order, double lam_min, double lam_max, double* c) {
+    if (!c || order < 0 || order > DWF_PV_POLY_MAX) return DWF_EINVAL;
+    if (!(lam_min > 0.0) || !(lam_max > lam_min) || !std::isfinite(lam_max)) return DWF_EINVAL;
+    // r(x) = 1 - x p(x) = T_n(a + b x) / T_n(a), n = order + 1: power-series
+    // coefficients of T_j(a + b x) from T_{j+1} = 2 (a + b x) T_j - T_{j-1}
+    const int n = order + 1;
+    const double a = (lam_max + lam_min) / (lam_max - lam_min), b = -2.0 / (lam_max - lam_min);
+    double t0[DWF_PV_POLY_MAX + 3] = {0.0}, t1[DWF_PV_POLY_MAX + 3] = {0.0};
+    t0[0] = 1.0;            // T_0
+    t1[0] = a; t1[1] = b;   // T_1
+    for (int j = 1; j < n; ++j) {
+        double nx[DWF_PV_POLY_MAX + 3] = {0.0};
+        for (int i = 0; i <= j; ++i) {
+            nx[i] += 2.0 * a * t1[i];
+            nx[i + 1] += 2.0 * b * t1[i];
+        }
+        for (int i = 0; i <= j + 1; ++i) nx[i] -= t0[i];
+        for (int i = 0; i <= n; ++i) { t0[i] = t1[i]; t1[i] = nx[i]; }
+    }
+    // t1 now holds T_n(a + b x); p(x) = -(r_1 + r_2 x + ...) with r = t1 / t1[0]
+    for (int k = 0; k <= order; ++k) c[k] = -t1[k + 1] / t1[0];
+    return DWF_OK;
 }
 
 int dwf_fine_config(int shape, int chunk) { return set_fine_config(shape, chunk) ? DWF_OK : DWF_EINVAL; }
@@ -188,6 +251,8 @@ void dwf_mg_default_params(dwf_mg_params* p, int nlevels) {
     p->coarsest_solver = DWF_COARSEST_CGNR;
     p->coarsest_restart = 16;
     p->transfer = DWF_TRANSFER_WALL;
+    p->pv_poly_order = 0;
+    for (int k = 0; k <= DWF_PV_POLY_MAX; ++k) p->pv_poly[k] = (k == 0) ? 1.0 : 0.0;
 }
 
 int mg_deflation_info(const dwf_mg* mg, int* nev, int* iters, double* worst_residual, double* lambdas) {
@@ -217,6 +282,9 @@ int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, do
         return DWF_EINVAL;
     if (p->coarsest_solver == DWF_COARSEST_GCR && p->coarsest_nev > 0) return DWF_EUNSUPPORTED;
     if (p->transfer != DWF_TRANSFER_WALL && p->transfer != DWF_TRANSFER_BULK) return DWF_EINVAL;
+    if (p->pv_poly_order < 0 || p->pv_poly_order > DWF_PV_POLY_MAX) return DWF_EINVAL;
+    for (int k = 0; k <= p->pv_poly_order; ++k)
+        if (!std::isfinite(p->pv_poly[k])) return DWF_EINVAL;
     if (p->transfer == DWF_TRANSFER_BULK)
         for (int l = 0; l < p->nlevels; ++l)
             if (p->Ls_coarse[l] != (l == 0 ? Ls : p->Ls_coarse[l - 1])) return DWF_EINVAL;

@@ -116,6 +116,23 @@ __global__ void k_sub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n) {
     GRID_STRIDE(i, n) out[i] = a[i] - b[i];
 }
 
+// y = a x + b y (b == 0: y = a x, whatever y held)
+template <typename T>
+__global__ void k_axpby(double a, const cpx<T>* x, double b, cpx<T>* y, size_t n) {
+    const T ta = (T)a, tb = (T)b;
+    if (b == 0.0) {
+        GRID_STRIDE(i, n) y[i] = ta * x[i];
+    } else {
+        GRID_STRIDE(i, n) y[i] = ta * x[i] + tb * y[i];
+    }
+}
+template <typename T> hipError_t vaxpby(double a, const cpx<T>* x, double b, cpx<T>* y, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby<T>, ew_grid(n, 1), dim3(kBlock), 0, st, a, x, b, y, n);
+    return hipGetLastError();
+}
+template hipError_t vaxpby<float>(double, const cpx<float>*, double, cpx<float>*, size_t, hipStream_t);
+template hipError_t vaxpby<double>(double, const cpx<double>*, double, cpx<double>*, size_t, hipStream_t);
+
 template <typename T> hipError_t vzero(cpx<T>* x, size_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_zero<T>, ew_grid(n, 1), dim3(kBlock), 0, st, x, n);
     return hipGetLastError();

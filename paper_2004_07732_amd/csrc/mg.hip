@@ -120,21 +120,51 @@ hipError_t Hierarchy::apply_dw(int l, const cpx<T>* in, cpx<T>* out, double mass
     return coarse_apply<T>(L.links, L.link_prec, in, out, g, ncol, mass, M5, dag, false, 0.0, skip, stride, st);
 }
 
+// Polynomial correction of the PV preconditioning (remark after eq. NormalExp,
+// App. A): y = p(X) w, X = D_PV D_PV^dag, by Horner's scheme (y = c_K w, then
+// y = c_k w + X y), on the fine level
+template <typename T>
+hipError_t Hierarchy::pv_poly(const cpx<T>* w, cpx<T>* y, cpx<T>* z, int ncol, hipStream_t st, const int* skip) {
+    const int K = prm.pv_poly_order;
+    const size_t n = levels[0].vec_elems() * ncol;
+    hipError_t e = vaxpby<T>(prm.pv_poly[K], w, 0.0, y, n, st);
+    for (int k = K - 1; k >= 0 && e == hipSuccess; --k) {
+        e = apply_dw<T>(0, y, z, 1.0, true, ncol, st, skip);
+        if (e == hipSuccess) e = apply_dw<T>(0, z, y, 1.0, false, ncol, st, skip);
+        if (e == hipSuccess) e = vaxpby<T>(prm.pv_poly[k], w, 1.0, y, n, st);
+    }
+    return e;
+}
+
+// A = D_PV^dag D_DW (on the fine level with the PV polynomial: D_PV^dag p(X) D_DW)
 template <typename T>
 hipError_t Hierarchy::apply_A(int l, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp, int ncol, hipStream_t st,
                               const int* skip) {
     hipError_t e = apply_dw<T>(l, in, tmp, m, false, ncol, st, skip);
     if (e != hipSuccess) return e;
-    if (l == 0 && !capturing_) cnt_.fine_applies += 2;
+    if (l == 0 && !capturing_) cnt_.fine_applies += a_cost(0);
+    if (l == 0 && prm.pv_poly_order > 0) {
+        cpx<T>* y = C<T>(work_[0].py);
+        e = pv_poly<T>(tmp, y, C<T>(work_[0].pz), ncol, st, skip);
+        if (e != hipSuccess) return e;
+        return apply_dw<T>(l, y, out, 1.0, true, ncol, st, skip);
+    }
     return apply_dw<T>(l, tmp, out, 1.0, true, ncol, st, skip);
 }
 
+// A^dag = D_DW^dag D_PV (with the PV polynomial: D_DW^dag p(X) D_PV; p(X) is Hermitian)
 template <typename T>
 hipError_t Hierarchy::apply_Adag(int l, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp, int ncol, hipStream_t st,
                                  const int* skip) {
     hipError_t e = apply_dw<T>(l, in, tmp, 1.0, false, ncol, st, skip);
     if (e != hipSuccess) return e;
-    if (l == 0 && !capturing_) cnt_.fine_applies += 2;
+    if (l == 0 && !capturing_) cnt_.fine_applies += a_cost(0);
+    if (l == 0 && prm.pv_poly_order > 0) {
+        cpx<T>* y = C<T>(work_[0].py);
+        e = pv_poly<T>(tmp, y, C<T>(work_[0].pz), ncol, st, skip);
+        if (e != hipSuccess) return e;
+        return apply_dw<T>(l, y, out, m, true, ncol, st, skip);
+    }
     return apply_dw<T>(l, tmp, out, m, true, ncol, st, skip);
 }
 
@@ -202,6 +232,10 @@ int Hierarchy::alloc_level_work(int l, int ncol) {
     auto A = [&](size_t bytes) { return dalloc(bytes); };
     w.r = A(vb); w.x = A(vb); w.tmp = A(vb); w.tmp2 = A(vb); w.rhs = A(vb);
     if (!w.r || !w.x || !w.tmp || !w.tmp2 || !w.rhs) return DWF_EHIP;
+    if (l == 0 && prm.pv_poly_order > 0) {
+        w.py = A(vb); w.pz = A(vb);
+        if (!w.py || !w.pz) return DWF_EHIP;
+    }
     if (w.kmax > 0) {
         w.P = A(vb * w.kmax);
         w.W = A(vb * w.kmax);
@@ -461,7 +495,7 @@ int Hierarchy::smooth(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t s
     };
     if (use_graphs_ && st == st_) {
         if (int e = run_graph(GraphKey{1, l, ncol, r, z}, st, body)) return e;
-        if (l == 0) cnt_.fine_applies += 2 * (ns + 1);
+        if (l == 0) cnt_.fine_applies += a_cost(0) * (ns + 1);
         return DWF_OK;
     }
     return body();
@@ -703,6 +737,11 @@ int Hierarchy::solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol,
         r64_ = (cpx<double>*)dalloc(sizeof(cpx<double>) * nt);
         t64_ = (cpx<double>*)dalloc(sizeof(cpx<double>) * nt);
         if (!r64_ || !t64_) return DWF_EHIP;
+        if (prm.pv_poly_order > 0) {
+            y64_ = (cpx<double>*)dalloc(sizeof(cpx<double>) * nt);
+            z64_ = (cpx<double>*)dalloc(sizeof(cpx<double>) * nt);
+            if (!y64_ || !z64_) return DWF_EHIP;
+        }
         r64_cols_ = ncol;
     }
     double* d_s = work_[0].gcr.rr;   // scratch for column norms between inner solves
@@ -736,9 +775,15 @@ int Hierarchy::solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol,
         if (status == DWF_ENAN) break;
         if (all) { status = DWF_OK; break; }
         if (outer >= prm.max_outer || total_it >= prm.max_iters) { status = DWF_NOT_CONVERGED; break; }
-        // inner right-hand side D_PV^dagger r in the inner precision
-        HIPCHK(fine_dw<double>(L.U64, r64_, t64_, nullptr, L.Lx, L.Ly, L.Ls, ncol, 1.0, M5, true, nullptr, 1, st));
-        cnt_.fine_applies += 1;
+        // inner right-hand side D_PV^dagger r (with the PV polynomial D_PV^dagger p(X) r)
+        if (prm.pv_poly_order > 0) {
+            HIPCHK(pv_poly<double>(r64_, y64_, z64_, ncol, st));
+            HIPCHK(fine_dw<double>(L.U64, y64_, t64_, nullptr, L.Lx, L.Ly, L.Ls, ncol, 1.0, M5, true, nullptr, 1, st));
+            cnt_.fine_applies += 1 + 2 * prm.pv_poly_order;
+        } else {
+            HIPCHK(fine_dw<double>(L.U64, r64_, t64_, nullptr, L.Lx, L.Ly, L.Ls, ncol, 1.0, M5, true, nullptr, 1, st));
+            cnt_.fine_applies += 1;
+        }
         HIPCHK(norm2<double>(t64_, n, ncol, d_s, rw_, st));
         HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));

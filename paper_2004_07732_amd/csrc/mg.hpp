@@ -51,6 +51,8 @@ struct LevelWork {
     void* Ws = nullptr;           // [ksmooth]
     void* rs = nullptr;
     void* zt = nullptr;           // K-cycle output scratch
+    void* py = nullptr;           // fine level with the PV polynomial: p(X) w and X's intermediate
+    void* pz = nullptr;
     // coarse-grid buffers of the K-cycle on this level (level l's precision)
     void* rc_local = nullptr;     // restricted residual in this level's precision
     void* ec_local = nullptr;
@@ -102,6 +104,8 @@ private:
     int scal_cols_ = 0;
     cpx<double>* r64_ = nullptr;
     cpx<double>* t64_ = nullptr;
+    cpx<double>* y64_ = nullptr;   // PV polynomial of the FP64 right-hand side
+    cpx<double>* z64_ = nullptr;
     int r64_cols_ = 0;
     SolveCounters cnt_{};
     // solves run on a stream of the context, so that fixed launch sequences
@@ -142,6 +146,11 @@ private:
     // operators on level l in precision T
     template <typename T> hipError_t apply_dw(int l, const cpx<T>* in, cpx<T>* out, double mass, bool dag,
                                               int ncol, hipStream_t st, const int* skip = nullptr);
+    // stencil applications of one A (or A^dag) on level l
+    int a_cost(int l) const { return (l == 0 && prm.pv_poly_order > 0) ? 2 * prm.pv_poly_order + 2 : 2; }
+    // y = p(X) w on the fine level, X = D_PV D_PV^dag, p from prm.pv_poly (z: scratch)
+    template <typename T> hipError_t pv_poly(const cpx<T>* w, cpx<T>* y, cpx<T>* z, int ncol, hipStream_t st,
+                                             const int* skip = nullptr);
     template <typename T> hipError_t apply_A(int l, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp, int ncol,
                                              hipStream_t st, const int* skip = nullptr);
     template <typename T> hipError_t apply_Adag(int l, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp, int ncol,

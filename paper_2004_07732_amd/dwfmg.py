@@ -38,6 +38,7 @@ MG_OP_WILSON, MG_OP_WILSON_DAG, MG_OP_RESTRICT, MG_OP_PROLONG, MG_OP_KCYCLE = 5,
 COARSEST_CGNR, COARSEST_GCR = 0, 1
 KRYLOV_CGNR, KRYLOV_BICGSTAB = 0, 1
 TRANSFER_WALL, TRANSFER_BULK = 0, 1
+PV_POLY_MAX = 3
 FINE_AUTO, FINE_ROW, FINE_TILE_64x8, FINE_TILE_32x16, FINE_TILE_128x4 = -1, 0, 1, 2, 3
 
 
@@ -61,6 +62,8 @@ def lib() -> ctypes.CDLL:
         L.dwf_apply.argtypes = [vp, vp, vp, i, i, i, i, d, d, i, vp]
         L.dwf_pv_apply.argtypes = [vp, vp, vp, i, i, i, i, d, d, i, i, vp]
         L.dwf_fine_config.argtypes = [i, i]
+        L.dwf_pv_poly_apply.argtypes = [vp, vp, vp, i, i, i, i, d, d, ctypes.POINTER(d), i, i, vp]
+        L.dwf_pv_poly_chebyshev.argtypes = [i, d, d, ctypes.POINTER(d)]
         L.dwf_wilson_apply.argtypes = [vp, vp, vp, i, i, i, d, i, vp]
         L.dwf_gamma5R.argtypes = [vp, vp, i, i, i, i, i, vp]
         L.dwf_gauge_transform.argtypes = [vp, vp, vp, vp, vp, i, i, i, i, vp]
@@ -86,7 +89,8 @@ def lib() -> ctypes.CDLL:
         L.dwf_release_scratch.argtypes = []
         L.dwf_strerror.argtypes = [i]
         L.dwf_strerror.restype = ctypes.c_char_p
-        for name in ("dwf_apply", "dwf_pv_apply", "dwf_fine_config", "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
+        for name in ("dwf_apply", "dwf_pv_apply", "dwf_fine_config", "dwf_pv_poly_apply", "dwf_pv_poly_chebyshev",
+                     "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
                      "dwf_pack", "dwf_unpack", "dwf_force", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
                      "mg_time_op", "dwf_norm2", "mg_update_links", "mg_solve_batch",
                      "mg_level_info", "mg_deflation_info", "mg_destroy", "dwf_release_scratch",
@@ -138,6 +142,8 @@ class CParams(ctypes.Structure):
         ("coarsest_solver", ctypes.c_int),
         ("coarsest_restart", ctypes.c_int),
         ("transfer", ctypes.c_int),
+        ("pv_poly_order", ctypes.c_int),
+        ("pv_poly", ctypes.c_double * (PV_POLY_MAX + 1)),
     ]
 
 
@@ -183,6 +189,7 @@ class MGParams:
     coarsest_solver: int = COARSEST_CGNR   # CGNR on A^dag A (Table 2), or COARSEST_GCR: GCR on A
     coarsest_restart: int = 16
     transfer: int = 0              # TRANSFER_WALL (the paper's method) or TRANSFER_BULK (Sec. 4.1)
+    pv_poly: Optional[List[float]] = None   # c_0..c_K of the PV polynomial on the fine level (None: A itself)
 
     @property
     def nlevels(self) -> int:
@@ -203,6 +210,13 @@ class MGParams:
                      "max_iters", "max_outer", "coarsest_nev", "eig_degree", "eig_maxit", "eig_tol",
                      "coarsest_solver", "coarsest_restart", "transfer"):
             setattr(c, name, getattr(self, name))
+        if self.pv_poly is not None:
+            coef = [float(v) for v in self.pv_poly]
+            if not 1 <= len(coef) <= PV_POLY_MAX + 1:
+                raise ValueError(f"pv_poly takes 1..{PV_POLY_MAX + 1} coefficients")
+            c.pv_poly_order = len(coef) - 1
+            for k, v in enumerate(coef):
+                c.pv_poly[k] = v
         return c
 
 
@@ -269,6 +283,27 @@ def dwf_apply(U, psi, m_f, M5, dagger=False, out=None, stream=None):
     _check(lib().dwf_apply(_ptr(U), _ptr(psi), _ptr(out), Lx, Ly, Ls, nrhs, float(m_f), float(M5), flags,
                            _stream(stream)), "dwf_apply")
     return out
+
+
+def dwf_pv_poly_apply(U, psi, m_f, M5, c, dagger=False, out=None, stream=None):
+    """out = D_PV^dag p(D_PV D_PV^dag) D_DW psi, p(X) = sum_k c[k] X^k (or the adjoint)."""
+    _need(U, "U", psi.dtype)
+    _need(psi, "psi")
+    Lx, Ly, Ls, nrhs = _fine_dims(U, psi)
+    out = torch.empty_like(psi) if out is None else out
+    _need(out, "out", psi.dtype, psi.shape)
+    coef = (ctypes.c_double * len(c))(*[float(v) for v in c])
+    flags = _prec(psi) | (DWF_DAGGER if dagger else 0)
+    _check(lib().dwf_pv_poly_apply(_ptr(U), _ptr(psi), _ptr(out), Lx, Ly, Ls, nrhs, float(m_f), float(M5), coef,
+                                   len(c) - 1, flags, _stream(stream)), "dwf_pv_poly_apply")
+    return out
+
+
+def pv_poly_chebyshev(order, lam_min=1.0, lam_max=25.0):
+    """Coefficients of the degree-`order` polynomial p minimising max |1 - x p(x)| on [lam_min, lam_max]."""
+    coef = (ctypes.c_double * (order + 1))()
+    _check(lib().dwf_pv_poly_chebyshev(int(order), float(lam_min), float(lam_max), coef), "dwf_pv_poly_chebyshev")
+    return list(coef)
 
 
 def dwf_fine_config(shape, chunk=1):

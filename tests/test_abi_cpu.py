@@ -71,3 +71,32 @@ def test_argument_errors_are_reported_before_any_device_work(libdwf):
     assert libdwf.dwf_apply(1, 2, 3, 4, 4, 4, 1, float("nan"), -1.0, 0, None) == -1
     libdwf.mg_solve.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_double, vp, vp]
     assert libdwf.mg_solve(None, 1, 2, 1, 1e-10, None, None) == -5
+
+
+@pytest.mark.parametrize("order,lo,hi", [(0, 1.0, 25.0), (1, 1.0, 25.0), (2, 1.0, 30.0), (3, 0.5, 12.0)])
+def test_pv_poly_chebyshev_coefficients_match_the_oracle(libdwf, order, lo, hi):
+    """The library's minimax coefficients (host code, a three-term recurrence)
+    against the oracle's (numpy's Chebyshev-to-power-series conversion)."""
+    import numpy as np
+    from oracle import dwf_oracle as O
+    d = ctypes.c_double
+    libdwf.dwf_pv_poly_chebyshev.argtypes = [ctypes.c_int, d, d, ctypes.POINTER(d)]
+    c = (d * (order + 1))()
+    assert libdwf.dwf_pv_poly_chebyshev(order, lo, hi, c) == 0
+    want = O.pv_poly_chebyshev(order, lo, hi)
+    assert np.allclose(np.array(c[:]), want, rtol=1e-12, atol=1e-15)
+
+
+def test_pv_poly_arguments_rejected_on_the_host(libdwf):
+    d, vp, i = ctypes.c_double, ctypes.c_void_p, ctypes.c_int
+    libdwf.dwf_pv_poly_chebyshev.argtypes = [i, d, d, ctypes.POINTER(d)]
+    c = (d * 8)()
+    assert libdwf.dwf_pv_poly_chebyshev(4, 1.0, 25.0, c) == -1
+    assert libdwf.dwf_pv_poly_chebyshev(1, 25.0, 1.0, c) == -1
+    assert libdwf.dwf_pv_poly_chebyshev(1, 0.0, 1.0, c) == -1
+    libdwf.dwf_pv_poly_apply.argtypes = [vp, vp, vp, i, i, i, i, d, d, ctypes.POINTER(d), i, i, vp]
+    one = (d * 1)(1.0)
+    assert libdwf.dwf_pv_poly_apply(1, 2, 3, 4, 4, 4, 1, 0.1, -1.0, one, 4, 0, None) == -1
+    assert libdwf.dwf_pv_poly_apply(1, 2, 3, 4, 4, 4, 1, 0.1, -1.0, None, 0, 0, None) == -1
+    nan = (d * 1)(float("nan"))
+    assert libdwf.dwf_pv_poly_apply(1, 2, 3, 4, 4, 4, 1, 0.1, -1.0, nan, 0, 0, None) == -1

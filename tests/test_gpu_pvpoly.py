@@ -1,0 +1,98 @@
+"""Polynomial correction of the PV preconditioning on the GPU (the remark after
+eq. NormalExp and App. A): the operator D_PV^dag p(D_PV D_PV^dag) D_DW against
+the oracle, its use as the fine-level operator of the multigrid solve, and the
+solve with the Chebyshev-weighted polynomial reaching the true residual."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dwf_oracle as O
+from paper_2004_07732_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+dwfmg = pytest.importorskip("paper_2004_07732_amd.dwfmg")
+DEV = "cuda"
+
+
+def T(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+COEFS = {0: [0.9], 1: [1.6, -0.3], 2: [2.1, -0.9, 0.11], 3: [2.4, -1.3, 0.3, -0.02]}
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_pv_poly_apply_matches_oracle(order, dagger):
+    Lx, Ly, Ls, nrhs, m, M5 = 12, 8, 6, 2, 0.04, -1.0
+    U = inputs.metropolis_u1(Lx, Ly, 6.0, 20, 700 + order).U
+    psi = inputs.gaussian_field((nrhs, Ls, Ly, Lx, 2), 710 + order)
+    c = COEFS[order]
+    want = O.pv_poly_dw(U, psi, m, M5, c, dagger=dagger)
+    got = dwfmg.dwf_pv_poly_apply(T(U), T(psi), m, M5, c, dagger=dagger).cpu().numpy()
+    assert rel(got, want) < 1e-13
+    got32 = dwfmg.dwf_pv_poly_apply(T(U).to(torch.complex64), T(psi).to(torch.complex64), m, M5, c,
+                                    dagger=dagger).cpu().numpy().astype(np.complex128)
+    assert rel(got32, want) < 1e-5 * (order + 1)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_pv_poly_order_zero_is_the_pv_mode_bit_for_bit(dtype):
+    Lx, Ly, Ls, m, M5 = 16, 8, 4, 0.02, -1.0
+    U = T(inputs.metropolis_u1(Lx, Ly, 6.0, 10, 720).U).to(dtype)
+    psi = T(inputs.gaussian_field((1, Ls, Ly, Lx, 2), 721)).to(dtype)
+    for dag, mode in ((False, dwfmg.DWF_PVDAG_DW), (True, dwfmg.DWF_PVDAG_DW_DAG)):
+        a = dwfmg.dwf_pv_poly_apply(U, psi, m, M5, [1.0], dagger=dag)
+        b = dwfmg.dwf_pv_apply(U, psi, m, M5, mode=mode)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+def test_fine_level_operator_uses_the_polynomial():
+    L, Ls, m, M5 = 16, 4, 0.05, -1.0
+    U = inputs.metropolis_u1(L, L, 6.0, 20, 730).U
+    start = inputs.gaussian_field((4, L, L, 2), 731)
+    c = dwfmg.pv_poly_chebyshev(2, 1.0, 25.0)
+    p = dwfmg.MGParams(nvec=[4], block=[(4, 4)], Ls_coarse=[2], setup_iters=0, fine_prec=dwfmg.P_F64, pv_poly=c)
+    mg = dwfmg.MG(T(U), Ls, m, M5, p, [T(start)])
+    x = inputs.gaussian_field((2, Ls, L, L, 2), 732)
+    got = mg.level_op(0, dwfmg.MG_OP_A, T(x), 2).cpu().numpy()
+    assert rel(got, O.pv_poly_dw(U, x, m, M5, c)) < 1e-13
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_mg_solve_with_chebyshev_polynomial(order):
+    """The polynomial-corrected fine operator inside the K-cycle solve reaches
+    1e-10 in the true residual of D_DW x = b.  The counts are printed beside the
+    plain operator's: the paper leaves open whether the extra applications pay
+    (measured: they do not with this weighting, which shrinks the low modes that
+    the coarse operator, built for p = 1, has to match)."""
+    L, Ls, m, M5, tol = 32, 8, 0.02, -1.0, 1e-10
+    U = inputs.metropolis_u1(L, L, 6.0, 60, 740).U
+    b = inputs.gaussian_field((1, Ls, L, L, 2), 741)
+    start = T(inputs.gaussian_field((8, L, L, 2), 742))
+    out = {}
+    for name, coef in (("plain", None), (f"cheb{order}", dwfmg.pv_poly_chebyshev(order, 1.0, 25.0))):
+        p = dwfmg.MGParams(nvec=[8], block=[(4, 4)], Ls_coarse=[2], pv_poly=coef)
+        mg = dwfmg.MG(T(U), Ls, m, M5, p, [start])
+        x, st = mg.solve(T(b), tol)
+        res = np.linalg.norm(b[0] - O.dwf(U, x[0].cpu().numpy(), m, M5)) / np.linalg.norm(b[0])
+        assert res <= tol and st.true_rel_residual <= tol
+        out[name] = (st.fine_iters, st.fine_applies)
+    print(f"32^2 x 8 (fine iterations, fine applications): {out}")
+
+
+def test_pv_poly_parameter_errors():
+    L, Ls = 16, 4
+    U = T(inputs.metropolis_u1(L, L, 6.0, 10, 750).U)
+    s = T(inputs.gaussian_field((4, L, L, 2), 751))
+    with pytest.raises(ValueError):
+        dwfmg.MGParams(nvec=[4], block=[(4, 4)], Ls_coarse=[2], pv_poly=[1, 0, 0, 0, 0]).to_c()
+    with pytest.raises(dwfmg.DwfError):
+        dwfmg.MG(U, Ls, 0.05, -1.0, dwfmg.MGParams(nvec=[4], block=[(4, 4)], Ls_coarse=[2], setup_iters=0,
+                                                    pv_poly=[1.0, float("nan")]), [s])
