@@ -364,6 +364,8 @@ def main():
             rows[name] = {"solves_per_s": 1.0 / tv, "mg": {"nvec": wlv["nvec"], "block": wlv["block"],
                                                           "Ls_coarse": wlv["Ls_coarse"]},
                           "coarsest": {k: v for k, v in kw.items() if k.startswith("coarsest")}, **stats_dict(stv)}
+            if kw.get("pv_poly") is not None:
+                rows[name]["pv_poly"] = list(kw["pv_poly"])
             log(f"[bench] {name}: {tv * 1e3:.1f} ms/solve, fine applies {stv.fine_applies}")
             mgv.close()
         wl4 = dict(wl, Ls_coarse=[4] * len(wl["nvec"]))
@@ -375,6 +377,9 @@ def main():
         variant("three_level", dict(WORKLOADS["dwf256_ls16_mg3"]), **head)
         # the fastest shape measured: 8 null vectors, coarse Ls 2
         variant("nvec8_Ls2", dict(wl, nvec=[8], Ls_coarse=[2]), **head)
+        # the polynomial correction of the PV preconditioning (App. A): minimax weighting of
+        # degree 2 over [1, 25], the free-field range of D_PV D_PV^dag
+        variant("pv_poly_cheb2", wl, pv_poly=dwfmg.pv_poly_chebyshev(2, 1.0, 25.0), **head)
 
     if not args.quick:
         # the paper's solver comparison: Krylov solves of the same system without multigrid (FP64)
