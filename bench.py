@@ -340,7 +340,10 @@ def main():
     n, nsites, Lsc = c["n"], c["Lx"] * c["Ly"], c["Ls"]
     link_bytes = 4  # bfloat16 complex
     vec_bytes = 16 if make_params(dwfmg, wl, True).vec_prec[0] == dwfmg.P_F64 else 8
-    coarse_bytes = nsites * (5 * n * n * link_bytes + 2 * Lsc * n * vec_bytes)
+    # per coarse site: the site term and the two forward hops of BF16 links (the backward
+    # hops are the sigma_3-adjoints of the neighbours' forward hops), the vector read once
+    # and written once
+    coarse_bytes = nsites * (3 * n * n * link_bytes + 2 * Lsc * n * vec_bytes)
     achieved = coarse_bytes / (t_coarse_ms * 1e-3) / 1e9
     traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse_mfma.hip"), coarse_bytes)
     log(f"[bench] coarse stencil {t_coarse_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")

@@ -176,7 +176,7 @@ typedef struct {
     int    nlevels;                       /* coarse levels, 1..DWF_MAX_LEVELS           */
     int    nvec[DWF_MAX_LEVELS];          /* generated near-null vectors per level      */
     int    block[DWF_MAX_LEVELS][2];      /* aggregate size (bx, by) per level          */
-    int    Ls_coarse[DWF_MAX_LEVELS];     /* fifth extent on each coarse level          */
+    int    Ls_coarse[DWF_MAX_LEVELS];     /* fifth extent on each coarse level, 2..32   */
     int    link_prec[DWF_MAX_LEVELS];     /* DWF_P_* storage of each coarse kernel      */
     int    vec_prec[DWF_MAX_LEVELS];      /* DWF_P_F64 / DWF_P_F32 Krylov vectors       */
     int    fine_prec;                     /* DWF_P_F64 or DWF_P_F32 inner fine solve    */
@@ -243,7 +243,7 @@ void dwf_mg_default_params(dwf_mg_params* p, int nlevels);
  * D_W(m_setup) D_W(m_setup)^dagger v = 0 (Sec. 3.1), chiral doubling, block
  * Gram-Schmidt, Galerkin kernel.  Allocates device memory owned by the
  * context.  Errors: DWF_EINVAL (sizes not divisible by the blocks, nvec larger
- * than the block dimension, Ls < 2), DWF_EUNSUPPORTED (2*nvec not in
+ * than the block dimension, Ls < 2, a coarse Ls outside 2..32), DWF_EUNSUPPORTED (2*nvec not in
  * {4,8,12,16,24,32,48,64}), DWF_EBREAKDOWN (dependent null vectors), DWF_EHIP. */
 int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, double M5,
              const dwf_mg_params* params, const void* const* null_starts, void* stream);

@@ -293,7 +293,7 @@ int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, do
         const int bx = p->block[l][0], by = p->block[l][1], nv = p->nvec[l];
         if (bx < 1 || by < 1 || lx % bx || ly % by || nv < 1) return DWF_EINVAL;
         if (nv > bx * by * (n / 2)) return DWF_EINVAL;
-        if (p->Ls_coarse[l] < 2 || p->Ls_coarse[l] > 8) return DWF_EINVAL;
+        if (p->Ls_coarse[l] < 2 || p->Ls_coarse[l] > kMaxCoarseLs) return DWF_EINVAL;
         if (!valid_prec(p->link_prec[l], true) || !valid_prec(p->vec_prec[l], false)) return DWF_EINVAL;
         if (!null_starts[l]) return DWF_EINVAL;
         const int nn = 2 * nv;
@@ -371,7 +371,7 @@ int dwf_norm2(const void* x, size_t n, int ncol, double* out, void* stream) {
     static double* partial = nullptr;
     static int cap_cols = 0;
     RedWork rw;
-    rw.nblk = 512;
+    rw.nblk = kRedBlocks;
     rw.max_q = 1;
     rw.max_cols = ncol;
     if (ncol > cap_cols) {

@@ -10,6 +10,8 @@
 // CG, CGNR and GCR coefficients live on the device and a per-column `done` /
 // `stop` flag turns later updates into no-ops.  Accumulation is FP64 for both
 // FP32 and FP64 vectors.
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace dwf {
@@ -69,8 +71,10 @@ __device__ __forceinline__ void sum_partials(int nq, int nb, const RedWork& rw, 
     block_reduce<NQ>(w, nq, sh, tot);
 }
 
+// at least two entries per thread: a block's partial sums cost about as much as
+// streaming a few thousand entries, so small vectors take fewer, fuller blocks
 inline dim3 red_grid(size_t n, int ncol, const RedWork& rw) {
-    long long nb = (long long)((n + kBlock - 1) / kBlock);
+    long long nb = (long long)((n + 2 * kBlock - 1) / (2 * kBlock));
     if (nb > rw.nblk) nb = rw.nblk;
     if (nb < 1) nb = 1;
     return dim3((unsigned)nb, (unsigned)ncol);
@@ -455,10 +459,17 @@ k_gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int wan
     if (want_norm) write_partials<1>(v, 1, rw, col, sh, tot);
 }
 
-// ---- fused GCR iteration (see kernels.hpp)
-template <typename T>
+// calls f(std::integral_constant<int, j>) for a run-time j in Js...
+template <typename F, int... Js>
+void with_j(int j, F&& f, std::integer_sequence<int, Js...>) {
+    ((j == Js ? (f(std::integral_constant<int, Js>{}), 0) : 0), ...);
+}
+
+// ---- fused GCR iteration (see kernels.hpp); the direction count j is a template
+// argument, so that every load of an iteration is unconditional and in flight at once
+template <typename T, int j>
 __global__ void __launch_bounds__(kBlock)
-k_gcr_dots(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w, const cpx<T>* r, size_t n, const int* stop,
+k_gcr_dots(const cpx<T>* W, size_t wstride, const cpx<T>* w, const cpx<T>* r, size_t n, const int* stop,
            RedWork rw) {
     SHARED_RED;
     const int col = blockIdx.y;
@@ -487,9 +498,9 @@ k_gcr_dots(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w, const cpx<T>
     write_partials<35>(v, 2 * j + 3, rw, col, sh, tot);
 }
 
-template <typename T>
+template <typename T, int j>
 __global__ void __launch_bounds__(kBlock)
-k_gcr_fused_update(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx<T>* r, cpx<T>* copy, size_t n,
+k_gcr_fused_update(const cpx<T>* W, size_t wstride, cpx<T>* w, cpx<T>* r, cpx<T>* copy, size_t n,
                    double tol2, const int* stop_in, int* stop_out, GcrDev g) {
     const int col = blockIdx.y;
     const bool stopped = stop_in[col] != 0;
@@ -674,11 +685,15 @@ hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx
                           const RedWork& rw, hipStream_t st) {
     if (j < 0 || j > 15 || 2 * j + 3 > kGcrTot || 2 * j + 3 > rw.max_q) return hipErrorInvalidValue;
     const dim3 grid = red_grid(n, ncol, rw);
-    hipLaunchKernelGGL(k_gcr_dots<T>, grid, dim3(kBlock), 0, st, W, wstride, j, w, r, n, stop_in, rw);
-    hipLaunchKernelGGL(k_fin_store_q, dim3(2 * j + 3, ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g.tot,
-                       (size_t)kGcrTot);
-    hipLaunchKernelGGL(k_gcr_fused_update<T>, ew_grid(n, ncol), dim3(kBlock), 0, st, W, wstride, j, w, r, copy, n,
-                       tol2, stop_in, stop_out, g);
+    auto launch = [&](auto jc) {
+        constexpr int J = decltype(jc)::value;
+        hipLaunchKernelGGL((k_gcr_dots<T, J>), grid, dim3(kBlock), 0, st, W, wstride, w, r, n, stop_in, rw);
+        hipLaunchKernelGGL(k_fin_store_q, dim3(2 * J + 3, ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g.tot,
+                           (size_t)kGcrTot);
+        hipLaunchKernelGGL((k_gcr_fused_update<T, J>), ew_grid(n, ncol), dim3(kBlock), 0, st, W, wstride, w, r,
+                           copy, n, tol2, stop_in, stop_out, g);
+    };
+    with_j(j, launch, std::make_integer_sequence<int, 16>{});
     return hipGetLastError();
 }
 template <typename T>

@@ -28,14 +28,23 @@
 // 16-byte fragments; the staging loads are branch-free (dead columns read a
 // valid address and are zeroed) so that the compiler keeps them all in flight.
 //
-// Links layout for this kernel: in fragment order, so that every load of a
-// wave reads 1 KB contiguous: [site][row tile m][inner step ks][lane][4] with
-// lane = q + 16 kg holding row 16 m + q, inner entries j = 16 ks + 4 kg + e of
-// the row [d*n + k] (d: hop, k: column of that hop's block), each a complex
-// 16-bit pair (re low, im high).  The site-local terms (the M5 + 1 shift and
-// the fifth-dimension hops through hatP_pm with the -m corners, eq. coarsenDW)
-// and sigma_3 for the adjoint (hat-D_W^dagger = sigma_3 hat-D_W sigma_3) are
-// applied in the epilogue.
+// Links layout for this kernel: only the site term and the two forward hops are
+// stored.  The Galerkin operator of a gamma_5-hermitian fine operator with a
+// chirally doubled prolongator is sigma_3-hermitian link by link: the hop from
+// x back to x - mu is sigma_3 Y_{x-mu,+mu}^dagger sigma_3 (every fine hop across
+// the face between the two aggregates appears in both, reversed).  The
+// backward hops are therefore read from the neighbour's forward links,
+// transposed by the load pattern, conjugated and signed on the bits, which cuts
+// the link bytes of a launch from 5 n^2 to 3 n^2 per site (a neighbour's links
+// are usually still in L2 from the wave that read them as its own).
+// Stored in fragment order, so that every own-link load of a wave reads 1 KB
+// contiguous: [site][row tile m][inner step ks][lane][4] with lane = q + 16 kg
+// holding row 16 m + q, inner entries j = 16 ks + 4 kg + e of the row
+// [h*n + k] (h: 0 site term, 1 hop +x, 2 hop +y; k: column of that hop's
+// block), each a complex 16-bit pair (re low, im high).  The site-local terms
+// (the M5 + 1 shift and the fifth-dimension hops through hatP_pm with the -m
+// corners, eq. coarsenDW) and sigma_3 for the adjoint (hat-D_W^dagger =
+// sigma_3 hat-D_W sigma_3) are applied in the epilogue.
 #include <algorithm>
 #include <cstdlib>
 
@@ -96,14 +105,28 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
     constexpr int MT = N / 16;                    // row tiles = waves per site
     constexpr int SPB = (MT >= 4) ? 1 : 4 / MT;   // sites per block
     constexpr int KS = 5 * N / 16;                // inner steps of 16 complex entries
+    constexpr int KS3 = 3 * N / 16;               // stored inner steps (site term, +x, +y)
     constexpr int H = N / 2;                      // chirality boundary (sigma_3)
+    static_assert(H % 4 == 0, "the four output rows of a lane share their chirality");
     constexpr int SLAB = 5 * TW * N;              // LDS entries per site, part and form (d, c8, k)
     constexpr int PER = (SLAB + MT * 64 - 1) / (MT * 64);   // staged entries per thread (the last may be partial)
     // staged vectors as B fragments, [site][hi/lo][form][(d*TW + c8)*N + k], each entry a
     // complex 16-bit pair in the order the matrix instruction takes it: form 0 feeds the
     // real-output columns ([re, -im]), form 1 the imaginary-output columns ([im, re]), so
     // the lanes read their operands ready-made
-    __shared__ __attribute__((aligned(16))) uint32_t sB[SPB][2][2][SLAB];
+    // (padded to PER * MT * 64 entries: the last round of staging writes needs no guard)
+    // Per wave, sT: the neighbours' forward-hop fragments of its backward hops, as
+    // 16 x 16 matrices of complex 16-bit pairs with row stride 20 words (the
+    // transposed reads of a wavefront then fall in distinct banks).  With several
+    // column tiles the transpose is done once before the tile loop and sT shares
+    // its memory with sB; with one tile both are live across the same barrier.
+    constexpr int SBW = SPB * 2 * 2 * PER * MT * 64;   // words of sB
+    constexpr int TS = 16 * 20;
+    constexpr int STW = SPB * MT * 2 * MT * TS;       // words of sT
+    constexpr bool SHARE = (TW == 8);
+    __shared__ __attribute__((aligned(16))) uint32_t smem[SHARE ? (SBW > STW ? SBW : STW) : SBW + STW];
+    auto& sB = *reinterpret_cast<uint32_t (*)[SPB][2][2][PER * MT * 64]>(smem);
+    auto& sT = *reinterpret_cast<uint32_t (*)[SPB * MT][2][MT][TS]>(smem + (SHARE ? 0 : SBW));
     __shared__ float smax[SPB][MT];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -124,22 +147,93 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
     }
 
     // all link fragments of this wave's 16 rows, loaded once (32-bit offsets from
-    // the uniform base pointers: the launcher keeps every array under 4 GiB)
+    // the uniform base pointers: the launcher keeps every array under 4 GiB; a site
+    // past the end reads site 0 and computes nothing that is stored).
+    // Hop order d: 0 site, 1 +x, 2 -x, 3 +y, 4 -y; inner step ks = d * MT + kb.
     u32x4 a[KS];
-    if (valid_site) {
-        const uint32_t lf = ((uint32_t)site * MT + m) * KS * 64 + lane;
+    auto load_links = [&]() {
+        const uint32_t own = ((uint32_t)nb[0] * MT + m) * KS3 * 64 + lane;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) a[ks] = links[lf + ks * 64];
+        for (int kb = 0; kb < MT; ++kb) {
+            a[0 * MT + kb] = links[own + (0 * MT + kb) * 64];
+            a[1 * MT + kb] = links[own + (1 * MT + kb) * 64];
+            a[3 * MT + kb] = links[own + (2 * MT + kb) * 64];
+        }
+        // backward hop entry [i][k] = s_i s_k conj(Y_fwd(neighbour)[k][i]), i = 16 m + q,
+        // k = 16 kb + 4 kg + e.  The neighbour's fragments (row tile kb, inner step of
+        // the forward hop's column block m) are loaded as stored, 1 KB contiguous per
+        // wave load, and transposed through LDS below.  The conjugation and s_k are
+        // folded into the staged vector forms and s_i into the epilogue, so that the
+        // transposed words feed the matrix instruction unchanged.
+#pragma unroll
+        for (int kb = 0; kb < MT; ++kb) {
+            a[2 * MT + kb] = links[(((uint32_t)nb[2] * MT + kb) * KS3 + 1 * MT + m) * 64 + lane];
+            a[4 * MT + kb] = links[(((uint32_t)nb[4] * MT + kb) * KS3 + 2 * MT + m) * 64 + lane];
+        }
+    };
+    // transpose of the backward-hop fragments: each lane writes its stored row piece
+    // (row q, entries 4 kg..4 kg+3 of the 16 x 16 block) and, after the block barrier
+    // that follows, reads entries [4 kg + e][q], e = 0..3 (row k, column i)
+    auto put_bwd = [&]() {
+#pragma unroll
+        for (int kb = 0; kb < MT; ++kb) {
+            *reinterpret_cast<u32x4*>(&sT[wave][0][kb][q * 20 + 4 * kg]) = a[2 * MT + kb];
+            *reinterpret_cast<u32x4*>(&sT[wave][1][kb][q * 20 + 4 * kg]) = a[4 * MT + kb];
+        }
+    };
+    auto get_bwd = [&]() {
+#pragma unroll
+        for (int kb = 0; kb < MT; ++kb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                a[2 * MT + kb][e] = sT[wave][0][kb][(4 * kg + e) * 20 + q];
+                a[4 * MT + kb][e] = sT[wave][1][kb][(4 * kg + e) * 20 + q];
+            }
+    };
+    // Memory counters complete in issue order, so a wait for one load is a wait for
+    // every older one.  With several column tiles the links come first (every tile
+    // needs them); with one tile they are issued after the flag and staging loads,
+    // so that the waits before the LDS writes leave them in flight.
+    if (TW == 8) {
+        load_links();
+        put_bwd();
+        __syncthreads();
+        get_bwd();
+        __syncthreads();   // sT is sB from here on
     }
 
-    const int ntile = (C + TW - 1) / TW;
+    // the launcher takes tiles of 2 or 4 columns only when they hold every column:
+    // then the tile loop is straight-line code (a loop would make the compiler wait
+    // for the link loads at its head, before the first staging load is issued)
+    const int ntile = (TW < 8) ? 1 : (C + TW - 1) / TW;
     const int tid_in_site = threadIdx.x - sl * MT * 64;
     for (int t = 0; t < ntile; ++t) {
         const int cbase = TW * t;
+        // live columns of the tile: lanes c8 < TW read one flag each, a ballot
+        // makes the mask (the same for the whole wavefront).  Issued first, so
+        // that waiting for it does not wait for the loads below.  Every lane loads
+        // (straight-line code): lanes past TW or past the end read a valid repeat,
+        // and without flags a word of the input is read and ignored.
+        const int cf = (lane < TW && cbase + lane < C) ? cbase + lane : 0;
+        const int* fp = skip ? skip + (uint32_t)(cf / Ls) * sks : reinterpret_cast<const int*>(in);
+        const int flag = *fp & (skip ? -1 : 0);
+        const bool lane_live = lane < TW && cbase + lane < C && flag == 0;
+        // the site-local terms of this lane's outputs: column cbase + q % 8 (a column
+        // past the end reads column 0 and is not written), rows i0..i0+3, slice s and
+        // its fifth-dimension neighbour so
+        const int cl = (cbase + (q & 7) < C) ? cbase + (q & 7) : 0;
+        const int rhs = cl / Ls, s = cl - rhs * Ls;
+        const int i0 = 16 * m + 4 * kg;
+        const bool minus = (i0 >= H);
+        const bool from_up = DAG ? !minus : minus;
+        int so;
+        float f = 1.f;
+        if (from_up) { so = s + 1; if (so == Ls) { so = 0; f = mwrap; } }
+        else         { so = s - 1; if (so < 0) { so = Ls - 1; f = mwrap; } }
         // stage the five neighbour vectors of columns cbase..cbase+TW-1, entries
         // e = (d * TW + c8) * N + k.  The loads do not depend on the column flags
-        // (columns past the end read column 0), so all of them, and the flag load
-        // below, are in flight together; dead columns are zeroed afterwards.
+        // (columns past the end read column 0), so all of them are in flight
+        // together; dead columns are zeroed afterwards.
         cpx<T> v[PER];
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
@@ -149,13 +243,28 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
             const int c = (cbase + c8 < C) ? cbase + c8 : 0;
             v[p] = in[((uint32_t)c * nsites + nb[d]) * N + k];
         }
-        // live columns of the tile: lanes c8 < TW read one flag each, a ballot
-        // makes the mask (the same for the whole wavefront)
-        bool lane_live = false;
-        if (lane < TW) {
-            const int c = cbase + lane;
-            lane_live = c < C && !(skip && skip[(uint32_t)(c / Ls) * sks]);
+        // the site-local terms (a site past the end reads site 0): with one tile last
+        // in this group, since the compiler converts them as soon as they arrive and
+        // waiting for them then finds every other load issued; with several tiles
+        // after the LDS barrier, where they need no registers during the staging
+        float cr[4], ci[4], hr[4], hi[4];
+        // (only lanes of an existing column slot load: with tiles of 2 or 4 columns
+        // the others would repeat column 0, and every lane address costs the address
+        // unit a cycle share; the rest take zeros)
+        auto load_local = [&]() {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { cr[e] = ci[e] = hr[e] = hi[e] = 0.f; }
+            if ((q & 7) < TW) {
+                load4<T>(in + ((uint32_t)cl * nsites + nb[0]) * N + i0, cr, ci);
+                load4<T>(in + ((uint32_t)(rhs * Ls + so) * nsites + nb[0]) * N + i0, hr, hi);
+            }
+        };
+        if (TW < 8) {
+            load_links();
+            load_local();
         }
+        // keep the uses below (the ballot first) from being scheduled above the loads
+        __builtin_amdgcn_sched_barrier(0);
         const unsigned live = (unsigned)(__ballot(lane_live) & ((1ull << TW) - 1));
         auto col_ok = [&](int c) { return ((live >> (c - cbase)) & 1u) != 0; };
         float vr[PER], vi[PER];
@@ -164,11 +273,13 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         for (int p = 0; p < PER; ++p) {
             const int e = min(tid_in_site + p * MT * 64, SLAB - 1);
             const int k = e % N;
-            const int c8 = (e / N) % TW;
-            // dead columns zeroed and the sigma_3 sign of the adjoint applied on the bits
-            // (exact; selects on loaded values would again become branches)
+            const int c8 = (e / N) % TW, d = (e / N) / TW;
+            const bool bwd = (d == 2 || d == 4);
+            // dead columns zeroed and on the bits (exact; selects on loaded values would
+            // again become branches) the sign s_k: sigma_3 of the adjoint, and for the
+            // backward hops sigma_3 of the sigma_3-adjoint links
             const uint32_t keep = (valid_site && col_ok(cbase + c8)) ? 0xffffffffu : 0u;
-            const uint32_t sign = (DAG && k >= H) ? 0x80000000u : 0u;
+            const uint32_t sign = (k >= H && DAG != bwd) ? 0x80000000u : 0u;
             const float re = __uint_as_float((__float_as_uint((float)v[p].re) & keep) ^ (sign & keep));
             const float im = __uint_as_float((__float_as_uint((float)v[p].im) & keep) ^ (sign & keep));
             vr[p] = re;
@@ -190,25 +301,47 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
                 unscale = ldexpf(1.f, ex);
             }
         }
-        if (valid_site) {
+        // (straight-line: written for every site and slot, zeros where the site or the
+        // column is dead, so that no load is sunk into a branch)
 #pragma unroll
-            for (int p = 0; p < PER; ++p) {
-                const int e = tid_in_site + p * MT * 64;   // LDS slot (d * TW + c8) * N + k
-                const float re = vr[p] * scale, im = vi[p] * scale;
-                const uint32_t hre = HF::bits(re), him = HF::bits(im);
-                const uint32_t lre = HF::bits(re - HF::value(hre)), lim = HF::bits(im - HF::value(him));
-                if ((p + 1) * MT * 64 <= SLAB || e < SLAB) {
-                    sB[sl][0][0][e] = hre | ((him ^ 0x8000u) << 16);
-                    sB[sl][0][1][e] = him | (hre << 16);
-                    sB[sl][1][0][e] = lre | ((lim ^ 0x8000u) << 16);
-                    sB[sl][1][1][e] = lim | (lre << 16);
-                }
+        for (int p = 0; p < PER; ++p) {
+            const int e = tid_in_site + p * MT * 64;   // LDS slot (d * TW + c8) * N + k
+            const int d = (min(e, SLAB - 1) / N) / TW;
+            // forward hops (links as stored): [re, -im] and [im, re]; backward hops
+            // (conjugated links): [re, im] and [im, -re]
+            const uint32_t x0 = (d == 2 || d == 4) ? 0u : 0x8000u, x1 = x0 ^ 0x8000u;
+            const float re = vr[p] * scale, im = vi[p] * scale;
+            const uint32_t hre = HF::bits(re), him = HF::bits(im);
+            const uint32_t lre = HF::bits(re - HF::value(hre)), lim = HF::bits(im - HF::value(him));
+            sB[sl][0][0][e] = hre | ((him ^ x0) << 16);
+            sB[sl][0][1][e] = him | ((hre ^ x1) << 16);
+            sB[sl][1][0][e] = lre | ((lim ^ x0) << 16);
+            sB[sl][1][1][e] = lim | ((lre ^ x1) << 16);
+        }
+        if (TW < 8) put_bwd();
+        __syncthreads();
+        if (TW < 8) get_bwd();
+        // (with TW < 8 the B columns TW..7 repeat staged columns and feed only unused outputs)
+        // forward hops and site term in acc, backward hops in acb (their row sign s_i
+        // is applied below)
+        // The site-local terms start the accumulator: this lane's part (real for
+        // q < 8, imaginary for q >= 8, picked on the bits) of cdiag psi_s + f psi_so,
+        // scaled by 1 / unscale and the adjoint's row sign (both exact), so that the
+        // epilogue needs no load of its own.
+        if (TW == 8) load_local();
+        const float osg = (DAG && minus) ? -1.f : 1.f;
+        f32x4 acc, acb = {0.f, 0.f, 0.f, 0.f};
+        {
+            const uint32_t mre = imag_col ? 0u : 0xffffffffu;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float lr = cdiag * cr[e] + f * hr[e], li = cdiag * ci[e] + f * hi[e];
+                const float l = __uint_as_float((__float_as_uint(lr) & mre) | (__float_as_uint(li) & ~mre));
+                acc[e] = l * scale * osg;
             }
         }
-        __syncthreads();
-        // (with TW < 8 the B columns TW..7 repeat staged columns and feed only unused outputs)
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        if (valid_site) {
+        {   // (unconditional, so that no load feeding it is sunk into a branch; a dead
+            // site multiplies zeros and stores nothing)
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 const int d = (ks * 16) / N;
@@ -216,37 +349,30 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
                 const int off = (d * TW + (q & 7) % TW) * N + kd;
                 const u32x4 uh = *reinterpret_cast<const u32x4*>(&sB[sl][0][form][off]);
                 const u32x4 ul = *reinterpret_cast<const u32x4*>(&sB[sl][1][form][off]);
-                acc = HF::mma(a[ks], uh, acc);
-                acc = HF::mma(a[ks], ul, acc);
+                if (d == 2 || d == 4) {
+                    acb = HF::mma(a[ks], uh, acb);
+                    acb = HF::mma(a[ks], ul, acb);
+                } else {
+                    acc = HF::mma(a[ks], uh, acc);
+                    acc = HF::mma(a[ks], ul, acc);
+                }
             }
+        }
+        {
+            const float si = minus ? -1.f : 1.f;   // rows i0..i0+3 share the chirality
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] += si * acb[e];
         }
         // lanes q and q^8 hold the real and imaginary parts of the same outputs
         f32x4 p;
 #pragma unroll
         for (int e = 0; e < 4; ++e) p[e] = __shfl_xor(acc[e], 8, 64);
         const bool wr = valid_site && !imag_col && col_ok(cbase + (q & 7));
-        const int c = wr ? cbase + (q & 7) : 0;
-        const int rhs = c / Ls, s = c - rhs * Ls;
-        const int i0 = 16 * m + 4 * kg;
-        const bool minus = (i0 >= H);
-        const bool from_up = DAG ? !minus : minus;
-        int so;
-        float f = 1.f;
-        if (from_up) { so = s + 1; if (so == Ls) { so = 0; f = mwrap; } }
-        else         { so = s - 1; if (so < 0) { so = Ls - 1; f = mwrap; } }
-        if (wr) {   // (only the writing lanes load the site-local terms)
-            float cr[4], ci[4], hr[4], hi[4];
-            load4<T>(in + ((uint32_t)c * nsites + site) * N + i0, cr, ci);
-            load4<T>(in + ((uint32_t)(rhs * Ls + so) * nsites + site) * N + i0, hr, hi);
-            cpx<T>* dst = out + ((uint32_t)c * nsites + site) * N + i0;
+        if (wr) {
+            cpx<T>* dst = out + ((uint32_t)cl * nsites + site) * N + i0;
+            const float u = unscale * osg;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                float re = acc[e] * unscale, im = p[e] * unscale;
-                if (DAG && minus) { re = -re; im = -im; }
-                re += cdiag * cr[e] + f * hr[e];
-                im += cdiag * ci[e] + f * hi[e];
-                dst[e] = {(T)re, (T)im};
-            }
+            for (int e = 0; e < 4; ++e) dst[e] = {(T)(acc[e] * u), (T)(p[e] * u)};
         }
         __syncthreads();   // sB and smax are rewritten for the next column tile
     }
@@ -265,7 +391,7 @@ hipError_t launch_n(const void* links, const cpx<T>* in, cpx<T>* out, const Coar
     const float cd = (float)(M5 + 1.0), mw = (float)(-m);
     // the kernel indexes the vectors and links with 32-bit offsets
     const double vec_bytes = (double)g.Ls * ncol * nsites * N * sizeof(cpx<T>);
-    const double link_bytes = (double)nsites * 5 * N * N * 4;
+    const double link_bytes = (double)nsites * 3 * N * N * 4;
     if (vec_bytes >= 4294967296.0 || link_bytes >= 4294967296.0) return hipErrorInvalidValue;
     if (g.Ls * ncol <= 2) {   // one tile of 2 columns (one right-hand side on 2 coarse slices)
         if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true, 2>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
@@ -305,13 +431,16 @@ hipError_t coarse_apply_mfma(const void* links, int link_prec, const cpx<T>* in,
     return launch_p<false, T>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
 }
 
-// FP64 column layout blk[k][i] -> fragment order [site][m][ks][lane][e] complex 16-bit pairs
+size_t links_fragment16_entries(int nsites, int n) { return (size_t)nsites * 3 * n * n; }
+
+// FP64 column layout blk[d][k][i] (d: 0 site, 1 +x, 2 -x, 3 +y, 4 -y) -> fragment order
+// [site][m][ks][lane][e] of the site term and the forward hops, complex 16-bit pairs
 // (round to nearest even); see the layout note at the top of this file
 __global__ void k_links_fragment16(const cpx<double>* in, uint32_t* out, int nsites, int n, int f16) {
-    const long long total = (long long)nsites * 5 * n * n;
+    const long long total = (long long)nsites * 3 * n * n;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const int ks_n = 5 * n / 16;
+    const int ks_n = 3 * n / 16;
     const int e = (int)(t & 3);
     const int lane = (int)((t >> 2) & 63);
     const long long frag = t >> 8;                     // (site * (n/16) + m) * ks_n + ks
@@ -321,7 +450,8 @@ __global__ void k_links_fragment16(const cpx<double>* in, uint32_t* out, int nsi
     const int site = (int)(sm / (n / 16));
     const int i = 16 * m + (lane & 15);
     const int j = 16 * ks + 4 * (lane >> 4) + e;
-    const int d = j / n, k = j - d * n;
+    const int h = j / n, k = j - h * n;
+    const int d = (h == 2) ? 3 : h;                    // stored hops: site, +x, +y
     const cpx<double> v = in[(((size_t)site * 5 + d) * n + k) * n + i];
     uint32_t re, im;
     if (f16) {
@@ -336,7 +466,7 @@ __global__ void k_links_fragment16(const cpx<double>* in, uint32_t* out, int nsi
 
 hipError_t convert_links_fragment16(const cpx<double>* in, void* out, int link_prec, int nsites, int n, hipStream_t st) {
     if (n % 16) return hipErrorInvalidValue;
-    const long long total = (long long)nsites * 5 * n * n;
+    const long long total = (long long)links_fragment16_entries(nsites, n);
     hipLaunchKernelGGL(k_links_fragment16, dim3(grid_for(total)), dim3(kBlock), 0, st, in, (uint32_t*)out, nsites, n,
                        link_prec == P_F16 ? 1 : 0);
     return hipGetLastError();

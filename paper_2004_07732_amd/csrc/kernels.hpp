@@ -17,6 +17,10 @@ std::recursive_mutex& runtime_mutex();
 // ------------------------------------------------------------ reductions
 // Deterministic two-kernel reduction: every block writes its partial sums to
 // `partial`; a one-block-per-column finaliser adds them in block order.
+// Partial-sum blocks per column: enough waves in flight to stream a coarse
+// vector (a few MB) at full bandwidth, few enough that a finaliser adds the
+// partials of one quantity with a handful of loads per thread.
+constexpr int kRedBlocks = 2048;
 struct RedWork {
     double* partial = nullptr;     // [ncol][nq][nblk]
     int nblk = 0;                  // blocks per column
@@ -51,6 +55,14 @@ hipError_t wilson2d(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int 
 struct CoarseGeom {
     int Lx, Ly, Ls, n;             // coarse extents and dof per site (n = 2 nvec)
 };
+// largest coarse fifth extent (the bulk transfer keeps the fine Ls on every level)
+constexpr int kMaxCoarseLs = 32;
+// LDS entries (complex, arithmetic type) per wavefront of the VALU coarse kernel:
+// the five staged neighbour vectors of all slices, then the partition sums of
+// one pass of 8 slices when 64 / n > 1 lanes share a row
+__host__ __device__ constexpr int coarse_lds_per_wave(int n, int Ls) {
+    return 5 * n * Ls + ((n <= 64 && 64 / n > 1) ? 8 * 64 : 0);
+}
 template <typename T>
 hipError_t coarse_apply(const void* links, int link_prec, const cpx<T>* in, cpx<T>* out,
                         const CoarseGeom& g, int ncol, double m, double M5, bool dagger,
@@ -65,6 +77,9 @@ hipError_t coarse_apply_mfma(const void* links, int link_prec, const cpx<T>* in,
                              int ncol, double m, double M5, bool dagger, const int* skip, int sks, hipStream_t st);
 hipError_t convert_links_fragment16(const cpx<double>* in, void* out, int link_prec, int nsites, int n,
                                     hipStream_t st);
+// complex 16-bit entries of that storage: the site term and the two forward hops
+// (the backward hops are the sigma_3-adjoints of the neighbours' forward hops)
+size_t links_fragment16_entries(int nsites, int n);
 
 // ------------------------------------------------------------ BLAS-1 (T = float/double)
 template <typename T> hipError_t vzero(cpx<T>* x, size_t n, hipStream_t st);

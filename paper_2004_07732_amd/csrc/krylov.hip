@@ -81,7 +81,7 @@ int krylov_solve(const cpx<double>* U, const cpx<double>* b, cpx<double>* x, int
     const size_t n = (size_t)Lx * Ly * Ls * 2;   // complex entries of one 5-d field
     Work w;
     RedWork rw{};
-    rw.nblk = 512;
+    rw.nblk = kRedBlocks;
     rw.max_q = 4;
     rw.max_cols = 1;
     double* dres = nullptr;

@@ -283,7 +283,7 @@ int Hierarchy::alloc_level_work(int l, int ncol) {
 
 int Hierarchy::ensure_scalars(int maxc) {
     if (maxc <= scal_cols_) return DWF_OK;
-    rw_.nblk = 512;
+    rw_.nblk = kRedBlocks;
     rw_.max_q = 40;
     rw_.max_cols = maxc;
     rw_.partial = (double*)dalloc(sizeof(double) * (size_t)maxc * rw_.max_q * rw_.nblk);
@@ -705,9 +705,10 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
         if (c.link_prec == P_F64) {
             c.links = c.links64;
         } else {
-            c.links = dalloc(cplx_bytes(c.link_prec) * nl);
+            const bool frag = coarse_mfma_supported(c.n, c.link_prec);
+            c.links = dalloc(cplx_bytes(c.link_prec) * (frag ? links_fragment16_entries(c.nsites, c.n) : nl));
             if (!c.links) return DWF_EHIP;
-            if (coarse_mfma_supported(c.n, c.link_prec))
+            if (frag)
                 HIPCHK(convert_links_fragment16(c.links64, c.links, c.link_prec, c.nsites, c.n, st));
             else
                 HIPCHK(convert_links(c.links64, c.links, c.link_prec, nl, st));

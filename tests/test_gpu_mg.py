@@ -95,6 +95,24 @@ def test_coarse_operators_fp64(op, level):
     assert rel(got, want) < 1e-13
 
 
+@pytest.mark.parametrize("op", ["dw", "dw_dag", "A"])
+@pytest.mark.parametrize("nvec,block,Lsc", [(4, (4, 4), 12), (24, (8, 4), 10), (2, (4, 4), 17)])
+def test_coarse_operators_fp64_long_fifth_dimension(op, nvec, block, Lsc):
+    """FP64 coarse operator on coarse fifth extents that take two or three passes of
+    the kernel's 8-slice loop (with and without lanes sharing a row)."""
+    m, M5 = 0.05, -1.0
+    U, mg, omg = build_pair(16, 4, m, M5, [(nvec, block, Lsc)], 325)
+    lev = omg.levels[1]
+    info = mg.info(1)
+    ncol = 2
+    x = inputs.gaussian_field((ncol, info["Ls"], info["Ly"], info["Lx"], info["n"]), 326)
+    code = {"dw": dwfmg.MG_OP_DW, "dw_dag": dwfmg.MG_OP_DW_DAG, "A": dwfmg.MG_OP_A}[op]
+    got = mg.level_op(1, code, T(x), ncol).cpu().numpy()
+    want = {"dw": lambda: lev.dw(x, m, M5), "dw_dag": lambda: lev.dw(x, m, M5, dagger=True),
+            "A": lambda: omg.A(1, x)}[op]()
+    assert rel(got, want) < 1e-13
+
+
 @pytest.mark.parametrize("level", [0, 1])
 def test_wall_transfer_parity(level):
     U, mg, omg = build_pair(16, 6, 0.05, -1.0, LEVELS_3, 330)
@@ -174,7 +192,10 @@ def bf16_stencil(S, prec="bf16"):
                                                            # one tile of at most 2 columns
                                                            (16, 1, "f64", (4, 4), 2), (16, 1, "f32", (4, 4), 2),
                                                            (24, 1, "f64", (8, 4), 2), (8, 1, "f64", (4, 4), 2),
-                                                           (16, 2, "f64", (4, 4), 2)])
+                                                           (16, 2, "f64", (4, 4), 2),
+                                                           # coarse fifth extents beyond one 8-slice pass
+                                                           (16, 1, "f64", (4, 4), 12), (8, 2, "f32", (4, 4), 16),
+                                                           (6, 1, "f64", (4, 4), 12)])
 @pytest.mark.parametrize("op", ["dw", "dw_dag", "A"])
 @pytest.mark.parametrize("lprec", ["bf16", "f16"])
 def test_coarse_bf16_matrix_core_parity(nvec, ncol, vec_prec, block, Lsc, op, lprec):

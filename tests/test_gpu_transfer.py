@@ -116,3 +116,51 @@ def test_bulk_and_wall_transfer_solves():
         assert res <= 1e-10
         counts[transfer] = (st.fine_iters, st.fine_applies, st.level_iters[0])
     print(f"64^2 x 8, L^_s 8: wall {counts['wall']}, bulk {counts['bulk']} (fine iters, fine applies, coarse iters)")
+
+
+def test_bulk_transfer_at_fifth_extent_16():
+    """The bulk transfer keeps L^_s = L_s = 16 on the coarse level, beyond one pass
+    of the coarse kernels' slice loop; the solve reaches 1e-10 like the wall transfer."""
+    L, Ls, m, M5 = 32, 16, 0.02, -1.0
+    U = inputs.metropolis_u1(L, L, 6.0, 100, 931).U
+    b = inputs.gaussian_field((1, Ls, L, L, 2), 930)
+    start = inputs.gaussian_field((8, L, L, 2), 932)
+    counts = {}
+    for transfer, code in (("wall", dwfmg.TRANSFER_WALL), ("bulk", dwfmg.TRANSFER_BULK)):
+        p = dwfmg.MGParams(nvec=[8], block=[(4, 4)], Ls_coarse=[Ls], transfer=code)
+        mg = dwfmg.MG(T(U), Ls, m, M5, p, [T(start)])
+        x, st = mg.solve(T(b), 1e-10)
+        res = np.linalg.norm(b[0] - O.dwf(U, x[0].cpu().numpy(), m, M5)) / np.linalg.norm(b[0])
+        assert res <= 1e-10
+        counts[transfer] = (st.fine_iters, st.fine_applies, st.level_iters[0])
+    print(f"32^2 x 16, L^_s 16: wall {counts['wall']}, bulk {counts['bulk']} (fine iters, fine applies, coarse iters)")
+
+
+def test_wall_transfer_coarse_ls_sweep():
+    """Sec. 4.2: with the wall-only transfer the coarse fifth extent is free.  Every
+    L^_s from 2 to 32 preconditions the 32^2 x 16 solve to 1e-10 (mixed precision,
+    BF16 coarse links); the counts are printed."""
+    L, Ls, m, M5 = 32, 16, 0.02, -1.0
+    U = inputs.metropolis_u1(L, L, 6.0, 100, 941).U
+    b = inputs.gaussian_field((1, Ls, L, L, 2), 940)
+    start = inputs.gaussian_field((8, L, L, 2), 942)
+    counts = {}
+    for Lsc in (2, 4, 8, 12, 16, 32):
+        # the mixed-precision form: BF16 coarse links on the matrix cores
+        p = dwfmg.MGParams(nvec=[8], block=[(4, 4)], Ls_coarse=[Lsc], link_prec=[dwfmg.P_BF16],
+                           vec_prec=[dwfmg.P_F64], fine_prec=dwfmg.P_F32)
+        mg = dwfmg.MG(T(U), Ls, m, M5, p, [T(start)])
+        x, st = mg.solve(T(b), 1e-10)
+        res = np.linalg.norm(b[0] - O.dwf(U, x[0].cpu().numpy(), m, M5)) / np.linalg.norm(b[0])
+        assert res <= 1e-10, (Lsc, res)
+        counts[Lsc] = (st.fine_iters, st.level_iters[0])
+    print(f"32^2 x 16 wall transfer, L^_s -> (fine iters, coarse iters): {counts}")
+
+
+def test_coarse_ls_limits():
+    L, Ls = 8, 4
+    U = inputs.metropolis_u1(L, L, 6.0, 10, 951).U
+    start = inputs.gaussian_field((2, L, L, 2), 952)
+    for bad in (1, 33):
+        with pytest.raises(dwfmg.DwfError):
+            dwfmg.MG(T(U), Ls, 0.05, -1.0, dwfmg.MGParams(nvec=[2], block=[(4, 4)], Ls_coarse=[bad]), [T(start)])
