@@ -538,6 +538,25 @@ def prolong_wall(P: Prolongator, ec: np.ndarray, chir_f: np.ndarray, Ls_f: int) 
     return chiral_permute(perm, chir_f)
 
 
+def restrict_slice1(P: Prolongator, r: np.ndarray, Ls_c: int) -> np.ndarray:
+    """The other reading of eq. TruncProjectInterpolate's "s = 1", kept as a
+    test toggle: both chiralities of the unpermuted fine slice 1, restricted by
+    the 2-d P^dagger onto the unpermuted coarse slice 1, zero elsewhere (no
+    chiral permutation on either level)."""
+    wc = restrict2d(P, r[..., 0, :, :, :])
+    chat = np.zeros(r.shape[:-4] + (Ls_c,) + wc.shape[-3:], dtype=np.complex128)
+    chat[..., 0, :, :, :] = wc
+    return chat
+
+
+def prolong_slice1(P: Prolongator, ec: np.ndarray, Ls_f: int) -> np.ndarray:
+    """Adjoint of restrict_slice1: P applied to coarse slice 1 onto fine slice 1."""
+    wf = prolong2d(P, ec[..., 0, :, :, :])
+    e = np.zeros(ec.shape[:-4] + (Ls_f,) + wf.shape[-3:], dtype=np.complex128)
+    e[..., 0, :, :, :] = wf
+    return e
+
+
 # ----------------------------------------------------------------------------
 # Krylov solvers (Sec. 3, Table kcycle)
 # ----------------------------------------------------------------------------
@@ -747,7 +766,8 @@ class MGParams:
     inter_restart: int = 16
     coarsest_tol: float = 0.05
     coarsest_maxit: int = 1024
-    transfer: str = "wall"         # "wall": eq. TruncProjectInterpolate; "bulk": Sec. 4.1's alternative
+    transfer: str = "wall"         # "wall": eq. TruncProjectInterpolate; "bulk": Sec. 4.1's alternative;
+                                   # "slice1": the literal unpermuted slice 1 (test toggle)
 
 
 @dataclass
@@ -814,12 +834,16 @@ class MG:
         lev = self.levels[l]
         if self.params.transfer == "bulk":
             return restrict_bulk(lev.P, r)
+        if self.params.transfer == "slice1":
+            return restrict_slice1(lev.P, r, self.levels[l + 1].Ls)
         return restrict_wall(lev.P, r, lev.chir, self.levels[l + 1].Ls)
 
     def prolong(self, l, e):
         lev = self.levels[l]
         if self.params.transfer == "bulk":
             return prolong_bulk(lev.P, e)
+        if self.params.transfer == "slice1":
+            return prolong_slice1(lev.P, e, lev.Ls)
         return prolong_wall(lev.P, e, lev.chir, lev.Ls)
 
     def local_colinearity(self, v):

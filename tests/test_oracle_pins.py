@@ -492,6 +492,35 @@ def test_wall_transfer_adjoint_and_identity():
     assert np.max(np.abs(back - ew)) < 1e-14
 
 
+def test_slice1_transfer_against_the_wall_transfer():
+    """The literal-slice toggle: adjoint pair, R P = 1 on coarse slice 1, support on
+    slice 1 only, and on a field that lives on slice 1 with chirality - only it is
+    exactly the wall transfer (which takes chirality - from slice 1 and
+    chirality + from slice Ls); with chirality + on slice 1 the two differ."""
+    L, Ls, Lsc, nvec = 8, 6, 4, 3
+    P = make_prolongator(L, (4, 4), nvec, 1, 74)
+    chir = np.array([1.0, -1.0])
+    r = cgauss((Ls, L, L, 2), 75)
+    e = cgauss((Lsc, 2, 2, 2 * nvec), 76)
+    Pe = O.prolong_slice1(P, e, Ls)
+    Rr = O.restrict_slice1(P, r, Lsc)
+    assert abs(np.vdot(Pe, r) - np.vdot(e, Rr)) < 1e-12 * np.linalg.norm(r) * np.linalg.norm(e)
+    assert np.all(Pe[1:] == 0) and np.all(Rr[1:] == 0)
+    e1 = np.zeros_like(e)
+    e1[0] = e[0]
+    assert np.max(np.abs(O.restrict_slice1(P, O.prolong_slice1(P, e1, Ls), Lsc) - e1)) < 1e-14
+    r2 = r.copy()
+    r2[1:] = cgauss((Ls - 1, L, L, 2), 77)       # other slices do not enter
+    assert np.array_equal(O.restrict_slice1(P, r2, Lsc), Rr)
+    rm = np.zeros_like(r)
+    rm[0][..., 1] = r[0][..., 1]                  # chirality - on slice 1
+    assert np.max(np.abs(O.restrict_slice1(P, rm, Lsc) - O.restrict_wall(P, rm, chir, Lsc))) < 1e-14
+    rp = np.zeros_like(r)
+    rp[0][..., 0] = r[0][..., 0]                  # chirality + on slice 1: the wall transfer ignores it
+    assert np.linalg.norm(O.restrict_wall(P, rp, chir, Lsc)) == 0.0
+    assert np.linalg.norm(O.restrict_slice1(P, rp, Lsc)) > 0.1 * np.linalg.norm(rp)
+
+
 def test_bulk_transfer_adjoint_identity_and_range():
     """The bulk transfer of Sec. 4.1: R P = 1 (P^dag P = 1 per slice), P is the
     adjoint of R, and a field in the range of P has zero local colinearity."""
