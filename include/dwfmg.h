@@ -72,6 +72,7 @@ extern "C" {
 /* transfer between levels */
 #define DWF_TRANSFER_WALL 0
 #define DWF_TRANSFER_BULK 1
+#define DWF_TRANSFER_SLICE1 2
 
 /* coarsest-level solver */
 #define DWF_COARSEST_CGNR 0
@@ -210,7 +211,13 @@ typedef struct {
                                              paper's method); DWF_TRANSFER_BULK: the 2-d
                                              prolongator on every slice (Sec. 4.1's
                                              alternative; needs Ls_coarse equal to the
-                                             finer level's Ls on every level)          */
+                                             finer level's Ls on every level);
+                                             DWF_TRANSFER_SLICE1: a test toggle for the
+                                             reading of the transfer's "s = 1": both
+                                             chiralities on the unpermuted first slice
+                                             (fine and coarse) instead of the wall pair
+                                             P- psi_1 + P+ psi_Ls of the permuted basis
+                                             (Sec. 2.2)                                */
     int    pv_poly_order;                 /* 0: the fine-level operator is the paper's
                                              A = D_PV^dag D_DW; K = 1..DWF_PV_POLY_MAX:
                                              A_p = D_PV^dag p(D_PV D_PV^dag) D_DW with

@@ -281,7 +281,8 @@ int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, do
     if (p->coarsest_solver == DWF_COARSEST_GCR && (p->coarsest_restart < 1 || p->coarsest_restart > 16))
         return DWF_EINVAL;
     if (p->coarsest_solver == DWF_COARSEST_GCR && p->coarsest_nev > 0) return DWF_EUNSUPPORTED;
-    if (p->transfer != DWF_TRANSFER_WALL && p->transfer != DWF_TRANSFER_BULK) return DWF_EINVAL;
+    if (p->transfer != DWF_TRANSFER_WALL && p->transfer != DWF_TRANSFER_BULK && p->transfer != DWF_TRANSFER_SLICE1)
+        return DWF_EINVAL;
     if (p->pv_poly_order < 0 || p->pv_poly_order > DWF_PV_POLY_MAX) return DWF_EINVAL;
     for (int k = 0; k <= p->pv_poly_order; ++k)
         if (!std::isfinite(p->pv_poly[k])) return DWF_EINVAL;

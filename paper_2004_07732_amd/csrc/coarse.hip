@@ -32,9 +32,10 @@ coarse_kernel(const L* __restrict__ links, const cpx<T>* __restrict__ in, cpx<T>
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int site = (int)xcd_block(blockIdx.x, gridDim.x) * wpb + wave;
     const int col = blockIdx.y;
-    // per wave: the five staged neighbour vectors, then (P > 1) the partition sums of one pass
+    // per wave: the five staged neighbour vectors; the partition sums of a pass (P > 1)
+    // follow them, or with a single pass overwrite them
     cpx<A>* my = reinterpret_cast<cpx<A>*>(smem_raw) + (size_t)wave * coarse_lds_per_wave(N, Ls);
-    cpx<A>* scr = my + (size_t)5 * N * Ls;
+    cpx<A>* scr = (Ls <= MAXS) ? my : my + (size_t)5 * N * Ls;
     const bool valid = (site < nsites) && !(skip && skip[(size_t)col * skip_stride]);
 
     int nb[5] = {0, 0, 0, 0, 0};
@@ -77,6 +78,7 @@ coarse_kernel(const L* __restrict__ links, const cpx<T>* __restrict__ in, cpx<T>
         }
         // partition sums in a fixed order
         if (P > 1) {
+            if (Ls <= MAXS) __syncthreads();   // (they overwrite the staged vectors)
             if (valid && part < P) {
 #pragma unroll
                 for (int s = 0; s < MAXS; ++s)

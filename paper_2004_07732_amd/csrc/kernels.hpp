@@ -58,10 +58,11 @@ struct CoarseGeom {
 // largest coarse fifth extent (the bulk transfer keeps the fine Ls on every level)
 constexpr int kMaxCoarseLs = 32;
 // LDS entries (complex, arithmetic type) per wavefront of the VALU coarse kernel:
-// the five staged neighbour vectors of all slices, then the partition sums of
-// one pass of 8 slices when 64 / n > 1 lanes share a row
+// the five staged neighbour vectors of all slices, and the partition sums of a
+// pass of 8 slices when 64 / n > 1 lanes share a row.  With one pass (Ls <= 8)
+// the sums overwrite the staged vectors, which are dead by then.
 __host__ __device__ constexpr int coarse_lds_per_wave(int n, int Ls) {
-    return 5 * n * Ls + ((n <= 64 && 64 / n > 1) ? 8 * 64 : 0);
+    return Ls <= 8 ? ((5 * n > 64) ? 5 * n : 64) * Ls : 5 * n * Ls + ((n <= 64 && 64 / n > 1) ? 8 * 64 : 0);
 }
 template <typename T>
 hipError_t coarse_apply(const void* links, int link_prec, const cpx<T>* in, cpx<T>* out,
@@ -182,6 +183,7 @@ struct TransferGeom {
     int nc;                // internal dof per chirality on the fine level
     int bx, by;            // aggregate
     int Lsc, nvec;         // coarse fifth extent, coarse vectors per chirality
+    int literal = 0;       // 1: both chiralities on the unpermuted first slice (test toggle)
 };
 template <typename T>
 hipError_t restrict_wall(const cpx<T>* V, const cpx<T>* r, cpx<T>* rc, const TransferGeom& g, int ncol, hipStream_t st);

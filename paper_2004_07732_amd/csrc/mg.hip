@@ -187,6 +187,7 @@ hipError_t Hierarchy::restrict_to(int l, const cpx<T>* r, void* rc_next, int nco
     const Level& L = levels[l];
     const Level& N = levels[l + 1];
     TransferGeom g{L.Lx, L.Ly, L.Ls, L.n / 2, L.bx, L.by, N.Ls, L.nvec_next};
+    g.literal = prm.transfer == DWF_TRANSFER_SLICE1 ? 1 : 0;
     const cpx<T>* V;
     if constexpr (std::is_same<T, float>::value) V = L.V32; else V = L.V64;
     const bool bulk = prm.transfer == DWF_TRANSFER_BULK;
@@ -205,6 +206,7 @@ hipError_t Hierarchy::prolong_from(int l, const void* ec_next, cpx<T>* e, int nc
     const Level& L = levels[l];
     const Level& N = levels[l + 1];
     TransferGeom g{L.Lx, L.Ly, L.Ls, L.n / 2, L.bx, L.by, N.Ls, L.nvec_next};
+    g.literal = prm.transfer == DWF_TRANSFER_SLICE1 ? 1 : 0;
     const cpx<T>* V;
     if constexpr (std::is_same<T, float>::value) V = L.V32; else V = L.V64;
     const bool bulk = prm.transfer == DWF_TRANSFER_BULK;

@@ -29,8 +29,9 @@ __global__ void k_restrict_wall(const cpx<T>* __restrict__ V, const cpx<T>* __re
     const int c = a / g.nvec, k = a - c * g.nvec;
     const int X = cs % cX, Y = cs / cX;
     const int V2 = g.Lx * g.Ly;
-    // chirality - comes from fine slice 1, chirality + from fine slice Ls
-    const int sf = (c == 1) ? 0 : g.Ls - 1;
+    // chirality - comes from fine slice 1, chirality + from fine slice Ls (the
+    // literal toggle takes both from fine slice 1)
+    const int sf = (c == 1 || g.literal) ? 0 : g.Ls - 1;
     const cpx<T>* rs = r + ((size_t)col * g.Ls + sf) * V2 * nf;
     cpx<double> acc = {0.0, 0.0};
     for (int by = 0; by < g.by; ++by)
@@ -44,7 +45,7 @@ __global__ void k_restrict_wall(const cpx<T>* __restrict__ V, const cpx<T>* __re
             }
         }
     cpx<T>* out = rc + (size_t)col * g.Lsc * csites * ncd;
-    const int swall = (c == 1) ? 0 : g.Lsc - 1;
+    const int swall = (c == 1 || g.literal) ? 0 : g.Lsc - 1;
     for (int s = 0; s < g.Lsc; ++s) {
         cpx<T> v = {T(0), T(0)};
         if (s == swall) v = {(T)acc.re, (T)acc.im};
@@ -69,7 +70,7 @@ __global__ void k_prolong_wall(const cpx<T>* __restrict__ V, const cpx<T>* __res
     const int c = af / g.nc, j = af - c * g.nc;
     const int x = site % g.Lx, y = site / g.Lx;
     const int cs = (y / g.by) * cX + x / g.bx;
-    const int swall_c = (c == 1) ? 0 : g.Lsc - 1;
+    const int swall_c = (c == 1 || g.literal) ? 0 : g.Lsc - 1;
     const cpx<T>* ev = ec + (((size_t)col * g.Lsc + swall_c) * csites + cs) * ncd + c * g.nvec;
     const cpx<T>* vrow = V + (((size_t)site * 2 + c) * g.nc + j) * g.nvec;
     cpx<double> acc = {0.0, 0.0};
@@ -79,7 +80,7 @@ __global__ void k_prolong_wall(const cpx<T>* __restrict__ V, const cpx<T>* __res
         acc.im += (double)v.re * x.im + (double)v.im * x.re;
     }
     cpx<T>* out = e + (size_t)col * g.Ls * V2 * nf;
-    const int swall_f = (c == 1) ? 0 : g.Ls - 1;
+    const int swall_f = (c == 1 || g.literal) ? 0 : g.Ls - 1;
     for (int s = 0; s < g.Ls; ++s) {
         cpx<T> v = {T(0), T(0)};
         if (s == swall_f) v = {(T)acc.re, (T)acc.im};

@@ -37,7 +37,7 @@ MG_OP_DW, MG_OP_DW_DAG, MG_OP_PV, MG_OP_PV_DAG, MG_OP_A = 0, 1, 2, 3, 4
 MG_OP_WILSON, MG_OP_WILSON_DAG, MG_OP_RESTRICT, MG_OP_PROLONG, MG_OP_KCYCLE = 5, 6, 7, 8, 9
 COARSEST_CGNR, COARSEST_GCR = 0, 1
 KRYLOV_CGNR, KRYLOV_BICGSTAB = 0, 1
-TRANSFER_WALL, TRANSFER_BULK = 0, 1
+TRANSFER_WALL, TRANSFER_BULK, TRANSFER_SLICE1 = 0, 1, 2
 PV_POLY_MAX = 3
 FINE_AUTO, FINE_ROW, FINE_TILE_64x8, FINE_TILE_32x16, FINE_TILE_128x4 = -1, 0, 1, 2, 3
 
@@ -188,7 +188,8 @@ class MGParams:
     eig_tol: float = 1e-3
     coarsest_solver: int = COARSEST_CGNR   # CGNR on A^dag A (Table 2), or COARSEST_GCR: GCR on A
     coarsest_restart: int = 16
-    transfer: int = 0              # TRANSFER_WALL (the paper's method) or TRANSFER_BULK (Sec. 4.1)
+    transfer: int = 0              # TRANSFER_WALL (the paper's method), TRANSFER_BULK (Sec. 4.1) or
+                                   # TRANSFER_SLICE1 (the literal-slice reading, a test toggle)
     pv_poly: Optional[List[float]] = None   # c_0..c_K of the PV polynomial on the fine level (None: A itself)
 
     @property

@@ -32,7 +32,7 @@ def pair(L, Ls, m, levels, seed, transfer, beta=6.0, **kw):
         starts.append(inputs.gaussian_field((nv, Lc, Lc, n), seed + 10 + li))
         Lc //= bx
         n = 2 * nv
-    code = dwfmg.TRANSFER_BULK if transfer == "bulk" else dwfmg.TRANSFER_WALL
+    code = {"wall": dwfmg.TRANSFER_WALL, "bulk": dwfmg.TRANSFER_BULK, "slice1": dwfmg.TRANSFER_SLICE1}[transfer]
     params = dwfmg.MGParams(nvec=[l[0] for l in levels], block=[l[1] for l in levels],
                             Ls_coarse=[l[2] for l in levels], link_prec=[dwfmg.P_F64] * len(levels),
                             vec_prec=[dwfmg.P_F64] * len(levels), fine_prec=dwfmg.P_F64, setup_iters=0, transfer=code,
@@ -46,8 +46,11 @@ def pair(L, Ls, m, levels, seed, transfer, beta=6.0, **kw):
 
 
 @pytest.mark.parametrize("level", [0, 1])
-def test_bulk_transfer_parity(level):
-    U, mg, omg = pair(16, 4, 0.05, [(4, (4, 4), 4), (2, (2, 2), 4)], 900, "bulk")
+@pytest.mark.parametrize("transfer", ["bulk", "slice1"])
+def test_transfer_variant_parity(level, transfer):
+    """Bulk transfer and the literal-slice toggle against the oracle on both levels."""
+    Lsc = (4, 4) if transfer == "bulk" else (3, 2)
+    U, mg, omg = pair(16, 4, 0.05, [(4, (4, 4), Lsc[0]), (2, (2, 2), Lsc[1])], 900, transfer)
     f, c = mg.info(level), mg.info(level + 1)
     r = inputs.gaussian_field((2, f["Ls"], f["Ly"], f["Lx"], f["n"]), 901)
     e = inputs.gaussian_field((2, c["Ls"], c["Ly"], c["Lx"], c["n"]), 902)
@@ -65,7 +68,7 @@ def test_bulk_transfer_requires_full_coarse_ls():
         dwfmg.MG(T(U), 4, 0.05, -1.0, p, [T(s)])
 
 
-@pytest.mark.parametrize("transfer", ["wall", "bulk"])
+@pytest.mark.parametrize("transfer", ["wall", "bulk", "slice1"])
 def test_diagnostics_match_oracle(transfer):
     """Local colinearity |(1 - P R) v| and oblique projector |(1 - P hat-A^{-1} R A) v|
     for low right eigenvectors v of the fine A (dense eigensolve) and a random
@@ -164,3 +167,26 @@ def test_coarse_ls_limits():
     for bad in (1, 33):
         with pytest.raises(dwfmg.DwfError):
             dwfmg.MG(T(U), Ls, 0.05, -1.0, dwfmg.MGParams(nvec=[2], block=[(4, 4)], Ls_coarse=[bad]), [T(start)])
+
+
+def test_literal_slice1_reading_against_the_wall_pair():
+    """The reading of the transfer's "s = 1" (slice 1 of the chirally permuted basis,
+    i.e. P- psi_1 + P+ psi_Ls) against the literal unpermuted slice 1 (a test toggle):
+    both are run on the same 32^2 x 16 problem and the counts printed.  The wall pair
+    must reach 1e-10; the literal slice is reported as it comes out (converged with its
+    residual at tol, or stopped at the iteration cap)."""
+    L, Ls, m, M5 = 32, 16, 0.02, -1.0
+    U = inputs.metropolis_u1(L, L, 6.0, 100, 961).U
+    b = inputs.gaussian_field((1, Ls, L, L, 2), 960)
+    start = inputs.gaussian_field((8, L, L, 2), 962)
+    out = {}
+    for name, code in (("wall pair", dwfmg.TRANSFER_WALL), ("literal slice 1", dwfmg.TRANSFER_SLICE1)):
+        p = dwfmg.MGParams(nvec=[8], block=[(4, 4)], Ls_coarse=[4], transfer=code, max_iters=300)
+        mg = dwfmg.MG(T(U), Ls, m, M5, p, [T(start)])
+        x, st = mg.solve(T(b), 1e-10, check=False)
+        res = np.linalg.norm(b[0] - O.dwf(U, x[0].cpu().numpy(), m, M5)) / np.linalg.norm(b[0])
+        out[name] = (st.status, st.fine_iters, st.level_iters[0], res)
+        if st.status == 0:
+            assert res <= 1e-10
+    print(f"32^2 x 16, L^_s 4 (status, fine iters, coarse iters, true residual): {out}")
+    assert out["wall pair"][0] == 0
