@@ -245,8 +245,8 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         }
         // the site-local terms (a site past the end reads site 0): with one tile last
         // in this group, since the compiler converts them as soon as they arrive and
-        // waiting for them then finds every other load issued; with several tiles
-        // after the LDS barrier, where they need no registers during the staging
+        // waiting for them then finds every other load issued; with several tiles in
+        // the epilogue, by the writing lanes only (measured faster there)
         float cr[4], ci[4], hr[4], hi[4];
         // (only lanes of an existing column slot load: with tiles of 2 or 4 columns
         // the others would repeat column 0, and every lane address costs the address
@@ -324,14 +324,13 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         // (with TW < 8 the B columns TW..7 repeat staged columns and feed only unused outputs)
         // forward hops and site term in acc, backward hops in acb (their row sign s_i
         // is applied below)
-        // The site-local terms start the accumulator: this lane's part (real for
-        // q < 8, imaginary for q >= 8, picked on the bits) of cdiag psi_s + f psi_so,
-        // scaled by 1 / unscale and the adjoint's row sign (both exact), so that the
-        // epilogue needs no load of its own.
-        if (TW == 8) load_local();
+        // With one tile the site-local terms start the accumulator: this lane's part
+        // (real for q < 8, imaginary for q >= 8, picked on the bits) of
+        // cdiag psi_s + f psi_so, scaled by 1 / unscale and the adjoint's row sign
+        // (both exact), so that the epilogue needs no load of its own.
         const float osg = (DAG && minus) ? -1.f : 1.f;
-        f32x4 acc, acb = {0.f, 0.f, 0.f, 0.f};
-        {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f}, acb = {0.f, 0.f, 0.f, 0.f};
+        if (TW < 8) {
             const uint32_t mre = imag_col ? 0u : 0xffffffffu;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -371,8 +370,15 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         if (wr) {
             cpx<T>* dst = out + ((uint32_t)cl * nsites + site) * N + i0;
             const float u = unscale * osg;
+            if (TW == 8) {   // several tiles: the site-local terms are loaded here, by the writing lanes
+                load_local();
 #pragma unroll
-            for (int e = 0; e < 4; ++e) dst[e] = {(T)(acc[e] * u), (T)(p[e] * u)};
+                for (int e = 0; e < 4; ++e)
+                    dst[e] = {(T)(acc[e] * u + cdiag * cr[e] + f * hr[e]), (T)(p[e] * u + cdiag * ci[e] + f * hi[e])};
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dst[e] = {(T)(acc[e] * u), (T)(p[e] * u)};
+            }
         }
         __syncthreads();   // sB and smax are rewritten for the next column tile
     }
