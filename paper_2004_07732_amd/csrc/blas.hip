@@ -92,6 +92,13 @@ inline dim3 ew_grid(size_t n, int ncol) {
 
 #define SHARED_RED __shared__ double sh[kMaxQ * kWaves], tot[kMaxQ]
 
+// calls f(std::integral_constant<int, j>) for a run-time j in Js...
+template <typename F, int... Js>
+void with_j(int j, F&& f, std::integer_sequence<int, Js...>) {
+    ((j == Js ? (f(std::integral_constant<int, Js>{}), 0) : 0), ...);
+}
+
+
 template <typename T>
 __device__ __forceinline__ cpx<double> up(cpx<T> a) { return {(double)a.re, (double)a.im}; }
 
@@ -355,9 +362,9 @@ __device__ __forceinline__ cpx<double> cdiv_real(cpx<double> a, double d) {
 }
 }  // namespace
 
-template <typename T>
+template <typename T, int j>   // (j: directions, a template argument so that every load is unconditional)
 __global__ void __launch_bounds__(kBlock)
-k_gcr_multidot(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w, size_t n, GcrDev g, RedWork rw) {
+k_gcr_multidot(const cpx<T>* W, size_t wstride, const cpx<T>* w, size_t n, GcrDev g, RedWork rw) {
     SHARED_RED;
     const int col = blockIdx.y;
     const size_t o = (size_t)col * n;
@@ -379,9 +386,9 @@ k_gcr_multidot(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w, size_t n
     write_partials<32>(v, 2 * j, rw, col, sh, tot);
 }
 
-template <typename T>
+template <typename T, int j>
 __global__ void __launch_bounds__(kBlock)
-k_gcr_orth(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, const cpx<T>* r, size_t n, GcrDev g, RedWork rw) {
+k_gcr_orth(const cpx<T>* W, size_t wstride, cpx<T>* w, const cpx<T>* r, size_t n, GcrDev g, RedWork rw) {
     SHARED_RED;
     const int col = blockIdx.y;
     const bool stop = g.stop[col] != 0;
@@ -457,12 +464,6 @@ k_gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int wan
         v[0] += rd.re * rd.re + rd.im * rd.im;
     }
     if (want_norm) write_partials<1>(v, 1, rw, col, sh, tot);
-}
-
-// calls f(std::integral_constant<int, j>) for a run-time j in Js...
-template <typename F, int... Js>
-void with_j(int j, F&& f, std::integer_sequence<int, Js...>) {
-    ((j == Js ? (f(std::integral_constant<int, Js>{}), 0) : 0), ...);
 }
 
 // ---- fused GCR iteration (see kernels.hpp); the direction count j is a template
@@ -648,7 +649,9 @@ hipError_t gcr_multidot(const cpx<T>* W, size_t wstride, int j, const cpx<T>* w,
     if (j <= 0) return hipSuccess;
     if (j > 16) return hipErrorInvalidValue;
     dim3 grid = red_grid(n, ncol, rw);
-    hipLaunchKernelGGL(k_gcr_multidot<T>, grid, dim3(kBlock), 0, st, W, wstride, j, w, n, g, rw);
+    with_j(j, [&](auto jc) {
+        hipLaunchKernelGGL((k_gcr_multidot<T, decltype(jc)::value>), grid, dim3(kBlock), 0, st, W, wstride, w, n, g, rw);
+    }, std::make_integer_sequence<int, 17>{});
     hipLaunchKernelGGL(k_fin_store_q, dim3(2 * j, ncol), dim3(kBlock), 0, st, rw, (int)grid.x,
                        g.D + (size_t)j * g.kmax * 2, (size_t)g.kmax * g.kmax * 2);
     return hipGetLastError();
@@ -657,8 +660,11 @@ template <typename T>
 hipError_t gcr_orth(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, const cpx<T>* r, size_t n,
                     int ncol, const GcrDev& g, const RedWork& rw, hipStream_t st) {
     if (j > 16) return hipErrorInvalidValue;
+    if (j < 0) return hipErrorInvalidValue;
     dim3 grid = red_grid(n, ncol, rw);
-    hipLaunchKernelGGL(k_gcr_orth<T>, grid, dim3(kBlock), 0, st, W, wstride, j, w, r, n, g, rw);
+    with_j(j, [&](auto jc) {
+        hipLaunchKernelGGL((k_gcr_orth<T, decltype(jc)::value>), grid, dim3(kBlock), 0, st, W, wstride, w, r, n, g, rw);
+    }, std::make_integer_sequence<int, 17>{});
     hipLaunchKernelGGL(k_fin_gcr_orth, dim3(ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g, j);
     return hipGetLastError();
 }
