@@ -59,6 +59,8 @@ extern "C" {
 #define DWF_PV_DAG      1      /* out = D_PV^dagger psi                              */
 #define DWF_PVDAG_DW    2      /* out = D_PV^dagger D_DW(m) psi   (operator A)       */
 #define DWF_PVDAG_DW_DAG 3     /* out = D_DW(m)^dagger D_PV psi   (A^dagger)         */
+#define DWF_PVINV_DW    4      /* out = D_PV^-1 D_DW(m) psi (the exactly preconditioned
+                                  operator of Sec. 2.2) by an inner CGNR solve      */
 
 /* precision of a multigrid level's storage / arithmetic */
 #define DWF_P_F64   0
@@ -108,7 +110,13 @@ int dwf_fine_config(int shape, int chunk);
 
 /* Pauli-Villars forms (Sec. 2.2, eq. NormalExp): see the DWF_PV* modes.  The
  * product modes use a library-owned intermediate field (allocated on first use
- * and kept until dwf_release_scratch).  Same layout rules as dwf_apply. */
+ * and kept until dwf_release_scratch).  Same layout rules as dwf_apply.
+ * DWF_PVINV_DW (FP64 only; DWF_EUNSUPPORTED with DWF_PREC_F32) applies D_DW(m)
+ * and then solves D_PV out = D_DW psi for each right-hand side by CGNR to a
+ * relative residual of 1e-12 (D_PV is well conditioned: its free-field singular
+ * values are at least 1).  It allocates the solver's work vectors for the
+ * call, synchronises `stream`, and returns DWF_NOT_CONVERGED if the inner solve
+ * stops at its cap of 10000 iterations. */
 int dwf_pv_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs,
                  double m_f, double M5, int mode, int flags, void* stream);
 

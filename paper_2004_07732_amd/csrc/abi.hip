@@ -157,7 +157,28 @@ int dwf_fine_config(int shape, int chunk) { return set_fine_config(shape, chunk)
 int dwf_pv_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, double m_f,
                  double M5, int mode, int flags, void* stream) {
     if (!U || !psi || !out || psi == out || !dims_ok(Lx, Ly, Ls, nrhs)) return DWF_EINVAL;
-    if (!std::isfinite(m_f) || !std::isfinite(M5) || mode < DWF_PV || mode > DWF_PVDAG_DW_DAG) return DWF_EINVAL;
+    if (!std::isfinite(m_f) || !std::isfinite(M5) || mode < DWF_PV || mode > DWF_PVINV_DW) return DWF_EINVAL;
+    if (mode == DWF_PVINV_DW) {
+        if (flags & DWF_PREC_F32) return DWF_EUNSUPPORTED;
+        if (Ls < 2) return DWF_EINVAL;
+        // D_DW psi into the intermediate field, then D_PV out = D_DW psi per right-hand side
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        const size_t V = 2 * (size_t)Lx * Ly * Ls;
+        auto t = reinterpret_cast<cpx<double>*>(scratch(sizeof(cpx<double>) * V * nrhs));
+        if (!t) return DWF_EHIP;
+        const auto u = reinterpret_cast<const cpx<double>*>(U);
+        if (fine_dw<double>(u, reinterpret_cast<const cpx<double>*>(psi), t, nullptr, Lx, Ly, Ls, nrhs, m_f, M5, false,
+                            nullptr, 1, S(stream)) != hipSuccess)
+            return DWF_EHIP;
+        int worst = DWF_OK;
+        for (int r = 0; r < nrhs; ++r) {
+            const int e = krylov_solve(u, t + r * V, reinterpret_cast<cpx<double>*>(out) + r * V, Lx, Ly, Ls, 1.0, M5,
+                                       DWF_KRYLOV_CGNR, 0, 1e-12, 10000, nullptr, S(stream));
+            if (e < 0) return e;
+            if (e > worst) worst = e;
+        }
+        return worst;
+    }
     if (flags & DWF_PREC_F32) return pv_apply_t<float>(U, psi, out, Lx, Ly, Ls, nrhs, m_f, M5, mode, S(stream));
     return pv_apply_t<double>(U, psi, out, Lx, Ly, Ls, nrhs, m_f, M5, mode, S(stream));
 }

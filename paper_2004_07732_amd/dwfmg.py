@@ -29,7 +29,7 @@ DWF_EUNSUPPORTED = -6
 DWF_DAGGER = 1
 DWF_PREC_F32 = 2
 
-DWF_PV, DWF_PV_DAG, DWF_PVDAG_DW, DWF_PVDAG_DW_DAG = 0, 1, 2, 3
+DWF_PV, DWF_PV_DAG, DWF_PVDAG_DW, DWF_PVDAG_DW_DAG, DWF_PVINV_DW = 0, 1, 2, 3, 4
 P_F64, P_F32, P_BF16, P_F16 = 0, 1, 2, 3
 MAX_LEVELS = 3
 
@@ -314,7 +314,8 @@ def dwf_fine_config(shape, chunk=1):
 
 
 def dwf_pv_apply(U, psi, m_f, M5, mode=DWF_PVDAG_DW, out=None, stream=None):
-    """Pauli-Villars forms: DWF_PV, DWF_PV_DAG, DWF_PVDAG_DW (A), DWF_PVDAG_DW_DAG (A^dagger)."""
+    """Pauli-Villars forms: DWF_PV, DWF_PV_DAG, DWF_PVDAG_DW (A), DWF_PVDAG_DW_DAG (A^dagger),
+    DWF_PVINV_DW (D_PV^-1 D_DW by an inner CGNR solve to 1e-12, complex128 only)."""
     _need(U, "U", psi.dtype)
     _need(psi, "psi")
     Lx, Ly, Ls, nrhs = _fine_dims(U, psi)

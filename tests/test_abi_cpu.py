@@ -71,6 +71,11 @@ def test_argument_errors_are_reported_before_any_device_work(libdwf):
     assert libdwf.dwf_apply(1, 2, 3, 4, 4, 4, 1, float("nan"), -1.0, 0, None) == -1
     libdwf.mg_solve.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_double, vp, vp]
     assert libdwf.mg_solve(None, 1, 2, 1, 1e-10, None, None) == -5
+    # dwf_pv_apply: unknown mode; the exact D_PV^-1 D_DW mode has no FP32 form (DWF_EUNSUPPORTED)
+    libdwf.dwf_pv_apply.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp]
+    assert libdwf.dwf_pv_apply(1, 2, 3, 4, 4, 4, 1, 0.1, -1.0, 5, 0, None) == -1
+    assert libdwf.dwf_pv_apply(1, 2, 3, 4, 4, 4, 1, 0.1, -1.0, 4, 2, None) == -6
 
 
 @pytest.mark.parametrize("order,lo,hi", [(0, 1.0, 25.0), (1, 1.0, 25.0), (2, 1.0, 30.0), (3, 0.5, 12.0)])

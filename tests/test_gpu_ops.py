@@ -94,6 +94,32 @@ def test_pv_modes_fp64_parity(mode):
     assert rel(got.cpu().numpy(), want) < 1e-13
 
 
+def test_pv_inverse_mode_against_a_dense_solve():
+    """DWF_PVINV_DW: D_PV^-1 D_DW psi (the exactly preconditioned operator of Sec. 2.2)
+    against LU on the assembled D_PV of a small lattice, and on a larger one the
+    defining property D_PV out = D_DW psi with the oracle's operators."""
+    Lx, Ly, Ls, m, M5 = 8, 6, 4, 0.05, -1.0
+    U = gauge(Lx, Ly, 11)
+    psi = inputs.gaussian_field((2, Ls, Ly, Lx, 2), 12)
+    got = dwfmg.dwf_pv_apply(torch.from_numpy(U).to(DEV), torch.from_numpy(psi).to(DEV), m, M5,
+                             mode=dwfmg.DWF_PVINV_DW).cpu().numpy()
+    shape = (Ls, Ly, Lx, 2)
+    Dpv = O.assemble(lambda v: O.pv(U, v, M5), shape)
+    for r in range(2):
+        want = np.linalg.solve(Dpv, O.dwf(U, psi[r], m, M5).reshape(-1)).reshape(shape)
+        assert rel(got[r], want) < 1e-10
+    Lx, Ly, Ls = 32, 24, 8
+    U = gauge(Lx, Ly, 13)
+    psi = inputs.gaussian_field((1, Ls, Ly, Lx, 2), 14)
+    got = dwfmg.dwf_pv_apply(torch.from_numpy(U).to(DEV), torch.from_numpy(psi).to(DEV), m, M5,
+                             mode=dwfmg.DWF_PVINV_DW).cpu().numpy()
+    rhs = O.dwf(U, psi[0], m, M5)
+    assert rel(O.pv(U, got[0], M5), rhs) < 1e-11
+    with pytest.raises(dwfmg.DwfError):
+        dwfmg.dwf_pv_apply(torch.from_numpy(U).to(DEV).to(torch.complex64),
+                           torch.from_numpy(psi).to(DEV).to(torch.complex64), m, M5, mode=dwfmg.DWF_PVINV_DW)
+
+
 def test_dwf_full_size_fp64_and_fp32():
     """The 256^2 x Ls 16 operator of the solve benchmark, FP64 and FP32."""
     L, Ls, m, M5 = 256, 16, 0.01, -1.0
