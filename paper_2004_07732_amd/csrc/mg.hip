@@ -478,18 +478,24 @@ int Hierarchy::smooth(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t s
     cpx<T>* rs = C<T>(w.rs);
     cpx<T>* t = C<T>(w.tmp);
     cpx<T>* Az = C<T>(w.tmp2);
+    // the steps are the fused GCR iteration of the coarsest solve (inner products in
+    // one pass, orthogonalisation and residual update in a second) with a stopping
+    // threshold that is never met, so that all ns steps are taken
+    GcrDev& g = w.gsm;
     auto body = [&]() -> int {
         HIPCHK(apply_A<T>(l, z, Az, t, ncol, st));
         HIPCHK(vsub<T>(r, Az, rs, nt, st));
         HIPCHK(vconvert<T, T>(rs, Ps, nt, st));
+        HIPCHK(norm2<T>(rs, n, ncol, g.rr, rw_, st));
+        HIPCHK(gcr_dev_init(ncol, g, st));
         for (int j = 0; j < ns; ++j) {
             cpx<T>* Pj = Ps + (size_t)j * nt;
             cpx<T>* Wj = Ws + (size_t)j * nt;
+            const int* s_in = (j % 2 == 0) ? g.stop : g.stop2;
+            int* s_out = (j % 2 == 0) ? g.stop2 : g.stop;
             HIPCHK(apply_A<T>(l, Pj, Wj, t, ncol, st));
-            HIPCHK(gcr_multidot<T>(Ws, nt, j, Wj, n, ncol, w.gsm, rw_, st));
-            HIPCHK(gcr_orth<T>(Ws, nt, j, Wj, rs, n, ncol, w.gsm, rw_, st));
-            HIPCHK(gcr_rupdate<T>(Wj, rs, (j + 1 < ns) ? Ps + (size_t)(j + 1) * nt : nullptr, j, n, ncol, false,
-                                  w.gsm, rw_, st));
+            HIPCHK(gcr_fused_step<T>(Ws, nt, j, Wj, rs, (j + 1 < ns) ? Ps + (size_t)(j + 1) * nt : nullptr, n, ncol,
+                                     -1.0, s_in, s_out, g, rw_, st));
         }
         HIPCHK(gcr_solve(ns, ncol, w.gsm, st));
         HIPCHK((gcr_xupdate<T, T>(Ps, nt, ns, z, n, ncol, true, w.gsm, st)));
