@@ -603,32 +603,66 @@ __global__ void __launch_bounds__(kBlock) k_fin_gcr_rr(RedWork rw, int nb, GcrDe
     }
 }
 
-__global__ void k_gcr_solve(int k, int ncol, GcrDev g) {
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= ncol) return;
-    const size_t b = (size_t)col * g.kmax;
+// back substitution gam_j = (wr_j - sum_{l>j} D[l][j] gam_l) / nn_j, from arrays laid out
+// as in GcrDev (row stride ds of D); shared by the one-thread kernel and the x-update
+__device__ __forceinline__ void gcr_back_substitute(int k, const double* wr, const double* nn, const double* D,
+                                                    size_t ds, double* gam) {
     for (int j = k - 1; j >= 0; --j) {
-        cpx<double> gj = cdiv_real(ld2(&g.wr[2 * (b + j)]), g.nn[b + j]);
+        cpx<double> gj = cdiv_real(ld2(&wr[2 * j]), nn[j]);
         for (int l = j + 1; l < k; ++l) {
             // beta_{j l} = <w_j, A p_l> / |w_j|^2
-            cpx<double> bjl = cdiv_real(ld2(&g.D[((b + l) * g.kmax + j) * 2]), g.nn[b + j]);
-            cpx<double> gl = ld2(&g.gam[2 * (b + l)]);
+            cpx<double> bjl = cdiv_real(ld2(&D[(l * ds + j) * 2]), nn[j]);
+            cpx<double> gl = ld2(&gam[2 * l]);
             cpx<double> t = cmul(bjl, gl);
             gj.re -= t.re;
             gj.im -= t.im;
         }
-        g.gam[2 * (b + j)] = gj.re;
-        g.gam[2 * (b + j) + 1] = gj.im;
+        gam[2 * j] = gj.re;
+        gam[2 * j + 1] = gj.im;
     }
 }
 
+__global__ void k_gcr_solve(int k, int ncol, GcrDev g) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ncol) return;
+    const size_t b = (size_t)col * g.kmax;
+    gcr_back_substitute(k, g.wr + 2 * b, g.nn + b, g.D + b * g.kmax * 2, (size_t)g.kmax, g.gam + 2 * b);
+}
+
 template <typename T, typename Tx>
-__global__ void k_gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int accumulate, GcrDev g) {
+__global__ void k_gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int accumulate, GcrDev g,
+                              int solve) {
     const int col = blockIdx.y;
     const size_t o = (size_t)col * n;
+    const double* gam = g.gam + 2 * (size_t)col * g.kmax;
+    __shared__ double sD[16 * 16 * 2], snn[16], swr[32], sgam[32];
+    if (solve) {
+        // every block solves the small triangular system itself (the same arithmetic in
+        // the same order as the one-thread kernel): the entries are loaded in parallel
+        // into LDS, one thread substitutes, block 0 stores gam
+        const size_t b = (size_t)col * g.kmax;
+        for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+            const int l = t / k, j = t - l * k;
+            sD[(l * 16 + j) * 2] = g.D[((b + l) * g.kmax + j) * 2];
+            sD[(l * 16 + j) * 2 + 1] = g.D[((b + l) * g.kmax + j) * 2 + 1];
+        }
+        if (threadIdx.x < k) {
+            snn[threadIdx.x] = g.nn[b + threadIdx.x];
+            swr[2 * threadIdx.x] = g.wr[2 * (b + threadIdx.x)];
+            swr[2 * threadIdx.x + 1] = g.wr[2 * (b + threadIdx.x) + 1];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            gcr_back_substitute(k, swr, snn, sD, 16, sgam);
+            if (blockIdx.x == 0)
+                for (int i = 0; i < 2 * k; ++i) g.gam[2 * b + i] = sgam[i];
+        }
+        __syncthreads();
+        gam = sgam;
+    }
     cpx<double> c[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) c[i] = (i < k) ? ld2(&g.gam[2 * ((size_t)col * g.kmax + i)]) : cpx<double>{0.0, 0.0};
+    for (int i = 0; i < 16; ++i) c[i] = (i < k) ? cpx<double>{gam[2 * i], gam[2 * i + 1]} : cpx<double>{0.0, 0.0};
     GRID_STRIDE(e, n) {
         cpx<double> acc = {0.0, 0.0};
         if (accumulate) acc = {(double)x[o + e].re, (double)x[o + e].im};
@@ -723,7 +757,15 @@ hipError_t gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_
                        bool accumulate, const GcrDev& g, hipStream_t st) {
     if (k > 16) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_gcr_xupdate<T, Tx>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, pstride, k, x, n,
-                       accumulate ? 1 : 0, g);
+                       accumulate ? 1 : 0, g, 0);
+    return hipGetLastError();
+}
+template <typename T, typename Tx>
+hipError_t gcr_solve_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int ncol,
+                             bool accumulate, const GcrDev& g, hipStream_t st) {
+    if (k < 0 || k > 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gcr_xupdate<T, Tx>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, pstride, k, x, n,
+                       accumulate ? 1 : 0, g, 1);
     return hipGetLastError();
 }
 
@@ -775,5 +817,7 @@ template hipError_t vadd<float, float>(const cpx<float>*, cpx<float>*, size_t, h
 template hipError_t gcr_xupdate<float, float>(const cpx<float>*, size_t, int, cpx<float>*, size_t, int, bool, const GcrDev&, hipStream_t);
 template hipError_t gcr_xupdate<double, double>(const cpx<double>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
 template hipError_t gcr_xupdate<float, double>(const cpx<float>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
+template hipError_t gcr_solve_xupdate<float, float>(const cpx<float>*, size_t, int, cpx<float>*, size_t, int, bool, const GcrDev&, hipStream_t);
+template hipError_t gcr_solve_xupdate<double, double>(const cpx<double>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
 
 }  // namespace dwf

@@ -175,6 +175,10 @@ hipError_t gcr_solve(int k, int ncol, const GcrDev& g, hipStream_t st);
 template <typename T, typename Tx>
 hipError_t gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int ncol,
                        bool accumulate, const GcrDev& g, hipStream_t st);
+// gcr_solve followed by gcr_xupdate in one launch (each block substitutes for itself)
+template <typename T, typename Tx>
+hipError_t gcr_solve_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int ncol,
+                             bool accumulate, const GcrDev& g, hipStream_t st);
 
 // ------------------------------------------------------------ transfer (Sec. 2.3)
 // Prolongator V[site][c][j][k] (nc internal dof per chirality, nvec coarse vectors).

@@ -432,8 +432,7 @@ int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol
             HIPCHK(gcr_fused_step<T>(W, nt, k, Wk, r, k + 1 < kmax ? P + (size_t)(k + 1) * nt : nullptr, n, ncol,
                                      tol2, s_in, s_out, g, rw_, st));
         }
-        HIPCHK(gcr_solve(kmax, ncol, g, st));
-        HIPCHK((gcr_xupdate<T, T>(P, nt, kmax, x, n, ncol, true, g, st)));
+        HIPCHK((gcr_solve_xupdate<T, T>(P, nt, kmax, x, n, ncol, true, g, st)));
         HIPCHK(apply_A<T>(l, x, t2, t, ncol, st));
         HIPCHK(vsub<T>(b, t2, r, nt, st));
         HIPCHK(gcr_fused_cycle_end<T>(r, n, ncol, (kmax % 2 == 0) ? g.stop : g.stop2, g, rw_, st));
@@ -497,8 +496,7 @@ int Hierarchy::smooth(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t s
             HIPCHK(gcr_fused_step<T>(Ws, nt, j, Wj, rs, (j + 1 < ns) ? Ps + (size_t)(j + 1) * nt : nullptr, n, ncol,
                                      -1.0, s_in, s_out, g, rw_, st));
         }
-        HIPCHK(gcr_solve(ns, ncol, w.gsm, st));
-        HIPCHK((gcr_xupdate<T, T>(Ps, nt, ns, z, n, ncol, true, w.gsm, st)));
+        HIPCHK((gcr_solve_xupdate<T, T>(Ps, nt, ns, z, n, ncol, true, w.gsm, st)));
         return DWF_OK;
     };
     if (use_graphs_ && st == st_) {
@@ -569,8 +567,7 @@ int Hierarchy::fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* r
     };
     auto flush = [&]() -> int {
         if (k == 0) return DWF_OK;
-        HIPCHK(gcr_solve(k, ncol, g, st));
-        HIPCHK((gcr_xupdate<T, T>(P, nt, k, x, n, ncol, true, g, st)));
+        HIPCHK((gcr_solve_xupdate<T, T>(P, nt, k, x, n, ncol, true, g, st)));
         k = 0;
         return DWF_OK;
     };
