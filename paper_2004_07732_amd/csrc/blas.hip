@@ -123,8 +123,12 @@ __global__ void k_add(const cpx<Tx>* x, cpx<Ty>* y, size_t n) {
     }
 }
 template <typename T>
-__global__ void k_sub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n) {
-    GRID_STRIDE(i, n) out[i] = a[i] - b[i];
+__global__ void k_sub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, cpx<T>* out2, size_t n) {
+    GRID_STRIDE(i, n) {
+        const cpx<T> v = a[i] - b[i];
+        out[i] = v;
+        if (out2) out2[i] = v;
+    }
 }
 
 // y = a x + b y (b == 0: y = a x, whatever y held)
@@ -160,7 +164,12 @@ hipError_t vadd(const cpx<Tx>* x, cpx<Ty>* y, size_t n, hipStream_t st) {
 }
 template <typename T>
 hipError_t vsub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_sub<T>, ew_grid(n, 1), dim3(kBlock), 0, st, a, b, out, n);
+    hipLaunchKernelGGL(k_sub<T>, ew_grid(n, 1), dim3(kBlock), 0, st, a, b, out, (cpx<T>*)nullptr, n);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t vsub2(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, cpx<T>* out2, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_sub<T>, ew_grid(n, 1), dim3(kBlock), 0, st, a, b, out, out2, n);
     return hipGetLastError();
 }
 
@@ -789,6 +798,7 @@ hipError_t check_finite(const cpx<T>* x, size_t n, int* flag, hipStream_t st) {
 #define INST_T(T)                                                                                       \
     template hipError_t vzero<T>(cpx<T>*, size_t, hipStream_t);                                         \
     template hipError_t vsub<T>(const cpx<T>*, const cpx<T>*, cpx<T>*, size_t, hipStream_t);            \
+    template hipError_t vsub2<T>(const cpx<T>*, const cpx<T>*, cpx<T>*, cpx<T>*, size_t, hipStream_t);  \
     template hipError_t norm2<T>(const cpx<T>*, size_t, int, double*, const RedWork&, hipStream_t);     \
     template hipError_t cdot<T>(const cpx<T>*, const cpx<T>*, size_t, int, double*, const RedWork&, hipStream_t); \
     template hipError_t cg_init<T>(const cpx<T>*, size_t, int, CgScal*, double, const RedWork&, hipStream_t); \

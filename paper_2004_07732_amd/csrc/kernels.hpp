@@ -88,6 +88,9 @@ template <typename Ti, typename To> hipError_t vconvert(const cpx<Ti>* in, cpx<T
 // y += x (mixed precision allowed: x in Tx, y in Ty)
 template <typename Tx, typename Ty> hipError_t vadd(const cpx<Tx>* x, cpx<Ty>* y, size_t n, hipStream_t st);
 template <typename T> hipError_t vsub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n, hipStream_t st);
+// out = a - b, also written to out2
+template <typename T> hipError_t vsub2(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, cpx<T>* out2, size_t n,
+                                       hipStream_t st);
 // y = a x + b y with real a, b (b == 0 overwrites y)
 template <typename T> hipError_t vaxpby(double a, const cpx<T>* x, double b, cpx<T>* y, size_t n, hipStream_t st);
 

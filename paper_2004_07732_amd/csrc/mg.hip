@@ -415,13 +415,13 @@ int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol
     const double tol2 = tol * tol;
     HIPCHK(vzero<T>(x, nt, st));
     HIPCHK((vconvert<T, T>(b, r, nt, st)));
+    HIPCHK((vconvert<T, T>(b, P, nt, st)));   // the first search direction (later cycles: by the residual pass)
     HIPCHK(norm2<T>(b, n, ncol, g.rr, rw_, st));
     HIPCHK(gcr_dev_init(ncol, g, st));
     // one restart cycle: kmax fused iterations (inner products, then one pass that orthogonalises
     // the new direction and updates the residual; the stop flags alternate between two buffers so
     // that no kernel writes the flags it reads), the solution update, and the true residual
     auto cycle = [&]() -> int {
-        HIPCHK((vconvert<T, T>(r, P, nt, st)));
         for (int k = 0; k < kmax; ++k) {
             cpx<T>* Pk = P + (size_t)k * nt;
             cpx<T>* Wk = W + (size_t)k * nt;
@@ -434,7 +434,7 @@ int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol
         }
         HIPCHK((gcr_solve_xupdate<T, T>(P, nt, kmax, x, n, ncol, true, g, st)));
         HIPCHK(apply_A<T>(l, x, t2, t, ncol, st));
-        HIPCHK(vsub<T>(b, t2, r, nt, st));
+        HIPCHK(vsub2<T>(b, t2, r, P, nt, st));   // true residual, also the next cycle's first direction
         HIPCHK(gcr_fused_cycle_end<T>(r, n, ncol, (kmax % 2 == 0) ? g.stop : g.stop2, g, rw_, st));
         return DWF_OK;
     };
