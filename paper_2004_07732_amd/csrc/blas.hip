@@ -269,6 +269,24 @@ __global__ void __launch_bounds__(kBlock) k_norm2_part(const cpx<T>* x, size_t n
     write_partials<1>(v, 1, rw, col, sh, tot);
 }
 
+// r = b - Ax (also into P0), with the partial sums of |r|^2 per column
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sub_norm2_part(const cpx<T>* b, const cpx<T>* Ax, cpx<T>* r, cpx<T>* P0,
+                                                           size_t n, RedWork rw) {
+    SHARED_RED;
+    const int col = blockIdx.y;
+    const size_t o = (size_t)col * n;
+    double v[1] = {0.0};
+    GRID_STRIDE(i, n) {
+        const cpx<T> d = b[o + i] - Ax[o + i];
+        r[o + i] = d;
+        P0[o + i] = d;
+        const cpx<double> a = up(d);
+        v[0] += a.re * a.re + a.im * a.im;
+    }
+    write_partials<1>(v, 1, rw, col, sh, tot);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cdot_part(const cpx<T>* a, const cpx<T>* b, size_t n, RedWork rw) {
     SHARED_RED;
@@ -753,6 +771,14 @@ hipError_t gcr_fused_cycle_end(const cpx<T>* r, size_t n, int ncol, const int* s
     hipLaunchKernelGGL(k_fin_gcr_cycle, dim3(ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g, stop_src);
     return hipGetLastError();
 }
+template <typename T>
+hipError_t gcr_residual_cycle_end(const cpx<T>* b, const cpx<T>* Ax, cpx<T>* r, cpx<T>* P0, size_t n, int ncol,
+                                  const int* stop_src, const GcrDev& g, const RedWork& rw, hipStream_t st) {
+    const dim3 grid = red_grid(n, ncol, rw);
+    hipLaunchKernelGGL(k_sub_norm2_part<T>, grid, dim3(kBlock), 0, st, b, Ax, r, P0, n, rw);
+    hipLaunchKernelGGL(k_fin_gcr_cycle, dim3(ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g, stop_src);
+    return hipGetLastError();
+}
 hipError_t gcr_dev_init(int ncol, const GcrDev& g, hipStream_t st) {
     hipLaunchKernelGGL(k_gcr_dev_init, dim3(grid_for(ncol, 64)), dim3(64), 0, st, ncol, g);
     return hipGetLastError();
@@ -812,6 +838,7 @@ hipError_t check_finite(const cpx<T>* x, size_t n, int* flag, hipStream_t st) {
     template hipError_t gcr_rupdate_dev<T>(const cpx<T>*, cpx<T>*, cpx<T>*, int, size_t, int, double, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_fused_step<T>(const cpx<T>*, size_t, int, cpx<T>*, cpx<T>*, cpx<T>*, size_t, int, double, const int*, int*, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_fused_cycle_end<T>(const cpx<T>*, size_t, int, const int*, const GcrDev&, const RedWork&, hipStream_t); \
+    template hipError_t gcr_residual_cycle_end<T>(const cpx<T>*, const cpx<T>*, cpx<T>*, cpx<T>*, size_t, int, const int*, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t check_finite<T>(const cpx<T>*, size_t, int*, hipStream_t);
 
 INST_T(float)

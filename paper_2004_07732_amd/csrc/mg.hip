@@ -434,8 +434,8 @@ int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol
         }
         HIPCHK((gcr_solve_xupdate<T, T>(P, nt, kmax, x, n, ncol, true, g, st)));
         HIPCHK(apply_A<T>(l, x, t2, t, ncol, st));
-        HIPCHK(vsub2<T>(b, t2, r, P, nt, st));   // true residual, also the next cycle's first direction
-        HIPCHK(gcr_fused_cycle_end<T>(r, n, ncol, (kmax % 2 == 0) ? g.stop : g.stop2, g, rw_, st));
+        // true residual and its norm, also the next cycle's first direction
+        HIPCHK(gcr_residual_cycle_end<T>(b, t2, r, P, n, ncol, (kmax % 2 == 0) ? g.stop : g.stop2, g, rw_, st));
         return DWF_OK;
     };
     const int max_cycles = std::max(1, (maxit + kmax - 1) / kmax);
