@@ -799,6 +799,12 @@ template <typename T, typename Tx>
 hipError_t gcr_solve_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int ncol,
                              bool accumulate, const GcrDev& g, hipStream_t st) {
     if (k < 0 || k > 16) return hipErrorInvalidValue;
+    // (the substitution is serial in every block: beyond 8 directions the separate
+    // one-thread kernel is cheaper, measured with 16)
+    if (k > 8) {
+        if (hipError_t e = gcr_solve(k, ncol, g, st)) return e;
+        return gcr_xupdate<T, Tx>(P, pstride, k, x, n, ncol, accumulate, g, st);
+    }
     hipLaunchKernelGGL((k_gcr_xupdate<T, Tx>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, pstride, k, x, n,
                        accumulate ? 1 : 0, g, 1);
     return hipGetLastError();
