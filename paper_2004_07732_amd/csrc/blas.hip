@@ -606,6 +606,15 @@ __global__ void __launch_bounds__(kBlock) k_fin_gcr_cycle(RedWork rw, int nb, Gc
     }
 }
 
+// restart of the device-driven GCR on the recursive residual: the next first
+// direction is r, and the stop flags of the last step move to g.stop
+template <typename T>
+__global__ void k_gcr_restart(const cpx<T>* r, cpx<T>* P0, size_t n, const int* stop_src, int* stop, int ncol) {
+    if (blockIdx.x == 0 && stop_src != stop)
+        for (int c = threadIdx.x; c < ncol; c += blockDim.x) stop[c] = stop_src[c];
+    GRID_STRIDE(i, n) P0[i] = r[i];
+}
+
 __global__ void k_gcr_dev_init(int ncol, GcrDev g) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncol) return;
@@ -779,6 +788,13 @@ hipError_t gcr_residual_cycle_end(const cpx<T>* b, const cpx<T>* Ax, cpx<T>* r, 
     hipLaunchKernelGGL(k_fin_gcr_cycle, dim3(ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g, stop_src);
     return hipGetLastError();
 }
+template <typename T>
+hipError_t gcr_restart(const cpx<T>* r, cpx<T>* P0, size_t n, int ncol, const int* stop_src, const GcrDev& g,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_gcr_restart<T>, ew_grid(n * ncol, 1), dim3(kBlock), 0, st, r, P0, n * ncol, stop_src, g.stop,
+                       ncol);
+    return hipGetLastError();
+}
 hipError_t gcr_dev_init(int ncol, const GcrDev& g, hipStream_t st) {
     hipLaunchKernelGGL(k_gcr_dev_init, dim3(grid_for(ncol, 64)), dim3(64), 0, st, ncol, g);
     return hipGetLastError();
@@ -844,6 +860,7 @@ hipError_t check_finite(const cpx<T>* x, size_t n, int* flag, hipStream_t st) {
     template hipError_t gcr_rupdate_dev<T>(const cpx<T>*, cpx<T>*, cpx<T>*, int, size_t, int, double, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_fused_step<T>(const cpx<T>*, size_t, int, cpx<T>*, cpx<T>*, cpx<T>*, size_t, int, double, const int*, int*, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_fused_cycle_end<T>(const cpx<T>*, size_t, int, const int*, const GcrDev&, const RedWork&, hipStream_t); \
+    template hipError_t gcr_restart<T>(const cpx<T>*, cpx<T>*, size_t, int, const int*, const GcrDev&, hipStream_t); \
     template hipError_t gcr_residual_cycle_end<T>(const cpx<T>*, const cpx<T>*, cpx<T>*, cpx<T>*, size_t, int, const int*, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t check_finite<T>(const cpx<T>*, size_t, int*, hipStream_t);
 

@@ -172,6 +172,11 @@ hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx
 template <typename T>
 hipError_t gcr_fused_cycle_end(const cpx<T>* r, size_t n, int ncol, const int* stop_src, const GcrDev& g,
                                const RedWork& rw, hipStream_t st);
+// next restart cycle on the recursive residual: P0 = r, and the stop flags of the
+// cycle's last step (stop_src) become g.stop
+template <typename T>
+hipError_t gcr_restart(const cpx<T>* r, cpx<T>* P0, size_t n, int ncol, const int* stop_src, const GcrDev& g,
+                       hipStream_t st);
 // r = b - Ax, also written to P0 (the next cycle's first direction), then the same
 // cycle-end bookkeeping as gcr_fused_cycle_end on |r|^2, in two launches
 template <typename T>

@@ -394,9 +394,12 @@ int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st)
 // Unpreconditioned GCR(kmax) on A with every decision on the device (the
 // stop flags are reset by gcr_dev_init at the start of every solve): each
 // cycle runs kmax fused iterations whose kernels turn into no-ops for
-// converged columns, then updates x and recomputes the true residual and its
-// norm exactly.  The host reads
-// the stop flags once per cycle; a cycle is captured once as a HIP graph.
+// converged columns, then updates x and restarts from the recursive residual
+// (in FP64 over the few hundred iterations of a coarsest solve to a loose
+// tolerance it stays within rounding of the true one; recomputing it cost two
+// coarse stencils per cycle).  The stop decision is the recursive one in either
+// case.  The host reads the stop flags once per cycle; a cycle is captured once
+// as a HIP graph.
 template <typename T>
 int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol, int maxit, int restart,
                          int* iters_out, hipStream_t st) {
@@ -410,7 +413,6 @@ int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol
     cpx<T>* P = C<T>(w.P);
     cpx<T>* W = C<T>(w.W);
     cpx<T>* t = C<T>(w.tmp);
-    cpx<T>* t2 = C<T>(w.tmp2);
     GcrDev& g = w.gcr;
     const double tol2 = tol * tol;
     HIPCHK(vzero<T>(x, nt, st));
@@ -420,7 +422,7 @@ int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol
     HIPCHK(gcr_dev_init(ncol, g, st));
     // one restart cycle: kmax fused iterations (inner products, then one pass that orthogonalises
     // the new direction and updates the residual; the stop flags alternate between two buffers so
-    // that no kernel writes the flags it reads), the solution update, and the true residual
+    // that no kernel writes the flags it reads), the solution update, and the restart
     auto cycle = [&]() -> int {
         for (int k = 0; k < kmax; ++k) {
             cpx<T>* Pk = P + (size_t)k * nt;
@@ -433,9 +435,9 @@ int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol
                                      tol2, s_in, s_out, g, rw_, st));
         }
         HIPCHK((gcr_solve_xupdate<T, T>(P, nt, kmax, x, n, ncol, true, g, st)));
-        HIPCHK(apply_A<T>(l, x, t2, t, ncol, st));
-        // true residual and its norm, also the next cycle's first direction
-        HIPCHK(gcr_residual_cycle_end<T>(b, t2, r, P, n, ncol, (kmax % 2 == 0) ? g.stop : g.stop2, g, rw_, st));
+        // the next cycle continues from the recursive residual (its norm and the stop
+        // flags are those of the last fused step)
+        HIPCHK(gcr_restart<T>(r, P, n, ncol, (kmax % 2 == 0) ? g.stop : g.stop2, g, st));
         return DWF_OK;
     };
     const int max_cycles = std::max(1, (maxit + kmax - 1) / kmax);
