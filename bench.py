@@ -6,7 +6,7 @@ relative residual of 1e-10 on a 256^2 x Ls 16 lattice (beta 6, m_f 0.01,
 M5 = -1) with the 2-level hierarchy (4x4 aggregates, 16 null vectors, coarse
 Ls 2), mixed precision (FP32 fine level, BF16 coarse links on the matrix
 cores, FP64 outer defect correction and FP64 coarse Krylov vectors).  The
-coarsest level runs restarted GCR(8) on hat-A to 0.25 by default.  Rows beside
+coarsest level runs restarted GCR(6) on hat-A to 0.25 by default.  Rows beside
 the headline: the paper's parameter table throughout (coarse Ls 4, coarsest
 CGNR to 0.05), coarse Ls 4 with GCR, three levels, 8 null vectors.
 
@@ -126,8 +126,8 @@ def cpu_baseline(wl, stats, U_np, coarsest):
         # one CGNR iteration applies A and A^dagger; each call adds one A^dagger
         coarse_A = 2.0 * stats.level_iters[0] + stats.level_calls[0]
     else:
-        # one GCR iteration applies A; each restart cycle adds one for the true residual
-        coarse_A = stats.level_iters[0] * (1.0 + 1.0 / coarsest["coarsest_restart"]) + stats.level_calls[0]
+        # one GCR iteration applies A (from a zero start; restarts continue from the recursive residual)
+        coarse_A = float(stats.level_iters[0])
     t_solve = fine_A * tA + coarse_A * tAc
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": (f"oracle unit costs on the host: D_PV^dag D_DW at {L}^2 x {Ls} = {tA:.3f} s, "
@@ -228,7 +228,7 @@ def main():
     ap.add_argument("--workload", default="dwf256_ls16_mg2", choices=sorted(WORKLOADS))
     ap.add_argument("--coarsest", choices=["cgnr", "gcr"], default="gcr",
                     help="coarsest-level solver: restarted GCR on A (default) or CGNR on A^dag A as in the paper")
-    ap.add_argument("--coarsest-restart", type=int, default=8)
+    ap.add_argument("--coarsest-restart", type=int, default=6)
     ap.add_argument("--coarsest-tol", type=float, default=None,
                     help="coarsest relative tolerance (default 0.25 with GCR, 0.05 with CGNR)")
     ap.add_argument("--nev", type=int, default=0,
