@@ -123,12 +123,8 @@ __global__ void k_add(const cpx<Tx>* x, cpx<Ty>* y, size_t n) {
     }
 }
 template <typename T>
-__global__ void k_sub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, cpx<T>* out2, size_t n) {
-    GRID_STRIDE(i, n) {
-        const cpx<T> v = a[i] - b[i];
-        out[i] = v;
-        if (out2) out2[i] = v;
-    }
+__global__ void k_sub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n) {
+    GRID_STRIDE(i, n) out[i] = a[i] - b[i];
 }
 
 // y = a x + b y (b == 0: y = a x, whatever y held)
@@ -164,12 +160,7 @@ hipError_t vadd(const cpx<Tx>* x, cpx<Ty>* y, size_t n, hipStream_t st) {
 }
 template <typename T>
 hipError_t vsub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_sub<T>, ew_grid(n, 1), dim3(kBlock), 0, st, a, b, out, (cpx<T>*)nullptr, n);
-    return hipGetLastError();
-}
-template <typename T>
-hipError_t vsub2(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, cpx<T>* out2, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_sub<T>, ew_grid(n, 1), dim3(kBlock), 0, st, a, b, out, out2, n);
+    hipLaunchKernelGGL(k_sub<T>, ew_grid(n, 1), dim3(kBlock), 0, st, a, b, out, n);
     return hipGetLastError();
 }
 
@@ -264,24 +255,6 @@ __global__ void __launch_bounds__(kBlock) k_norm2_part(const cpx<T>* x, size_t n
     double v[1] = {0.0};
     GRID_STRIDE(i, n) {
         cpx<double> a = up(xc[i]);
-        v[0] += a.re * a.re + a.im * a.im;
-    }
-    write_partials<1>(v, 1, rw, col, sh, tot);
-}
-
-// r = b - Ax (also into P0), with the partial sums of |r|^2 per column
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sub_norm2_part(const cpx<T>* b, const cpx<T>* Ax, cpx<T>* r, cpx<T>* P0,
-                                                           size_t n, RedWork rw) {
-    SHARED_RED;
-    const int col = blockIdx.y;
-    const size_t o = (size_t)col * n;
-    double v[1] = {0.0};
-    GRID_STRIDE(i, n) {
-        const cpx<T> d = b[o + i] - Ax[o + i];
-        r[o + i] = d;
-        P0[o + i] = d;
-        const cpx<double> a = up(d);
         v[0] += a.re * a.re + a.im * a.im;
     }
     write_partials<1>(v, 1, rw, col, sh, tot);
@@ -596,16 +569,6 @@ k_gcr_fused_update(const cpx<T>* W, size_t wstride, cpx<T>* w, cpx<T>* r, cpx<T>
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_fin_gcr_cycle(RedWork rw, int nb, GcrDev g, const int* stop_src) {
-    SHARED_RED;
-    const int col = blockIdx.x;
-    sum_partials<1>(1, nb, rw, col, sh, tot);
-    if (threadIdx.x == 0) {
-        g.rr[col] = tot[0];
-        g.stop[col] = stop_src[col];
-    }
-}
-
 // restart of the device-driven GCR on the recursive residual: the next first
 // direction is r, and the stop flags of the last step move to g.stop
 template <typename T>
@@ -622,21 +585,6 @@ __global__ void k_gcr_dev_init(int ncol, GcrDev g) {
     g.bb[c] = b;
     g.it[c] = 0;
     g.stop[c] = finite(b) ? (b == 0.0 ? 1 : 0) : 2;
-}
-
-__global__ void __launch_bounds__(kBlock) k_fin_gcr_rr(RedWork rw, int nb, GcrDev g, double tol2) {
-    SHARED_RED;
-    const int col = blockIdx.x;
-    sum_partials<1>(1, nb, rw, col, sh, tot);
-    if (threadIdx.x == 0) {
-        const double rr = tot[0];
-        g.rr[col] = rr;
-        if (g.stop[col] == 0) {
-            g.it[col] += 1;
-            if (!finite(rr)) g.stop[col] = 2;
-            else if (rr <= tol2 * g.bb[col]) g.stop[col] = 1;
-        }
-    }
 }
 
 // back substitution gam_j = (wr_j - sum_{l>j} D[l][j] gam_l) / nn_j, from arrays laid out
@@ -748,14 +696,6 @@ hipError_t gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n
     return hipGetLastError();
 }
 template <typename T>
-hipError_t gcr_rupdate_dev(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int ncol, double tol2,
-                           const GcrDev& g, const RedWork& rw, hipStream_t st) {
-    dim3 grid = red_grid(n, ncol, rw);
-    hipLaunchKernelGGL(k_gcr_rupdate<T>, grid, dim3(kBlock), 0, st, w, r, copy, j, n, 1, g, rw);
-    hipLaunchKernelGGL(k_fin_gcr_rr, dim3(ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g, tol2);
-    return hipGetLastError();
-}
-template <typename T>
 hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx<T>* r, cpx<T>* copy, size_t n,
                           int ncol, double tol2, const int* stop_in, int* stop_out, const GcrDev& g,
                           const RedWork& rw, hipStream_t st) {
@@ -770,22 +710,6 @@ hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx
                            copy, n, tol2, stop_in, stop_out, g);
     };
     with_j(j, launch, std::make_integer_sequence<int, 16>{});
-    return hipGetLastError();
-}
-template <typename T>
-hipError_t gcr_fused_cycle_end(const cpx<T>* r, size_t n, int ncol, const int* stop_src, const GcrDev& g,
-                               const RedWork& rw, hipStream_t st) {
-    const dim3 grid = red_grid(n, ncol, rw);
-    hipLaunchKernelGGL(k_norm2_part<T>, grid, dim3(kBlock), 0, st, r, n, rw, (const int*)nullptr, 1);
-    hipLaunchKernelGGL(k_fin_gcr_cycle, dim3(ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g, stop_src);
-    return hipGetLastError();
-}
-template <typename T>
-hipError_t gcr_residual_cycle_end(const cpx<T>* b, const cpx<T>* Ax, cpx<T>* r, cpx<T>* P0, size_t n, int ncol,
-                                  const int* stop_src, const GcrDev& g, const RedWork& rw, hipStream_t st) {
-    const dim3 grid = red_grid(n, ncol, rw);
-    hipLaunchKernelGGL(k_sub_norm2_part<T>, grid, dim3(kBlock), 0, st, b, Ax, r, P0, n, rw);
-    hipLaunchKernelGGL(k_fin_gcr_cycle, dim3(ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g, stop_src);
     return hipGetLastError();
 }
 template <typename T>
@@ -846,7 +770,6 @@ hipError_t check_finite(const cpx<T>* x, size_t n, int* flag, hipStream_t st) {
 #define INST_T(T)                                                                                       \
     template hipError_t vzero<T>(cpx<T>*, size_t, hipStream_t);                                         \
     template hipError_t vsub<T>(const cpx<T>*, const cpx<T>*, cpx<T>*, size_t, hipStream_t);            \
-    template hipError_t vsub2<T>(const cpx<T>*, const cpx<T>*, cpx<T>*, cpx<T>*, size_t, hipStream_t);  \
     template hipError_t norm2<T>(const cpx<T>*, size_t, int, double*, const RedWork&, hipStream_t);     \
     template hipError_t cdot<T>(const cpx<T>*, const cpx<T>*, size_t, int, double*, const RedWork&, hipStream_t); \
     template hipError_t cg_init<T>(const cpx<T>*, size_t, int, CgScal*, double, const RedWork&, hipStream_t); \
@@ -857,11 +780,8 @@ hipError_t check_finite(const cpx<T>* x, size_t n, int* flag, hipStream_t st) {
     template hipError_t gcr_multidot<T>(const cpx<T>*, size_t, int, const cpx<T>*, size_t, int, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_orth<T>(const cpx<T>*, size_t, int, cpx<T>*, const cpx<T>*, size_t, int, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_rupdate<T>(const cpx<T>*, cpx<T>*, cpx<T>*, int, size_t, int, bool, const GcrDev&, const RedWork&, hipStream_t); \
-    template hipError_t gcr_rupdate_dev<T>(const cpx<T>*, cpx<T>*, cpx<T>*, int, size_t, int, double, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_fused_step<T>(const cpx<T>*, size_t, int, cpx<T>*, cpx<T>*, cpx<T>*, size_t, int, double, const int*, int*, const GcrDev&, const RedWork&, hipStream_t); \
-    template hipError_t gcr_fused_cycle_end<T>(const cpx<T>*, size_t, int, const int*, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t gcr_restart<T>(const cpx<T>*, cpx<T>*, size_t, int, const int*, const GcrDev&, hipStream_t); \
-    template hipError_t gcr_residual_cycle_end<T>(const cpx<T>*, const cpx<T>*, cpx<T>*, cpx<T>*, size_t, int, const int*, const GcrDev&, const RedWork&, hipStream_t); \
     template hipError_t check_finite<T>(const cpx<T>*, size_t, int*, hipStream_t);
 
 INST_T(float)

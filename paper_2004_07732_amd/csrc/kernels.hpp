@@ -88,9 +88,6 @@ template <typename Ti, typename To> hipError_t vconvert(const cpx<Ti>* in, cpx<T
 // y += x (mixed precision allowed: x in Tx, y in Ty)
 template <typename Tx, typename Ty> hipError_t vadd(const cpx<Tx>* x, cpx<Ty>* y, size_t n, hipStream_t st);
 template <typename T> hipError_t vsub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n, hipStream_t st);
-// out = a - b, also written to out2
-template <typename T> hipError_t vsub2(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, cpx<T>* out2, size_t n,
-                                       hipStream_t st);
 // y = a x + b y with real a, b (b == 0 overwrites y)
 template <typename T> hipError_t vaxpby(double a, const cpx<T>* x, double b, cpx<T>* y, size_t n, hipStream_t st);
 
@@ -153,10 +150,6 @@ hipError_t gcr_rupdate(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n
                        bool want_norm, const GcrDev& g, const RedWork& rw, hipStream_t st);
 // device-driven GCR: bb = rr (= |b|^2), it = 0, stop = 1 when bb == 0, 2 when not finite
 hipError_t gcr_dev_init(int ncol, const GcrDev& g, hipStream_t st);
-// gcr_rupdate with the norm, then on the device: it += 1 and stop = (rr <= tol2 bb) for live columns
-template <typename T>
-hipError_t gcr_rupdate_dev(const cpx<T>* w, cpx<T>* r, cpx<T>* copy, int j, size_t n, int ncol, double tol2,
-                           const GcrDev& g, const RedWork& rw, hipStream_t st);
 // Fused GCR iteration j (device-driven solve, no preconditioner), three launches:
 //   dots:   tot = [|w|^2, <w, r>, <W_i, w> (i < j)] in one pass;
 //   update: every block derives c_i = <W_i, w>/nn_i, |w'|^2 = |w|^2 - sum |<W_i, w>|^2/nn_i and
@@ -168,20 +161,11 @@ template <typename T>
 hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx<T>* r, cpx<T>* copy, size_t n,
                           int ncol, double tol2, const int* stop_in, int* stop_out, const GcrDev& g,
                           const RedWork& rw, hipStream_t st);
-// end of a fused cycle: rr = |r|^2 exactly, stop = stop_src
-template <typename T>
-hipError_t gcr_fused_cycle_end(const cpx<T>* r, size_t n, int ncol, const int* stop_src, const GcrDev& g,
-                               const RedWork& rw, hipStream_t st);
 // next restart cycle on the recursive residual: P0 = r, and the stop flags of the
 // cycle's last step (stop_src) become g.stop
 template <typename T>
 hipError_t gcr_restart(const cpx<T>* r, cpx<T>* P0, size_t n, int ncol, const int* stop_src, const GcrDev& g,
                        hipStream_t st);
-// r = b - Ax, also written to P0 (the next cycle's first direction), then the same
-// cycle-end bookkeeping as gcr_fused_cycle_end on |r|^2, in two launches
-template <typename T>
-hipError_t gcr_residual_cycle_end(const cpx<T>* b, const cpx<T>* Ax, cpx<T>* r, cpx<T>* P0, size_t n, int ncol,
-                                  const int* stop_src, const GcrDev& g, const RedWork& rw, hipStream_t st);
 // back substitution for gam over directions 0..k-1
 hipError_t gcr_solve(int k, int ncol, const GcrDev& g, hipStream_t st);
 // x (+)= sum_{i<k} gam[i] P_i ; `accumulate` false overwrites x

@@ -111,6 +111,20 @@ def test_coarsest_gcr_solve_matches_cgnr_solve(nrhs):
     assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) < 1e-8
 
 
+@pytest.mark.parametrize("restart", [5, 6])
+def test_coarsest_gcr_restart_lengths(restart):
+    """Odd and even restart lengths (the stop flags of the last fused step sit in one or
+    the other of the two flag buffers, and restarts continue from the recursive residual):
+    both precondition the solve to the 1e-10 true residual for two right-hand sides."""
+    levels = [(4, (4, 4), 4)]
+    L, Ls, m = 32, 8, 0.01
+    b = T(inputs.gaussian_field((2, Ls, L, L, 2), 710))
+    _, mg, _ = hierarchy(L, Ls, m, levels, 711, coarsest_solver=dwfmg.COARSEST_GCR, coarsest_restart=restart)
+    x, st = mg.solve(b, tol=1e-10)
+    assert st.true_rel_residual <= 1e-10
+    assert st.level_calls[0] > 0 and st.level_iters[0] > 0
+
+
 def test_coarsest_gcr_three_levels():
     levels = [(4, (4, 4), 3), (4, (2, 2), 2)]
     b = T(inputs.gaussian_field((1, 8, 32, 32, 2), 708))
