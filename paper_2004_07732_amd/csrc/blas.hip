@@ -174,6 +174,17 @@ __global__ void __launch_bounds__(kBlock) k_fin_store(RedWork rw, int nq, int nb
 }
 
 // the same sums with one block per (quantity, column): for many quantities
+// the same with one wavefront per (quantity, column): no barrier, all loads in flight
+__global__ void __launch_bounds__(64) k_fin_store_q1(RedWork rw, int nb, double* out, size_t stride) {
+    const int q = blockIdx.x, col = blockIdx.y;
+    const double* part = rw.partial + (size_t)col * rw.max_q * rw.nblk + (size_t)q * rw.nblk;
+    double s = 0.0;
+#pragma unroll 8
+    for (int b = threadIdx.x; b < nb; b += 64) s += part[b];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) out[(size_t)col * stride + q] = s;
+}
+
 __global__ void __launch_bounds__(kBlock) k_fin_store_q(RedWork rw, int nb, double* out, size_t stride) {
     __shared__ double sh[kWaves];
     const int q = blockIdx.x, col = blockIdx.y;
@@ -704,7 +715,7 @@ hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx
     auto launch = [&](auto jc) {
         constexpr int J = decltype(jc)::value;
         hipLaunchKernelGGL((k_gcr_dots<T, J>), grid, dim3(kBlock), 0, st, W, wstride, w, r, n, stop_in, rw);
-        hipLaunchKernelGGL(k_fin_store_q, dim3(2 * J + 3, ncol), dim3(kBlock), 0, st, rw, (int)grid.x, g.tot,
+        hipLaunchKernelGGL(k_fin_store_q1, dim3(2 * J + 3, ncol), dim3(64), 0, st, rw, (int)grid.x, g.tot,
                            (size_t)kGcrTot);
         hipLaunchKernelGGL((k_gcr_fused_update<T, J>), ew_grid(n, ncol), dim3(kBlock), 0, st, W, wstride, w, r,
                            copy, n, tol2, stop_in, stop_out, g);
