@@ -48,7 +48,7 @@ extern "C" {
 #define DWF_EBREAKDOWN    -3   /* Krylov breakdown (zero or non-finite norm)         */
 #define DWF_ENAN          -4   /* non-finite value in the input or the iteration     */
 #define DWF_ENOSETUP      -5   /* context missing or not set up                      */
-#define DWF_EUNSUPPORTED  -6   /* a size or option this build does not support       */
+#define DWF_EUNSUPPORTED  -6   /* a size or option the library does not support      */
 
 /* ---------------------------------------------------------------- flags */
 #define DWF_DAGGER     1       /* apply the adjoint                                  */

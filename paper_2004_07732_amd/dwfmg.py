@@ -52,11 +52,12 @@ _lib = None
 
 
 def lib() -> ctypes.CDLL:
-    """Load libdwfmg.so (built in-tree by __graft_entry__.build())."""
+    """Load libdwfmg.so (built in-tree by `python -m paper_2004_07732_amd.build`)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              f"(python -m paper_2004_07732_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
         vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
         L.dwf_apply.argtypes = [vp, vp, vp, i, i, i, i, d, d, i, vp]
