@@ -626,7 +626,7 @@ __global__ void k_gcr_solve(int k, int ncol, GcrDev g) {
 
 template <typename T, typename Tx>
 __global__ void k_gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int accumulate, GcrDev g,
-                              int solve) {
+                              int solve, const cpx<T>* rsrc, cpx<T>* p0dst, const int* stop_src, int ncol) {
     const int col = blockIdx.y;
     const size_t o = (size_t)col * n;
     const double* gam = g.gam + 2 * (size_t)col * g.kmax;
@@ -658,6 +658,8 @@ __global__ void k_gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x
     cpx<double> c[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) c[i] = (i < k) ? cpx<double>{gam[2 * i], gam[2 * i + 1]} : cpx<double>{0.0, 0.0};
+    if (stop_src && stop_src != g.stop && blockIdx.x == 0 && blockIdx.y == 0)
+        for (int cc = threadIdx.x; cc < ncol; cc += blockDim.x) g.stop[cc] = stop_src[cc];
     GRID_STRIDE(e, n) {
         cpx<double> acc = {0.0, 0.0};
         if (accumulate) acc = {(double)x[o + e].re, (double)x[o + e].im};
@@ -669,6 +671,8 @@ __global__ void k_gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x
                 acc.im += c[i].re * p.im + c[i].im * p.re;
             }
         x[o + e] = {(Tx)acc.re, (Tx)acc.im};
+        // restart: the residual becomes the first direction (after P_0 was read above)
+        if (p0dst) p0dst[o + e] = rsrc[o + e];
     }
 }
 
@@ -743,7 +747,7 @@ hipError_t gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_
                        bool accumulate, const GcrDev& g, hipStream_t st) {
     if (k > 16) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_gcr_xupdate<T, Tx>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, pstride, k, x, n,
-                       accumulate ? 1 : 0, g, 0);
+                       accumulate ? 1 : 0, g, 0, (const cpx<T>*)nullptr, (cpx<T>*)nullptr, (const int*)nullptr, 0);
     return hipGetLastError();
 }
 template <typename T, typename Tx>
@@ -757,7 +761,19 @@ hipError_t gcr_solve_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x,
         return gcr_xupdate<T, Tx>(P, pstride, k, x, n, ncol, accumulate, g, st);
     }
     hipLaunchKernelGGL((k_gcr_xupdate<T, Tx>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, pstride, k, x, n,
-                       accumulate ? 1 : 0, g, 1);
+                       accumulate ? 1 : 0, g, 1, (const cpx<T>*)nullptr, (cpx<T>*)nullptr, (const int*)nullptr, 0);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t gcr_solve_xupdate_restart(cpx<T>* P, size_t pstride, int k, cpx<T>* x, size_t n, int ncol, const cpx<T>* r,
+                                     const int* stop_src, const GcrDev& g, hipStream_t st) {
+    if (k < 0 || k > 16) return hipErrorInvalidValue;
+    if (k > 8) {
+        if (hipError_t e = gcr_solve_xupdate<T, T>(P, pstride, k, x, n, ncol, true, g, st)) return e;
+        return gcr_restart<T>(r, P, n, ncol, stop_src, g, st);
+    }
+    hipLaunchKernelGGL((k_gcr_xupdate<T, T>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, pstride, k, x, n, 1, g, 1, r, P,
+                       stop_src, ncol);
     return hipGetLastError();
 }
 
@@ -810,5 +826,7 @@ template hipError_t gcr_xupdate<double, double>(const cpx<double>*, size_t, int,
 template hipError_t gcr_xupdate<float, double>(const cpx<float>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
 template hipError_t gcr_solve_xupdate<float, float>(const cpx<float>*, size_t, int, cpx<float>*, size_t, int, bool, const GcrDev&, hipStream_t);
 template hipError_t gcr_solve_xupdate<double, double>(const cpx<double>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
+template hipError_t gcr_solve_xupdate_restart<float>(cpx<float>*, size_t, int, cpx<float>*, size_t, int, const cpx<float>*, const int*, const GcrDev&, hipStream_t);
+template hipError_t gcr_solve_xupdate_restart<double>(cpx<double>*, size_t, int, cpx<double>*, size_t, int, const cpx<double>*, const int*, const GcrDev&, hipStream_t);
 
 }  // namespace dwf

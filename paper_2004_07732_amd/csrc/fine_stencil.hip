@@ -361,19 +361,28 @@ static int tuned_cfg(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return heuristic;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return heuristic; }
+    // each candidate: the best of three runs of ten launches (launch-rate and cache
+    // noise made single short runs pick the slower kernel now and then); the
+    // heuristic choice is kept unless another is faster by more than 5%
     int best = heuristic;
-    float best_t = 1e30f;
+    float best_t = 1e30f, heur_t = 1e30f;
     for (int c : cand) {
         if (launch_fine<R>(U, in, out, nullptr, Lx, Ly, Ls, ncol, m, M5, dagger, nullptr, 1, c, st) != hipSuccess)
             continue;
-        (void)hipEventRecord(e0, st);
-        for (int r = 0; r < 5; ++r)
-            (void)launch_fine<R>(U, in, out, nullptr, Lx, Ly, Ls, ncol, m, M5, dagger, nullptr, 1, c, st);
-        (void)hipEventRecord(e1, st);
-        (void)hipEventSynchronize(e1);
-        float t = 0.f;
-        if (hipEventElapsedTime(&t, e0, e1) == hipSuccess && t < best_t) { best_t = t; best = c; }
+        float tc = 1e30f;
+        for (int trial = 0; trial < 3; ++trial) {
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < 10; ++r)
+                (void)launch_fine<R>(U, in, out, nullptr, Lx, Ly, Ls, ncol, m, M5, dagger, nullptr, 1, c, st);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, e0, e1) == hipSuccess && t < tc) tc = t;
+        }
+        if (c == heuristic) heur_t = tc;
+        if (tc < best_t) { best_t = tc; best = c; }
     }
+    if (heur_t < 1e30f && heur_t <= 1.05f * best_t) best = heuristic;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     cache[key] = best;

@@ -176,6 +176,11 @@ hipError_t gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_
 template <typename T, typename Tx>
 hipError_t gcr_solve_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int ncol,
                              bool accumulate, const GcrDev& g, hipStream_t st);
+// gcr_solve_xupdate (accumulating) and gcr_restart (P_0 = r, stop flags from stop_src)
+// in one launch for k <= 8
+template <typename T>
+hipError_t gcr_solve_xupdate_restart(cpx<T>* P, size_t pstride, int k, cpx<T>* x, size_t n, int ncol, const cpx<T>* r,
+                                     const int* stop_src, const GcrDev& g, hipStream_t st);
 
 // ------------------------------------------------------------ transfer (Sec. 2.3)
 // Prolongator V[site][c][j][k] (nc internal dof per chirality, nvec coarse vectors).

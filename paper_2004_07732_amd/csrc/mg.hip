@@ -434,10 +434,9 @@ int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol
             HIPCHK(gcr_fused_step<T>(W, nt, k, Wk, r, k + 1 < kmax ? P + (size_t)(k + 1) * nt : nullptr, n, ncol,
                                      tol2, s_in, s_out, g, rw_, st));
         }
-        HIPCHK((gcr_solve_xupdate<T, T>(P, nt, kmax, x, n, ncol, true, g, st)));
-        // the next cycle continues from the recursive residual (its norm and the stop
-        // flags are those of the last fused step)
-        HIPCHK(gcr_restart<T>(r, P, n, ncol, (kmax % 2 == 0) ? g.stop : g.stop2, g, st));
+        // solution update, and the next cycle continues from the recursive residual (its
+        // norm and the stop flags are those of the last fused step)
+        HIPCHK(gcr_solve_xupdate_restart<T>(P, nt, kmax, x, n, ncol, r, (kmax % 2 == 0) ? g.stop : g.stop2, g, st));
         return DWF_OK;
     };
     const int max_cycles = std::max(1, (maxit + kmax - 1) / kmax);
