@@ -295,14 +295,15 @@ static inline bool tile_fits(int shape, int Lx, int Ly) {
 }
 
 static inline int pick_cfg(int Lx, int Ly, int Ls, int ncol) {
-    // the first tile shape that divides the lattice, else the row kernel; chunks
-    // as long as possible while the grid still gives every CU several workgroups
+    // the first tile shape that divides the lattice, else the row kernel; chunks of at
+    // most 8 slices (measured best at the HBM-bound shapes), shorter while the grid
+    // would not give every CU several workgroups
     const long long want = 256LL * 64 * 16;
     const long long sites = (long long)Lx * Ly * ncol;
     int shape = 0;
     for (int k = 1; k <= kNumTiles && !shape; ++k)
         if (tile_fits(k, Lx, Ly)) shape = k;
-    int cs = std::min(Ls, kCfgStride - 1);
+    int cs = std::min(std::min(Ls, 8), kCfgStride - 1);
     while (cs > 2 && sites * ((Ls + cs - 1) / cs) < want) cs = (cs + 1) / 2;
     return shape * kCfgStride + cs;
 }
@@ -363,7 +364,7 @@ static int tuned_cfg(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return heuristic; }
     // each candidate: the best of three runs of ten launches (launch-rate and cache
     // noise made single short runs pick the slower kernel now and then); the
-    // heuristic choice is kept unless another is faster by more than 5%
+    // heuristic choice is kept unless another is faster by more than 3%
     int best = heuristic;
     float best_t = 1e30f, heur_t = 1e30f;
     for (int c : cand) {
@@ -382,7 +383,7 @@ static int tuned_cfg(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int
         if (c == heuristic) heur_t = tc;
         if (tc < best_t) { best_t = tc; best = c; }
     }
-    if (heur_t < 1e30f && heur_t <= 1.05f * best_t) best = heuristic;
+    if (heur_t < 1e30f && heur_t <= 1.03f * best_t) best = heuristic;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     cache[key] = best;
