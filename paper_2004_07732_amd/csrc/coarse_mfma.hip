@@ -17,9 +17,11 @@
 // largest entry near 1 (exact, undone in the epilogue), which keeps FP16 in
 // range whatever the magnitude of the Krylov vectors.
 //
-// Work split: one wavefront per (coarse site, 16-row tile).  A wave loads all
-// of its link fragments up front (every link element is read exactly once per
-// apply, with all loads in flight together) and keeps them in registers while
+// Work split: one wavefront per (coarse site, 16-row tile), one workgroup per
+// site.  A wave loads all of its link fragments up front (a site's own link
+// elements are read once per apply, the backward hops' from the neighbours'
+// forward links, mostly in L2; all loads in flight together) and keeps them in
+// registers while
 // it walks the column tiles (8 columns, or 4 or 2 when there are at most that
 // many).  The
 // five neighbour vectors of a column tile are staged once per site in LDS,
@@ -103,7 +105,7 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
                    float cdiag, float mwrap) {
     using HF = Half<F16>;
     constexpr int MT = N / 16;                    // row tiles = waves per site
-    constexpr int SPB = (MT >= 4) ? 1 : 4 / MT;   // sites per block
+    constexpr int SPB = 1;                        // sites per block (measured: one is best)
     constexpr int KS = 5 * N / 16;                // inner steps of 16 complex entries
     constexpr int KS3 = 3 * N / 16;               // stored inner steps (site term, +x, +y)
     constexpr int H = N / 2;                      // chirality boundary (sigma_3)
@@ -390,7 +392,7 @@ template <bool F16, typename T, int N>
 hipError_t launch_n(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol, double m,
                     double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
     constexpr int MT = N / 16;
-    constexpr int SPB = (MT >= 4) ? 1 : 4 / MT;
+    constexpr int SPB = 1;
     const int nsites = g.Lx * g.Ly;
     dim3 grid((nsites + SPB - 1) / SPB), block(64 * MT * SPB);
     const u32x4* lk = reinterpret_cast<const u32x4*>(links);
