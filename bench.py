@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0   # dense matrix-core BF16 peak of MI355X
 METRIC = "DWF solves/s to 1e-10 at 256\u00b2\u00d7Ls16, mixed vs FP64; D_dw stencil HBM GB/s"
 
 WORKLOADS = {
@@ -347,6 +348,38 @@ def main():
     achieved = coarse_bytes / (t_coarse_ms * 1e-3) / 1e9
     traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse_mfma.hip"), coarse_bytes)
     log(f"[bench] coarse stencil {t_coarse_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
+    # matrix-core use of the same launch. A wave owns 16 output rows of one site and a tile
+    # of up to TW (slice, column) pairs (TW = 2, 4 or 8 by Ls_coarse * ncol; several tiles
+    # only at TW = 8); per tile it issues one 16x16x32 BF16 product per 16 complex inner
+    # entries of the five blocks and per half (hi, lo) of the split vector.
+    C = Lsc * 1
+    tw = 2 if C <= 2 else (4 if C <= 4 else 8)
+    ntile = 1 if tw < 8 else -(-C // 8)
+    mfma_per_launch = nsites * (n // 16) * ntile * 2 * (5 * n // 16)
+    issued_tf = mfma_per_launch * 16 * 16 * 32 * 2 / (t_coarse_ms * 1e-3) / 1e12
+    useful_tf = nsites * Lsc * 5 * n * n * 8 / (t_coarse_ms * 1e-3) / 1e12
+    coarse_mfma = {"mfma_per_launch": mfma_per_launch, "issued_TFLOP_s": issued_tf,
+                   "algorithmic_TFLOP_s": useful_tf, "peak_bf16_TFLOP_s": PEAK_BF16_TFLOPS,
+                   "frac_issued": issued_tf / PEAK_BF16_TFLOPS, "frac_algorithmic": useful_tf / PEAK_BF16_TFLOPS}
+    # whole-solve HBM model of the headline solve: fine stencils (FP32: vector read and written,
+    # links once per apply), two coarse stencils per coarsest iteration (A-hat = D_PV-hat^dag
+    # D_DW-hat), and the coarsest GCR(k) vector algebra: at direction j the multi-dot reads
+    # j + 2 vectors and the fused update reads j + 2 and writes 3; each cycle's solution
+    # update reads k directions and x, writes x, and restarts (read r, write p_0): k + 4.
+    # The fine-level vector algebra is not counted, so the fraction is a lower bound.
+    k = args.coarsest_restart
+    fine_apply_bytes = 2 * Ls * L * L * 2 * 8 + 2 * L * L * 8
+    coarse_vec = nsites * Lsc * n * vec_bytes
+    ci = stats.level_iters[0]
+    solve_bytes = (stats.fine_applies * fine_apply_bytes + 2 * ci * coarse_bytes
+                   + ci * (k * k + 7 * k + 4) / k * coarse_vec) if args.coarsest == "gcr" else None
+    solve_roofline = None
+    if solve_bytes is not None:
+        gbs = solve_bytes / t_step / 1e9
+        solve_roofline = {"bound": "hbm", "model_bytes": solve_bytes, "achieved": gbs, "peak": PEAK_HBM_GBS,
+                          "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "lower_bound": True}
+        log(f"[bench] coarse matrix cores {issued_tf:.0f} TFLOP/s issued ({issued_tf / PEAK_BF16_TFLOPS:.3f}); "
+            f"whole solve {solve_bytes / 1e9:.0f} GB modelled, {gbs:.0f} GB/s = {gbs / PEAK_HBM_GBS:.3f}")
 
     rows = {}
     if not args.quick:
@@ -442,6 +475,8 @@ def main():
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic, "algorithmic_bytes": coarse_bytes, "us_per_launch": t_coarse_ms * 1e3},
         "cpu_baseline": cpu,
+        "coarse_mfma": coarse_mfma,
+        "solve_roofline": solve_roofline,
         "fp64": fp64,
         "mixed_vs_fp64": (mixed_sps / fp64["solves_per_s"]) if fp64 else None,
         "rows": rows,
