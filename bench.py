@@ -130,7 +130,17 @@ def cpu_baseline(wl, stats, U_np, coarsest):
         # one GCR iteration applies A (from a zero start; restarts continue from the recursive residual)
         coarse_A = float(stats.level_iters[0])
     t_solve = fine_A * tA + coarse_A * tAc
+    # the oracle's D_DW bandwidth by the stencil byte formula (FP64: vector read and written, links once)
+    d_bytes = 2 * Ls * L * L * 2 * 16 + 2 * L * L * 16
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model, "host_cpus": os.cpu_count(),
+            "oracle_dw_GB_s": 2 * d_bytes / tA / 1e9,
             "sample": (f"oracle unit costs on the host: D_PV^dag D_DW at {L}^2 x {Ls} = {tA:.3f} s, "
                        f"coarse hat-A at {L // bx}^2 x {Lsc} x {2 * nv} dof = {tAc:.3f} s; "
                        f"times the counts of one GPU solve ({fine_A:.0f} fine A, {coarse_A:.0f} coarse A); "
@@ -224,7 +234,7 @@ def stencil_rows(dwfmg, inputs, torch, m, M5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dwf256_ls16_mg2", choices=sorted(WORKLOADS))
     ap.add_argument("--coarsest", choices=["cgnr", "gcr"], default="gcr",
