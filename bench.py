@@ -147,6 +147,38 @@ def cpu_baseline(wl, stats, U_np, coarsest):
                        f"Krylov vector algebra not counted")}
 
 
+def coarse_stencil_bytes(nsites, n, Ls_c, ncol, link_bytes, vec_bytes):
+    """Algorithmic bytes of one coarse D_DW launch: per coarse site the site term
+    and the two forward hops of the links (the backward hops are the
+    sigma_3-adjoints of the neighbours' forward hops), and every vector entry read
+    once and written once."""
+    return nsites * (3 * n * n * link_bytes + 2 * Ls_c * ncol * n * vec_bytes)
+
+
+def coarse_mfma_per_launch(nsites, n, Ls_c, ncol):
+    """Matrix-core products (16x16x32, BF16) one coarse launch issues.  A wave owns
+    16 output rows of one site and a tile of up to TW (slice, column) pairs (TW = 2,
+    4 or 8 by Ls_c * ncol; several tiles only at TW = 8); per tile it issues one
+    product per 16 complex inner entries of the five blocks and per half (hi, lo)
+    of the split vector."""
+    C = Ls_c * ncol
+    tw = 2 if C <= 2 else (4 if C <= 4 else 8)
+    ntile = 1 if tw < 8 else -(-C // 8)
+    return nsites * (n // 16) * ntile * 2 * (5 * n // 16)
+
+
+def solve_model_bytes(fine_applies, coarse_iters, k, L, Ls, coarse_launch_bytes, coarse_vec_bytes):
+    """HBM bytes of one solve by a model (a lower bound): the fine FP32 stencils
+    (vector read and written, links once per apply), two coarse stencils per
+    coarsest iteration (A-hat = D_PV-hat^dag D_DW-hat), and the coarsest GCR(k)
+    vector algebra: at direction j the multi-dot reads j + 2 vectors and the fused
+    update reads j + 2 and writes 3; each cycle's solution update and restart move
+    k + 4.  The fine-level vector algebra is not counted."""
+    fine_apply = 2 * Ls * L * L * 2 * 8 + 2 * L * L * 8
+    return (fine_applies * fine_apply + 2 * coarse_iters * coarse_launch_bytes
+            + coarse_iters * (k * k + 7 * k + 4) / k * coarse_vec_bytes)
+
+
 def timed(mg, b, steps, warmup, tol=1e-10):
     """Mean seconds of `steps` solves after `warmup` untimed ones (the solve is
     synchronous: it returns after the true residual is known)."""
@@ -351,38 +383,19 @@ def main():
     n, nsites, Lsc = c["n"], c["Lx"] * c["Ly"], c["Ls"]
     link_bytes = 4  # bfloat16 complex
     vec_bytes = 16 if make_params(dwfmg, wl, True).vec_prec[0] == dwfmg.P_F64 else 8
-    # per coarse site: the site term and the two forward hops of BF16 links (the backward
-    # hops are the sigma_3-adjoints of the neighbours' forward hops), the vector read once
-    # and written once
-    coarse_bytes = nsites * (3 * n * n * link_bytes + 2 * Lsc * n * vec_bytes)
+    coarse_bytes = coarse_stencil_bytes(nsites, n, Lsc, 1, link_bytes, vec_bytes)
     achieved = coarse_bytes / (t_coarse_ms * 1e-3) / 1e9
     traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse_mfma.hip"), coarse_bytes)
     log(f"[bench] coarse stencil {t_coarse_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
-    # matrix-core use of the same launch. A wave owns 16 output rows of one site and a tile
-    # of up to TW (slice, column) pairs (TW = 2, 4 or 8 by Ls_coarse * ncol; several tiles
-    # only at TW = 8); per tile it issues one 16x16x32 BF16 product per 16 complex inner
-    # entries of the five blocks and per half (hi, lo) of the split vector.
-    C = Lsc * 1
-    tw = 2 if C <= 2 else (4 if C <= 4 else 8)
-    ntile = 1 if tw < 8 else -(-C // 8)
-    mfma_per_launch = nsites * (n // 16) * ntile * 2 * (5 * n // 16)
+    mfma_per_launch = coarse_mfma_per_launch(nsites, n, Lsc, 1)
     issued_tf = mfma_per_launch * 16 * 16 * 32 * 2 / (t_coarse_ms * 1e-3) / 1e12
     useful_tf = nsites * Lsc * 5 * n * n * 8 / (t_coarse_ms * 1e-3) / 1e12
     coarse_mfma = {"mfma_per_launch": mfma_per_launch, "issued_TFLOP_s": issued_tf,
                    "algorithmic_TFLOP_s": useful_tf, "peak_bf16_TFLOP_s": PEAK_BF16_TFLOPS,
                    "frac_issued": issued_tf / PEAK_BF16_TFLOPS, "frac_algorithmic": useful_tf / PEAK_BF16_TFLOPS}
-    # whole-solve HBM model of the headline solve: fine stencils (FP32: vector read and written,
-    # links once per apply), two coarse stencils per coarsest iteration (A-hat = D_PV-hat^dag
-    # D_DW-hat), and the coarsest GCR(k) vector algebra: at direction j the multi-dot reads
-    # j + 2 vectors and the fused update reads j + 2 and writes 3; each cycle's solution
-    # update reads k directions and x, writes x, and restarts (read r, write p_0): k + 4.
-    # The fine-level vector algebra is not counted, so the fraction is a lower bound.
-    k = args.coarsest_restart
-    fine_apply_bytes = 2 * Ls * L * L * 2 * 8 + 2 * L * L * 8
-    coarse_vec = nsites * Lsc * n * vec_bytes
-    ci = stats.level_iters[0]
-    solve_bytes = (stats.fine_applies * fine_apply_bytes + 2 * ci * coarse_bytes
-                   + ci * (k * k + 7 * k + 4) / k * coarse_vec) if args.coarsest == "gcr" else None
+    solve_bytes = (solve_model_bytes(stats.fine_applies, stats.level_iters[0], args.coarsest_restart, L, Ls,
+                                     coarse_bytes, nsites * Lsc * n * vec_bytes)
+                   if args.coarsest == "gcr" else None)
     solve_roofline = None
     if solve_bytes is not None:
         gbs = solve_bytes / t_step / 1e9

@@ -1,0 +1,51 @@
+"""Host-side checks of the benchmark script, without a GPU: the multi-GPU
+refusal, and its byte and matrix-core counts against figures worked out by
+hand for the 256^2 x Ls 16 workload (4x4 aggregates, 16 null vectors, so 64^2
+coarse sites with n = 32 coarse components, coarse Ls 2)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402  (imports only the standard library at module level)
+
+
+def test_more_than_one_gpu_is_refused_before_any_device_work():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
+
+
+def test_coarse_launch_bytes_worked_example():
+    # links: 3 blocks of 32 x 32 BF16 complex (4 B) = 12 288 B per site; vectors:
+    # 2 slices x 32 FP64 complex (16 B), read and written = 2 048 B per site
+    assert bench.coarse_stencil_bytes(4096, 32, 2, 1, 4, 16) == 4096 * (12288 + 2048) == 58_720_256
+    # 16 right-hand sides: the links once, the vectors 16 times
+    assert bench.coarse_stencil_bytes(4096, 32, 2, 16, 4, 16) == 4096 * (12288 + 16 * 2048)
+
+
+def test_coarse_matrix_core_count_worked_example():
+    # one tile of two columns: 2 waves per site (16 rows each), 10 inner steps of 16
+    # complex entries over the five 32 x 32 blocks, a hi and a lo product each
+    assert bench.coarse_mfma_per_launch(4096, 32, 2, 1) == 4096 * 2 * 10 * 2 == 163_840
+    # four columns still fit one tile; 32 (slice, column) pairs take four tiles of 8
+    assert bench.coarse_mfma_per_launch(4096, 32, 4, 1) == 163_840
+    assert bench.coarse_mfma_per_launch(4096, 32, 2, 16) == 4 * 163_840
+    # 9 pairs: two tiles of 8
+    assert bench.coarse_mfma_per_launch(64, 16, 9, 1) == 64 * 1 * 2 * 2 * 5
+
+
+def test_whole_solve_byte_model_worked_example():
+    # one fine FP32 apply at 256^2 x 16: 2 x 16 x 65536 x 2 x 8 B of vectors plus
+    # 2 x 65536 x 8 B of links = 34 603 008 B
+    fine = 34_603_008
+    coarse_vec = 4096 * 2 * 32 * 16
+    # GCR(6): per cycle sum_{j<6} (2j + 7) = 72 vector passes, plus 6 + 4 for the
+    # solution update and restart: 82 passes per 6 iterations
+    got = bench.solve_model_bytes(10, 12, 6, 256, 16, 58_720_256, coarse_vec)
+    want = 10 * fine + 2 * 12 * 58_720_256 + 12 * 82 / 6 * coarse_vec
+    assert abs(got - want) <= 1e-6 * want
