@@ -1,0 +1,310 @@
+"""Pins of the oracle's multigrid set-up and smoother against characterisations
+that do not restate the oracle's code:
+
+* the null-vector relaxation (Sec. 3.1, Table kcycle setup row) is conjugate
+  gradients on B v = 0, B = D_W D_W^dagger Hermitian positive definite, so its
+  k-th iterate minimises the B-norm over v0 + K_k(B, B v0) (a property of CG,
+  checked here by a dense minimisation over an orthonormal Krylov basis);
+* chiral doubling (Sec. 3.1) gives the prolongator columns P_+ v_k and P_- v_k
+  block by block (checked against the chiral projectors applied directly);
+* the smoothed K-cycle (Sec. 2.3 summary, Table kcycle: no pre-smoothing, 8
+  GCR post-smoothing steps) is z0 + y with z0 = Prol hat-A^{-1} Restr r and y
+  the minimal-residual correction of r - A z0 over K_8(A, r - A z0) (GCR with
+  p = r and full orthogonalisation is a minimal-residual method).
+
+Each pin comes with one-line mutations of the oracle's arithmetic, planted on
+the CPU in local copies, that the pin must reject.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dwf_oracle as O
+from paper_2004_07732_amd import inputs
+
+
+def cgauss(shape, seed):
+    return inputs.gaussian_field(shape, seed)
+
+
+def hot_links(L, seed):
+    return inputs.links_from_theta(inputs.random_theta(L, L, seed))
+
+
+def krylov_basis(A, v, k):
+    """Orthonormal basis of K_k(A, v) = span{v, A v, ..., A^{k-1} v} (Arnoldi,
+    Gram-Schmidt applied twice)."""
+    Q = np.zeros((A.shape[0], k), dtype=np.complex128)
+    q = v / np.linalg.norm(v)
+    for j in range(k):
+        Q[:, j] = q
+        w = A @ q
+        for _ in range(2):
+            w = w - Q[:, :j + 1] @ (Q[:, :j + 1].conj().T @ w)
+        q = w / np.linalg.norm(w)
+    return Q
+
+
+# ----------------------------------------------------------------------------- CG on B v = 0
+def _setup_operator(L=4, ms=0.3, seed=5):
+    U = hot_links(L, seed)
+    B = lambda v: O.wilson(U, O.wilson(U, v, ms, dagger=True), ms)
+    Bd = O.assemble(B, (L, L, 2))
+    return B, Bd
+
+
+def cg_minimisation_error(cg_fn, steps=6):
+    """max_k |v_k - v*_k| / |v0| with v*_k the minimiser of v^dag B v over
+    v0 + K_k(B, B v0)."""
+    L = 4
+    B, Bd = _setup_operator(L)
+    v0 = cgauss((L, L, 2), 6)
+    x0 = v0.reshape(-1)
+    worst = 0.0
+    for k in range(1, steps + 1):
+        vk, it = cg_fn(B, v0, 0.0, k)
+        assert it == k
+        Q = krylov_basis(Bd, Bd @ x0, k)
+        c = np.linalg.solve(Q.conj().T @ Bd @ Q, -(Q.conj().T @ (Bd @ x0)))
+        want = x0 + Q @ c
+        worst = max(worst, np.linalg.norm(vk.reshape(-1) - want) / np.linalg.norm(x0))
+    return worst
+
+
+def test_cg_homogeneous_minimises_the_B_norm_over_the_krylov_space():
+    """k = 1..6 CG steps on B v = 0 from v0 equal the B-norm minimiser over
+    v0 + K_k(B, B v0), by a dense solve on an orthonormal Krylov basis."""
+    assert cg_minimisation_error(O.cg_homogeneous) < 1e-10
+
+
+def test_cg_homogeneous_stops_at_the_first_iterate_below_tolerance():
+    """Stopping rule (READING of the setup tolerance): the first j with
+    |B v_j| <= tol |B v_0|, or the cap."""
+    L = 4
+    B, _ = _setup_operator(L)
+    v0 = cgauss((L, L, 2), 7)
+    tol = 1e-4
+    v, it = O.cg_homogeneous(B, v0, tol, 250)
+    b0 = np.linalg.norm(B(v0))
+    assert 1 < it < 250
+    assert np.linalg.norm(B(v)) <= tol * b0 * (1 + 1e-12)
+    vprev, _ = O.cg_homogeneous(B, v0, 0.0, it - 1)
+    assert np.linalg.norm(B(vprev)) > tol * b0
+    v3, it3 = O.cg_homogeneous(B, v0, tol, 3)
+    assert it3 == 3
+
+
+def _cg_mut(kind):
+    """cg_homogeneous with one planted mistake."""
+    def cg(apply_B, v0, tol, maxit):
+        v = v0.copy()
+        r = apply_B(v) if kind == "residual_sign" else -apply_B(v)
+        p = r.copy()
+        rr = O.vdot(r, r).real
+        rr0 = rr
+        it = 0
+        while it < maxit and rr > tol * tol * rr0:
+            Bp = apply_B(p)
+            alpha = rr / (O.vdot(Bp, Bp).real if kind == "alpha" else O.vdot(p, Bp).real)
+            v = v + alpha * p
+            r = r - alpha * Bp
+            rr_new = O.vdot(r, r).real
+            beta = rr / rr_new if kind == "beta" else rr_new / rr
+            p = r + beta * p
+            rr = rr_new
+            it += 1
+        return v, it
+    return cg
+
+
+@pytest.mark.parametrize("kind", ["residual_sign", "alpha", "beta"])
+def test_cg_pin_rejects_mutations(kind):
+    assert cg_minimisation_error(_cg_mut(kind)) > 1e-6
+
+
+# ----------------------------------------------------------------------------- chiral doubling
+def chiral_columns_error(fn):
+    """Prolonging the coarse unit vector (X, c, k) of Prolongator(fn(v)) must give
+    (1 + s_c sigma3)/2 v_k on the sites of aggregate X and zero elsewhere, on
+    the fine level (n = 2, sigma3 = gamma5) and on a coarse level (n = 6,
+    sigma3 = diag(1, 1, 1, -1, -1, -1))."""
+    worst = 0.0
+    for n, L, block, nv in ((2, 4, (2, 2), 3), (6, 4, (2, 2), 2)):
+        nc = n // 2
+        chir = O.chirality(nc)
+        v = cgauss((nv, L, L, n), 40 + n)
+        P = O.Prolongator(V=fn(v, chir), block=block)
+        cY, cX = P.coarse_shape
+        for Yc in range(cY):
+            for Xc in range(cX):
+                mask = np.zeros((L, L, 1))
+                mask[Yc * block[0]:(Yc + 1) * block[0], Xc * block[1]:(Xc + 1) * block[1]] = 1.0
+                for c, sc in ((0, 1.0), (1, -1.0)):
+                    proj = 0.5 * (1.0 + sc * chir)
+                    for k in range(nv):
+                        e = np.zeros((cY, cX, 2 * nv), dtype=np.complex128)
+                        e[Yc, Xc, c * nv + k] = 1.0
+                        got = O.prolong2d(P, e)
+                        want = mask * proj * v[k]
+                        worst = max(worst, float(np.max(np.abs(got - want))))
+    return worst
+
+
+def test_chiral_doubling_columns_are_the_chiral_projections():
+    assert chiral_columns_error(O.fine_to_chiral_columns) == 0.0
+
+
+def _chiral_mut(kind):
+    def fn(v, chir):
+        nv, Ly, Lx, n = v.shape
+        nc = n // 2
+        V = v.reshape(nv, Ly, Lx, 2, nc)
+        if kind == "chirality_swap":
+            V = V[:, :, :, ::-1, :]
+        elif kind == "vector_order":
+            V = V[::-1]
+        elif kind == "conjugate":
+            V = np.conj(V)
+        return V.transpose(1, 2, 3, 4, 0).copy()
+    return fn
+
+
+@pytest.mark.parametrize("kind", ["chirality_swap", "vector_order", "conjugate"])
+def test_chiral_pin_rejects_mutations(kind):
+    assert chiral_columns_error(_chiral_mut(kind)) > 1e-3
+
+
+def test_mg_prolongator_spans_the_projected_null_vectors():
+    """On an oracle hierarchy: gamma5 P = P sigma3 exactly, P^dag P = 1, and per
+    aggregate and chirality the first k orthonormal columns span
+    {P_c v_1 .. P_c v_k} restricted to the aggregate (classical Gram-Schmidt in
+    the order of the null vectors, Sec. 2.3)."""
+    L, Ls, m, M5 = 4, 4, 0.1, -1.0
+    U = inputs.metropolis_u1(L, L, 3.0, 10, 3).U
+    nv, block = 3, (2, 2)
+    params = O.MGParams(levels=[O.LevelParams(nvec=nv, block=block, Ls=2, setup_iters=20)])
+    starts = [cgauss((nv, L, L, 2), 91)]
+    mg = O.MG(U, Ls, m, M5, params, starts)
+    P = mg.levels[0].P
+    cY, cX = P.coarse_shape
+    Pd = O.assemble(lambda e: O.prolong2d(P, e), (cY, cX, 2 * nv))
+    g5 = np.kron(np.eye(L * L), O.GAMMA5)
+    s3 = np.kron(np.eye(cY * cX), np.diag(O.chirality(nv)))
+    assert np.max(np.abs(g5 @ Pd - Pd @ s3)) == 0.0
+    assert np.max(np.abs(Pd.conj().T @ Pd - np.eye(Pd.shape[1]))) < 1e-14
+    # the relaxed vectors, recomputed with the same operator and starts
+    Bop = lambda v: O.wilson(U, O.wilson(U, v, params.m_setup, dagger=True), params.m_setup)
+    vs = [O.cg_homogeneous(Bop, starts[0][k], 1e-4, 20)[0] for k in range(nv)]
+    for Yc in range(cY):
+        for Xc in range(cX):
+            mask = np.zeros((L, L, 1))
+            mask[Yc * block[0]:(Yc + 1) * block[0], Xc * block[1]:(Xc + 1) * block[1]] = 1.0
+            for c, proj in ((0, O.P_PLUS), (1, O.P_MINUS)):
+                raw = np.stack([(mask * O.spin_mul(proj, vs[k])).reshape(-1) for k in range(nv)], axis=1)
+                cols = Pd.reshape(L, L, 2, cY, cX, 2 * nv)[..., Yc, Xc, c * nv:(c + 1) * nv].reshape(-1, nv)
+                for k in range(1, nv + 1):
+                    Qk, _ = np.linalg.qr(raw[:, :k])
+                    resid = cols[:, :k] - Qk @ (Qk.conj().T @ cols[:, :k])
+                    assert np.max(np.abs(resid)) < 1e-12
+
+
+# ----------------------------------------------------------------------------- smoothed K-cycle
+def _small_hierarchy(smooth_iters=8):
+    L, Ls, m, M5 = 4, 4, 0.1, -1.0
+    U = inputs.metropolis_u1(L, L, 3.0, 10, 3).U
+    params = O.MGParams(levels=[O.LevelParams(nvec=2, block=(2, 2), Ls=2, setup_iters=20)],
+                        smooth_iters=smooth_iters, coarsest_tol=1e-14, coarsest_maxit=5000)
+    starts = [cgauss((2, L, L, 2), 91)]
+    return O.MG(U, Ls, m, M5, params, starts), (Ls, L, L, 2)
+
+
+def kcycle_error(mg_cls=O.MG, gcr_fn=None, steps=8):
+    """|M(r) - (z0 + y)| / |M(r)| with z0 = Prol hat-A^{-1} Restr r (dense coarse
+    solve) and y = argmin |r - A z0 - A y| over y in K_steps(A, r - A z0)."""
+    mg, shape = _small_hierarchy(steps)
+    mg.__class__ = mg_cls
+    r = cgauss(shape, 92)
+    saved = O.gcr
+    if gcr_fn is not None:
+        O.gcr = gcr_fn
+    try:
+        got = mg.kcycle(0, r)
+    finally:
+        O.gcr = saved
+    A0 = O.assemble(lambda v: mg.A(0, v), shape)
+    cshape = (2, 2, 2, 4)
+    Ac = O.assemble(lambda v: mg.A(1, v), cshape)
+    rc = mg.restrict(0, r)
+    ec = np.linalg.solve(Ac, rc.reshape(-1)).reshape(rc.shape)
+    z0 = mg.prolong(0, ec).reshape(-1)
+    rs = r.reshape(-1) - A0 @ z0
+    Q = krylov_basis(A0, rs, steps)
+    c, *_ = np.linalg.lstsq(A0 @ Q, rs, rcond=None)
+    want = z0 + Q @ c
+    return np.linalg.norm(got.reshape(-1) - want) / np.linalg.norm(want)
+
+
+def test_smoothed_kcycle_is_coarse_correction_plus_minimal_residual_steps():
+    assert kcycle_error() < 1e-9
+
+
+class _MGSmoothSign(O.MG):
+    def kcycle(self, l, r):
+        e = self.coarse_solve(l + 1, self.restrict(l, r))
+        z0 = self.prolong(l, e)
+        rs = r - self.A(l, z0)
+        zs, _ = O.gcr(lambda v: self.A(l, v), rs, 0.0, self.params.smooth_iters, self.params.smooth_iters)
+        return z0 - zs
+
+
+class _MGSmoothResidual(O.MG):
+    def kcycle(self, l, r):
+        e = self.coarse_solve(l + 1, self.restrict(l, r))
+        z0 = self.prolong(l, e)
+        rs = r + self.A(l, z0)
+        zs, _ = O.gcr(lambda v: self.A(l, v), rs, 0.0, self.params.smooth_iters, self.params.smooth_iters)
+        return z0 + zs
+
+
+class _MGSmoothShort(O.MG):
+    def kcycle(self, l, r):
+        e = self.coarse_solve(l + 1, self.restrict(l, r))
+        z0 = self.prolong(l, e)
+        rs = r - self.A(l, z0)
+        zs, _ = O.gcr(lambda v: self.A(l, v), rs, 0.0, self.params.smooth_iters - 1, self.params.smooth_iters)
+        return z0 + zs
+
+
+def _gcr_no_p_update(apply_A, b, tol, maxit, restart, precond=None, x0=None):
+    """O.gcr with the direction left out of the orthogonalisation."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    bnorm = O.norm(b)
+    it = 0
+    ps, qs = [], []
+    while it < maxit and O.norm(r) > tol * bnorm:
+        p = r.copy()
+        q = apply_A(p)
+        for pi, qi in zip(ps, qs):
+            beta = O.vdot(qi, q)
+            q = q - beta * qi
+        qn = O.norm(q)
+        q, p = q / qn, p / qn
+        alpha = O.vdot(q, r)
+        x = x + alpha * p
+        r = r - alpha * q
+        ps.append(p)
+        qs.append(q)
+        it += 1
+    return x, it
+
+
+@pytest.mark.parametrize("mut", ["sign", "residual", "short", "gcr_p"])
+def test_kcycle_pin_rejects_mutations(mut):
+    if mut == "gcr_p":
+        err = kcycle_error(gcr_fn=_gcr_no_p_update)
+    else:
+        cls = {"sign": _MGSmoothSign, "residual": _MGSmoothResidual, "short": _MGSmoothShort}[mut]
+        err = kcycle_error(mg_cls=cls)
+    assert err > 1e-6
