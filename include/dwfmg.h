@@ -110,7 +110,9 @@ int dwf_fine_config(int shape, int chunk);
 
 /* Pauli-Villars forms (Sec. 2.2, eq. NormalExp): see the DWF_PV* modes.  The
  * product modes use a library-owned intermediate field (allocated on first use
- * and kept until dwf_release_scratch).  Same layout rules as dwf_apply.
+ * and kept until dwf_release_scratch; a call on one stream waits, on the
+ * device, for the previous call's use of it on another).  Same layout rules as
+ * dwf_apply.
  * DWF_PVINV_DW (FP64 only; DWF_EUNSUPPORTED with DWF_PREC_F32) applies D_DW(m)
  * and then solves D_PV out = D_DW psi for each right-hand side by CGNR to a
  * relative residual of 1e-12 (D_PV is well conditioned: its free-field singular

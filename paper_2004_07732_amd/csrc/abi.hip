@@ -26,21 +26,55 @@ bool dims_ok(int Lx, int Ly, int Ls, int nrhs) {
            (long long)Lx * Ly * Ls * nrhs < (1LL << 40);
 }
 
-// library-owned intermediate field of the product modes of dwf_pv_apply
-std::mutex g_scratch_mu;
-void* g_scratch = nullptr;
-size_t g_scratch_bytes = 0;
+// A library-owned device buffer shared by calls that may come on different
+// streams.  acquire() makes the caller's stream wait for the work that the
+// previous call queued on the buffer; release() marks the end of the caller's
+// queued work.  (Inside a graph capture neither is recorded: the capturing
+// caller orders its own work.)
+struct SharedBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t last = nullptr;
+    bool pending = false;
+};
 
-void* scratch(size_t bytes) {
-    if (bytes <= g_scratch_bytes) return g_scratch;
-    std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
-    if (g_scratch) { hipDeviceSynchronize(); hipFree(g_scratch); }
-    g_scratch = nullptr;
-    g_scratch_bytes = 0;
-    if (hipMalloc(&g_scratch, bytes) != hipSuccess) return nullptr;
-    g_scratch_bytes = bytes;
-    return g_scratch;
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
 }
+
+void* acquire(SharedBuf& b, size_t bytes, hipStream_t st) {
+    if (bytes > b.bytes) {
+        std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
+        if (b.p) { (void)hipDeviceSynchronize(); (void)hipFree(b.p); }
+        b.p = nullptr;
+        b.bytes = 0;
+        b.pending = false;
+        if (hipMalloc(&b.p, bytes) != hipSuccess) { b.p = nullptr; return nullptr; }
+        b.bytes = bytes;
+    }
+    if (!b.last && hipEventCreateWithFlags(&b.last, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (b.pending && !capturing(st) && hipStreamWaitEvent(st, b.last, 0) != hipSuccess) return nullptr;
+    return b.p;
+}
+
+int release(SharedBuf& b, hipStream_t st, int status) {
+    if (!capturing(st) && hipEventRecord(b.last, st) == hipSuccess) b.pending = true;
+    return status;
+}
+
+void drop(SharedBuf& b) {
+    std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
+    if (b.p) { (void)hipDeviceSynchronize(); (void)hipFree(b.p); }
+    b.p = nullptr;
+    b.bytes = 0;
+    b.pending = false;
+}
+
+// the intermediate fields of the product modes of dwf_pv_apply / dwf_pv_poly_apply,
+// and the partial sums of dwf_norm2
+std::mutex g_scratch_mu;
+SharedBuf g_fields, g_partials;
 
 template <typename R>
 int pv_apply_t(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, double m,
@@ -55,31 +89,24 @@ int pv_apply_t(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls
         case DWF_PVDAG_DW_DAG: {
             std::lock_guard<std::mutex> lk(g_scratch_mu);
             const size_t bytes = sizeof(cpx<R>) * 2 * (size_t)Lx * Ly * Ls * nrhs;
-            auto t = reinterpret_cast<cpx<R>*>(scratch(bytes));
+            auto t = reinterpret_cast<cpx<R>*>(acquire(g_fields, bytes, st));
             if (!t) return DWF_EHIP;
-            if (mode == DWF_PVDAG_DW) {
-                if (fine_dw<R>(u, in, t, nullptr, Lx, Ly, Ls, nrhs, m, M5, false, nullptr, 1, st) != hipSuccess) return DWF_EHIP;
-                return hip_status(fine_dw<R>(u, t, o, nullptr, Lx, Ly, Ls, nrhs, 1.0, M5, true, nullptr, 1, st));
-            }
-            if (fine_dw<R>(u, in, t, nullptr, Lx, Ly, Ls, nrhs, 1.0, M5, false, nullptr, 1, st) != hipSuccess) return DWF_EHIP;
-            return hip_status(fine_dw<R>(u, t, o, nullptr, Lx, Ly, Ls, nrhs, m, M5, true, nullptr, 1, st));
+            const double m1 = (mode == DWF_PVDAG_DW) ? m : 1.0, m2 = (mode == DWF_PVDAG_DW) ? 1.0 : m;
+            if (fine_dw<R>(u, in, t, nullptr, Lx, Ly, Ls, nrhs, m1, M5, false, nullptr, 1, st) != hipSuccess)
+                return release(g_fields, st, DWF_EHIP);
+            return release(g_fields, st,
+                           hip_status(fine_dw<R>(u, t, o, nullptr, Lx, Ly, Ls, nrhs, m2, M5, true, nullptr, 1, st)));
         }
         default: return DWF_EINVAL;
     }
 }
 
 // out = D_PV^dag p(X) D_DW psi (or D_DW^dag p(X) D_PV psi), X = D_PV D_PV^dag,
-// p(X) w by Horner's scheme: y = c_K w, then y = c_k w + X y for k = K-1..0
+// p(X) w by Horner's scheme: y = c_K w, then y = c_k w + X y for k = K-1..0;
+// t holds three fields of n complex entries
 template <typename R>
-int pv_poly_apply_t(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, double m,
-                    double M5, const double* c, int order, bool dag, hipStream_t st) {
-    auto u = reinterpret_cast<const cpx<R>*>(U);
-    auto in = reinterpret_cast<const cpx<R>*>(psi);
-    auto o = reinterpret_cast<cpx<R>*>(out);
-    const size_t n = (size_t)2 * Lx * Ly * Ls * nrhs;
-    std::lock_guard<std::mutex> lk(g_scratch_mu);
-    auto t = reinterpret_cast<cpx<R>*>(scratch(sizeof(cpx<R>) * 3 * n));
-    if (!t) return DWF_EHIP;
+int pv_poly_chain(const cpx<R>* u, const cpx<R>* in, cpx<R>* o, cpx<R>* t, size_t n, int Lx, int Ly, int Ls, int nrhs,
+                  double m, double M5, const double* c, int order, bool dag, hipStream_t st) {
     cpx<R>* w = t;
     cpx<R>* y = t + n;
     cpx<R>* z = t + 2 * n;
@@ -94,6 +121,21 @@ int pv_poly_apply_t(const void* U, const void* psi, void* out, int Lx, int Ly, i
     }
     return hip_status(dag ? D(y, o, m, true) : D(y, o, 1.0, true));
 }
+
+template <typename R>
+int pv_poly_apply_t(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, double m,
+                    double M5, const double* c, int order, bool dag, hipStream_t st) {
+    auto u = reinterpret_cast<const cpx<R>*>(U);
+    auto in = reinterpret_cast<const cpx<R>*>(psi);
+    auto o = reinterpret_cast<cpx<R>*>(out);
+    const size_t n = (size_t)2 * Lx * Ly * Ls * nrhs;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto t = reinterpret_cast<cpx<R>*>(acquire(g_fields, sizeof(cpx<R>) * 3 * n, st));
+    if (!t) return DWF_EHIP;
+    const int status = pv_poly_chain<R>(u, in, o, t, n, Lx, Ly, Ls, nrhs, m, M5, c, order, dag, st);
+    return release(g_fields, st, status);
+}
+
 
 bool valid_prec(int p, bool link) {
     if (p == DWF_P_F64 || p == DWF_P_F32) return true;
@@ -164,20 +206,20 @@ int dwf_pv_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int 
         // D_DW psi into the intermediate field, then D_PV out = D_DW psi per right-hand side
         std::lock_guard<std::mutex> lk(g_scratch_mu);
         const size_t V = 2 * (size_t)Lx * Ly * Ls;
-        auto t = reinterpret_cast<cpx<double>*>(scratch(sizeof(cpx<double>) * V * nrhs));
+        auto t = reinterpret_cast<cpx<double>*>(acquire(g_fields, sizeof(cpx<double>) * V * nrhs, S(stream)));
         if (!t) return DWF_EHIP;
         const auto u = reinterpret_cast<const cpx<double>*>(U);
         if (fine_dw<double>(u, reinterpret_cast<const cpx<double>*>(psi), t, nullptr, Lx, Ly, Ls, nrhs, m_f, M5, false,
                             nullptr, 1, S(stream)) != hipSuccess)
-            return DWF_EHIP;
+            return release(g_fields, S(stream), DWF_EHIP);
         int worst = DWF_OK;
         for (int r = 0; r < nrhs; ++r) {
             const int e = krylov_solve(u, t + r * V, reinterpret_cast<cpx<double>*>(out) + r * V, Lx, Ly, Ls, 1.0, M5,
                                        DWF_KRYLOV_CGNR, 0, 1e-12, 10000, nullptr, S(stream));
-            if (e < 0) return e;
+            if (e < 0) return release(g_fields, S(stream), e);
             if (e > worst) worst = e;
         }
-        return worst;
+        return release(g_fields, S(stream), worst);
     }
     if (flags & DWF_PREC_F32) return pv_apply_t<float>(U, psi, out, Lx, Ly, Ls, nrhs, m_f, M5, mode, S(stream));
     return pv_apply_t<double>(U, psi, out, Lx, Ly, Ls, nrhs, m_f, M5, mode, S(stream));
@@ -390,20 +432,13 @@ int mg_solve_batch(int nctx, dwf_mg* const* ctx, const void* const* b, void* con
 int dwf_norm2(const void* x, size_t n, int ncol, double* out, void* stream) {
     if (!x || !out || ncol < 1 || n == 0) return DWF_EINVAL;
     std::lock_guard<std::mutex> lk(g_scratch_mu);
-    static double* partial = nullptr;
-    static int cap_cols = 0;
     RedWork rw;
     rw.nblk = kRedBlocks;
     rw.max_q = 1;
     rw.max_cols = ncol;
-    if (ncol > cap_cols) {
-        std::lock_guard<std::recursive_mutex> rlk(runtime_mutex());
-        if (partial) { hipDeviceSynchronize(); hipFree(partial); partial = nullptr; cap_cols = 0; }
-        if (hipMalloc(&partial, sizeof(double) * (size_t)rw.nblk * ncol) != hipSuccess) return DWF_EHIP;
-        cap_cols = ncol;
-    }
-    rw.partial = partial;
-    return hip_status(norm2<double>((const cpx<double>*)x, n, ncol, out, rw, S(stream)));
+    rw.partial = reinterpret_cast<double*>(acquire(g_partials, sizeof(double) * (size_t)rw.nblk * ncol, S(stream)));
+    if (!rw.partial) return DWF_EHIP;
+    return release(g_partials, S(stream), hip_status(norm2<double>((const cpx<double>*)x, n, ncol, out, rw, S(stream))));
 }
 
 int mg_update_links(dwf_mg* mg, const void* U, void* stream) {
@@ -444,13 +479,8 @@ int mg_destroy(dwf_mg* mg) {
 
 int dwf_release_scratch(void) {
     std::lock_guard<std::mutex> lk(g_scratch_mu);
-    std::lock_guard<std::recursive_mutex> rlk(runtime_mutex());
-    if (g_scratch) {
-        hipDeviceSynchronize();
-        hipFree(g_scratch);
-    }
-    g_scratch = nullptr;
-    g_scratch_bytes = 0;
+    drop(g_fields);
+    drop(g_partials);
     return DWF_OK;
 }
 
