@@ -49,6 +49,8 @@ extern "C" {
 #define DWF_ENAN          -4   /* non-finite value in the input or the iteration     */
 #define DWF_ENOSETUP      -5   /* context missing or not set up                      */
 #define DWF_EUNSUPPORTED  -6   /* a size or option the library does not support      */
+#define DWF_ESCRATCH      -7   /* input larger than the static scratch of an
+                                  allocation-free entry point                        */
 
 /* ---------------------------------------------------------------- flags */
 #define DWF_DAGGER     1       /* apply the adjoint                                  */
@@ -121,6 +123,26 @@ int dwf_fine_config(int shape, int chunk);
  * stops at its cap of 10000 iterations. */
 int dwf_pv_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs,
                  double m_f, double M5, int mode, int flags, void* stream);
+
+/* Allocation-free variant of dwf_pv_apply, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Modes DWF_PV, DWF_PV_DAG, DWF_PVDAG_DW and
+ * DWF_PVDAG_DW_DAG give the same results as dwf_pv_apply, bit for bit;
+ * DWF_PVINV_DW returns DWF_EUNSUPPORTED (its inner solver allocates).  The
+ * intermediate field of the product modes lives in a static device array of
+ * dwf_pv_apply_noalloc_max_bytes() bytes (64 MiB) per GPU, reserved when the
+ * library's code object is loaded on that GPU and held until the process
+ * ends; a product whose intermediate field (16 B per complex entry in FP64,
+ * 8 B in FP32: 2 Lx Ly Ls nrhs entries) is larger returns DWF_ESCRATCH.  The
+ * call allocates nothing, never synchronises and never times the stencil (it
+ * uses a pinned or already-tuned launch configuration, else the heuristic
+ * one).  Every call on one GPU shares that GPU's array: calls whose work
+ * overlaps on the device (two streams, or two threads) race and give wrong
+ * results; order them on one stream.  The calling thread's current device must
+ * be the device of `stream`.  Same layout rules and errors as dwf_pv_apply. */
+int dwf_pv_apply_noalloc(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs,
+                         double m_f, double M5, int mode, int flags, void* stream);
+size_t dwf_pv_apply_noalloc_max_bytes(void);
 
 /* Polynomial correction of the PV preconditioning (the remark after eq.
  * NormalExp; App. A): out = D_PV^dag p(D_PV D_PV^dag) D_DW(m_f) psi with

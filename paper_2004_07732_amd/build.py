@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libdwfmg.so")
 ARCH = os.environ.get("DWF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["fine_stencil.hip", "blas.hip", "coarse.hip", "coarse_mfma.hip", "transfer.hip", "setup.hip", "util.hip",
-           "mg.hip", "deflate.hip", "krylov.hip", "abi.hip"]
+           "mg.hip", "deflate.hip", "krylov.hip", "abi.hip", "noalloc.hip"]
 # dense block products of the coarsest-level eigensolver
 LIBS = ["-L/opt/rocm/lib", "-lrocblas", "-lrocsolver", "-Wl,-rpath,/opt/rocm/lib"]
 

@@ -494,6 +494,7 @@ const char* dwf_strerror(int code) {
         case DWF_ENAN: return "non-finite value";
         case DWF_ENOSETUP: return "multigrid context missing or not set up";
         case DWF_EUNSUPPORTED: return "unsupported size or option";
+        case DWF_ESCRATCH: return "input larger than the static scratch of an allocation-free entry point";
         default: return "unknown status";
     }
 }

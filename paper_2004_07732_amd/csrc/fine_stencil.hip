@@ -319,7 +319,7 @@ static hipError_t launch_fine(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, co
 // in the file named by DWF_TUNE_CACHE when that is set.
 template <typename R>
 static int tuned_cfg(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int Ly, int Ls, int ncol,
-                     double m, double M5, bool dagger, hipStream_t st) {
+                     double m, double M5, bool dagger, hipStream_t st, bool may_time = true) {
     static std::mutex mu;
     static std::map<std::string, int> cache;
     static bool loaded = false;
@@ -329,9 +329,10 @@ static int tuned_cfg(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int
     char keyb[128];
     std::snprintf(keyb, sizeof keyb, "fine_dw2/%zu/%d/%d/%d/%d/%d", sizeof(R), Lx, Ly, Ls, ncol, dagger ? 1 : 0);
     const std::string key(keyb);
-    // inside a graph capture: use a choice already made, never time
+    // inside a graph capture, or for a caller that must not synchronise: use a
+    // choice already made, never time
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
+    if (!may_time || hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
         std::lock_guard<std::mutex> lk(mu);
         auto it = cache.find(key);
         return it != cache.end() ? it->second : heuristic;
@@ -405,16 +406,29 @@ bool set_fine_config(int shape, int chunk) {
 }
 
 template <typename R>
-hipError_t fine_dw(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b,
-                   int Lx, int Ly, int Ls, int ncol, double m, double M5, bool dagger,
-                   const int* skip, int skip_stride, hipStream_t st) {
+static hipError_t fine_dw_impl(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b, int Lx, int Ly,
+                               int Ls, int ncol, double m, double M5, bool dagger, const int* skip, int skip_stride,
+                               hipStream_t st, bool may_time) {
     const int pin = g_fine_pin.load(std::memory_order_relaxed);
     int cfg;
     if (pin >= 0 && (pin / kCfgStride == 0 || tile_fits(pin / kCfgStride, Lx, Ly)))
         cfg = (pin / kCfgStride) * kCfgStride + std::min(pin % kCfgStride, Ls);
     else
-        cfg = tuned_cfg<R>(U, in, out, Lx, Ly, Ls, ncol, m, M5, dagger, st);
+        cfg = tuned_cfg<R>(U, in, out, Lx, Ly, Ls, ncol, m, M5, dagger, st, may_time);
     return launch_fine<R>(U, in, out, b, Lx, Ly, Ls, ncol, m, M5, dagger, skip, skip_stride, cfg, st);
+}
+
+template <typename R>
+hipError_t fine_dw(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b,
+                   int Lx, int Ly, int Ls, int ncol, double m, double M5, bool dagger,
+                   const int* skip, int skip_stride, hipStream_t st) {
+    return fine_dw_impl<R>(U, in, out, b, Lx, Ly, Ls, ncol, m, M5, dagger, skip, skip_stride, st, true);
+}
+
+template <typename R>
+hipError_t fine_dw_untimed(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int Ly, int Ls, int ncol,
+                           double m, double M5, bool dagger, hipStream_t st) {
+    return fine_dw_impl<R>(U, in, out, nullptr, Lx, Ly, Ls, ncol, m, M5, dagger, nullptr, 1, st, false);
 }
 
 template <typename R, int TX, int TY>
@@ -489,6 +503,8 @@ hipError_t wilson2d(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int 
 
 template hipError_t fine_dw<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, const cpx<float>*, int, int, int, int, double, double, bool, const int*, int, hipStream_t);
 template hipError_t fine_dw<double>(const cpx<double>*, const cpx<double>*, cpx<double>*, const cpx<double>*, int, int, int, int, double, double, bool, const int*, int, hipStream_t);
+template hipError_t fine_dw_untimed<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, int, int, int, int, double, double, bool, hipStream_t);
+template hipError_t fine_dw_untimed<double>(const cpx<double>*, const cpx<double>*, cpx<double>*, int, int, int, int, double, double, bool, hipStream_t);
 template hipError_t wilson2d<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, int, int, int, double, bool, hipStream_t);
 template hipError_t wilson2d<double>(const cpx<double>*, const cpx<double>*, cpx<double>*, int, int, int, double, bool, hipStream_t);
 

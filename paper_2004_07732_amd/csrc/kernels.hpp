@@ -41,6 +41,11 @@ template <typename R>
 hipError_t fine_dw(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, const cpx<R>* b,
                    int Lx, int Ly, int Ls, int ncol, double m, double M5, bool dagger,
                    const int* skip, int skip_stride, hipStream_t st);
+// the same operator without the autotuner's timing runs (a pinned or previously
+// tuned configuration, else the heuristic one): no synchronisation, no events
+template <typename R>
+hipError_t fine_dw_untimed(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int Ly, int Ls, int ncol,
+                           double m, double M5, bool dagger, hipStream_t st);
 // pin the fine stencil's launch configuration (shape -1: automatic choice);
 // returns false for an unknown shape or chunk
 bool set_fine_config(int shape, int chunk);

@@ -25,6 +25,7 @@ DWF_EBREAKDOWN = -3
 DWF_ENAN = -4
 DWF_ENOSETUP = -5
 DWF_EUNSUPPORTED = -6
+DWF_ESCRATCH = -7
 
 DWF_DAGGER = 1
 DWF_PREC_F32 = 2
@@ -62,6 +63,9 @@ def lib() -> ctypes.CDLL:
         vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
         L.dwf_apply.argtypes = [vp, vp, vp, i, i, i, i, d, d, i, vp]
         L.dwf_pv_apply.argtypes = [vp, vp, vp, i, i, i, i, d, d, i, i, vp]
+        L.dwf_pv_apply_noalloc.argtypes = [vp, vp, vp, i, i, i, i, d, d, i, i, vp]
+        L.dwf_pv_apply_noalloc_max_bytes.argtypes = []
+        L.dwf_pv_apply_noalloc_max_bytes.restype = sz
         L.dwf_fine_config.argtypes = [i, i]
         L.dwf_pv_poly_apply.argtypes = [vp, vp, vp, i, i, i, i, d, d, ctypes.POINTER(d), i, i, vp]
         L.dwf_pv_poly_chebyshev.argtypes = [i, d, d, ctypes.POINTER(d)]
@@ -90,7 +94,7 @@ def lib() -> ctypes.CDLL:
         L.dwf_release_scratch.argtypes = []
         L.dwf_strerror.argtypes = [i]
         L.dwf_strerror.restype = ctypes.c_char_p
-        for name in ("dwf_apply", "dwf_pv_apply", "dwf_fine_config", "dwf_pv_poly_apply", "dwf_pv_poly_chebyshev",
+        for name in ("dwf_apply", "dwf_pv_apply", "dwf_pv_apply_noalloc", "dwf_fine_config", "dwf_pv_poly_apply", "dwf_pv_poly_chebyshev",
                      "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
                      "dwf_pack", "dwf_unpack", "dwf_force", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
                      "mg_time_op", "dwf_norm2", "mg_update_links", "mg_solve_batch",
@@ -325,6 +329,25 @@ def dwf_pv_apply(U, psi, m_f, M5, mode=DWF_PVDAG_DW, out=None, stream=None):
     _check(lib().dwf_pv_apply(_ptr(U), _ptr(psi), _ptr(out), Lx, Ly, Ls, nrhs, float(m_f), float(M5), int(mode),
                               _prec(psi), _stream(stream)), "dwf_pv_apply")
     return out
+
+
+def dwf_pv_apply_noalloc(U, psi, m_f, M5, mode=DWF_PVDAG_DW, out=None, stream=None):
+    """dwf_pv_apply without device allocation (modes DWF_PV .. DWF_PVDAG_DW_DAG): the
+    intermediate field lives in the library's static per-GPU array (see
+    noalloc_max_bytes()); calls that overlap on one GPU race."""
+    _need(U, "U", psi.dtype)
+    _need(psi, "psi")
+    Lx, Ly, Ls, nrhs = _fine_dims(U, psi)
+    out = torch.empty_like(psi) if out is None else out
+    _need(out, "out", psi.dtype, psi.shape)
+    _check(lib().dwf_pv_apply_noalloc(_ptr(U), _ptr(psi), _ptr(out), Lx, Ly, Ls, nrhs, float(m_f), float(M5),
+                                      int(mode), _prec(psi), _stream(stream)), "dwf_pv_apply_noalloc")
+    return out
+
+
+def noalloc_max_bytes() -> int:
+    """Size of the static scratch array of dwf_pv_apply_noalloc (bytes per GPU)."""
+    return int(lib().dwf_pv_apply_noalloc_max_bytes())
 
 
 def dwf_wilson_apply(U, psi, M, dagger=False, out=None, stream=None):
