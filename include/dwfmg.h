@@ -55,6 +55,8 @@ extern "C" {
 /* ---------------------------------------------------------------- flags */
 #define DWF_DAGGER     1       /* apply the adjoint                                  */
 #define DWF_PREC_F32   2       /* fields (and U) are complex64 instead of complex128 */
+#define DWF_PV_SOURCE  4       /* mg_solve: solve D_DW x = D_PV b (the propagator
+                                  form of Sec. 2.2) instead of D_DW x = b          */
 
 /* dwf_pv_apply modes */
 #define DWF_PV          0      /* out = D_PV psi                                     */
@@ -196,6 +198,13 @@ int dwf_unpack(const void* in_c64, void* out_c128, size_t n, void* stream);
 int dwf_force(const void* U, const void* X, const void* Y, double* F, int Lx, int Ly, int Ls,
               int nrhs, void* stream);
 
+/* Bandwidth reference for the stencil figures: copies `bytes` (a multiple of 16,
+ * both pointers 16-byte aligned, not overlapping) from src to dst with the
+ * library's streaming copy kernel, once to warm up and then `iters` times
+ * between two HIP events on `stream`; *gb_per_s = 2 bytes iters / time (read
+ * plus write).  Synchronises `stream`. */
+int dwf_copy_bandwidth(const void* src, void* dst, size_t bytes, int iters, double* gb_per_s, void* stream);
+
 /* out[c] = |x_c|^2 (FP64 accumulation, deterministic order) for ncol columns
  * of n complex128 each; out is a device array of ncol doubles. */
 int dwf_norm2(const void* x, size_t n, int ncol, double* out, void* stream);
@@ -275,37 +284,60 @@ typedef struct {
 
 void dwf_mg_default_params(dwf_mg_params* p, int nlevels);
 
+/* Device memory of a hierarchy, in bytes: the levels' operators and
+ * prolongators, the setup relaxation and (with coarsest_nev > 0) eigensolver
+ * temporaries, and every solve buffer for up to max_nrhs right-hand sides per
+ * group (the setup temporaries share bytes with the solve buffers).  Host only,
+ * no device work.  0 when the arguments would make mg_setup return an error. */
+size_t mg_workspace_bytes(int Lx, int Ly, int Ls, int max_nrhs, const dwf_mg_params* params);
+
 /* Build the hierarchy for gauge field U (complex128 [2][Ly][Lx], device).
  * null_starts[l] (device, complex128 [nvec_l][Ly_l][Lx_l][n_l]) are the
  * starting vectors of level l's setup relaxation, with n_0 = 2 and
  * n_l = 2*nvec_{l-1}; they are copied, not kept.  Per level: CG on
  * D_W(m_setup) D_W(m_setup)^dagger v = 0 (Sec. 3.1), chiral doubling, block
- * Gram-Schmidt, Galerkin kernel.  Allocates device memory owned by the
- * context.  Errors: DWF_EINVAL (sizes not divisible by the blocks, nvec larger
- * than the block dimension, Ls < 2, a coarse Ls outside 2..32), DWF_EUNSUPPORTED (2*nvec not in
- * {4,8,12,16,24,32,48,64}), DWF_EBREAKDOWN (dependent null vectors), DWF_EHIP. */
+ * Gram-Schmidt, Galerkin kernel.
+ * Memory: every device buffer of the hierarchy is carved from `workspace`
+ * (caller-owned device memory of ws_bytes >= mg_workspace_bytes(Lx, Ly, Ls,
+ * max_nrhs, params), 256-byte aligned), which must outlive the context; with
+ * workspace == NULL the library makes that one allocation itself and frees it
+ * in mg_destroy.  After mg_setup returns, no call on the context allocates
+ * device memory.  (With coarsest_nev > 0 the setup's dense eigensolver steps
+ * call rocBLAS / rocSOLVER, which keep their own device workspace in the
+ * context's library handle until mg_destroy.)  The context also owns a HIP
+ * stream, events and pinned host mirrors for scalar read-back.
+ * Errors: DWF_EINVAL (sizes not divisible by the blocks, nvec larger than the
+ * block dimension, Ls < 2, a coarse Ls outside 2..32, max_nrhs outside
+ * 1..4096, a workspace too small or misaligned), DWF_EUNSUPPORTED (2*nvec not
+ * in {4,8,12,16,24,32,48,64}), DWF_EBREAKDOWN (dependent null vectors),
+ * DWF_EHIP. */
 int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, double M5,
-             const dwf_mg_params* params, const void* const* null_starts, void* stream);
+             const dwf_mg_params* params, const void* const* null_starts, int max_nrhs,
+             void* workspace, size_t ws_bytes, void* stream);
 
-/* Solve D_DW(m_f) x = b for nrhs right-hand sides b, x [nrhs][Ls][Ly][Lx][2]
- * complex128 (device): flexible GCR on D_PV^dagger D_DW with the K-cycle as
- * preconditioner (Sec. 2.3 summary) inside an FP64 defect correction, until
- * |b - D_DW x| <= tol |b| for every rhs (FP64 true residual).  x is
- * overwritten (zero initial guess).  Synchronises `stream` at the end.
- * Returns DWF_NOT_CONVERGED when the caps are hit (x is the last iterate). */
-int mg_solve(dwf_mg* mg, const void* b, void* x, int nrhs, double tol, dwf_solve_stats* st,
+/* Solve D_DW(m_f) x = b (or, with flags = DWF_PV_SOURCE, D_DW(m_f) x = D_PV b)
+ * for nrhs right-hand sides b, x [nrhs][Ls][Ly][Lx][2] complex128 (device):
+ * flexible GCR on D_PV^dagger D_DW with the K-cycle as preconditioner (Sec. 2.3
+ * summary) inside an FP64 defect correction, until |b' - D_DW x| <= tol |b'|
+ * for every rhs, b' being the right-hand side of the system solved (FP64 true
+ * residual).  Right-hand sides are solved in groups of at most the context's
+ * max_nrhs; the statistics add up over the groups (true_rel_residual is the
+ * worst).  x is overwritten (zero initial guess).  Synchronises `stream` at
+ * the end.  Returns DWF_NOT_CONVERGED when the caps are hit (x is the last
+ * iterate), DWF_EINVAL for an unknown flag. */
+int mg_solve(dwf_mg* mg, const void* b, void* x, int nrhs, double tol, int flags, dwf_solve_stats* st,
              void* stream);
 
 /* Batched multi-lattice solve: solves ctx[i] for nrhs[i] right-hand sides
- * b[i] -> x[i] (layouts as for mg_solve) for i < nctx, all at once.  Each
- * context works on its own HIP stream from its own host thread, so lattices of
- * different sizes proceed concurrently on the GPU; every context still
- * converges on its own FP64 true residual.  stats may be NULL, else an array
- * of nctx.  Waits for `stream` before starting and returns when all are done.
- * Returns the worst status (hard errors before soft ones). Contexts must be
- * distinct. */
+ * b[i] -> x[i] (layouts and flags as for mg_solve) for i < nctx, all at once.
+ * Each context works on its own HIP stream from its own host thread, so
+ * lattices of different sizes proceed concurrently on the GPU; every context
+ * still converges on its own FP64 true residual.  stats may be NULL, else an
+ * array of nctx.  Waits for `stream` before starting and returns when all are
+ * done.  Returns the worst status (hard errors before soft ones). Contexts
+ * must be distinct. */
 int mg_solve_batch(int nctx, dwf_mg* const* ctx, const void* const* b, void* const* x, const int* nrhs,
-                   double tol, dwf_solve_stats* stats, void* stream);
+                   double tol, int flags, dwf_solve_stats* stats, void* stream);
 
 /* ---------------------------------------------------------------- Krylov baselines */
 #define DWF_KRYLOV_CGNR     0
@@ -340,7 +372,9 @@ int mg_update_links(dwf_mg* mg, const void* U, void* stream);
 
 /* Level operators of a built hierarchy, for testing and diagnostics.  Fields
  * are complex128 in the level's layout ([ncol][Ls_l][Ly_l][Lx_l][n_l]; 2-d
- * fields have Ls_l = 1) and are converted to the level's working precision. */
+ * fields have Ls_l = 1) and are converted to the level's working precision.
+ * They run in the context's solve buffers: 1 <= ncol <= max_nrhs (else
+ * DWF_EINVAL); synchronises `stream`. */
 #define MG_OP_DW         0     /* D_DW(m)                                         */
 #define MG_OP_DW_DAG     1
 #define MG_OP_PV         2     /* D_PV                                            */
@@ -355,7 +389,7 @@ int mg_level_op(dwf_mg* mg, int level, int op, const void* in, void* out, int nc
                 void* stream);
 
 /* Timing of one level operator (the kernels the solve runs, on the level's
- * working precision and storage): `in` (complex128, as for mg_level_op) is
+ * working precision and storage; ncol <= max_nrhs): `in` (complex128, as for mg_level_op) is
  * converted once, then the operator runs `iters` times back to back on
  * `stream`, bracketed by HIP events; *avg_ms receives the mean time per
  * application.  Ops: MG_OP_DW, MG_OP_DW_DAG, MG_OP_PV, MG_OP_PV_DAG, MG_OP_A. */

@@ -328,11 +328,15 @@ int mg_deflation_info(const dwf_mg* mg, int* nev, int* iters, double* worst_resi
     return DWF_OK;
 }
 
-int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, double M5, const dwf_mg_params* p,
-             const void* const* null_starts, void* stream) {
-    if (!out || !U || !p || !null_starts) return DWF_EINVAL;
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// argument checks shared by mg_workspace_bytes and mg_setup
+int check_mg_args(int Lx, int Ly, int Ls, double m_f, double M5, const dwf_mg_params* p, int max_nrhs) {
+    if (!p) return DWF_EINVAL;
     if (!dims_ok(Lx, Ly, Ls, 1) || Ls < 2 || !std::isfinite(m_f) || !std::isfinite(M5)) return DWF_EINVAL;
+    if (max_nrhs < 1 || max_nrhs > 4096) return DWF_EINVAL;
     if (p->nlevels < 1 || p->nlevels > DWF_MAX_LEVELS) return DWF_EINVAL;
     if (p->outer_restart < 1 || p->outer_restart > 16 || p->smooth_iters < 0 || p->smooth_iters > 16) return DWF_EINVAL;
     if (p->nlevels > 1 && (p->inter_restart < 1 || p->inter_restart > 16)) return DWF_EINVAL;
@@ -359,7 +363,6 @@ int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, do
         if (nv > bx * by * (n / 2)) return DWF_EINVAL;
         if (p->Ls_coarse[l] < 2 || p->Ls_coarse[l] > kMaxCoarseLs) return DWF_EINVAL;
         if (!valid_prec(p->link_prec[l], true) || !valid_prec(p->vec_prec[l], false)) return DWF_EINVAL;
-        if (!null_starts[l]) return DWF_EINVAL;
         const int nn = 2 * nv;
         if (nn != 4 && nn != 8 && nn != 12 && nn != 16 && nn != 24 && nn != 32 && nn != 48 && nn != 64)
             return DWF_EUNSUPPORTED;
@@ -368,9 +371,29 @@ int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, do
         ly /= by;
         n = nn;
     }
+    return DWF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mg_workspace_bytes(int Lx, int Ly, int Ls, int max_nrhs, const dwf_mg_params* p) {
+    if (check_mg_args(Lx, Ly, Ls, 0.0, -1.0, p, max_nrhs) != DWF_OK) return 0;
+    return Hierarchy::workspace_bytes(Lx, Ly, Ls, *p, max_nrhs);
+}
+
+int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, double M5, const dwf_mg_params* p,
+             const void* const* null_starts, int max_nrhs, void* workspace, size_t ws_bytes, void* stream) {
+    if (!out || !U || !p || !null_starts) return DWF_EINVAL;
+    *out = nullptr;
+    if (int e = check_mg_args(Lx, Ly, Ls, m_f, M5, p, max_nrhs)) return e;
+    for (int l = 0; l < p->nlevels; ++l)
+        if (!null_starts[l]) return DWF_EINVAL;
     dwf_mg* mg = new (std::nothrow) dwf_mg;
     if (!mg) return DWF_EHIP;
-    int e = mg->h.setup((const cpx<double>*)U, Lx, Ly, Ls, m_f, M5, *p, null_starts, S(stream));
+    int e = mg->h.setup((const cpx<double>*)U, Lx, Ly, Ls, m_f, M5, *p, null_starts, max_nrhs, workspace, ws_bytes,
+                        S(stream));
     if (e != DWF_OK) {
         delete mg;
         return e;
@@ -380,11 +403,12 @@ int mg_setup(dwf_mg** out, const void* U, int Lx, int Ly, int Ls, double m_f, do
     return DWF_OK;
 }
 
-int mg_solve(dwf_mg* mg, const void* b, void* x, int nrhs, double tol, dwf_solve_stats* st, void* stream) {
+int mg_solve(dwf_mg* mg, const void* b, void* x, int nrhs, double tol, int flags, dwf_solve_stats* st, void* stream) {
     if (!mg || !mg->ready) return DWF_ENOSETUP;
     if (!b || !x || b == x || nrhs < 1 || !(tol > 0.0) || !std::isfinite(tol)) return DWF_EINVAL;
+    if (flags & ~DWF_PV_SOURCE) return DWF_EINVAL;
     if (st) std::memset(st, 0, sizeof(*st));
-    int e = mg->h.solve((const cpx<double>*)b, (cpx<double>*)x, nrhs, tol, st, S(stream));
+    int e = mg->h.solve((const cpx<double>*)b, (cpx<double>*)x, nrhs, tol, flags, st, S(stream));
     if (st) st->status = e;
     return e;
 }
@@ -396,8 +420,9 @@ int mg_level_op(dwf_mg* mg, int level, int op, const void* in, void* out, int nc
 }
 
 int mg_solve_batch(int nctx, dwf_mg* const* ctx, const void* const* b, void* const* x, const int* nrhs, double tol,
-                   dwf_solve_stats* stats, void* stream) {
+                   int flags, dwf_solve_stats* stats, void* stream) {
     if (nctx < 1 || !ctx || !b || !x || !nrhs || !(tol > 0.0) || !std::isfinite(tol)) return DWF_EINVAL;
+    if (flags & ~DWF_PV_SOURCE) return DWF_EINVAL;
     for (int i = 0; i < nctx; ++i) {
         if (!ctx[i] || !ctx[i]->ready) return DWF_ENOSETUP;
         if (!b[i] || !x[i] || b[i] == x[i] || nrhs[i] < 1) return DWF_EINVAL;
@@ -413,7 +438,7 @@ int mg_solve_batch(int nctx, dwf_mg* const* ctx, const void* const* b, void* con
     for (int i = 0; i < nctx; ++i) {
         workers.emplace_back([&, i]() {
             std::memset(&st[i], 0, sizeof(st[i]));
-            codes[i] = ctx[i]->h.solve((const cpx<double>*)b[i], (cpx<double>*)x[i], nrhs[i], tol, &st[i],
+            codes[i] = ctx[i]->h.solve((const cpx<double>*)b[i], (cpx<double>*)x[i], nrhs[i], tol, flags, &st[i],
                                        ctx[i]->h.stream());
             st[i].status = codes[i];
         });
@@ -427,6 +452,29 @@ int mg_solve_batch(int nctx, dwf_mg* const* ctx, const void* const* b, void* con
         else if (c > 0 && worst == DWF_OK) worst = c;
     }
     return worst;
+}
+
+int dwf_copy_bandwidth(const void* src, void* dst, size_t bytes, int iters, double* gb_per_s, void* stream) {
+    if (!src || !dst || src == dst || !gb_per_s || iters < 1 || bytes < 16 || (bytes & 15) ||
+        (reinterpret_cast<uintptr_t>(src) & 15) || (reinterpret_cast<uintptr_t>(dst) & 15))
+        return DWF_EINVAL;
+    hipStream_t st = S(stream);
+    const size_t words = bytes / 16;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return DWF_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return DWF_EHIP; }
+    int status = DWF_OK;
+    float ms = 0.f;
+    if (stream_copy(src, dst, words, st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess) status = DWF_EHIP;
+    for (int i = 0; i < iters && status == DWF_OK; ++i)
+        if (stream_copy(src, dst, words, st) != hipSuccess) status = DWF_EHIP;
+    if (status == DWF_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        status = DWF_EHIP;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status == DWF_OK) *gb_per_s = 2.0 * (double)bytes * iters / ((double)ms * 1e-3) / 1e9;
+    return status;
 }
 
 int dwf_norm2(const void* x, size_t n, int ncol, double* out, void* stream) {

@@ -12,6 +12,8 @@
 // FP32 and FP64 vectors.
 #include <utility>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace dwf {
@@ -161,6 +163,33 @@ hipError_t vadd(const cpx<Tx>* x, cpx<Ty>* y, size_t n, hipStream_t st) {
 template <typename T>
 hipError_t vsub(const cpx<T>* a, const cpx<T>* b, cpx<T>* out, size_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_sub<T>, ew_grid(n, 1), dim3(kBlock), 0, st, a, b, out, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ streaming copy (bandwidth reference)
+// dst = src in 16-byte words: every thread issues the loads of four words (one
+// per grid stride) before their stores, which are nontemporal.  Used to measure
+// the copy bandwidth the stencil figures are compared with.
+typedef unsigned int sc_u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(kBlock) k_stream_copy(const sc_u32x4* __restrict__ src, sc_u32x4* __restrict__ dst,
+                                                        size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const sc_u32x4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(src[i], dst + i);
+}
+
+hipError_t stream_copy(const void* src, void* dst, size_t words, hipStream_t st) {
+    // 8 workgroups of 256 threads per compute unit
+    const unsigned grid = (unsigned)std::max<size_t>(1, std::min<size_t>((words + kBlock - 1) / kBlock, 256 * 8));
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(kBlock), 0, st, reinterpret_cast<const sc_u32x4*>(src),
+                       reinterpret_cast<sc_u32x4*>(dst), words);
     return hipGetLastError();
 }
 

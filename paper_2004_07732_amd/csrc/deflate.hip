@@ -81,15 +81,94 @@ __global__ void k_resid(cpx<double>* out, const cpx<double>* w, const cpx<double
     }
 }
 
-// C[i][c] /= lambda_i (C is nev x ncol, column-major)
-__global__ void k_scale_rows(cpx<double>* C, const double* lam, int nev, int ncol) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nev * ncol) return;
-    const double l = lam[t % nev];
-    C[t] = {C[t].re / l, C[t].im / l};
+// ---- deflated start of a coarsest solve, e0 = V Lambda^{-1} V^dag z (per column of z)
+// Column tiles of the projection kernels: each wave reads an element of V once
+// for up to kDeflTile right-hand sides.
+constexpr int kDeflTile = 8;
+
+// part[c][i][b] = sum over block b's slice of conj(V_i) z_c, for the columns
+// c0 .. c0 + nc of the tile (blockIdx.y); wave w of the block takes i = w, w + 4, ...
+template <int NC>
+__global__ __launch_bounds__(256) void k_defl_dots(const cpx<double>* __restrict__ V, const cpx<double>* __restrict__ z,
+                                                   double* __restrict__ part, size_t n, int nev, int ncol) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int b = blockIdx.x, c0 = blockIdx.y * NC;
+    const int nc = min(NC, ncol - c0);
+    const size_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const size_t lo = (size_t)b * chunk, hi = min(n, lo + chunk);
+    for (int i = wave; i < nev; i += 4) {
+        double ar[NC], ai[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ar[c] = ai[c] = 0.0;
+        const cpx<double>* vi = V + (size_t)i * n;
+        for (size_t e = lo + lane; e < hi; e += 64) {
+            const cpx<double> v = vi[e];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (c < nc) {
+                    const cpx<double> w = z[(size_t)(c0 + c) * n + e];
+                    ar[c] += v.re * w.re + v.im * w.im;
+                    ai[c] += v.re * w.im - v.im * w.re;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double r = ar[c], m = ai[c];
+            for (int off = 32; off > 0; off >>= 1) {
+                r += __shfl_down(r, off);
+                m += __shfl_down(m, off);
+            }
+            if (lane == 0 && c < nc) {
+                const size_t o = (((size_t)(c0 + c) * nev + i) * gridDim.x + b) * 2;
+                part[o] = r;
+                part[o + 1] = m;
+            }
+        }
+    }
 }
 
-constexpr int kDeflCols = 64;   // right-hand sides projected per pair of block products
+// C[c][i] = (sum_b part[c][i][b]) / lambda_i, in block order
+__global__ void k_defl_coef(const double* __restrict__ part, const double* __restrict__ lam, cpx<double>* C, int nev,
+                            int ncol, int nblk) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nev * ncol) return;
+    const int i = t % nev;
+    const double* p = part + (size_t)t * nblk * 2;
+    double r = 0.0, m = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        r += p[2 * b];
+        m += p[2 * b + 1];
+    }
+    C[t] = {r / lam[i], m / lam[i]};
+}
+
+// x_c[e] = sum_i V_i[e] C[c][i] for the columns of the tile (blockIdx.y)
+template <int NC>
+__global__ __launch_bounds__(256) void k_defl_expand(const cpx<double>* __restrict__ V, const cpx<double>* __restrict__ C,
+                                                     cpx<double>* __restrict__ x, size_t n, int nev, int ncol) {
+    const int c0 = blockIdx.y * NC;
+    const int nc = min(NC, ncol - c0);
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        double ar[NC], ai[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ar[c] = ai[c] = 0.0;
+        for (int i = 0; i < nev; ++i) {
+            const cpx<double> v = V[(size_t)i * n + e];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (c < nc) {
+                    const cpx<double> k = C[(size_t)(c0 + c) * nev + i];
+                    ar[c] += v.re * k.re - v.im * k.im;
+                    ai[c] += v.re * k.im + v.im * k.re;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < nc) x[(size_t)(c0 + c) * n + e] = {ar[c], ai[c]};
+    }
+}
 
 inline unsigned grid1(size_t n) {
     size_t g = (n + kBlock - 1) / kBlock;
@@ -117,46 +196,27 @@ int Hierarchy::deflation_setup(hipStream_t st) {
     const size_t n = L.vec_elems();
     if ((size_t)nev >= n) return DWF_EINVAL;
     // nk Ritz vectors are kept at a thick restart, the Lanczos basis holds m (+1)
-    const int nk = (int)std::min<size_t>((size_t)nev + std::max(16, nev / 4), n - 1);
-    const int m = (int)std::min<size_t>((size_t)nk + std::max(32, nev / 2), n);
+    int nk = 0, m = 0;
+    deflation_dims(nev, n, nk, m);
     const bool verbose = std::getenv("DWF_VERBOSE") != nullptr;
     if (!blas_) {
         if (rocblas_create_handle(&blas_) != rocblas_status_success) return DWF_EHIP;
     }
     RBCHK(rocblas_set_stream(blas_, st));
     RBCHK(rocblas_set_pointer_mode(blas_, rocblas_pointer_mode_host));
-    if (int e = ensure_scalars(std::max(nk, 64))) return e;
-
+    // the temporaries were laid out with the hierarchy (over the solve buffers)
+    DeflTmp& D = dtmp_;
+    if (D.nk != nk || D.m != m || !D.Vb) return DWF_EINVAL;
     using zc = std::complex<double>;
-    const size_t nb = (size_t)(m + 1) * n, nkb = (size_t)nk * n;
-    cpx<double>* Vb = nullptr;                       // Lanczos basis, m+1 columns
-    cpx<double> *Ub = nullptr, *HUb = nullptr, *Xb = nullptr, *Wb = nullptr;   // nk columns each
-    cpx<double> *P0 = nullptr, *P1 = nullptr, *P2 = nullptr, *Hh = nullptr, *t1 = nullptr, *t2 = nullptr;
-    cpx<double> *G = nullptr, *Ysd = nullptr, *cdev = nullptr;
-    double *lam = nullptr, *E = nullptr, *nrm = nullptr;
-    rocblas_int* info = nullptr;
-    std::vector<void*> owned;
-    auto get = [&](void** p, size_t bytes) {
-        std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
-        if (hipMalloc(p, bytes) != hipSuccess) return false;
-        owned.push_back(*p);
-        return true;
-    };
+    const size_t nkb = (size_t)nk * n;
+    cpx<double>* Vb = D.Vb;
+    cpx<double> *Ub = D.Ub, *HUb = D.HUb, *Xb = D.Xb, *Wb = D.Wb;
+    cpx<double> *P0 = D.P0, *P1 = D.P1, *P2 = D.P2, *Hh = D.Hh, *t1 = D.t1, *t2 = D.t2;
+    cpx<double> *G = D.G, *Ysd = D.Ysd, *cdev = D.cdev;
+    double *lam = D.lam, *E = D.E, *nrm = D.nrm;
+    rocblas_int* info = reinterpret_cast<rocblas_int*>(D.info);
     const size_t zb = sizeof(cpx<double>);
-    const bool ok = get((void**)&Vb, nb * zb) && get((void**)&Ub, nkb * zb) && get((void**)&HUb, nkb * zb) &&
-                    get((void**)&Xb, nkb * zb) && get((void**)&Wb, nkb * zb) && get((void**)&P0, n * zb) &&
-                    get((void**)&P1, n * zb) && get((void**)&P2, n * zb) && get((void**)&Hh, n * zb) &&
-                    get((void**)&t1, n * zb) && get((void**)&t2, n * zb) &&
-                    get((void**)&G, (size_t)m * m * zb) && get((void**)&Ysd, (size_t)m * m * zb) &&
-                    get((void**)&cdev, 2 * (size_t)(m + 1) * zb) && get((void**)&lam, sizeof(double) * m) &&
-                    get((void**)&E, sizeof(double) * m) && get((void**)&nrm, sizeof(double) * nk) &&
-                    get((void**)&info, sizeof(rocblas_int));
-    auto cleanup = [&]() {
-        (void)hipStreamSynchronize(st);
-        std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
-        for (void* p : owned) (void)hipFree(p);
-    };
-    if (!ok) { cleanup(); return DWF_EHIP; }
+    auto cleanup = [&]() { (void)hipStreamSynchronize(st); };
 
     int status = DWF_OK;
     const auto t_start = std::chrono::steady_clock::now();
@@ -380,10 +440,7 @@ int Hierarchy::deflation_setup(hipStream_t st) {
         eig_iters_ = steps;
         eig_worst_ = worst;
         // keep the nev lowest eigenpairs of H (columns 0..nev of X, ascending)
-        if (!def_V_) def_V_ = (cpx<double>*)dalloc(zb * n * nev);
-        if (!def_lam_) def_lam_ = (double*)dalloc(sizeof(double) * nev);
-        if (!def_C_) def_C_ = (cpx<double>*)dalloc(zb * nev * kDeflCols);
-        if (!def_V_ || !def_lam_ || !def_C_) { status = DWF_EHIP; break; }
+        if (!def_V_ || !def_lam_ || !def_C_ || !def_part_) { status = DWF_EINVAL; break; }
         HIPCHK(hipMemcpyAsync(def_V_, Xb, zb * n * nev, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(def_lam_, lam, sizeof(double) * nev, hipMemcpyDeviceToDevice, st));
         def_lam_host_.assign(lh.begin(), lh.begin() + nev);
@@ -400,19 +457,17 @@ int Hierarchy::deflation_setup(hipStream_t st) {
 // e0 = V Lambda^{-1} V^dag z for ncol columns of z (n each), written to x
 int Hierarchy::deflate_guess(int l, const cpx<double>* z, cpx<double>* x, int ncol, hipStream_t st) {
     const size_t n = levels[l].vec_elems();
-    const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
-    auto rb = [](const cpx<double>* p) { return (rocblas_double_complex*)(p); };
-    RBCHK(rocblas_set_stream(blas_, st));
-    for (int c0 = 0; c0 < ncol; c0 += kDeflCols) {
-        const int nc = std::min(kDeflCols, ncol - c0);
-        RBCHK(rocblas_zgemm(blas_, rocblas_operation_conjugate_transpose, rocblas_operation_none, def_nev_, nc,
-                            (rocblas_int)n, &one, rb(def_V_), (rocblas_int)n, rb(z + c0 * n), (rocblas_int)n, &zero,
-                            rb(def_C_), def_nev_));
-        hipLaunchKernelGGL(k_scale_rows, dim3((def_nev_ * nc + 255) / 256), dim3(256), 0, st, def_C_, def_lam_,
-                           def_nev_, nc);
-        RBCHK(rocblas_zgemm(blas_, rocblas_operation_none, rocblas_operation_none, (rocblas_int)n, nc, def_nev_, &one,
-                            rb(def_V_), (rocblas_int)n, rb(def_C_), def_nev_, &zero, rb(x + c0 * n), (rocblas_int)n));
-    }
+    const int nev = def_nev_;
+    if (ncol > max_ncol_) return DWF_EINVAL;
+    const dim3 gd(kDeflBlocks, (ncol + kDeflTile - 1) / kDeflTile);
+    hipLaunchKernelGGL(k_defl_dots<kDeflTile>, gd, dim3(256), 0, st, def_V_, z, def_part_, n, nev, ncol);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_defl_coef, dim3((nev * ncol + 255) / 256), dim3(256), 0, st, def_part_, def_lam_, def_C_, nev,
+                       ncol, kDeflBlocks);
+    HIPCHK(hipGetLastError());
+    const dim3 ge(grid1(n), (ncol + kDeflTile - 1) / kDeflTile);
+    hipLaunchKernelGGL(k_defl_expand<kDeflTile>, ge, dim3(kBlock), 0, st, def_V_, def_C_, x, n, nev, ncol);
+    HIPCHK(hipGetLastError());
     return DWF_OK;
 }
 

@@ -96,6 +96,9 @@ template <typename T> hipError_t vsub(const cpx<T>* a, const cpx<T>* b, cpx<T>* 
 // y = a x + b y with real a, b (b == 0 overwrites y)
 template <typename T> hipError_t vaxpby(double a, const cpx<T>* x, double b, cpx<T>* y, size_t n, hipStream_t st);
 
+// dst = src for `words` 16-byte words (a streaming copy: the bandwidth reference)
+hipError_t stream_copy(const void* src, void* dst, size_t words, hipStream_t st);
+
 // per column: out[c] = |x_c|^2
 template <typename T>
 hipError_t norm2(const cpx<T>* x, size_t n, int ncol, double* out, const RedWork& rw, hipStream_t st);

@@ -51,7 +51,7 @@ Hierarchy::~Hierarchy() {
     clear_graphs();
     destroy_blas();
     std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
-    for (void* p : allocs_) (void)hipFree(p);
+    if (ws_owned_) (void)hipFree(ws_owned_);
     if (h_scal_) (void)hipHostFree(h_scal_);
     if (h_int_) (void)hipHostFree(h_int_);
     if (h_cg_) (void)hipHostFree(h_cg_);
@@ -95,14 +95,6 @@ int Hierarchy::run_graph(const GraphKey& key, hipStream_t st, F&& enqueue) {
     }
     HIPCHK(hipGraphLaunch(it->second, st));
     return DWF_OK;
-}
-
-void* Hierarchy::dalloc(size_t bytes) {
-    std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
-    void* p = nullptr;
-    if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) return nullptr;
-    allocs_.push_back(p);
-    return p;
 }
 
 // ------------------------------------------------------------ level operators
@@ -233,33 +225,33 @@ int Hierarchy::alloc_level_work(int l, int ncol) {
     w.ksmooth = coarsest ? 0 : prm.smooth_iters;
     auto A = [&](size_t bytes) { return dalloc(bytes); };
     w.r = A(vb); w.x = A(vb); w.tmp = A(vb); w.tmp2 = A(vb); w.rhs = A(vb);
-    if (!w.r || !w.x || !w.tmp || !w.tmp2 || !w.rhs) return DWF_EHIP;
+    if (!w.r || !w.x || !w.tmp || !w.tmp2 || !w.rhs) return DWF_EINVAL;
     if (l == 0 && prm.pv_poly_order > 0) {
         w.py = A(vb); w.pz = A(vb);
-        if (!w.py || !w.pz) return DWF_EHIP;
+        if (!w.py || !w.pz) return DWF_EINVAL;
     }
     if (w.kmax > 0) {
         w.P = A(vb * w.kmax);
         w.W = A(vb * w.kmax);
-        if (!w.P || !w.W) return DWF_EHIP;
+        if (!w.P || !w.W) return DWF_EINVAL;
     }
     if (w.ksmooth > 0) {
         w.Ps = A(vb * (w.ksmooth + 1));
         w.Ws = A(vb * w.ksmooth);
         w.rs = A(vb);
         w.zt = A(vb);
-        if (!w.Ps || !w.Ws || !w.rs || !w.zt) return DWF_EHIP;
+        if (!w.Ps || !w.Ws || !w.rs || !w.zt) return DWF_EINVAL;
     }
     if (!coarsest) {
         const Level& N = levels[l + 1];
         const size_t cb = N.vec_elems() * cplx_bytes(L.vec_prec) * ncol;
         w.rc_local = A(cb);
         w.ec_local = A(cb);
-        if (!w.rc_local || !w.ec_local) return DWF_EHIP;
+        if (!w.rc_local || !w.ec_local) return DWF_EINVAL;
     } else {
         w.cp = A(vb); w.cw = A(vb); w.cz = A(vb);
         w.cg = (CgScal*)A(sizeof(CgScal) * ncol);
-        if (!w.cp || !w.cw || !w.cz || !w.cg) return DWF_EHIP;
+        if (!w.cp || !w.cw || !w.cz || !w.cg) return DWF_EINVAL;
     }
     auto mk_gcr = [&](GcrDev& g, int kmax) -> int {
         g.kmax = kmax;
@@ -274,45 +266,12 @@ int Hierarchy::alloc_level_work(int l, int ncol) {
         g.stop2 = (int*)A(sizeof(int) * ncol);
         g.tot = (double*)A(sizeof(double) * kGcrTot * ncol);
         if (!g.D || !g.nn || !g.wr || !g.gam || !g.rr || !g.stop || !g.bb || !g.it || !g.stop2 || !g.tot)
-            return DWF_EHIP;
-        if (hipMemset(g.stop, 0, sizeof(int) * ncol) != hipSuccess) return DWF_EHIP;
+            return DWF_EINVAL;
+        zero_at_setup_.emplace_back(g.stop, sizeof(int) * ncol);
         return DWF_OK;
     };
-    if (w.kmax > 0 && mk_gcr(w.gcr, w.kmax) != DWF_OK) return DWF_EHIP;
-    if (w.ksmooth > 0 && mk_gcr(w.gsm, w.ksmooth) != DWF_OK) return DWF_EHIP;
-    return DWF_OK;
-}
-
-int Hierarchy::ensure_scalars(int maxc) {
-    if (maxc <= scal_cols_) return DWF_OK;
-    rw_.nblk = kRedBlocks;
-    rw_.max_q = 40;
-    rw_.max_cols = maxc;
-    rw_.partial = (double*)dalloc(sizeof(double) * (size_t)maxc * rw_.max_q * rw_.nblk);
-    if (!rw_.partial) return DWF_EHIP;
-    std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
-    if (h_scal_) hipHostFree(h_scal_);
-    if (h_int_) hipHostFree(h_int_);
-    if (h_cg_) hipHostFree(h_cg_);
-    HIPCHK(hipHostMalloc((void**)&h_scal_, sizeof(double) * 4 * maxc, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&h_int_, sizeof(int) * 4 * maxc, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&h_cg_, sizeof(CgScal) * maxc, hipHostMallocDefault));
-    if (!d_flag_) d_flag_ = (int*)dalloc(sizeof(int) * 4);
-    if (!d_flag_) return DWF_EHIP;
-    scal_cols_ = maxc;
-    return DWF_OK;
-}
-
-int Hierarchy::ensure_work(int ncol, hipStream_t st) {
-    if (ncol <= work_cols_) return DWF_OK;
-    HIPCHK(hipStreamSynchronize(st));
-    if (st_) HIPCHK(hipStreamSynchronize(st_));
-    clear_graphs();   // captured launches refer to the buffers being replaced
-    if (int e = ensure_scalars(std::max(ncol, 64))) return e;
-    work_.assign(levels.size(), LevelWork{});
-    for (int l = 0; l < (int)levels.size(); ++l)
-        if (int e = alloc_level_work(l, ncol)) return e;
-    work_cols_ = ncol;
+    if (w.kmax > 0 && mk_gcr(w.gcr, w.kmax) != DWF_OK) return DWF_EINVAL;
+    if (w.ksmooth > 0 && mk_gcr(w.gsm, w.ksmooth) != DWF_OK) return DWF_EINVAL;
     return DWF_OK;
 }
 
@@ -337,11 +296,6 @@ int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st)
     if constexpr (std::is_same<T, double>::value) {
         if (def_nev_ > 0 && l == (int)levels.size() - 1) {
             // start from e0 = V Lambda^{-1} V^dag A^dag b; keep |A^dag b| as the reference
-            if (ncol > def_ref_cols_) {
-                def_ref_cols_ = std::max(ncol, 64);
-                def_ref_ = (double*)dalloc(sizeof(double) * def_ref_cols_);
-                if (!def_ref_) return DWF_EHIP;
-            }
             HIPCHK(norm2<T>(z, n, ncol, def_ref_, rw_, st));
             if (int e = deflate_guess(l, z, x, ncol, st)) return e;
             HIPCHK(apply_A<T>(l, x, q, t, ncol, st));
@@ -623,12 +577,11 @@ int Hierarchy::null_vectors(int l, const cpx<double>* start, cpx<double>* v, hip
     const int nv = prm.nvec[l];
     const size_t n = L.field2d_elems();
     const size_t nt = n * nv;
-    cpx<double>* r = (cpx<double>*)dalloc(nt * sizeof(cpx<double>));
-    cpx<double>* p = (cpx<double>*)dalloc(nt * sizeof(cpx<double>));
-    cpx<double>* t = (cpx<double>*)dalloc(nt * sizeof(cpx<double>));
-    cpx<double>* q = (cpx<double>*)dalloc(nt * sizeof(cpx<double>));
-    CgScal* s = (CgScal*)dalloc(sizeof(CgScal) * nv);
-    if (!r || !p || !t || !q || !s) return DWF_EHIP;
+    cpx<double>* r = stmp_.r;
+    cpx<double>* p = stmp_.p;
+    cpx<double>* t = stmp_.t;
+    cpx<double>* q = stmp_.q;
+    CgScal* s = stmp_.s;
     const double ms = prm.m_setup;
     HIPCHK(vconvert<double, double>(start, v, nt, st));
     // r = -B v, B = D_W(ms) D_W(ms)^dagger
@@ -658,37 +611,186 @@ int Hierarchy::null_vectors(int l, const cpx<double>* start, cpx<double>* v, hip
     return DWF_OK;
 }
 
-int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, double M5_,
-                     const dwf_mg_params& p, const void* const* null_starts, hipStream_t st) {
-    prm = p;
-    m = m_;
-    M5 = M5_;
+// Level geometry from the parameters, and every device buffer carved from the
+// arena ws_ (counting mode: sizes only).  Persistent buffers first; then the
+// solve buffers for max_ncol columns, with the setup and eigensolver
+// temporaries laid over the same bytes (setup finishes before any solve).
+int Hierarchy::plan(int Lx, int Ly, int Ls, int max_ncol) {
+    const dwf_mg_params& p = prm;
     levels.clear();
-    if (!st_) HIPCHK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
-    if (!ev_in_) HIPCHK(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
-    const char* ng = std::getenv("DWF_NO_GRAPHS");
-    use_graphs_ = !(ng && ng[0] == '1');
+    work_.clear();
+    zero_at_setup_.clear();
+    max_ncol_ = max_ncol;
     Level f;
     f.Lx = Lx; f.Ly = Ly; f.Ls = Ls; f.n = 2; f.nsites = Lx * Ly; f.fine = true;
     f.vec_prec = p.fine_prec;
-    f.U64 = (cpx<double>*)dalloc(sizeof(cpx<double>) * 2 * f.nsites);
-    f.U32 = (cpx<float>*)dalloc(sizeof(cpx<float>) * 2 * f.nsites);
-    if (!f.U64 || !f.U32) return DWF_EHIP;
-    HIPCHK(hipMemcpyAsync(f.U64, U, sizeof(cpx<double>) * 2 * f.nsites, hipMemcpyDeviceToDevice, st));
-    HIPCHK((vconvert<double, float>(f.U64, f.U32, 2 * (size_t)f.nsites, st)));
     levels.push_back(f);
-    // scalar scratch for the setup CG (nvec columns)
-    if (int e = ensure_scalars(64)) return e;
     for (int l = 0; l < p.nlevels; ++l) {
         Level& L = levels[l];
         const int nv = p.nvec[l], bx = p.block[l][0], by = p.block[l][1];
         L.nvec_next = nv; L.bx = bx; L.by = by;
+        Level c;
+        c.Lx = L.Lx / bx; c.Ly = L.Ly / by; c.Ls = p.Ls_coarse[l]; c.n = 2 * nv;
+        c.nsites = c.Lx * c.Ly; c.fine = false;
+        c.vec_prec = p.vec_prec[l];
+        c.link_prec = p.link_prec[l];
+        levels.push_back(c);
+    }
+    auto T = [&](size_t bytes) { return dalloc(bytes); };
+    const size_t zb = sizeof(cpx<double>);
+    // ---- persistent: operators and prolongators
+    Level& F = levels[0];
+    F.U64 = (cpx<double>*)T(zb * 2 * F.nsites);
+    F.U32 = (cpx<float>*)T(sizeof(cpx<float>) * 2 * F.nsites);
+    if (!F.U64 || !F.U32) return DWF_EINVAL;
+    size_t max_setup = 0;   // complex entries of one level's null-vector block
+    for (int l = 0; l < p.nlevels; ++l) {
+        Level& L = levels[l];
+        Level& c = levels[l + 1];
+        const size_t n2 = L.field2d_elems() * L.nvec_next;
+        max_setup = std::max(max_setup, n2);
+        L.V64 = (cpx<double>*)T(zb * n2);
+        L.V32 = (cpx<float>*)T(sizeof(cpx<float>) * n2);
+        const size_t nl = (size_t)c.nsites * 5 * c.n * c.n;
+        c.links64 = (cpx<double>*)T(zb * nl);
+        if (!L.V64 || !L.V32 || !c.links64) return DWF_EINVAL;
+        if (c.link_prec == P_F64) {
+            c.links = c.links64;
+        } else {
+            const bool frag = coarse_mfma_supported(c.n, c.link_prec);
+            c.links = T(cplx_bytes(c.link_prec) * (frag ? links_fragment16_entries(c.nsites, c.n) : nl));
+            if (!c.links) return DWF_EINVAL;
+        }
+    }
+    // ---- persistent: reduction partials, flags, FP64 solve vectors, deflation space
+    const int lc = (int)levels.size() - 1;
+    const size_t nc_el = levels[lc].vec_elems();
+    int dnk = 0, dm = 0;
+    if (p.coarsest_nev > 0) deflation_dims(p.coarsest_nev, nc_el, dnk, dm);
+    rw_.nblk = kRedBlocks;
+    rw_.max_q = 40;
+    rw_.max_cols = std::max({max_ncol, 64, dnk});
+    rw_.partial = (double*)T(sizeof(double) * (size_t)rw_.max_cols * rw_.max_q * rw_.nblk);
+    d_flag_ = (int*)T(sizeof(int) * 4);
+    const size_t nf = F.vec_elems() * max_ncol;
+    r64_ = (cpx<double>*)T(zb * nf);
+    t64_ = (cpx<double>*)T(zb * nf);
+    bp64_ = (cpx<double>*)T(zb * nf);
+    if (!rw_.partial || !d_flag_ || !r64_ || !t64_ || !bp64_) return DWF_EINVAL;
+    if (p.pv_poly_order > 0) {
+        y64_ = (cpx<double>*)T(zb * nf);
+        z64_ = (cpx<double>*)T(zb * nf);
+        if (!y64_ || !z64_) return DWF_EINVAL;
+    }
+    if (p.coarsest_nev > 0) {
+        const int nev = p.coarsest_nev;
+        def_V_ = (cpx<double>*)T(zb * nc_el * nev);
+        def_lam_ = (double*)T(sizeof(double) * nev);
+        def_C_ = (cpx<double>*)T(zb * (size_t)nev * max_ncol);
+        def_part_ = (double*)T(sizeof(double) * 2 * (size_t)nev * max_ncol * kDeflBlocks);
+        def_ref_ = (double*)T(sizeof(double) * max_ncol);
+        if (!def_V_ || !def_lam_ || !def_C_ || !def_part_ || !def_ref_) return DWF_EINVAL;
+    }
+    // ---- solve buffers
+    const size_t w0 = ws_.off;
+    work_.assign(levels.size(), LevelWork{});
+    for (int l = 0; l < (int)levels.size(); ++l)
+        if (int e = alloc_level_work(l, max_ncol)) return e;
+    const size_t w1 = ws_.off;
+    // ---- setup temporaries over the solve buffers
+    ws_.off = w0;
+    int max_nv = 1;
+    for (int l = 0; l < p.nlevels; ++l) max_nv = std::max(max_nv, p.nvec[l]);
+    stmp_.v = (cpx<double>*)T(zb * max_setup);
+    stmp_.r = (cpx<double>*)T(zb * max_setup);
+    stmp_.p = (cpx<double>*)T(zb * max_setup);
+    stmp_.t = (cpx<double>*)T(zb * max_setup);
+    stmp_.q = (cpx<double>*)T(zb * max_setup);
+    stmp_.s = (CgScal*)T(sizeof(CgScal) * max_nv);
+    if (!stmp_.v || !stmp_.r || !stmp_.p || !stmp_.t || !stmp_.q || !stmp_.s) return DWF_EINVAL;
+    const size_t s1 = ws_.off;
+    size_t d1 = w0;
+    if (p.coarsest_nev > 0) {
+        ws_.off = w0;
+        DeflTmp& d = dtmp_;
+        d.nk = dnk;
+        d.m = dm;
+        const size_t nb = (size_t)(dm + 1) * nc_el, nkb = (size_t)dnk * nc_el;
+        d.Vb = (cpx<double>*)T(zb * nb);
+        d.Ub = (cpx<double>*)T(zb * nkb);
+        d.HUb = (cpx<double>*)T(zb * nkb);
+        d.Xb = (cpx<double>*)T(zb * nkb);
+        d.Wb = (cpx<double>*)T(zb * nkb);
+        cpx<double>** vecs[] = {&d.P0, &d.P1, &d.P2, &d.Hh, &d.t1, &d.t2};
+        for (auto pp : vecs) *pp = (cpx<double>*)T(zb * nc_el);
+        d.G = (cpx<double>*)T(zb * (size_t)dm * dm);
+        d.Ysd = (cpx<double>*)T(zb * (size_t)dm * dm);
+        d.cdev = (cpx<double>*)T(zb * 2 * (size_t)(dm + 1));
+        d.lam = (double*)T(sizeof(double) * dm);
+        d.E = (double*)T(sizeof(double) * dm);
+        d.nrm = (double*)T(sizeof(double) * dnk);
+        d.info = (int*)T(sizeof(int) * 4);
+        if (!d.Vb || !d.Ub || !d.HUb || !d.Xb || !d.Wb || !d.P0 || !d.P1 || !d.P2 || !d.Hh || !d.t1 || !d.t2 ||
+            !d.G || !d.Ysd || !d.cdev || !d.lam || !d.E || !d.nrm || !d.info)
+            return DWF_EINVAL;
+        d1 = ws_.off;
+    }
+    ws_.off = std::max({w1, s1, d1});
+    return DWF_OK;
+}
+
+size_t Hierarchy::workspace_bytes(int Lx, int Ly, int Ls, const dwf_mg_params& p, int max_ncol) {
+    Hierarchy h;
+    h.prm = p;
+    h.ws_.counting = true;
+    h.ws_.cap = ~size_t(0) >> 1;
+    if (h.plan(Lx, Ly, Ls, max_ncol) != DWF_OK) return 0;
+    return h.ws_.off;
+}
+
+int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, double M5_,
+                     const dwf_mg_params& p, const void* const* null_starts, int max_ncol, void* ws,
+                     size_t ws_bytes, hipStream_t st) {
+    prm = p;
+    m = m_;
+    M5 = M5_;
+    if (max_ncol < 1) return DWF_EINVAL;
+    const size_t need = workspace_bytes(Lx, Ly, Ls, p, max_ncol);
+    if (need == 0) return DWF_EINVAL;
+    if (ws) {
+        if (ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) return DWF_EINVAL;
+    } else {
+        std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
+        HIPCHK(hipMalloc(&ws_owned_, need));
+        ws = ws_owned_;
+        ws_bytes = need;
+    }
+    ws_ = Arena{};
+    ws_.base = static_cast<char*>(ws);
+    ws_.cap = ws_bytes;
+    if (int e = plan(Lx, Ly, Ls, max_ncol)) return e;
+    {
+        std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
+        if (!st_) HIPCHK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+        if (!ev_in_) HIPCHK(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
+        const int hc = std::max(rw_.max_cols, 64);
+        HIPCHK(hipHostMalloc((void**)&h_scal_, sizeof(double) * 4 * hc, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&h_int_, sizeof(int) * 4 * hc, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&h_cg_, sizeof(CgScal) * hc, hipHostMallocDefault));
+    }
+    const char* ng = std::getenv("DWF_NO_GRAPHS");
+    use_graphs_ = !(ng && ng[0] == '1');
+    for (auto& z : zero_at_setup_) HIPCHK(hipMemsetAsync(z.first, 0, z.second, st));
+    Level& f = levels[0];
+    HIPCHK(hipMemcpyAsync(f.U64, U, sizeof(cpx<double>) * 2 * f.nsites, hipMemcpyDeviceToDevice, st));
+    HIPCHK((vconvert<double, float>(f.U64, f.U32, 2 * (size_t)f.nsites, st)));
+    for (int l = 0; l < p.nlevels; ++l) {
+        Level& L = levels[l];
+        Level& c = levels[l + 1];
+        const int nv = L.nvec_next, bx = L.bx, by = L.by;
         const int nc = L.n / 2;
         const size_t n2 = L.field2d_elems();
-        cpx<double>* v = (cpx<double>*)dalloc(sizeof(cpx<double>) * n2 * nv);
-        L.V64 = (cpx<double>*)dalloc(sizeof(cpx<double>) * n2 * nv);
-        L.V32 = (cpx<float>*)dalloc(sizeof(cpx<float>) * n2 * nv);
-        if (!v || !L.V64 || !L.V32) return DWF_EHIP;
+        cpx<double>* v = stmp_.v;
         if (int e = null_vectors(l, reinterpret_cast<const cpx<double>*>(null_starts[l]), v, st)) return e;
         HIPCHK(chiral_columns(v, L.V64, L.nsites, nc, nv, st));
         HIPCHK(hipMemsetAsync(d_flag_, 0, sizeof(int), st));
@@ -698,28 +800,15 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
         HIPCHK(hipStreamSynchronize(st));
         if (bad) return DWF_EBREAKDOWN;
         HIPCHK((vconvert<double, float>(L.V64, L.V32, n2 * nv, st)));
-        Level c;
-        c.Lx = L.Lx / bx; c.Ly = L.Ly / by; c.Ls = p.Ls_coarse[l]; c.n = 2 * nv;
-        c.nsites = c.Lx * c.Ly; c.fine = false;
-        c.vec_prec = p.vec_prec[l];
-        c.link_prec = p.link_prec[l];
         const size_t nl = (size_t)c.nsites * 5 * c.n * c.n;
-        c.links64 = (cpx<double>*)dalloc(sizeof(cpx<double>) * nl);
-        if (!c.links64) return DWF_EHIP;
         if (L.fine) HIPCHK(galerkin_fine(L.U64, L.V64, c.links64, L.Lx, L.Ly, nv, bx, by, st));
         else HIPCHK(galerkin_coarse(L.links64, L.V64, c.links64, L.Lx, L.Ly, nc, nv, bx, by, st));
-        if (c.link_prec == P_F64) {
-            c.links = c.links64;
-        } else {
-            const bool frag = coarse_mfma_supported(c.n, c.link_prec);
-            c.links = dalloc(cplx_bytes(c.link_prec) * (frag ? links_fragment16_entries(c.nsites, c.n) : nl));
-            if (!c.links) return DWF_EHIP;
-            if (frag)
+        if (c.link_prec != P_F64) {
+            if (coarse_mfma_supported(c.n, c.link_prec))
                 HIPCHK(convert_links_fragment16(c.links64, c.links, c.link_prec, c.nsites, c.n, st));
             else
                 HIPCHK(convert_links(c.links64, c.links, c.link_prec, nl, st));
         }
-        levels.push_back(c);
     }
     HIPCHK(hipStreamSynchronize(st));
     if (int e = deflation_setup(st)) return e;
@@ -727,29 +816,59 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
 }
 
 // ------------------------------------------------------------ solve
-int Hierarchy::solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol, dwf_solve_stats* stats,
+// Right-hand sides in groups of at most max_ncol columns; the statistics add
+// up over the groups (the residual is the worst, the status the worst code).
+int Hierarchy::solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol, int flags, dwf_solve_stats* stats,
                      hipStream_t caller) {
     auto t0 = std::chrono::steady_clock::now();
-    if (int e = ensure_work(ncol, caller)) return e;
+    if (ncol < 1 || max_ncol_ < 1) return DWF_EINVAL;
     // run on the context's stream, after everything already queued on the caller's
     HIPCHK(hipEventRecord(ev_in_, caller));
     HIPCHK(hipStreamWaitEvent(st_, ev_in_, 0));
-    hipStream_t st = st_;
+    const size_t n1 = levels[0].vec_elems();
+    dwf_solve_stats tot{};
+    int worst = DWF_OK;
+    for (int c0 = 0; c0 < ncol; c0 += max_ncol_) {
+        const int nc = std::min(max_ncol_, ncol - c0);
+        dwf_solve_stats g{};
+        const int e = solve_group(b + (size_t)c0 * n1, x + (size_t)c0 * n1, nc, tol, flags, &g, st_);
+        if (e < 0 && (worst >= 0 || e < worst)) worst = e;
+        else if (e > 0 && worst == DWF_OK) worst = e;
+        tot.outer_steps += g.outer_steps;
+        tot.fine_iters += g.fine_iters;
+        tot.fine_applies += g.fine_applies;
+        for (int l = 0; l < DWF_MAX_LEVELS; ++l) {
+            tot.level_iters[l] += g.level_iters[l];
+            tot.level_calls[l] += g.level_calls[l];
+        }
+        tot.true_rel_residual = std::max(tot.true_rel_residual, g.true_rel_residual);
+        if (e < 0) break;
+    }
+    // the caller's stream continues after the solve
+    HIPCHK(hipEventRecord(ev_in_, st_));
+    HIPCHK(hipStreamWaitEvent(caller, ev_in_, 0));
+    auto t1 = std::chrono::steady_clock::now();
+    if (stats) {
+        *stats = tot;
+        stats->status = worst;
+        stats->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    return worst;
+}
+
+int Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, double tol, int flags,
+                           dwf_solve_stats* stats, hipStream_t st) {
     cnt_ = SolveCounters{};
     const Level& L = levels[0];
     LevelWork& w = work_[0];
     const size_t n = L.vec_elems();
     const size_t nt = n * ncol;
-    if (!r64_ || r64_cols_ < ncol) {
-        r64_ = (cpx<double>*)dalloc(sizeof(cpx<double>) * nt);
-        t64_ = (cpx<double>*)dalloc(sizeof(cpx<double>) * nt);
-        if (!r64_ || !t64_) return DWF_EHIP;
-        if (prm.pv_poly_order > 0) {
-            y64_ = (cpx<double>*)dalloc(sizeof(cpx<double>) * nt);
-            z64_ = (cpx<double>*)dalloc(sizeof(cpx<double>) * nt);
-            if (!y64_ || !z64_) return DWF_EHIP;
-        }
-        r64_cols_ = ncol;
+    // the system solved: D_DW x = b, or D_DW x = D_PV b (the propagator form)
+    const cpx<double>* b = b_in;
+    if (flags & DWF_PV_SOURCE) {
+        HIPCHK(fine_dw<double>(L.U64, b_in, bp64_, nullptr, L.Lx, L.Ly, L.Ls, ncol, 1.0, M5, false, nullptr, 1, st));
+        cnt_.fine_applies += 1;
+        b = bp64_;
     }
     double* d_s = work_[0].gcr.rr;   // scratch for column norms between inner solves
     HIPCHK(norm2<double>(b, n, ncol, d_s, rw_, st));
@@ -821,7 +940,6 @@ int Hierarchy::solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol,
         if (it == 0) { status = DWF_NOT_CONVERGED; break; }
     }
     HIPCHK(hipStreamSynchronize(st));
-    auto t1 = std::chrono::steady_clock::now();
     if (stats) {
         stats->status = status;
         stats->outer_steps = outer;
@@ -832,7 +950,6 @@ int Hierarchy::solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol,
             stats->level_calls[l] = cnt_.level_calls[l];
         }
         stats->true_rel_residual = worst;
-        stats->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
     return status;
 }
@@ -854,23 +971,20 @@ int Hierarchy::level_op(int level, int op, const cpx<double>* in, cpx<double>* o
     if (level < 0 || level >= (int)levels.size() || ncol < 1) return DWF_EINVAL;
     const bool transfer = (op == MG_OP_RESTRICT || op == MG_OP_PROLONG || op == MG_OP_KCYCLE);
     if (transfer && level >= (int)levels.size() - 1) return DWF_EINVAL;
-    if (int e = ensure_work(ncol, st)) return e;
+    if (int e = check_cols(ncol)) return e;
     const Level& L = levels[level];
     const size_t nl = L.vec_elems() * ncol;
     const size_t n2 = L.field2d_elems() * ncol;
-    const bool is2d = (op == MG_OP_WILSON || op == MG_OP_WILSON_DAG);
-    const size_t nin_l = is2d ? n2 : nl;
     const int T32 = (L.vec_prec == P_F32);
-    const size_t eb = cplx_bytes(L.vec_prec);
-    void* bin = nullptr; void* bout = nullptr; void* btmp = nullptr; void* bn = nullptr;
+    // the level's own solve buffers (2-d fields fit: Ls >= 1); transfers use the
+    // next level's right-hand side and solution buffers
+    LevelWork& w = work_[level];
+    void* bin = w.rhs;
+    void* bout = w.x;
+    void* btmp = w.tmp;
     size_t nn = 0;
     if (transfer) nn = levels[level + 1].vec_elems() * ncol;
-    const size_t nbig = std::max(nl, n2);
-    std::unique_lock<std::recursive_mutex> lk(runtime_mutex());
-    HIPCHK(hipMalloc(&bin, nbig * eb));
-    HIPCHK(hipMalloc(&bout, nbig * eb));
-    HIPCHK(hipMalloc(&btmp, nbig * eb));
-    if (transfer) HIPCHK(hipMalloc(&bn, nn * cplx_bytes(levels[level + 1].vec_prec)));
+    void* bn = transfer ? (op == MG_OP_PROLONG ? work_[level + 1].x : work_[level + 1].rhs) : nullptr;
     int status = DWF_OK;
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
@@ -920,13 +1034,8 @@ int Hierarchy::level_op(int level, int op, const cpx<double>* in, cpx<double>* o
                 return DWF_EINVAL;
         }
     };
-    (void)nin_l;
     status = T32 ? run(float{}) : run(double{});
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(bin);
-    (void)hipFree(bout);
-    (void)hipFree(btmp);
-    if (bn) (void)hipFree(bn);
+    if (hipStreamSynchronize(st) != hipSuccess && status == DWF_OK) status = DWF_EHIP;
     return status;
 }
 
@@ -935,7 +1044,7 @@ int Hierarchy::time_op(int level, int op, const cpx<double>* in, int ncol, int i
     if (level < 0 || level >= (int)levels.size() || ncol < 1 || iters < 1 || !avg_ms) return DWF_EINVAL;
     if (op != MG_OP_DW && op != MG_OP_DW_DAG && op != MG_OP_PV && op != MG_OP_PV_DAG && op != MG_OP_A)
         return DWF_EINVAL;
-    if (int e = ensure_work(ncol, st)) return e;
+    if (int e = check_cols(ncol)) return e;
     const Level& L = levels[level];
     LevelWork& w = work_[level];
     const size_t nl = L.vec_elems() * ncol;

@@ -3,8 +3,11 @@
 
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
+#include <cstdint>
 #include <map>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "../../include/dwfmg.h"
@@ -71,15 +74,49 @@ struct SolveCounters {
     long long level_calls[DWF_MAX_LEVELS] = {0, 0, 0};
 };
 
+// Device memory of a hierarchy: one arena, the caller's workspace or a single
+// library allocation, carved once at setup.  In counting mode nothing is
+// dereferenced: take() only advances the offset (the size query).
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, off = 0;
+    bool counting = false;
+    void* take(size_t bytes) {
+        const size_t o = (off + 255) & ~size_t(255);
+        if (o + bytes > cap || o + bytes < o) return nullptr;
+        off = o + bytes;
+        return counting ? reinterpret_cast<void*>(uintptr_t(256) + o) : base + o;
+    }
+};
+
+// partial-sum blocks of the deflated start's projections
+constexpr int kDeflBlocks = 256;
+
+// Dimensions of the coarsest-level eigensolver: nk Ritz vectors kept at a thick
+// restart, a Lanczos basis of m (+1) columns, for nev wanted pairs of n entries.
+inline void deflation_dims(int nev, size_t n, int& nk, int& m) {
+    nk = (int)std::min<size_t>((size_t)nev + std::max(16, nev / 4), n - 1);
+    m = (int)std::min<size_t>((size_t)nk + std::max(32, nev / 2), n);
+}
+
 class Hierarchy {
 public:
     Hierarchy() = default;
     ~Hierarchy();
 
+    // Build the hierarchy in `ws` (ws_bytes, 256-byte aligned) or, with ws ==
+    // nullptr, in one device allocation of workspace_bytes(); solves take at
+    // most max_ncol right-hand sides at a time.
     int setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m, double M5,
-              const dwf_mg_params& p, const void* const* null_starts, hipStream_t st);
-    int solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol, dwf_solve_stats* stats,
+              const dwf_mg_params& p, const void* const* null_starts, int max_ncol, void* ws,
+              size_t ws_bytes, hipStream_t st);
+    // bytes of device memory a hierarchy needs (every level, setup and solve
+    // buffers for max_ncol columns); 0 if the layout cannot be formed
+    static size_t workspace_bytes(int Lx, int Ly, int Ls, const dwf_mg_params& p, int max_ncol);
+    // solves ncol right-hand sides, in groups of at most max_ncol
+    int solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol, int flags, dwf_solve_stats* stats,
               hipStream_t st);
+    int max_ncol() const { return max_ncol_; }
     int level_op(int level, int op, const cpx<double>* in, cpx<double>* out, int ncol, double mass,
                  hipStream_t st);
     int export_level(int level, cpx<double>* V, cpx<double>* kernel, hipStream_t st);
@@ -92,21 +129,43 @@ public:
     double m = 0.0, M5 = 0.0;
 
 private:
-    std::vector<void*> allocs_;
+    Arena ws_{};
+    void* ws_owned_ = nullptr;    // the arena, when the library allocated it
+    int max_ncol_ = 0;
+    std::vector<std::pair<void*, size_t>> zero_at_setup_;   // flags that start at zero
     std::vector<LevelWork> work_;
     RedWork rw_{};
-    int work_cols_ = 0;
     // pinned host mirrors for scalar read-back
     double* h_scal_ = nullptr;
     int* h_int_ = nullptr;
     CgScal* h_cg_ = nullptr;
     int* d_flag_ = nullptr;
-    int scal_cols_ = 0;
     cpx<double>* r64_ = nullptr;
     cpx<double>* t64_ = nullptr;
     cpx<double>* y64_ = nullptr;   // PV polynomial of the FP64 right-hand side
     cpx<double>* z64_ = nullptr;
-    int r64_cols_ = 0;
+    cpx<double>* bp64_ = nullptr;  // D_PV b for DWF_PV_SOURCE
+    // setup temporaries (they overlap the solve buffers, which setup does not use)
+    struct SetupTmp {
+        cpx<double>* v = nullptr;
+        cpx<double>* r = nullptr;
+        cpx<double>* p = nullptr;
+        cpx<double>* t = nullptr;
+        cpx<double>* q = nullptr;
+        CgScal* s = nullptr;
+    } stmp_{};
+    // eigensolver temporaries of the deflation setup (also overlapping the solve buffers)
+    struct DeflTmp {
+        int nk = 0, m = 0;
+        cpx<double> *Vb = nullptr, *Ub = nullptr, *HUb = nullptr, *Xb = nullptr, *Wb = nullptr;
+        cpx<double> *P0 = nullptr, *P1 = nullptr, *P2 = nullptr, *Hh = nullptr, *t1 = nullptr, *t2 = nullptr;
+        cpx<double> *G = nullptr, *Ysd = nullptr, *cdev = nullptr;
+        double *lam = nullptr, *E = nullptr, *nrm = nullptr;
+        int* info = nullptr;
+    } dtmp_{};
+    int plan(int Lx, int Ly, int Ls, int max_ncol);
+    int solve_group(const cpx<double>* b, cpx<double>* x, int ncol, double tol, int flags, dwf_solve_stats* stats,
+                    hipStream_t st);
     SolveCounters cnt_{};
     // solves run on a stream of the context, so that fixed launch sequences
     // (a chunk of coarsest CGNR iterations, a GCR smoother) can be captured
@@ -134,13 +193,12 @@ private:
     rocblas_handle blas_ = nullptr;
     cpx<double>* def_V_ = nullptr;
     double* def_lam_ = nullptr;
-    cpx<double>* def_C_ = nullptr;
+    cpx<double>* def_C_ = nullptr;   // projections of the deflated start [ncol][nev]
+    double* def_part_ = nullptr;     // their per-block partial sums
     double* def_ref_ = nullptr;   // |A^dag b|^2 per column, the CGNR reference
-    int def_ref_cols_ = 0;
 
-    void* dalloc(size_t bytes);
-    int ensure_work(int ncol, hipStream_t st);
-    int ensure_scalars(int maxc);
+    void* dalloc(size_t bytes) { return ws_.take(bytes < 256 ? 256 : bytes); }
+    int check_cols(int ncol) const { return (ncol >= 1 && ncol <= max_ncol_) ? DWF_OK : DWF_EINVAL; }
     int alloc_level_work(int l, int ncol);
 
     // operators on level l in precision T

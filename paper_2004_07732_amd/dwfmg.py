@@ -29,6 +29,7 @@ DWF_ESCRATCH = -7
 
 DWF_DAGGER = 1
 DWF_PREC_F32 = 2
+DWF_PV_SOURCE = 4
 
 DWF_PV, DWF_PV_DAG, DWF_PVDAG_DW, DWF_PVDAG_DW_DAG, DWF_PVINV_DW = 0, 1, 2, 3, 4
 P_F64, P_F32, P_BF16, P_F16 = 0, 1, 2, 3
@@ -77,15 +78,18 @@ def lib() -> ctypes.CDLL:
         L.dwf_force.argtypes = [vp, vp, vp, vp, i, i, i, i, vp]
         L.dwf_mg_default_params.argtypes = [ctypes.POINTER(CParams), i]
         L.dwf_mg_default_params.restype = None
+        L.mg_workspace_bytes.argtypes = [i, i, i, i, ctypes.POINTER(CParams)]
+        L.mg_workspace_bytes.restype = sz
         L.mg_setup.argtypes = [ctypes.POINTER(vp), vp, i, i, i, d, d, ctypes.POINTER(CParams),
-                               ctypes.POINTER(vp), vp]
-        L.mg_solve.argtypes = [vp, vp, vp, i, d, ctypes.POINTER(CStats), vp]
+                               ctypes.POINTER(vp), i, vp, sz, vp]
+        L.mg_solve.argtypes = [vp, vp, vp, i, d, i, ctypes.POINTER(CStats), vp]
         L.mg_level_op.argtypes = [vp, i, i, vp, vp, i, d, vp]
         L.mg_export.argtypes = [vp, i, vp, vp, vp]
         L.mg_time_op.argtypes = [vp, i, i, vp, i, i, ctypes.POINTER(d), vp]
         L.dwf_norm2.argtypes = [vp, sz, i, vp, vp]
+        L.dwf_copy_bandwidth.argtypes = [vp, vp, sz, i, ctypes.POINTER(d), vp]
         L.mg_solve_batch.argtypes = [i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
-                                     ctypes.POINTER(i), d, ctypes.POINTER(CStats), vp]
+                                     ctypes.POINTER(i), d, i, ctypes.POINTER(CStats), vp]
         L.mg_update_links.argtypes = [vp, vp, vp]
         L.mg_level_info.argtypes = [vp, i] + [ctypes.POINTER(i)] * 5
         L.mg_deflation_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(d), vp]
@@ -97,7 +101,7 @@ def lib() -> ctypes.CDLL:
         for name in ("dwf_apply", "dwf_pv_apply", "dwf_pv_apply_noalloc", "dwf_fine_config", "dwf_pv_poly_apply", "dwf_pv_poly_chebyshev",
                      "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
                      "dwf_pack", "dwf_unpack", "dwf_force", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
-                     "mg_time_op", "dwf_norm2", "mg_update_links", "mg_solve_batch",
+                     "mg_time_op", "dwf_norm2", "dwf_copy_bandwidth", "mg_update_links", "mg_solve_batch",
                      "mg_level_info", "mg_deflation_info", "mg_destroy", "dwf_release_scratch",
                      "dwf_krylov_solve"):
             getattr(L, name).restype = ctypes.c_int
@@ -431,6 +435,17 @@ def dwf_norm2(x, stream=None):
     return out
 
 
+def copy_bandwidth(nbytes: int = 2 ** 31, iters: int = 10, device="cuda", stream=None) -> float:
+    """GB/s (read + write) of the library's streaming copy over `nbytes`."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    out = ctypes.c_double()
+    _check(lib().dwf_copy_bandwidth(_ptr(src), _ptr(dst), nbytes, int(iters), ctypes.byref(out), _stream(stream)),
+           "dwf_copy_bandwidth")
+    return out.value
+
+
 def release_scratch():
     _check(lib().dwf_release_scratch(), "dwf_release_scratch")
 
@@ -462,8 +477,14 @@ def dwf_krylov_solve(U, b, m_f, M5, method=KRYLOV_BICGSTAB, ell=6, tol=1e-10, ma
     return x, _stats(st)
 
 
+def workspace_bytes(Lx: int, Ly: int, Ls: int, params: "MGParams", max_nrhs: int = 1) -> int:
+    """Device bytes a hierarchy needs (mg_workspace_bytes); 0 for invalid arguments."""
+    cp = params.to_c()
+    return int(lib().mg_workspace_bytes(int(Lx), int(Ly), int(Ls), int(max_nrhs), ctypes.byref(cp)))
+
+
 def solve_batch(mgs: Sequence["MG"], bs: Sequence[torch.Tensor], tol: float = 1e-10, stream=None,
-                check: bool = True):
+                check: bool = True, pv_source: bool = False):
     """Solve several lattices at once (mg_solve_batch): returns ([x_i], [stats_i])."""
     n = len(mgs)
     if n != len(bs) or n == 0:
@@ -479,18 +500,23 @@ def solve_batch(mgs: Sequence["MG"], bs: Sequence[torch.Tensor], tol: float = 1e
     VP = ctypes.c_void_p * n
     st = (CStats * n)()
     code = lib().mg_solve_batch(n, VP(*[m._h.value for m in mgs]), VP(*[b.data_ptr() for b in bs]),
-                                VP(*[x.data_ptr() for x in xs]), (ctypes.c_int * n)(*nr), float(tol), st,
-                                _stream(stream))
+                                VP(*[x.data_ptr() for x in xs]), (ctypes.c_int * n)(*nr), float(tol),
+                                DWF_PV_SOURCE if pv_source else 0, st, _stream(stream))
     if check:
         _check(code, "mg_solve_batch")
     return xs, [_stats(s) for s in st]
 
 
 class MG:
-    """Domain-wall multigrid hierarchy on one GPU (mg_setup / mg_solve)."""
+    """Domain-wall multigrid hierarchy on one GPU (mg_setup / mg_solve).
+
+    All device memory of the hierarchy lives in one torch tensor (`workspace`,
+    mg_workspace_bytes of it) unless the caller passes one; solves take
+    right-hand sides in groups of at most `max_nrhs`."""
 
     def __init__(self, U: torch.Tensor, Ls: int, m_f: float, M5: float, params: MGParams,
-                 null_starts: Sequence[torch.Tensor], stream=None):
+                 null_starts: Sequence[torch.Tensor], stream=None, max_nrhs: int = 1,
+                 workspace: Optional[torch.Tensor] = None):
         _need(U, "U", torch.complex128)
         if len(null_starts) < params.nlevels:
             raise ValueError("one null-vector start tensor per coarse level is required")
@@ -503,12 +529,22 @@ class MG:
                                               [None] * (MAX_LEVELS - len(null_starts))))
         self._h = ctypes.c_void_p()
         self._cp = params.to_c()
+        self.max_nrhs = int(max_nrhs)
+        need = lib().mg_workspace_bytes(self.Lx, self.Ly, Ls, self.max_nrhs, ctypes.byref(self._cp))
+        if need == 0:
+            raise DwfError(DWF_EINVAL, "mg_workspace_bytes")
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=U.device)
+        _need(workspace, "workspace")
+        self.workspace = workspace
         _check(lib().mg_setup(ctypes.byref(self._h), _ptr(U), self.Lx, self.Ly, Ls, float(m_f), float(M5),
-                              ctypes.byref(self._cp), arr, _stream(stream)), "mg_setup")
+                              ctypes.byref(self._cp), arr, self.max_nrhs, _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _stream(stream)), "mg_setup")
 
     def solve(self, b: torch.Tensor, tol: float = 1e-10, x: Optional[torch.Tensor] = None, stream=None,
-              check: bool = True):
-        """x with |b - D_DW x| <= tol |b| for every rhs; b [nrhs, Ls, Ly, Lx, 2] complex128."""
+              check: bool = True, pv_source: bool = False):
+        """x with |b - D_DW x| <= tol |b| for every rhs (pv_source: D_DW x = D_PV b);
+        b [nrhs, Ls, Ly, Lx, 2] complex128."""
         _need(b, "b", torch.complex128)
         bb = b if b.dim() == 5 else b.unsqueeze(0)
         if tuple(bb.shape[1:]) != (self.Ls, self.Ly, self.Lx, 2):
@@ -516,7 +552,8 @@ class MG:
         x = torch.empty_like(b) if x is None else x
         _need(x, "x", torch.complex128, b.shape)
         st = CStats()
-        code = lib().mg_solve(self._h, _ptr(b), _ptr(x), bb.shape[0], float(tol), ctypes.byref(st), _stream(stream))
+        code = lib().mg_solve(self._h, _ptr(b), _ptr(x), bb.shape[0], float(tol), DWF_PV_SOURCE if pv_source else 0,
+                              ctypes.byref(st), _stream(stream))
         stats = SolveStats(st.status, st.outer_steps, st.fine_iters, st.fine_applies, list(st.level_iters),
                            list(st.level_calls), st.true_rel_residual, st.solve_ms)
         if check:

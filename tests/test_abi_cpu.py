@@ -105,3 +105,78 @@ def test_pv_poly_arguments_rejected_on_the_host(libdwf):
     assert libdwf.dwf_pv_poly_apply(1, 2, 3, 4, 4, 4, 1, 0.1, -1.0, None, 0, 0, None) == -1
     nan = (d * 1)(float("nan"))
     assert libdwf.dwf_pv_poly_apply(1, 2, 3, 4, 4, 4, 1, 0.1, -1.0, nan, 0, 0, None) == -1
+
+
+def _headline_params(dwfmg, **kw):
+    p = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[dwfmg.P_F64],
+                       fine_prec=dwfmg.P_F32, coarsest_solver=dwfmg.COARSEST_GCR, coarsest_restart=6,
+                       coarsest_tol=0.25)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_workspace_bytes_on_the_host(libdwf):
+    """mg_workspace_bytes needs no device: it lays the hierarchy out in counting
+    mode.  At 256^2 x Ls 16 (16 null vectors, 4x4 aggregates, coarse Ls 2) the
+    layout holds at least the operators: FP64 + BF16 coarse links (5 FP64
+    blocks of 32^2 and 3 BF16 blocks per coarse site), FP64 + FP32
+    prolongator, FP64 + FP32 fine links."""
+    from paper_2004_07732_amd import dwfmg
+    L, Ls = 256, 16
+    p = _headline_params(dwfmg)
+    b1 = dwfmg.workspace_bytes(L, L, Ls, p, 1)
+    b16 = dwfmg.workspace_bytes(L, L, Ls, p, 16)
+    sites_c = (L // 4) ** 2
+    floor = (sites_c * 5 * 32 * 32 * 16 + sites_c * 3 * 32 * 32 * 4 + L * L * 2 * 16 * 24 + 2 * L * L * 24)
+    assert floor < b1 < b16 < 64 * b1
+    # the fine FP32 solve buffers grow with the column count: at least 16 of the outer GCR's
+    # 2 x 16 directions per extra column (16.8 MB per FP32 fine vector)
+    assert b16 - b1 >= 15 * 32 * (L * L * Ls * 2 * 8)
+    # deflation adds its space (nev coarsest vectors of 64^2 x 2 x 32 FP64) and eigensolver buffers
+    pc = _headline_params(dwfmg, coarsest_solver=dwfmg.COARSEST_CGNR, coarsest_nev=32)
+    assert dwfmg.workspace_bytes(L, L, Ls, pc, 1) - dwfmg.workspace_bytes(
+        L, L, Ls, _headline_params(dwfmg, coarsest_solver=dwfmg.COARSEST_CGNR), 1) >= 32 * sites_c * 2 * 32 * 16
+    # invalid arguments give 0
+    assert dwfmg.workspace_bytes(L, L, Ls, p, 0) == 0
+    assert dwfmg.workspace_bytes(L, 250, Ls, p, 1) == 0
+    assert dwfmg.workspace_bytes(L, L, 1, p, 1) == 0
+
+
+def _span(src, header):
+    """(start, end) of the brace-matched definition whose header matches `header`."""
+    m = re.search(header, src, flags=re.M)
+    assert m, header
+    i = src.index("{", m.end() - 1)
+    depth, j = 1, i + 1
+    while depth:
+        depth += {"{": 1, "}": -1}.get(src[j], 0)
+        j += 1
+    return m.start(), j
+
+
+def test_device_allocation_only_where_documented():
+    """After mg_setup no path of a hierarchy allocates device memory: the only
+    hipMalloc / hipFree calls in the library are the workspace that mg_setup
+    makes when the caller passes none (and its release), the library-owned
+    scratch of dwf_pv_apply / dwf_pv_poly_apply / dwf_norm2 (acquire / drop),
+    and the work vectors of dwf_krylov_solve (documented per call in the header).
+    The allocation-free entry point and everything a solve runs allocate nothing."""
+    allowed = {
+        "mg.hip": [r"^int Hierarchy::setup\(", r"^Hierarchy::~Hierarchy\(\)"],
+        "abi.hip": [r"^void\* acquire\(", r"^void drop\("],
+        "krylov.hip": [r"^struct Work \{"],
+    }
+    csrc = os.path.join(ROOT, "paper_2004_07732_amd", "csrc")
+    seen = set()
+    for fn in sorted(os.listdir(csrc)):
+        if not fn.endswith((".hip", ".hpp")):
+            continue
+        src = open(os.path.join(csrc, fn)).read()
+        spans = [_span(src, h) for h in allowed.get(fn, [])]
+        for m in re.finditer(r"\bhip(Malloc|Free|MallocManaged|ExtMallocWithFlags|MallocAsync|MallocPitch)\s*\(", src):
+            inside = [k for k, (a, b) in enumerate(spans) if a <= m.start() < b]
+            line = src.count("\n", 0, m.start()) + 1
+            assert inside, f"{fn}:{line}: device allocation outside the documented places"
+            seen.add((fn, inside[0]))
+    assert ("mg.hip", 0) in seen and ("abi.hip", 0) in seen

@@ -29,7 +29,7 @@ def hierarchy(L, Ls, m, levels, seed, oracle=False, **kw):
     params = dwfmg.MGParams(nvec=[l[0] for l in levels], block=[l[1] for l in levels],
                             Ls_coarse=[l[2] for l in levels], link_prec=[dwfmg.P_F64] * len(levels),
                             vec_prec=[dwfmg.P_F64] * len(levels), setup_iters=0, **kw)
-    mg = dwfmg.MG(T(U), Ls, m, -1.0, params, [T(s) for s in starts])
+    mg = dwfmg.MG(T(U), Ls, m, -1.0, params, [T(s) for s in starts], max_nrhs=4)
     omg = None
     if oracle:
         op = O.MGParams(levels=[O.LevelParams(nvec=l[0], block=(l[1][1], l[1][0]), Ls=l[2], setup_iters=0)

@@ -42,18 +42,20 @@ def test_large_combined_form_16_rhs():
     p = dwfmg.MGParams(nvec=[16, 24], block=[(4, 4), (2, 2)], Ls_coarse=[2, 2], link_prec=[dwfmg.P_BF16] * 2,
                        vec_prec=[dwfmg.P_F32, dwfmg.P_F64], fine_prec=dwfmg.P_F32,
                        coarsest_solver=dwfmg.COARSEST_GCR, coarsest_restart=8, coarsest_tol=0.25, max_iters=20000)
-    mg = dwfmg.MG(U, Ls, m, M5, p, starts)
+    mg = dwfmg.MG(U, Ls, m, M5, p, starts, max_nrhs=nrhs)
     say("[C5] hierarchy ready, solving 16 rhs")
     x, st = mg.solve(b, 1e-10)
     say(f"[C5] solve: {st.solve_ms / 1e3:.1f} s, fine iters {st.fine_iters}, fine applies {st.fine_applies}, "
         f"levels {st.level_iters} / {st.level_calls}, residual {st.true_rel_residual:.2e}")
     assert st.status == dwfmg.DWF_OK and st.true_rel_residual <= 1e-10
-    for j in (0, nrhs - 1):
+    worst = 0.0
+    for j in range(nrhs):
         xj = x[j].cpu().numpy()
         bj = b[j].cpu().numpy()
         res = np.linalg.norm(bj - O.dwf(g.U, xj, m, M5)) / np.linalg.norm(bj)
-        say(f"[C5] rhs {j}: oracle residual {res:.2e}")
-        assert res <= 1e-10
+        worst = max(worst, res)
+        assert res <= 1e-10, f"rhs {j}: oracle residual {res:.2e}"
+    say(f"[C5] all {nrhs} rhs: worst oracle residual {worst:.2e}")
 
 
 def test_batched_form_64_rhs_three_lattices():
@@ -71,7 +73,7 @@ def test_batched_form_64_rhs_three_lattices():
         p = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_F16],
                            vec_prec=[dwfmg.P_F64], fine_prec=dwfmg.P_F32, coarsest_solver=dwfmg.COARSEST_GCR,
                            coarsest_restart=8, coarsest_tol=0.25, max_iters=20000)
-        mgs.append(dwfmg.MG(torch.from_numpy(g.U).cuda(), Ls, m, M5, p, starts))
+        mgs.append(dwfmg.MG(torch.from_numpy(g.U).cuda(), Ls, m, M5, p, starts, max_nrhs=nr))
         b = torch.empty((nr, Ls, L, L, 2), dtype=torch.complex128, device="cuda")
         for j in range(nr):
             b[j] = torch.from_numpy(inputs.gaussian_field((Ls, L, L, 2), inputs.rhs_seed(cfg, L, j)))
@@ -83,33 +85,87 @@ def test_batched_form_64_rhs_three_lattices():
         say(f"[C3] L={L} nrhs={nr}: {st.solve_ms / 1e3:.1f} s, fine iters {st.fine_iters}, "
             f"coarse {st.level_iters[0]} in {st.level_calls[0]} calls, residual {st.true_rel_residual:.2e}")
         assert st.status == dwfmg.DWF_OK and st.true_rel_residual <= 1e-10
-        j = nr - 1
-        bj = b[j].cpu().numpy()
-        res = np.linalg.norm(bj - O.dwf(U, x[j].cpu().numpy(), m, M5)) / np.linalg.norm(bj)
-        assert res <= 1e-10
+        worst = 0.0
+        for j in range(nr):
+            bj = b[j].cpu().numpy()
+            res = np.linalg.norm(bj - O.dwf(U, x[j].cpu().numpy(), m, M5)) / np.linalg.norm(bj)
+            worst = max(worst, res)
+            assert res <= 1e-10, f"L={L} rhs {j}: oracle residual {res:.2e}"
+        say(f"[C3] L={L}: all {nr} rhs, worst oracle residual {worst:.2e}")
+
+
+def headline_inputs(nrhs):
+    """Gauge field, right-hand sides and null-vector starts of the benchmark's
+    headline workload (256^2 x Ls 16, beta 6, 200 sweeps)."""
+    L, Ls, cfg = 256, 16, 6
+    g = inputs.metropolis_u1(L, L, 6.0, 200, inputs.gauge_seed(4, L))
+    b = torch.empty((nrhs, Ls, L, L, 2), dtype=torch.complex128, device="cuda")
+    for j in range(nrhs):
+        b[j] = torch.from_numpy(inputs.gaussian_field((Ls, L, L, 2), inputs.rhs_seed(cfg, L, j)))
+    starts = [torch.from_numpy(inputs.gaussian_field((16, L, L, 2), inputs.null_start_seed(cfg, 0))).cuda()]
+    return g, b, starts
 
 
 @pytest.mark.parametrize("nrhs", [1, 16])
 def test_headline_configuration(nrhs):
     """The benchmark's own configuration at full size: 256^2 x Ls 16, beta 6,
     m_f 0.01, 2 levels (4x4 aggregates, 16 null vectors, coarse Ls 2), FP32 fine
-    level, BF16 matrix-core coarse links, FP64 coarse vectors, coarsest GCR(8) to
+    level, BF16 matrix-core coarse links, FP64 coarse vectors, coarsest GCR(6) to
     0.25, FP64 defect correction to 1e-10; the oracle recomputes the residual of
-    sampled right-hand sides."""
-    L, Ls, m, M5, cfg = 256, 16, 0.01, -1.0, 6
-    g = inputs.metropolis_u1(L, L, 6.0, 200, inputs.gauge_seed(4, L))
-    b = torch.empty((nrhs, Ls, L, L, 2), dtype=torch.complex128, device="cuda")
-    for j in range(nrhs):
-        b[j] = torch.from_numpy(inputs.gaussian_field((Ls, L, L, 2), inputs.rhs_seed(cfg, L, j)))
-    starts = [torch.from_numpy(inputs.gaussian_field((16, L, L, 2), inputs.null_start_seed(cfg, 0))).cuda()]
+    every right-hand side."""
+    L, Ls, m, M5 = 256, 16, 0.01, -1.0
+    g, b, starts = headline_inputs(nrhs)
     p = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[dwfmg.P_F64],
-                       fine_prec=dwfmg.P_F32, coarsest_solver=dwfmg.COARSEST_GCR, coarsest_restart=8,
+                       fine_prec=dwfmg.P_F32, coarsest_solver=dwfmg.COARSEST_GCR, coarsest_restart=6,
                        coarsest_tol=0.25)
-    mg = dwfmg.MG(torch.from_numpy(g.U).cuda(), Ls, m, M5, p, starts)
+    mg = dwfmg.MG(torch.from_numpy(g.U).cuda(), Ls, m, M5, p, starts, max_nrhs=nrhs)
     x, st = mg.solve(b, 1e-10)
     say(f"[headline] nrhs {nrhs}: {st.solve_ms:.0f} ms, fine iters {st.fine_iters}, residual {st.true_rel_residual:.2e}")
     assert st.status == dwfmg.DWF_OK and st.true_rel_residual <= 1e-10
-    for j in sorted({0, nrhs - 1}):
+    worst = 0.0
+    for j in range(nrhs):
         bj = b[j].cpu().numpy()
         res = np.linalg.norm(bj - O.dwf(g.U, x[j].cpu().numpy(), m, M5)) / np.linalg.norm(bj)
-        assert res <= 1e-10
+        worst = max(worst, res)
+        assert res <= 1e-10, f"rhs {j}: oracle residual {res:.2e}"
+    say(f"[headline] nrhs {nrhs}: worst oracle residual {worst:.2e}")
+
+
+def bf16_round(a):
+    """Round to bfloat16 (nearest even) through float32, as the library stores links."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("ncol", [1, 16])
+def test_headline_coarse_stencil_full_size(ncol):
+    """The coarse operator of the headline hierarchy at its full size (64^2
+    coarse sites x coarse Ls 2, 32 dof per site, BF16 links on the matrix cores,
+    FP64 vectors), element by element against the oracle's coarse operator
+    built by the oracle from the same gauge field and null-vector starts (no
+    relaxation, so both sides build the same prolongator) and rounded to BF16.
+    ncol = 1 is the launch the benchmark's roofline line times."""
+    L, Ls, m, M5, nv = 256, 16, 0.01, -1.0, 16
+    g = inputs.metropolis_u1(L, L, 6.0, 200, inputs.gauge_seed(4, L))
+    start = inputs.gaussian_field((nv, L, L, 2), inputs.null_start_seed(6, 0))
+    p = dwfmg.MGParams(nvec=[nv], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[dwfmg.P_F64],
+                       fine_prec=dwfmg.P_F32, setup_iters=0)
+    mg = dwfmg.MG(torch.from_numpy(g.U).cuda(), Ls, m, M5, p, [torch.from_numpy(start).cuda()], max_nrhs=ncol)
+    op = O.MGParams(levels=[O.LevelParams(nvec=nv, block=(4, 4), Ls=2, setup_iters=0)])
+    omg = O.MG(g.U, Ls, m, M5, op, [start])
+    S = omg.levels[1].S
+    Sb = O.Stencil(diag=bf16_round(S.diag.real) + 1j * bf16_round(S.diag.imag),
+                   hop=bf16_round(S.hop.real) + 1j * bf16_round(S.hop.imag), chir=S.chir)
+    x = inputs.gaussian_field((ncol, 2, L // 4, L // 4, 2 * nv), 7_100_000 + ncol)
+    for code, dag in ((dwfmg.MG_OP_DW, False), (dwfmg.MG_OP_DW_DAG, True)):
+        got = mg.level_op(1, code, torch.from_numpy(x).cuda(), ncol).cpu().numpy()
+        want = O.stencil_dwf(Sb, x, m, M5, dagger=dag)
+        err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+        emax = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+        say(f"[coarse full] ncol {ncol} dagger {dag}: rel 2-norm {err:.2e}, max elementwise {emax:.2e}")
+        # the FP64 vector enters the matrix cores as two BF16 parts, which carry 16
+        # significant bits: |x - hi - lo| <= 2^-16 |x| per entry; FP32 accumulation
+        # adds ~1e-7.  Bars: 2^-16 on the 2-norm, 4 x 2^-16 on the largest entry.
+        assert err < 2.0 ** -16 and emax < 4 * 2.0 ** -16

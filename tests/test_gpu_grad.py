@@ -80,3 +80,65 @@ def test_differentiation_form_full_size():
     S = action(th, T(phi), mg, tol=tol)
     S.backward()
     assert np.max(np.abs(th.grad.cpu().numpy() - F_o)) < 1e-6 * np.max(np.abs(F_o))
+
+
+def test_cancellation_free_finite_differences_full_size():
+    """256^2 x Ls 16, beta 6, m 0.01 (the differentiation workload): for 32
+    seeded links l, the central difference S(theta_l + h) - S(theta_l - h),
+    h = 1e-5, against 2 h dS/dtheta_l from the force kernel.
+
+    The difference is formed without cancellation.  With D_pm = D(theta_l pm h)
+    and Y_pm = D_pm^{-dag} phi, S_pm = |Y_pm|^2; writing Delta = Y_+ - Y_-,
+        D_+^dag Delta = (D_- - D_+)^dag Y_-   and   S_+ - S_- = Re <Delta, 2 Y_- + Delta>.
+    D_- - D_+ touches only the link's two hops (Sec. 2, the Wilson term):
+    its blocks are -(1 - gamma_mu)/2 dU from x to x+mu and
+    -(1 + gamma_mu)/2 dU^* back, dU = U_l (e^{-ih} - e^{ih}) = -2i sin(h) U_l,
+    so the source is written exactly on two sites.  Two multigrid solves per
+    link (adjoint solves as Gamma5 D^{-1} Gamma5), all to 1e-12."""
+    L, Ls, m, M5, tol, h = 256, 16, 0.01, -1.0, 1e-12, 1e-5
+    g = inputs.metropolis_u1(L, L, 6.0, 200, inputs.gauge_seed(4, L))
+    phi = inputs.gaussian_field((1, Ls, L, L, 2), 4256000)
+    params = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16],
+                            vec_prec=[dwfmg.P_F64], fine_prec=dwfmg.P_F32, coarsest_solver=dwfmg.COARSEST_GCR,
+                            coarsest_restart=6, coarsest_tol=0.25)
+    starts = [T(inputs.gaussian_field((16, L, L, 2), inputs.null_start_seed(4, 0)))]
+    Ut = T(g.U)
+    mg = dwfmg.MG(Ut, Ls, m, M5, params, starts)
+    phit = T(phi)
+
+    def adj_solve(rhs):
+        x, st = mg.solve(dwfmg.dwf_gamma5R(rhs), tol)
+        assert st.status == dwfmg.DWF_OK
+        return dwfmg.dwf_gamma5R(x)
+
+    Y = adj_solve(phit)
+    X, st = mg.solve(Y, tol)
+    F = dwfmg.dwf_force(Ut, X, Y).cpu().numpy()
+    rms = float(np.sqrt(np.mean(F ** 2)))
+    rng = np.random.default_rng(4256001)
+    links = [(int(rng.integers(2)), int(rng.integers(L)), int(rng.integers(L))) for _ in range(32)]
+    worst = 0.0
+    for k, (mu, y, x) in enumerate(links):
+        ph = np.exp(1j * h)
+        Um, Up = g.U.copy(), g.U.copy()
+        Um[mu, y, x] *= np.conj(ph)
+        Up[mu, y, x] *= ph
+        mg.update_links(T(Um))
+        Ym = adj_solve(phit)
+        Ymn = Ym.cpu().numpy()[0]
+        dU = -2j * np.sin(h) * g.U[mu, y, x]
+        yn, xn = (y, (x + 1) % L) if mu == 0 else ((y + 1) % L, x)
+        gam = O.GAMMA[mu]
+        src = np.zeros((1, Ls, L, L, 2), dtype=np.complex128)
+        src[0, :, yn, xn] = O.spin_mul(-0.5 * (O.IDENT2 - gam) * np.conj(dU), Ymn[:, y, x])
+        src[0, :, y, x] = O.spin_mul(-0.5 * (O.IDENT2 + gam) * dU, Ymn[:, yn, xn])
+        mg.update_links(T(Up))
+        Dl = adj_solve(T(src)).cpu().numpy()[0]
+        dS = float(np.vdot(Dl, 2 * Ymn + Dl).real)
+        fd = dS / (2 * h)
+        err = abs(fd - F[mu, y, x]) / max(abs(F[mu, y, x]), 1e-2 * rms)
+        worst = max(worst, err)
+        print(f"link {k} (mu={mu}, y={y}, x={x}): FD {fd:.10e}, force {F[mu, y, x]:.10e}, rel {err:.1e}", flush=True)
+        assert err < 1e-6
+    mg.update_links(Ut)
+    print(f"32 links at 256^2: worst relative difference {worst:.2e} (force rms {rms:.3e})", flush=True)

@@ -134,15 +134,20 @@ def test_dwf_full_size_fp64_and_fp32():
     assert err32 < 2e-7
 
 
-def test_dwf_bandwidth_shape_fp32_first_rhs():
+@pytest.mark.parametrize("dagger", [False, True])
+def test_dwf_bandwidth_shape_fp32_every_rhs(dagger):
     """512^2 x Ls 32 x 4 rhs (the stencil-bandwidth workload), FP32; the
-    oracle recomputes the first right-hand side in full."""
+    oracle recomputes every right-hand side in full from the same FP32 inputs."""
     L, Ls, nrhs, m, M5 = 512, 32, 4, 0.01, -1.0
     U = inputs.links_from_theta(inputs.random_theta(L, L, 8_000_000))
     psi = inputs.gaussian_field((nrhs, Ls, L, L, 2), 8_000_001).astype(np.complex64)
-    got = dwfmg.dwf_apply(torch.from_numpy(U.astype(np.complex64)).to(DEV), torch.from_numpy(psi).to(DEV), m, M5)
-    want = O.dwf(U.astype(np.complex64).astype(np.complex128), psi[:1].astype(np.complex128), m, M5)
-    assert rel(got[:1].cpu().numpy().astype(np.complex128), want) < 2e-7
+    got = dwfmg.dwf_apply(torch.from_numpy(U.astype(np.complex64)).to(DEV), torch.from_numpy(psi).to(DEV), m, M5,
+                          dagger=dagger).cpu().numpy()
+    U64 = U.astype(np.complex64).astype(np.complex128)
+    for j in range(nrhs):
+        want = O.dwf(U64, psi[j].astype(np.complex128), m, M5, dagger=dagger)
+        err = rel(got[j].astype(np.complex128), want)
+        assert err < 2e-7, f"rhs {j}: {err:.2e}"
 
 
 @pytest.mark.parametrize("dagger", [False, True])

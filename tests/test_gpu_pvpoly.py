@@ -59,7 +59,7 @@ def test_fine_level_operator_uses_the_polynomial():
     start = inputs.gaussian_field((4, L, L, 2), 731)
     c = dwfmg.pv_poly_chebyshev(2, 1.0, 25.0)
     p = dwfmg.MGParams(nvec=[4], block=[(4, 4)], Ls_coarse=[2], setup_iters=0, fine_prec=dwfmg.P_F64, pv_poly=c)
-    mg = dwfmg.MG(T(U), Ls, m, M5, p, [T(start)])
+    mg = dwfmg.MG(T(U), Ls, m, M5, p, [T(start)], max_nrhs=2)
     x = inputs.gaussian_field((2, Ls, L, L, 2), 732)
     got = mg.level_op(0, dwfmg.MG_OP_A, T(x), 2).cpu().numpy()
     assert rel(got, O.pv_poly_dw(U, x, m, M5, c)) < 1e-13

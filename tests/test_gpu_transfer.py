@@ -37,7 +37,7 @@ def pair(L, Ls, m, levels, seed, transfer, beta=6.0, **kw):
                             Ls_coarse=[l[2] for l in levels], link_prec=[dwfmg.P_F64] * len(levels),
                             vec_prec=[dwfmg.P_F64] * len(levels), fine_prec=dwfmg.P_F64, setup_iters=0, transfer=code,
                             **kw)
-    mg = dwfmg.MG(T(U), Ls, m, -1.0, params, [T(s) for s in starts])
+    mg = dwfmg.MG(T(U), Ls, m, -1.0, params, [T(s) for s in starts], max_nrhs=2)
     op = O.MGParams(levels=[O.LevelParams(nvec=l[0], block=(l[1][1], l[1][0]), Ls=l[2], setup_iters=0)
                             for l in levels], transfer=transfer,
                     smooth_iters=params.smooth_iters, coarsest_tol=params.coarsest_tol,

@@ -308,3 +308,37 @@ def test_kcycle_pin_rejects_mutations(mut):
         cls = {"sign": _MGSmoothSign, "residual": _MGSmoothResidual, "short": _MGSmoothShort}[mut]
         err = kcycle_error(mg_cls=cls)
     assert err > 1e-6
+
+
+# ----------------------------------------------------------------------------- finite differences
+def test_cancellation_free_difference_equals_naive_difference():
+    """The exact two-site source used by the full-size gradient check: with
+    Y_- = D_-^{-dag} phi and D_+^dag Delta = (D_- - D_+)^dag Y_-, where D_- - D_+
+    has the blocks -(1 - gamma_mu)/2 dU (x <- x+mu) and -(1 + gamma_mu)/2 dU^*
+    (x+mu <- x), dU = -2i sin(h) U_l, the difference S_+ - S_- equals
+    Re <Delta, 2 Y_- + Delta> and the naive |Y_+|^2 - |Y_-|^2 (dense solves,
+    4 x 4 x Ls 4, h = 1e-3 so that the naive difference is not lost to rounding)."""
+    L, Ls, m, M5, h = 4, 4, 0.05, -1.0, 1e-3
+    g = inputs.metropolis_u1(L, L, 3.0, 10, 17)
+    phi = cgauss((Ls, L, L, 2), 18)
+    shape = (Ls, L, L, 2)
+    for mu, y, x in ((0, 1, 3), (1, 3, 2), (0, 0, 0)):
+        Um, Up = g.U.copy(), g.U.copy()
+        Um[mu, y, x] *= np.exp(-1j * h)
+        Up[mu, y, x] *= np.exp(1j * h)
+        Dm = O.assemble(lambda v: O.dwf(Um, v, m, M5), shape)
+        Dp = O.assemble(lambda v: O.dwf(Up, v, m, M5), shape)
+        Ym = np.linalg.solve(Dm.conj().T, phi.reshape(-1))
+        Yp = np.linalg.solve(Dp.conj().T, phi.reshape(-1))
+        naive = float(np.vdot(Yp, Yp).real - np.vdot(Ym, Ym).real)
+        Ymf = Ym.reshape(shape)
+        dU = -2j * np.sin(h) * g.U[mu, y, x]
+        yn, xn = (y, (x + 1) % L) if mu == 0 else ((y + 1) % L, x)
+        src = np.zeros(shape, dtype=np.complex128)
+        src[:, yn, xn] = O.spin_mul(-0.5 * (O.IDENT2 - O.GAMMA[mu]) * np.conj(dU), Ymf[:, y, x])
+        src[:, y, x] = O.spin_mul(-0.5 * (O.IDENT2 + O.GAMMA[mu]) * dU, Ymf[:, yn, xn])
+        # the source is the dense (D_- - D_+)^dag Y_- exactly
+        assert np.max(np.abs(src.reshape(-1) - (Dm - Dp).conj().T @ Ym)) < 1e-15
+        Dl = np.linalg.solve(Dp.conj().T, src.reshape(-1))
+        free = float(np.vdot(Dl, 2 * Ym + Dl).real)
+        assert abs(free - naive) <= 1e-9 * abs(naive)
