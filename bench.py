@@ -92,45 +92,103 @@ def stored_traffic(kernel_src, algorithmic_bytes, summary="coarse_stencil_traffi
     return d.get("bytes_per_launch")
 
 
+def _oracle_unit_costs(O, inputs, U_np, L, Ls, m, M5, nv, block, Lsc):
+    """Seconds of one oracle D_DW apply on the fine lattice and one on the coarse
+    lattice of a hierarchy of this shape (prolongator from Gaussian vectors)."""
+    psi = inputs.gaussian_field((Ls, L, L, 2), 1)
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        O.dwf(U_np, psi, m, M5)
+    t_fine = (time.perf_counter() - t0) / reps
+    bx, by = block
+    V = inputs.gaussian_field((L, L, 2, 1, nv), 2)
+    P = O.Prolongator(V=O.block_orthonormalize(V, (by, bx)), block=(by, bx))
+    S = O.galerkin(O.wilson_stencil(U_np), P)
+    ec = inputs.gaussian_field((Lsc, L // by, L // bx, 2 * nv), 3)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        O.stencil_dwf(S, ec, m, M5)
+    t_coarse = (time.perf_counter() - t0) / reps
+    return t_fine, t_coarse
+
+
 def cpu_baseline(wl, stats, U_np, coarsest):
-    """The oracle, untuned, on the host: unit costs of its operator applications
-    on the same lattice and hierarchy shape, combined with the operation counts
-    of one GPU solve (a lower bound on the oracle's solve time: the Krylov
-    vector algebra is not counted)."""
+    """The oracle, untuned, on the host.
+
+    A whole oracle solve at the metric size does not fit a bounded sample (its
+    setup alone relaxes 16 null vectors for 250 CG steps at 256^2), so the
+    figure is a calibrated model:
+      1. a real oracle multigrid solve, timed end to end (setup excluded, as on
+         the GPU), at 32^2 x Ls 8 (beta 6, m 0.01; 4x4 aggregates, 8 null
+         vectors, coarse Ls 4, the paper's K-cycle with coarsest CGNR), with its
+         fine and coarse D_DW applications counted;
+      2. the model (applications x the oracle's unit cost per application) at
+         that size, and the ratio actual / model (the vector algebra and the
+         interpreter overhead the model leaves out);
+      3. at the metric size: the GPU solve's application counts x the oracle's
+         unit costs at 256^2 x 16 (fine) and 64^2 x 2 x 32 dof (coarse), times
+         that ratio.
+    Steps 1-3 run with the host's default thread pool and again on one thread."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import dwf_oracle as O
     from paper_2004_07732_amd import inputs
 
-    L, Ls, m, M5 = wl["L"], wl["Ls"], wl["m"], wl["M5"]
-    with threadpool_limits(limits=1):
-        psi = inputs.gaussian_field((Ls, L, L, 2), 1)
-        t0 = time.perf_counter()
-        reps = 2
-        for _ in range(reps):
-            O.pv_dag_dw(U_np, psi, m, M5)
-        tA = (time.perf_counter() - t0) / reps
-        # coarse operator of the same shape (prolongator from Gaussian vectors)
-        nv, (bx, by), Lsc = wl["nvec"][0], wl["block"][0], wl["Ls_coarse"][0]
-        V = inputs.gaussian_field((L, L, 2, 1, nv), 2)
-        P = O.Prolongator(V=O.block_orthonormalize(V, (by, bx)), block=(by, bx))
-        S = O.galerkin(O.wilson_stencil(U_np), P)
-        ec = inputs.gaussian_field((Lsc, L // by, L // bx, 2 * nv), 3)
-        t0 = time.perf_counter()
-        O.stencil_dwf(S, O.stencil_dwf(S, ec, m, M5), 1.0, M5, dagger=True)
-        tAc = time.perf_counter() - t0
-    fine_A = stats.fine_applies / 2.0
     if len(wl["nvec"]) != 1:
         return None
+    L, Ls, m, M5 = wl["L"], wl["Ls"], wl["m"], wl["M5"]
+    nv, block, Lsc = wl["nvec"][0], wl["block"][0], wl["Ls_coarse"][0]
+    # the GPU solve's counts: fine D_DW-type applications, coarse D_DW-type applications
+    # (one coarsest GCR iteration applies A-hat = D_PV-hat^dag D_DW-hat: two; CGNR: four, plus
+    # one A-hat^dag per call)
+    fine_D = float(stats.fine_applies)
     if coarsest["coarsest_solver"] == 0:
-        # one CGNR iteration applies A and A^dagger; each call adds one A^dagger
-        coarse_A = 2.0 * stats.level_iters[0] + stats.level_calls[0]
+        coarse_D = 4.0 * stats.level_iters[0] + 2.0 * stats.level_calls[0]
     else:
-        # one GCR iteration applies A (from a zero start; restarts continue from the recursive residual)
-        coarse_A = float(stats.level_iters[0])
-    t_solve = fine_A * tA + coarse_A * tAc
-    # the oracle's D_DW bandwidth by the stencil byte formula (FP64: vector read and written, links once)
+        coarse_D = 2.0 * stats.level_iters[0]
+    # calibration problem (config 1 of the scope table)
+    Lc, Lsc1, mc = 32, 8, 0.01
+    gc = inputs.metropolis_u1(Lc, Lc, 6.0, 200, inputs.gauge_seed(1, Lc))
+    bc = inputs.gaussian_field((Lsc1, Lc, Lc, 2), inputs.rhs_seed(1, Lc, 0))
+    startc = [inputs.gaussian_field((8, Lc, Lc, 2), inputs.null_start_seed(1, 0))]
+
+    def run(threads):
+        lim = {} if threads is None else {"limits": threads}
+        with threadpool_limits(**lim):
+            used = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+            mg = O.MG(gc.U, Lsc1, mc, M5, O.MGParams(levels=[O.LevelParams(nvec=8, block=(4, 4), Ls=4)]), startc)
+            counts = {"fine": 0, "coarse": 0}
+            dwf0, sdwf0 = O.dwf, O.stencil_dwf
+
+            def dwf_c(*a, **k):
+                counts["fine"] += 1
+                return dwf0(*a, **k)
+
+            def sdwf_c(*a, **k):
+                counts["coarse"] += 1
+                return sdwf0(*a, **k)
+            O.dwf, O.stencil_dwf = dwf_c, sdwf_c
+            try:
+                t0 = time.perf_counter()
+                xc, _ = mg.solve(bc, 1e-10)
+                t_actual = time.perf_counter() - t0
+            finally:
+                O.dwf, O.stencil_dwf = dwf0, sdwf0
+            res = float(np.linalg.norm(bc - O.dwf(gc.U, xc, mc, M5)) / np.linalg.norm(bc))
+            tf1, tc1 = _oracle_unit_costs(O, inputs, gc.U, Lc, Lsc1, mc, M5, 8, (4, 4), 4)
+            model1 = counts["fine"] * tf1 + counts["coarse"] * tc1
+            ratio = t_actual / model1
+            tf, tc = _oracle_unit_costs(O, inputs, U_np, L, Ls, m, M5, nv, block, Lsc)
+            t_solve = (fine_D * tf + coarse_D * tc) * ratio
+            return {"threads": used, "solves_per_s": 1.0 / t_solve, "t_solve_s": t_solve,
+                    "calibration": {"actual_s": t_actual, "model_s": model1, "ratio": ratio, "residual": res,
+                                    "fine_applies": counts["fine"], "coarse_applies": counts["coarse"]},
+                    "unit_s": {"fine_dw": tf, "coarse_dw": tc}}
+
+    all_threads = run(None)
+    one_thread = run(1)
     d_bytes = 2 * Ls * L * L * 2 * 16 + 2 * L * L * 16
     cpu_model = None
     try:
@@ -138,31 +196,40 @@ def cpu_baseline(wl, stats, U_np, coarsest):
             cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
     except OSError:
         pass
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+    a = all_threads
+    return {"value": a["solves_per_s"], "unit": "solves/s", "cores": a["threads"], "kind": "oracle",
             "cpu_model": cpu_model, "host_cpus": os.cpu_count(),
-            "oracle_dw_GB_s": 2 * d_bytes / tA / 1e9,
-            "sample": (f"oracle unit costs on the host: D_PV^dag D_DW at {L}^2 x {Ls} = {tA:.3f} s, "
-                       f"coarse hat-A at {L // bx}^2 x {Lsc} x {2 * nv} dof = {tAc:.3f} s; "
-                       f"times the counts of one GPU solve ({fine_A:.0f} fine A, {coarse_A:.0f} coarse A); "
-                       f"Krylov vector algebra not counted")}
+            "oracle_dw_GB_s": d_bytes / a["unit_s"]["fine_dw"] / 1e9,
+            "one_thread": {"value": one_thread["solves_per_s"], "calibration": one_thread["calibration"]},
+            "calibration": a["calibration"], "unit_s": a["unit_s"],
+            "sample": (f"a real oracle MG solve at 32^2 x 8 (4x4 aggregates, 8 null vectors, coarse Ls 4, "
+                       f"coarsest CGNR) took {a['calibration']['actual_s']:.2f} s = "
+                       f"{a['calibration']['ratio']:.2f} x its application model; at {L}^2 x {Ls}: "
+                       f"{fine_D:.0f} fine and {coarse_D:.0f} coarse D_DW applications of the GPU solve x the "
+                       f"oracle's unit costs ({a['unit_s']['fine_dw']:.3f} s, {a['unit_s']['coarse_dw']:.4f} s) "
+                       f"x that ratio = {a['t_solve_s']:.0f} s per solve")}
 
 
-def coarse_stencil_bytes(nsites, n, Ls_c, ncol, link_bytes, vec_bytes):
-    """Algorithmic bytes of one coarse D_DW launch: per coarse site the site term
-    and the two forward hops of the links (the backward hops are the
-    sigma_3-adjoints of the neighbours' forward hops), and every vector entry read
-    once and written once."""
-    return nsites * (3 * n * n * link_bytes + 2 * Ls_c * ncol * n * vec_bytes)
+def coarse_stencil_bytes(nsites, n, Ls_c, ncol, link_bytes, vec_bytes, link_blocks=5):
+    """Algorithmic bytes of one coarse D_DW launch: per coarse site the five
+    (2 nvec)^2 link blocks of the stencil (site term and four hops) once, and
+    every vector entry read once and written once.  With link_blocks = 3: the
+    bytes the kernel stores and reads from memory (the site term and the two
+    forward hops; the backward hops are the sigma_3-adjoints of the neighbours'
+    forward hops, re-read through the caches)."""
+    return nsites * (link_blocks * n * n * link_bytes + 2 * Ls_c * ncol * n * vec_bytes)
 
 
-def coarse_mfma_per_launch(nsites, n, Ls_c, ncol):
+def coarse_mfma_per_launch(nsites, n, Ls_c, ncol, tw=None):
     """Matrix-core products (16x16x32, BF16) one coarse launch issues.  A wave owns
     16 output rows of one site and a tile of up to TW (slice, column) pairs (TW = 2,
-    4 or 8 by Ls_c * ncol; several tiles only at TW = 8); per tile it issues one
-    product per 16 complex inner entries of the five blocks and per half (hi, lo)
-    of the split vector."""
+    4 or 8; by default the heuristic one for Ls_c * ncol; several tiles only at
+    TW = 8, whichever workgroups take them); per tile it issues one product per 16
+    complex inner entries of the five blocks and per half (hi, lo) of the split
+    vector."""
     C = Ls_c * ncol
-    tw = 2 if C <= 2 else (4 if C <= 4 else 8)
+    if tw is None:
+        tw = 2 if C <= 2 else (4 if C <= 4 else 8)
     ntile = 1 if tw < 8 else -(-C // 8)
     return nsites * (n // 16) * ntile * 2 * (5 * n // 16)
 
@@ -180,18 +247,29 @@ def solve_model_bytes(fine_applies, coarse_iters, k, L, Ls, coarse_launch_bytes,
 
 
 def timed(mg, b, steps, warmup, tol=1e-10):
-    """Mean seconds of `steps` solves after `warmup` untimed ones (the solve is
-    synchronous: it returns after the true residual is known)."""
+    """Seconds per solve over `steps` solves after `warmup` untimed ones: the
+    mean over the whole bracketed interval and the median of the per-solve
+    times (each solve is synchronous: it returns after the true residual is
+    known).  Returns (mean, median, stats, x)."""
+    import statistics
+
     import torch
-    st = None
+    st = x = None
     for _ in range(warmup):
-        _, st = mg.solve(b, tol)
+        x, st = mg.solve(b, tol)
     torch.cuda.synchronize()
+    times = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        _, st = mg.solve(b, tol)
+        t1 = time.perf_counter()
+        x, st = mg.solve(b, tol)
+        times.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / max(steps, 1), st
+    mean = (time.perf_counter() - t0) / max(steps, 1)
+    return mean, statistics.median(times), st, x
+
+
+ROW_SAMPLES = 5   # timed solves per row beside the headline (median reported)
 
 
 def stats_dict(st):
@@ -240,19 +318,10 @@ def stencil_rows(dwfmg, inputs, torch, m, M5):
             "i_fp32": one(256, 16, 1, torch.complex64, 8_000_001),
             "i_fp64": one(256, 16, 1, torch.complex128, 8_000_002),
             "iii_fp32_16rhs": one(256, 16, 16, torch.complex64, 8_000_003)}
-    # measured peak: device-to-device copy of 2 GiB (read 2 GiB + write 2 GiB)
-    a = torch.ones(2 ** 31 // 4, dtype=torch.float32, device="cuda")
-    c = torch.empty_like(a)
-    for _ in range(3):
-        c.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        c.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * 2 ** 31 / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
-    del a, c
+    # measured copy bandwidth: the library's streaming copy kernel over 2 GiB (read 2 GiB +
+    # write 2 GiB), median of five runs of ten copies
+    copy_gbs = sorted(dwfmg.copy_bandwidth(2 ** 31, 10) for _ in range(5))[2]
+    torch.cuda.empty_cache()
     for r in rows.values():
         r["frac_nominal"] = r["GB_s"] / PEAK_HBM_GBS
         r["frac_measured_copy"] = r["GB_s"] / copy_gbs
@@ -363,7 +432,8 @@ def main():
     # ---------------------------------------------------------------- headline: mixed precision, 1 rhs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True, args.nev, **head), starts)
+    mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True, args.nev, **head), starts,
+                  max_nrhs=1 if args.quick else 16)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"[bench] setup {setup_s:.2f} s")
@@ -371,26 +441,39 @@ def main():
         di = mg.deflation_info()
         log(f"[bench] deflation: nev {di['nev']}, {di['iters']} Lanczos steps, worst residual "
             f"{di['worst_residual']:.1e}, lambda {di['lambdas'][0]:.3e} .. {di['lambdas'][-1]:.3e}")
-    t_step, stats = timed(mg, b, args.steps, args.warmup)
+    t_step, t_median, stats, x_head = timed(mg, b, args.steps, args.warmup)
     mixed_sps = 1.0 / t_step
-    log(f"[bench] headline: {t_step * 1e3:.1f} ms/solve, residual {stats.true_rel_residual:.2e}, "
-        f"fine iters {stats.fine_iters}, coarse iters {stats.level_iters} calls {stats.level_calls}")
+    log(f"[bench] headline: {t_step * 1e3:.1f} ms/solve (median {t_median * 1e3:.1f}), residual "
+        f"{stats.true_rel_residual:.2e}, fine iters {stats.fine_iters}, coarse iters {stats.level_iters} "
+        f"calls {stats.level_calls}")
+    # the last timed solution's true residual, recomputed by the oracle's FP64 operator
+    oracle_residual = None
+    if not args.no_cpu_baseline:
+        from oracle import dwf_oracle as O
+        bn, xn = b[0].cpu().numpy(), x_head[0].cpu().numpy()
+        oracle_residual = float(np.linalg.norm(bn - O.dwf(g.U, xn, m, M5)) / np.linalg.norm(bn))
+        log(f"[bench] headline residual recomputed by the oracle: {oracle_residual:.2e}")
 
     # ---------------------------------------------------------------- dominant kernel: coarse stencil
     c = mg.info(1)
     xin = torch.from_numpy(inputs.gaussian_field((1, c["Ls"], c["Ly"], c["Lx"], c["n"]), 5)).cuda()
-    t_coarse_ms = mg.time_op(1, dwfmg.MG_OP_DW, xin, 1, iters=200)
+    # median of five runs of 200 back-to-back launches (HIP events on the stream they run on)
+    t_coarse_ms = sorted(mg.time_op(1, dwfmg.MG_OP_DW, xin, 1, iters=200) for _ in range(5))[2]
     n, nsites, Lsc = c["n"], c["Lx"] * c["Ly"], c["Ls"]
     link_bytes = 4  # bfloat16 complex
     vec_bytes = 16 if make_params(dwfmg, wl, True).vec_prec[0] == dwfmg.P_F64 else 8
     coarse_bytes = coarse_stencil_bytes(nsites, n, Lsc, 1, link_bytes, vec_bytes)
+    stored_bytes = coarse_stencil_bytes(nsites, n, Lsc, 1, link_bytes, vec_bytes, link_blocks=3)
     achieved = coarse_bytes / (t_coarse_ms * 1e-3) / 1e9
-    traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse_mfma.hip"), coarse_bytes)
-    log(f"[bench] coarse stencil {t_coarse_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
+    traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse_mfma.hip"), stored_bytes)
+    log(f"[bench] coarse stencil {t_coarse_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic (5 link blocks), "
+        f"{stored_bytes / (t_coarse_ms * 1e-3) / 1e9:.0f} GB/s on the 3 stored blocks")
+    tw, tpb = None, None
     mfma_per_launch = coarse_mfma_per_launch(nsites, n, Lsc, 1)
     issued_tf = mfma_per_launch * 16 * 16 * 32 * 2 / (t_coarse_ms * 1e-3) / 1e12
     useful_tf = nsites * Lsc * 5 * n * n * 8 / (t_coarse_ms * 1e-3) / 1e12
-    coarse_mfma = {"mfma_per_launch": mfma_per_launch, "issued_TFLOP_s": issued_tf,
+    coarse_mfma = {"tile_width": tw, "tiles_per_workgroup": tpb, "mfma_per_launch": mfma_per_launch,
+                   "issued_TFLOP_s": issued_tf,
                    "algorithmic_TFLOP_s": useful_tf, "peak_bf16_TFLOP_s": PEAK_BF16_TFLOPS,
                    "frac_issued": issued_tf / PEAK_BF16_TFLOPS, "frac_algorithmic": useful_tf / PEAK_BF16_TFLOPS}
     solve_bytes = (solve_model_bytes(stats.fine_applies, stats.level_iters[0], args.coarsest_restart, L, Ls,
@@ -409,8 +492,9 @@ def main():
         # 16 right-hand sides in one solve on the same hierarchy
         b16 = torch.from_numpy(np.stack([inputs.gaussian_field((Ls, L, L, 2), inputs.rhs_seed(wl["cfg"], L, j))
                                          for j in range(16)])).cuda()
-        t16, st16 = timed(mg, b16, 1, 1)
-        rows["batched_16rhs"] = {"solves_per_s": 16.0 / t16, "ms_per_batch": t16 * 1e3, **stats_dict(st16)}
+        _, t16, st16, _ = timed(mg, b16, ROW_SAMPLES, 1)
+        rows["batched_16rhs"] = {"solves_per_s": 16.0 / t16, "ms_per_batch": t16 * 1e3, "samples": ROW_SAMPLES,
+                                 **stats_dict(st16)}
         log(f"[bench] 16 rhs: {t16 * 1e3:.1f} ms per batch, {16.0 / t16:.3f} solves/s, "
             f"residual {st16.true_rel_residual:.2e}")
         del b16
@@ -419,9 +503,9 @@ def main():
     if not args.quick:
         def variant(name, wlv, **kw):
             mgv = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wlv, True, **kw), null_starts(inputs, wlv, torch))
-            tv, stv = timed(mgv, b, 1, 1)
-            rows[name] = {"solves_per_s": 1.0 / tv, "mg": {"nvec": wlv["nvec"], "block": wlv["block"],
-                                                          "Ls_coarse": wlv["Ls_coarse"]},
+            _, tv, stv, _ = timed(mgv, b, ROW_SAMPLES, 1)
+            rows[name] = {"solves_per_s": 1.0 / tv, "samples": ROW_SAMPLES,
+                          "mg": {"nvec": wlv["nvec"], "block": wlv["block"], "Ls_coarse": wlv["Ls_coarse"]},
                           "coarsest": {k: v for k, v in kw.items() if k.startswith("coarsest")}, **stats_dict(stv)}
             if kw.get("pv_poly") is not None:
                 rows[name]["pv_poly"] = list(kw["pv_poly"])
@@ -444,13 +528,16 @@ def main():
         # the paper's solver comparison: Krylov solves of the same system without multigrid (FP64)
         bf = b[0].contiguous()
         for name, meth, ell in (("krylov_cgnr", dwfmg.KRYLOV_CGNR, 0), ("krylov_bicgstab6", dwfmg.KRYLOV_BICGSTAB, 6)):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, sk = dwfmg.dwf_krylov_solve(U, bf, m, M5, method=meth, ell=max(ell, 1), tol=1e-10, maxit=200000,
-                                           check=False)
-            tk = time.perf_counter() - t0
-            rows[name] = {"solves_per_s": 1.0 / tk, "iterations": sk.fine_iters, "fine_applies": sk.fine_applies,
-                          "residual": sk.true_rel_residual, "status": sk.status}
+            tks = []
+            for _ in range(ROW_SAMPLES):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, sk = dwfmg.dwf_krylov_solve(U, bf, m, M5, method=meth, ell=max(ell, 1), tol=1e-10, maxit=200000,
+                                               check=False)
+                tks.append(time.perf_counter() - t0)
+            tk = sorted(tks)[len(tks) // 2]
+            rows[name] = {"solves_per_s": 1.0 / tk, "samples": ROW_SAMPLES, "iterations": sk.fine_iters,
+                          "fine_applies": sk.fine_applies, "residual": sk.true_rel_residual, "status": sk.status}
             log(f"[bench] {name}: {tk * 1e3:.1f} ms, {sk.fine_iters} iterations, {sk.fine_applies} applications, "
                 f"residual {sk.true_rel_residual:.2e}")
 
@@ -458,8 +545,8 @@ def main():
     fp64 = None
     if not args.no_fp64 and not args.quick:
         mg64 = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, False, **head), starts)
-        t64, st64 = timed(mg64, b, 1, 1)
-        fp64 = {"solves_per_s": 1.0 / t64, **stats_dict(st64)}
+        _, t64, st64, _ = timed(mg64, b, ROW_SAMPLES, 1)
+        fp64 = {"solves_per_s": 1.0 / t64, "samples": ROW_SAMPLES, **stats_dict(st64)}
         log(f"[bench] fp64 solve {t64 * 1e3:.1f} ms")
         mg64.close()
 
@@ -472,6 +559,7 @@ def main():
     if not args.no_cpu_baseline and not args.quick:
         log("[bench] timing the oracle on the host")
         cpu = cpu_baseline(wl, stats, g.U, head)
+        log(f"[bench] oracle baseline: {json.dumps(cpu)}")
 
     res = {
         "metric": METRIC,
@@ -481,6 +569,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 / mixed_sps,
+        "median_ms_per_step": t_median * 1e3,
+        "oracle_residual": oracle_residual,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -496,7 +586,10 @@ def main():
                                 "outer defect correction FP64"},
         "roofline": {"bound": "hbm", "kernel": "coarse_mfma_kernel (coarse D_DW apply, level 1)",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": traffic, "algorithmic_bytes": coarse_bytes, "us_per_launch": t_coarse_ms * 1e3},
+                     "traffic": traffic, "algorithmic_bytes": coarse_bytes, "us_per_launch": t_coarse_ms * 1e3,
+                     "stored_bytes": stored_bytes,
+                     "frac_stored_bytes": stored_bytes / (t_coarse_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     "frac_counter_bytes": (traffic / (t_coarse_ms * 1e-3) / 1e9 / PEAK_HBM_GBS) if traffic else None},
         "cpu_baseline": cpu,
         "coarse_mfma": coarse_mfma,
         "solve_roofline": solve_roofline,

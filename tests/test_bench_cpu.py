@@ -21,11 +21,14 @@ def test_more_than_one_gpu_is_refused_before_any_device_work():
 
 
 def test_coarse_launch_bytes_worked_example():
-    # links: 3 blocks of 32 x 32 BF16 complex (4 B) = 12 288 B per site; vectors:
-    # 2 slices x 32 FP64 complex (16 B), read and written = 2 048 B per site
-    assert bench.coarse_stencil_bytes(4096, 32, 2, 1, 4, 16) == 4096 * (12288 + 2048) == 58_720_256
+    # links by the per-site figure of the coarse stencil: 5 blocks of 32 x 32 BF16
+    # complex (4 B) = 20 480 B per site; vectors: 2 slices x 32 FP64 complex (16 B),
+    # read and written = 2 048 B per site
+    assert bench.coarse_stencil_bytes(4096, 32, 2, 1, 4, 16) == 4096 * (20480 + 2048) == 92_274_688
+    # the 3 blocks the kernel stores (site term, two forward hops): 12 288 B per site
+    assert bench.coarse_stencil_bytes(4096, 32, 2, 1, 4, 16, link_blocks=3) == 4096 * (12288 + 2048) == 58_720_256
     # 16 right-hand sides: the links once, the vectors 16 times
-    assert bench.coarse_stencil_bytes(4096, 32, 2, 16, 4, 16) == 4096 * (12288 + 16 * 2048)
+    assert bench.coarse_stencil_bytes(4096, 32, 2, 16, 4, 16) == 4096 * (20480 + 16 * 2048)
 
 
 def test_coarse_matrix_core_count_worked_example():
