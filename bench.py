@@ -468,8 +468,8 @@ def main():
     traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse_mfma.hip"), stored_bytes)
     log(f"[bench] coarse stencil {t_coarse_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic (5 link blocks), "
         f"{stored_bytes / (t_coarse_ms * 1e-3) / 1e9:.0f} GB/s on the 3 stored blocks")
-    tw, tpb = None, None
-    mfma_per_launch = coarse_mfma_per_launch(nsites, n, Lsc, 1)
+    tw, tpb = mg.coarse_config(1, 1)
+    mfma_per_launch = coarse_mfma_per_launch(nsites, n, Lsc, 1, tw)
     issued_tf = mfma_per_launch * 16 * 16 * 32 * 2 / (t_coarse_ms * 1e-3) / 1e12
     useful_tf = nsites * Lsc * 5 * n * n * 8 / (t_coarse_ms * 1e-3) / 1e12
     coarse_mfma = {"tile_width": tw, "tiles_per_workgroup": tpb, "mfma_per_launch": mfma_per_launch,

@@ -411,6 +411,16 @@ int mg_export(dwf_mg* mg, int level, void* prolongator, void* coarse_kernel, voi
  * order.  DWF_ENOSETUP without a set-up hierarchy. */
 int mg_deflation_info(const dwf_mg* mg, int* nev, int* iters, double* worst_residual, double* lambdas);
 
+/* Launch configuration of level l's matrix-core coarse stencil (l >= 1, BF16 or
+ * FP16 links with 2 nvec a multiple of 16) for ncol right-hand sides: the tile
+ * width (2, 4 or 8 (slice, rhs) columns per matrix-core tile) and the tiles one
+ * workgroup processes.  The library times the candidates at the first solve
+ * with ncol columns (DWF_AUTOTUNE=0: the heuristic, the narrowest tile that holds
+ * every column and all tiles in one workgroup); before that this reports the
+ * heuristic.  The choice never changes a result.  DWF_EUNSUPPORTED for a level
+ * without the matrix-core path. */
+int mg_coarse_config(const dwf_mg* mg, int level, int ncol, int dagger, int* tile_width, int* tiles_per_block);
+
 /* Geometry of level l: fills Lx, Ly, Ls, dof per site and nvec (0 on the coarsest). */
 int mg_level_info(const dwf_mg* mg, int level, int* Lx, int* Ly, int* Ls, int* n, int* nvec);
 

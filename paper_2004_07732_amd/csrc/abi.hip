@@ -431,19 +431,34 @@ int mg_solve_batch(int nctx, dwf_mg* const* ctx, const void* const* b, void* con
     }
     // every context starts after the caller's queued work
     if (hipStreamSynchronize(S(stream)) != hipSuccess) return DWF_EHIP;
+    // one host thread keeps every solve in flight: each runs on its context's
+    // stream until it needs scalars back on the host, and is resumed once that
+    // stream has caught up, while the other contexts' work proceeds on the GPU
     std::vector<int> codes(nctx, DWF_OK);
     std::vector<dwf_solve_stats> st(nctx);
-    std::vector<std::thread> workers;
-    workers.reserve(nctx);
+    std::vector<Task> tasks(nctx);
     for (int i = 0; i < nctx; ++i) {
-        workers.emplace_back([&, i]() {
-            std::memset(&st[i], 0, sizeof(st[i]));
-            codes[i] = ctx[i]->h.solve((const cpx<double>*)b[i], (cpx<double>*)x[i], nrhs[i], tol, flags, &st[i],
-                                       ctx[i]->h.stream());
-            st[i].status = codes[i];
-        });
+        std::memset(&st[i], 0, sizeof(st[i]));
+        ctx[i]->h.set_batch(true);
+        tasks[i] = ctx[i]->h.solve_task((const cpx<double>*)b[i], (cpx<double>*)x[i], nrhs[i], tol, flags, &st[i],
+                                        ctx[i]->h.stream());
+        tasks[i].start();
     }
-    for (auto& t : workers) t.join();
+    for (;;) {
+        bool all_done = true, progressed = false;
+        for (int i = 0; i < nctx; ++i) {
+            if (tasks[i].done()) continue;
+            all_done = false;
+            if (ctx[i]->h.poll()) progressed = true;
+        }
+        if (all_done) break;
+        if (!progressed) std::this_thread::yield();
+    }
+    for (int i = 0; i < nctx; ++i) {
+        ctx[i]->h.set_batch(false);
+        codes[i] = tasks[i].result();
+        st[i].status = codes[i];
+    }
     int worst = DWF_OK;
     for (int i = 0; i < nctx; ++i) {
         if (stats) stats[i] = st[i];
@@ -504,6 +519,12 @@ int mg_time_op(dwf_mg* mg, int level, int op, const void* in, int ncol, int iter
 int mg_export(dwf_mg* mg, int level, void* prolongator, void* coarse_kernel, void* stream) {
     if (!mg || !mg->ready) return DWF_ENOSETUP;
     return mg->h.export_level(level, (cpx<double>*)prolongator, (cpx<double>*)coarse_kernel, S(stream));
+}
+
+int mg_coarse_config(const dwf_mg* mg, int level, int ncol, int dagger, int* tile_width, int* tiles_per_block) {
+    if (!mg || !mg->ready) return DWF_ENOSETUP;
+    if (!tile_width || !tiles_per_block) return DWF_EINVAL;
+    return mg->h.coarse_config(level, ncol, dagger != 0, tile_width, tiles_per_block);
 }
 
 int mg_level_info(const dwf_mg* mg, int level, int* Lx, int* Ly, int* Ls, int* n, int* nvec) {

@@ -48,7 +48,12 @@
 // corners, eq. coarsenDW) and sigma_3 for the adjoint (hat-D_W^dagger =
 // sigma_3 hat-D_W sigma_3) are applied in the epilogue.
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -102,7 +107,7 @@ template <bool F16, typename T, int N, bool DAG, int TW>
 __global__ void __launch_bounds__(256)
 coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                    const int* __restrict__ skip, int sks, int Lx, int Ly, int Ls, int nsites, int ncol,
-                   float cdiag, float mwrap) {
+                   float cdiag, float mwrap, int tpb) {
     using HF = Half<F16>;
     constexpr int MT = N / 16;                    // row tiles = waves per site
     constexpr int SPB = 1;                        // sites per block (measured: one is best)
@@ -208,8 +213,11 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
     // then the tile loop is straight-line code (a loop would make the compiler wait
     // for the link loads at its head, before the first staging load is issued)
     const int ntile = (TW < 8) ? 1 : (C + TW - 1) / TW;
+    // tiles tpb * blockIdx.y .. of this workgroup (with TW < 8 the one tile)
+    const int t_lo = (TW < 8) ? 0 : (int)blockIdx.y * tpb;
+    const int t_hi = (TW < 8) ? 1 : min(ntile, t_lo + tpb);
     const int tid_in_site = threadIdx.x - sl * MT * 64;
-    for (int t = 0; t < ntile; ++t) {
+    for (int t = t_lo; t < t_hi; ++t) {
         const int cbase = TW * t;
         // live columns of the tile: lanes c8 < TW read one flag each, a ballot
         // makes the mask (the same for the whole wavefront).  Issued first, so
@@ -390,40 +398,126 @@ namespace {
 
 template <bool F16, typename T, int N>
 hipError_t launch_n(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol, double m,
-                    double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
+                    double M5, bool dagger, const int* skip, int sks, int tw, int tpb, hipStream_t st) {
     constexpr int MT = N / 16;
     constexpr int SPB = 1;
     const int nsites = g.Lx * g.Ly;
-    dim3 grid((nsites + SPB - 1) / SPB), block(64 * MT * SPB);
+    const int C = g.Ls * ncol;
+    if ((tw == 2 && C > 2) || (tw == 4 && C > 4) || (tw != 2 && tw != 4 && tw != 8) || tpb < 1)
+        return hipErrorInvalidValue;
+    const int ntile = (tw < 8) ? 1 : (C + tw - 1) / tw;
+    const int gy = (tw < 8) ? 1 : (ntile + tpb - 1) / tpb;
+    dim3 grid((nsites + SPB - 1) / SPB, gy), block(64 * MT * SPB);
     const u32x4* lk = reinterpret_cast<const u32x4*>(links);
     const float cd = (float)(M5 + 1.0), mw = (float)(-m);
     // the kernel indexes the vectors and links with 32-bit offsets
     const double vec_bytes = (double)g.Ls * ncol * nsites * N * sizeof(cpx<T>);
     const double link_bytes = (double)nsites * 3 * N * N * 4;
     if (vec_bytes >= 4294967296.0 || link_bytes >= 4294967296.0) return hipErrorInvalidValue;
-    if (g.Ls * ncol <= 2) {   // one tile of 2 columns (one right-hand side on 2 coarse slices)
-        if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true, 2>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
-        else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, false, 2>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
-    } else if (g.Ls * ncol <= 4) {   // one tile of 4 columns
-        if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true, 4>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
-        else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, false, 4>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
-    } else {
-        if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true, 8>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
-        else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, false, 8>), grid, block, 0, st, lk, in, out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw);
-    }
+#define DWF_COARSE_LAUNCH(TWV)                                                                                        \
+    do {                                                                                                              \
+        if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true, TWV>), grid, block, 0, st, lk, in, out,   \
+                                       skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw, tpb);                       \
+        else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, false, TWV>), grid, block, 0, st, lk, in, out,  \
+                                       skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw, tpb);                       \
+    } while (0)
+    if (tw == 2) DWF_COARSE_LAUNCH(2);        // one tile of 2 columns (one rhs on 2 coarse slices)
+    else if (tw == 4) DWF_COARSE_LAUNCH(4);   // one tile of 4 columns
+    else DWF_COARSE_LAUNCH(8);                // tiles of 8 columns, tpb of them per workgroup
+#undef DWF_COARSE_LAUNCH
     return hipGetLastError();
 }
 
 template <bool F16, typename T>
 hipError_t launch_p(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol, double m,
-                    double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
+                    double M5, bool dagger, const int* skip, int sks, int tw, int tpb, hipStream_t st) {
     switch (g.n) {
-        case 16: return launch_n<F16, T, 16>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
-        case 32: return launch_n<F16, T, 32>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
-        case 48: return launch_n<F16, T, 48>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
-        case 64: return launch_n<F16, T, 64>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
+        case 16: return launch_n<F16, T, 16>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
+        case 32: return launch_n<F16, T, 32>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
+        case 48: return launch_n<F16, T, 48>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
+        case 64: return launch_n<F16, T, 64>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// Launch configuration (tile width TW, tiles per workgroup) chosen by timing the
+// candidates once per coarse shape, column count, precisions and adjoint flag,
+// as the fine stencil's is (DWF_AUTOTUNE=0 keeps the heuristic).  The heuristic:
+// the narrowest tile that holds every column, all tiles in one workgroup.
+// Every configuration evaluates each output with the same arithmetic in the same
+// order, so the choice never changes a result.
+constexpr int kTpbStride = 1024;
+inline int pack_cfg(int tw, int tpb) { return tw * kTpbStride + tpb; }
+inline int heuristic_cfg(int C) {
+    const int tw = C <= 2 ? 2 : (C <= 4 ? 4 : 8);
+    return pack_cfg(tw, tw < 8 ? 1 : (C + 7) / 8);
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+
+std::string tune_key(bool f16, size_t tsz, const CoarseGeom& g, int ncol, bool dagger) {
+    char k[128];
+    std::snprintf(k, sizeof k, "coarse_mfma/%d/%zu/%d/%d/%d/%d/%d/%d", f16 ? 1 : 0, tsz, g.n, g.Lx, g.Ly, g.Ls, ncol,
+                  dagger ? 1 : 0);
+    return k;
+}
+
+template <bool F16, typename T>
+int choose_cfg(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol, double m, double M5,
+               bool dagger, hipStream_t st) {
+    const int C = g.Ls * ncol;
+    const int heur = heuristic_cfg(C);
+    const char* en = std::getenv("DWF_AUTOTUNE");
+    if (en && en[0] == '0') return heur;
+    const std::string key = tune_key(F16, sizeof(T), g, ncol, dagger);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        return it != g_tune_cache.end() ? it->second : heur;
+    }
+    std::lock_guard<std::recursive_mutex> rlk(runtime_mutex());
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) return it->second;
+    std::vector<int> cand;
+    if (C <= 2) cand.push_back(pack_cfg(2, 1));
+    if (C <= 4) cand.push_back(pack_cfg(4, 1));
+    const int ntile8 = (C + 7) / 8;
+    for (int tpb : {ntile8, (ntile8 + 1) / 2, (ntile8 + 3) / 4, 1}) {
+        const int c = pack_cfg(8, tpb);
+        if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    }
+    int best = heur;
+    if (cand.size() > 1) {
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return heur;
+        if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return heur; }
+        float best_t = 1e30f, heur_t = 1e30f;
+        for (int c : cand) {
+            const int tw = c / kTpbStride, tpb = c % kTpbStride;
+            if (launch_p<F16, T>(links, in, out, g, ncol, m, M5, dagger, nullptr, 1, tw, tpb, st) != hipSuccess)
+                continue;
+            float tc = 1e30f;
+            for (int trial = 0; trial < 3; ++trial) {
+                (void)hipEventRecord(e0, st);
+                for (int r = 0; r < 10; ++r)
+                    (void)launch_p<F16, T>(links, in, out, g, ncol, m, M5, dagger, nullptr, 1, tw, tpb, st);
+                (void)hipEventRecord(e1, st);
+                (void)hipEventSynchronize(e1);
+                float t = 0.f;
+                if (hipEventElapsedTime(&t, e0, e1) == hipSuccess && t < tc) tc = t;
+            }
+            if (c == heur) heur_t = tc;
+            if (tc < best_t) { best_t = tc; best = c; }
+        }
+        if (heur_t < 1e30f && heur_t <= 1.03f * best_t) best = heur;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    g_tune_cache[key] = best;
+    return best;
 }
 
 }  // namespace
@@ -435,8 +529,27 @@ bool coarse_mfma_supported(int n, int link_prec) {
 template <typename T>
 hipError_t coarse_apply_mfma(const void* links, int link_prec, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g,
                              int ncol, double m, double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
-    if (link_prec == P_F16) return launch_p<true, T>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
-    return launch_p<false, T>(links, in, out, g, ncol, m, M5, dagger, skip, sks, st);
+    if (link_prec == P_F16) {
+        const int c = choose_cfg<true, T>(links, in, out, g, ncol, m, M5, dagger, st);
+        return launch_p<true, T>(links, in, out, g, ncol, m, M5, dagger, skip, sks, c / kTpbStride, c % kTpbStride, st);
+    }
+    const int c = choose_cfg<false, T>(links, in, out, g, ncol, m, M5, dagger, st);
+    return launch_p<false, T>(links, in, out, g, ncol, m, M5, dagger, skip, sks, c / kTpbStride, c % kTpbStride, st);
+}
+
+bool coarse_mfma_config(int link_prec, int vec_prec, const CoarseGeom& g, int ncol, bool dagger, int* tw, int* tpb) {
+    if (!coarse_mfma_supported(g.n, link_prec)) return false;
+    const size_t tsz = (vec_prec == P_F32) ? sizeof(float) : sizeof(double);
+    const std::string key = tune_key(link_prec == P_F16, tsz, g, ncol, dagger);
+    int c = heuristic_cfg(g.Ls * ncol);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) c = it->second;
+    }
+    *tw = c / kTpbStride;
+    *tpb = c % kTpbStride;
+    return true;
 }
 
 size_t links_fragment16_entries(int nsites, int n) { return (size_t)nsites * 3 * n * n; }

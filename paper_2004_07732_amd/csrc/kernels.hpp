@@ -83,6 +83,9 @@ hipError_t coarse_apply_mfma(const void* links, int link_prec, const cpx<T>* in,
                              int ncol, double m, double M5, bool dagger, const int* skip, int sks, hipStream_t st);
 hipError_t convert_links_fragment16(const cpx<double>* in, void* out, int link_prec, int nsites, int n,
                                     hipStream_t st);
+// launch configuration the matrix-core path uses for this shape (the tuned one
+// once a call has timed it, else the heuristic): tile width and tiles per workgroup
+bool coarse_mfma_config(int link_prec, int vec_prec, const CoarseGeom& g, int ncol, bool dagger, int* tw, int* tpb);
 // complex 16-bit entries of that storage: the site term and the two forward hops
 // (the backward hops are the sigma_3-adjoints of the neighbours' forward hops)
 size_t links_fragment16_entries(int nsites, int n);

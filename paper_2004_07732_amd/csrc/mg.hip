@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
+#include <set>
 
 #include <cstdio>
 #include <cstdlib>
@@ -37,6 +38,16 @@ static void report_hip(hipError_t e, int line) {
         }                                           \
     } while (0)
 
+// the same inside coroutines
+#define CO_HIPCHK(...)                              \
+    do {                                            \
+        hipError_t e_ = (__VA_ARGS__);              \
+        if (e_ != hipSuccess) {                     \
+            report_hip(e_, __LINE__);               \
+            co_return DWF_EHIP;                     \
+        }                                           \
+    } while (0)
+
 namespace {
 template <typename T> inline cpx<T>* C(void* p) { return reinterpret_cast<cpx<T>*>(p); }
 template <typename T> inline const cpx<T>* C(const void* p) { return reinterpret_cast<const cpx<T>*>(p); }
@@ -56,12 +67,25 @@ Hierarchy::~Hierarchy() {
     if (h_int_) (void)hipHostFree(h_int_);
     if (h_cg_) (void)hipHostFree(h_cg_);
     if (ev_in_) (void)hipEventDestroy(ev_in_);
+    if (wait_ev_) (void)hipEventDestroy(wait_ev_);
     if (st_) (void)hipStreamDestroy(st_);
 }
 
 std::recursive_mutex& runtime_mutex() {
     static std::recursive_mutex m;
     return m;
+}
+
+bool Hierarchy::poll() {
+    if (!wait_h_) return false;
+    const hipError_t q = hipEventQuery(wait_ev_);
+    if (q == hipErrorNotReady) return false;
+    if (wait_slot_) *wait_slot_ = q;
+    std::coroutine_handle<> h = wait_h_;
+    wait_h_ = nullptr;
+    wait_slot_ = nullptr;
+    h.resume();
+    return true;
 }
 
 void Hierarchy::clear_graphs() {
@@ -277,7 +301,7 @@ int Hierarchy::alloc_level_work(int l, int ncol) {
 
 // ------------------------------------------------------------ CGNR (coarsest level)
 template <typename T>
-int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st) {
+Task Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st) {
     const Level& L = levels[l];
     LevelWork& w = work_[l];
     const size_t n = L.vec_elems();
@@ -289,24 +313,24 @@ int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st)
     cpx<T>* t = C<T>(w.tmp);
     CgScal* s = w.cg;
     const int* skip = cg_skip(s);
-    HIPCHK(vzero<T>(x, nt, st));
-    HIPCHK(vconvert<T, T>(b, r, nt, st));
-    HIPCHK(apply_Adag<T>(l, r, z, t, ncol, st));
+    CO_HIPCHK(vzero<T>(x, nt, st));
+    CO_HIPCHK(vconvert<T, T>(b, r, nt, st));
+    CO_HIPCHK(apply_Adag<T>(l, r, z, t, ncol, st));
     bool deflated = false;
     if constexpr (std::is_same<T, double>::value) {
         if (def_nev_ > 0 && l == (int)levels.size() - 1) {
             // start from e0 = V Lambda^{-1} V^dag A^dag b; keep |A^dag b| as the reference
-            HIPCHK(norm2<T>(z, n, ncol, def_ref_, rw_, st));
-            if (int e = deflate_guess(l, z, x, ncol, st)) return e;
-            HIPCHK(apply_A<T>(l, x, q, t, ncol, st));
-            HIPCHK(vsub<T>(b, q, r, nt, st));
-            HIPCHK(apply_Adag<T>(l, r, z, t, ncol, st));
+            CO_HIPCHK(norm2<T>(z, n, ncol, def_ref_, rw_, st));
+            if (int e = deflate_guess(l, z, x, ncol, st)) co_return e;
+            CO_HIPCHK(apply_A<T>(l, x, q, t, ncol, st));
+            CO_HIPCHK(vsub<T>(b, q, r, nt, st));
+            CO_HIPCHK(apply_Adag<T>(l, r, z, t, ncol, st));
             deflated = true;
         }
     }
-    HIPCHK(cg_init<T>(z, n, ncol, s, prm.coarsest_tol, rw_, st));
-    if (deflated) HIPCHK(cg_set_ref(s, def_ref_, ncol, st));
-    HIPCHK(vconvert<T, T>(z, p, nt, st));
+    CO_HIPCHK(cg_init<T>(z, n, ncol, s, prm.coarsest_tol, rw_, st));
+    if (deflated) CO_HIPCHK(cg_set_ref(s, def_ref_, ncol, st));
+    CO_HIPCHK(vconvert<T, T>(z, p, nt, st));
     const int maxit = prm.coarsest_maxit;
     int iters = 0;
     // one chunk of CGNR iterations; iterations past convergence or maxit are
@@ -324,12 +348,12 @@ int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st)
     };
     for (int it0 = 0; it0 < maxit; it0 += kCgChunk) {
         if (use_graphs_ && st == st_) {
-            if (int e = run_graph(GraphKey{0, l, ncol, b, x}, st, [&]() { return chunk(kCgChunk); })) return e;
+            if (int e = run_graph(GraphKey{0, l, ncol, b, x}, st, [&]() { return chunk(kCgChunk); })) co_return e;
         } else {
-            if (int e = chunk(kCgChunk)) return e;
+            if (int e = chunk(kCgChunk)) co_return e;
         }
-        HIPCHK(hipMemcpyAsync(h_cg_, s, sizeof(CgScal) * ncol, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        CO_HIPCHK(hipMemcpyAsync(h_cg_, s, sizeof(CgScal) * ncol, hipMemcpyDeviceToHost, st));
+        CO_HIPCHK(co_await sync(st));
         bool all = true;
         for (int c = 0; c < ncol; ++c)
             if (!h_cg_[c].done) all = false;
@@ -340,8 +364,8 @@ int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st)
     cnt_.level_iters[l - 1] += iters;
     cnt_.level_calls[l - 1] += 1;
     for (int c = 0; c < ncol; ++c)
-        if (h_cg_[c].done == 4) return DWF_ENAN;
-    return DWF_OK;
+        if (h_cg_[c].done == 4) co_return DWF_ENAN;
+    co_return DWF_OK;
 }
 
 // ------------------------------------------------------------ restarted GCR (coarsest level)
@@ -355,25 +379,25 @@ int Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st)
 // case.  The host reads the stop flags once per cycle; a cycle is captured once
 // as a HIP graph.
 template <typename T>
-int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol, int maxit, int restart,
+Task Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol, int maxit, int restart,
                          int* iters_out, hipStream_t st) {
     const Level& L = levels[l];
     LevelWork& w = work_[l];
     const size_t n = L.vec_elems();
     const size_t nt = n * ncol;
     const int kmax = std::min(restart, w.kmax);
-    if (kmax < 1) return DWF_EINVAL;
+    if (kmax < 1) co_return DWF_EINVAL;
     cpx<T>* r = C<T>(w.r);
     cpx<T>* P = C<T>(w.P);
     cpx<T>* W = C<T>(w.W);
     cpx<T>* t = C<T>(w.tmp);
     GcrDev& g = w.gcr;
     const double tol2 = tol * tol;
-    HIPCHK(vzero<T>(x, nt, st));
-    HIPCHK((vconvert<T, T>(b, r, nt, st)));
-    HIPCHK((vconvert<T, T>(b, P, nt, st)));   // the first search direction (later cycles: by the residual pass)
-    HIPCHK(norm2<T>(b, n, ncol, g.rr, rw_, st));
-    HIPCHK(gcr_dev_init(ncol, g, st));
+    CO_HIPCHK(vzero<T>(x, nt, st));
+    CO_HIPCHK((vconvert<T, T>(b, r, nt, st)));
+    CO_HIPCHK((vconvert<T, T>(b, P, nt, st)));   // the first search direction (later cycles: by the residual pass)
+    CO_HIPCHK(norm2<T>(b, n, ncol, g.rr, rw_, st));
+    CO_HIPCHK(gcr_dev_init(ncol, g, st));
     // one restart cycle: kmax fused iterations (inner products, then one pass that orthogonalises
     // the new direction and updates the residual; the stop flags alternate between two buffers so
     // that no kernel writes the flags it reads), the solution update, and the restart
@@ -396,27 +420,27 @@ int Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol
     const int max_cycles = std::max(1, (maxit + kmax - 1) / kmax);
     for (int c = 0; c < max_cycles; ++c) {
         if (use_graphs_ && st == st_) {
-            if (int e = run_graph(GraphKey{2, l, ncol, b, x}, st, cycle)) return e;
+            if (int e = run_graph(GraphKey{2, l, ncol, b, x}, st, cycle)) co_return e;
         } else if (int e = cycle()) {
-            return e;
+            co_return e;
         }
-        HIPCHK(hipMemcpyAsync(h_int_, g.stop, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        CO_HIPCHK(hipMemcpyAsync(h_int_, g.stop, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
+        CO_HIPCHK(co_await sync(st));
         bool all = true;
         for (int cc = 0; cc < ncol; ++cc)
             if (h_int_[cc] == 0) all = false;
         if (all) break;
     }
-    HIPCHK(hipMemcpyAsync(h_int_, g.stop, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_int_ + ncol, g.it, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    CO_HIPCHK(hipMemcpyAsync(h_int_, g.stop, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
+    CO_HIPCHK(hipMemcpyAsync(h_int_ + ncol, g.it, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
+    CO_HIPCHK(co_await sync(st));
     int it = 0, status = DWF_OK;
     for (int cc = 0; cc < ncol; ++cc) {
         it = std::max(it, h_int_[ncol + cc]);
         if (h_int_[cc] == 2) status = DWF_ENAN;
     }
     if (iters_out) *iters_out = it;
-    return status;
+    co_return status;
 }
 
 // ------------------------------------------------------------ GCR smoother
@@ -464,37 +488,37 @@ int Hierarchy::smooth(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t s
 
 // ------------------------------------------------------------ K-cycle
 template <typename T>
-int Hierarchy::kcycle(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t st) {
+Task Hierarchy::kcycle(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t st) {
     LevelWork& wn = work_[l + 1];
-    HIPCHK(restrict_to<T>(l, r, wn.rhs, ncol, st));
+    CO_HIPCHK(restrict_to<T>(l, r, wn.rhs, ncol, st));
     int e;
-    if (levels[l + 1].vec_prec == P_F32) e = coarse_solve<float>(l + 1, wn.rhs, wn.x, ncol, st);
-    else e = coarse_solve<double>(l + 1, wn.rhs, wn.x, ncol, st);
-    if (e < 0) return e;
-    HIPCHK(prolong_from<T>(l, wn.x, z, ncol, st));
-    if (work_[l].ksmooth > 0) return smooth<T>(l, r, z, ncol, st);
-    return DWF_OK;
+    if (levels[l + 1].vec_prec == P_F32) e = co_await coarse_solve<float>(l + 1, wn.rhs, wn.x, ncol, st);
+    else e = co_await coarse_solve<double>(l + 1, wn.rhs, wn.x, ncol, st);
+    if (e < 0) co_return e;
+    CO_HIPCHK(prolong_from<T>(l, wn.x, z, ncol, st));
+    if (work_[l].ksmooth > 0) co_return smooth<T>(l, r, z, ncol, st);
+    co_return DWF_OK;
 }
 
 template <typename T>
-int Hierarchy::coarse_solve(int l, const void* rhs, void* x, int ncol, hipStream_t st) {
+Task Hierarchy::coarse_solve(int l, const void* rhs, void* x, int ncol, hipStream_t st) {
     int it = 0, e;
     if (l == (int)levels.size() - 1) {
-        if (prm.coarsest_solver == DWF_COARSEST_CGNR) return cgnr<T>(l, C<T>(rhs), C<T>(x), ncol, st);
-        e = gcr_plain<T>(l, C<T>(rhs), C<T>(x), ncol, prm.coarsest_tol, prm.coarsest_maxit, prm.coarsest_restart,
-                         &it, st);
+        if (prm.coarsest_solver == DWF_COARSEST_CGNR) co_return co_await cgnr<T>(l, C<T>(rhs), C<T>(x), ncol, st);
+        e = co_await gcr_plain<T>(l, C<T>(rhs), C<T>(x), ncol, prm.coarsest_tol, prm.coarsest_maxit,
+                                  prm.coarsest_restart, &it, st);
     } else {
         std::vector<double> tol(ncol, prm.inter_tol);
-        e = fgcr<T>(l, C<T>(rhs), C<T>(x), ncol, tol.data(), prm.inter_maxit, prm.inter_restart, &it, st);
+        e = co_await fgcr<T>(l, C<T>(rhs), C<T>(x), ncol, tol.data(), prm.inter_maxit, prm.inter_restart, &it, st);
     }
     cnt_.level_iters[l - 1] += it;
     cnt_.level_calls[l - 1] += 1;
-    return e < 0 ? e : DWF_OK;
+    co_return e < 0 ? e : DWF_OK;
 }
 
 // ------------------------------------------------------------ flexible GCR with the K-cycle
 template <typename T>
-int Hierarchy::fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* rel_tol, int maxit, int restart,
+Task Hierarchy::fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* rel_tol, int maxit, int restart,
                     int* iters_out, hipStream_t st) {
     const Level& L = levels[l];
     LevelWork& w = work_[l];
@@ -507,11 +531,11 @@ int Hierarchy::fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* r
     cpx<T>* t = C<T>(w.tmp);
     cpx<T>* t2 = C<T>(w.tmp2);
     GcrDev& g = w.gcr;
-    HIPCHK(vzero<T>(x, nt, st));
-    HIPCHK(vconvert<T, T>(b, r, nt, st));
-    HIPCHK(norm2<T>(b, n, ncol, g.rr, rw_, st));
-    HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    CO_HIPCHK(vzero<T>(x, nt, st));
+    CO_HIPCHK(vconvert<T, T>(b, r, nt, st));
+    CO_HIPCHK(norm2<T>(b, n, ncol, g.rr, rw_, st));
+    CO_HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+    CO_HIPCHK(co_await sync(st));
     std::vector<double> bb(h_scal_, h_scal_ + ncol), rr(bb);
     std::vector<int> stop(ncol, 0);
     int it = 0, k = 0, status = DWF_OK;
@@ -534,41 +558,44 @@ int Hierarchy::fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* r
             if (!stop[c]) all = false;
         }
         if (all || it >= maxit) break;
-        if (changed || it == 0) if (int e = push_stop()) return e;
+        if (changed || it == 0) if (int e = push_stop()) co_return e;
         cpx<T>* Pk = P + (size_t)k * nt;
         cpx<T>* Wk = W + (size_t)k * nt;
-        if (int e = kcycle<T>(l, r, Pk, ncol, st)) if (e < 0) return e;
-        HIPCHK(apply_A<T>(l, Pk, Wk, t, ncol, st));
-        HIPCHK(gcr_multidot<T>(W, nt, k, Wk, n, ncol, g, rw_, st));
-        HIPCHK(gcr_orth<T>(W, nt, k, Wk, r, n, ncol, g, rw_, st));
-        HIPCHK(gcr_rupdate<T>(Wk, r, nullptr, k, n, ncol, true, g, rw_, st));
+        {
+            const int e = co_await kcycle<T>(l, r, Pk, ncol, st);
+            if (e < 0) co_return e;
+        }
+        CO_HIPCHK(apply_A<T>(l, Pk, Wk, t, ncol, st));
+        CO_HIPCHK(gcr_multidot<T>(W, nt, k, Wk, n, ncol, g, rw_, st));
+        CO_HIPCHK(gcr_orth<T>(W, nt, k, Wk, r, n, ncol, g, rw_, st));
+        CO_HIPCHK(gcr_rupdate<T>(Wk, r, nullptr, k, n, ncol, true, g, rw_, st));
         ++k;
         ++it;
-        HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        CO_HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+        CO_HIPCHK(co_await sync(st));
         for (int c = 0; c < ncol; ++c) if (!stop[c]) rr[c] = h_scal_[c];
         bool conv = true;
         for (int c = 0; c < ncol; ++c)
             if (!stop[c] && !(rr[c] <= rel_tol[c] * rel_tol[c] * bb[c])) conv = false;
         if (k == kmax || conv || it >= maxit) {
-            if (int e = flush()) return e;
+            if (int e = flush()) co_return e;
             if (!conv && it < maxit) {
                 // true residual for the next cycle
-                HIPCHK(apply_A<T>(l, x, t2, t, ncol, st));
-                HIPCHK(vsub<T>(b, t2, r, nt, st));
-                HIPCHK(norm2<T>(r, n, ncol, g.rr, rw_, st));
-                HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-                HIPCHK(hipStreamSynchronize(st));
+                CO_HIPCHK(apply_A<T>(l, x, t2, t, ncol, st));
+                CO_HIPCHK(vsub<T>(b, t2, r, nt, st));
+                CO_HIPCHK(norm2<T>(r, n, ncol, g.rr, rw_, st));
+                CO_HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+                CO_HIPCHK(co_await sync(st));
                 for (int c = 0; c < ncol; ++c) if (!stop[c]) rr[c] = h_scal_[c];
             }
         }
     }
-    if (int e = flush()) return e;
+    if (int e = flush()) co_return e;
     // clear the stop mask for the next caller of this level's GCR scalars
     std::fill(stop.begin(), stop.end(), 0);
-    if (int e = push_stop()) return e;
+    if (int e = push_stop()) co_return e;
     if (iters_out) *iters_out = it;
-    return status;
+    co_return status;
 }
 
 // ------------------------------------------------------------ setup
@@ -773,6 +800,7 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
         std::lock_guard<std::recursive_mutex> lk(runtime_mutex());
         if (!st_) HIPCHK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
         if (!ev_in_) HIPCHK(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
+        if (!wait_ev_) HIPCHK(hipEventCreateWithFlags(&wait_ev_, hipEventDisableTiming));
         const int hc = std::max(rw_.max_cols, 64);
         HIPCHK(hipHostMalloc((void**)&h_scal_, sizeof(double) * 4 * hc, hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void**)&h_int_, sizeof(int) * 4 * hc, hipHostMallocDefault));
@@ -818,20 +846,20 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
 // ------------------------------------------------------------ solve
 // Right-hand sides in groups of at most max_ncol columns; the statistics add
 // up over the groups (the residual is the worst, the status the worst code).
-int Hierarchy::solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol, int flags, dwf_solve_stats* stats,
-                     hipStream_t caller) {
+Task Hierarchy::solve_task(const cpx<double>* b, cpx<double>* x, int ncol, double tol, int flags,
+                           dwf_solve_stats* stats, hipStream_t caller) {
     auto t0 = std::chrono::steady_clock::now();
-    if (ncol < 1 || max_ncol_ < 1) return DWF_EINVAL;
+    if (ncol < 1 || max_ncol_ < 1) co_return DWF_EINVAL;
     // run on the context's stream, after everything already queued on the caller's
-    HIPCHK(hipEventRecord(ev_in_, caller));
-    HIPCHK(hipStreamWaitEvent(st_, ev_in_, 0));
+    CO_HIPCHK(hipEventRecord(ev_in_, caller));
+    CO_HIPCHK(hipStreamWaitEvent(st_, ev_in_, 0));
     const size_t n1 = levels[0].vec_elems();
     dwf_solve_stats tot{};
     int worst = DWF_OK;
     for (int c0 = 0; c0 < ncol; c0 += max_ncol_) {
         const int nc = std::min(max_ncol_, ncol - c0);
         dwf_solve_stats g{};
-        const int e = solve_group(b + (size_t)c0 * n1, x + (size_t)c0 * n1, nc, tol, flags, &g, st_);
+        const int e = co_await solve_group(b + (size_t)c0 * n1, x + (size_t)c0 * n1, nc, tol, flags, &g, st_);
         if (e < 0 && (worst >= 0 || e < worst)) worst = e;
         else if (e > 0 && worst == DWF_OK) worst = e;
         tot.outer_steps += g.outer_steps;
@@ -845,18 +873,23 @@ int Hierarchy::solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol,
         if (e < 0) break;
     }
     // the caller's stream continues after the solve
-    HIPCHK(hipEventRecord(ev_in_, st_));
-    HIPCHK(hipStreamWaitEvent(caller, ev_in_, 0));
+    CO_HIPCHK(hipEventRecord(ev_in_, st_));
+    CO_HIPCHK(hipStreamWaitEvent(caller, ev_in_, 0));
     auto t1 = std::chrono::steady_clock::now();
     if (stats) {
         *stats = tot;
         stats->status = worst;
         stats->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
-    return worst;
+    co_return worst;
 }
 
-int Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, double tol, int flags,
+int Hierarchy::solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol, int flags, dwf_solve_stats* stats,
+                     hipStream_t caller) {
+    return run(solve_task(b, x, ncol, tol, flags, stats, caller));
+}
+
+Task Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, double tol, int flags,
                            dwf_solve_stats* stats, hipStream_t st) {
     cnt_ = SolveCounters{};
     const Level& L = levels[0];
@@ -866,29 +899,49 @@ int Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, do
     // the system solved: D_DW x = b, or D_DW x = D_PV b (the propagator form)
     const cpx<double>* b = b_in;
     if (flags & DWF_PV_SOURCE) {
-        HIPCHK(fine_dw<double>(L.U64, b_in, bp64_, nullptr, L.Lx, L.Ly, L.Ls, ncol, 1.0, M5, false, nullptr, 1, st));
+        CO_HIPCHK(fine_dw<double>(L.U64, b_in, bp64_, nullptr, L.Lx, L.Ly, L.Ls, ncol, 1.0, M5, false, nullptr, 1, st));
         cnt_.fine_applies += 1;
         b = bp64_;
     }
+    // time the coarse operators' launch configurations for this column count
+    // before any of their launches is captured in a graph (captures use the choice)
+    if (!coarse_tuned_.count(ncol)) {
+        for (int l = 1; l < (int)levels.size(); ++l) {
+            const Level& Lc = levels[l];
+            if (!coarse_mfma_supported(Lc.n, Lc.link_prec)) continue;
+            const size_t nc = Lc.vec_elems() * ncol;
+            for (int dg = 0; dg < 2; ++dg) {
+                if (Lc.vec_prec == P_F32) {
+                    CO_HIPCHK(vzero<float>(C<float>(work_[l].rhs), nc, st));
+                    CO_HIPCHK(apply_dw<float>(l, C<float>(work_[l].rhs), C<float>(work_[l].tmp2), m, dg == 1, ncol, st));
+                } else {
+                    CO_HIPCHK(vzero<double>(C<double>(work_[l].rhs), nc, st));
+                    CO_HIPCHK(apply_dw<double>(l, C<double>(work_[l].rhs), C<double>(work_[l].tmp2), m, dg == 1, ncol,
+                                               st));
+                }
+            }
+        }
+        coarse_tuned_.insert(ncol);
+    }
     double* d_s = work_[0].gcr.rr;   // scratch for column norms between inner solves
-    HIPCHK(norm2<double>(b, n, ncol, d_s, rw_, st));
-    HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    CO_HIPCHK(norm2<double>(b, n, ncol, d_s, rw_, st));
+    CO_HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+    CO_HIPCHK(co_await sync(st));
     std::vector<double> bb(h_scal_, h_scal_ + ncol);
     for (int c = 0; c < ncol; ++c)
-        if (!std::isfinite(bb[c])) return DWF_ENAN;
-    HIPCHK(vzero<double>(x, nt, st));
+        if (!std::isfinite(bb[c])) co_return DWF_ENAN;
+    CO_HIPCHK(vzero<double>(x, nt, st));
     const double floor_tol = (L.vec_prec == P_F32) ? 1e-5 : 1e-13;
     const double inner_floor = prm.inner_tol > 0 ? prm.inner_tol : floor_tol;
     int status = DWF_NOT_CONVERGED, outer = 0, total_it = 0;
     double worst = 0.0;
     std::vector<double> rel(ncol, 1.0);
     while (true) {
-        HIPCHK(fine_dw<double>(L.U64, x, r64_, b, L.Lx, L.Ly, L.Ls, ncol, m, M5, false, nullptr, 1, st));
+        CO_HIPCHK(fine_dw<double>(L.U64, x, r64_, b, L.Lx, L.Ly, L.Ls, ncol, m, M5, false, nullptr, 1, st));
         cnt_.fine_applies += 1;
-        HIPCHK(norm2<double>(r64_, n, ncol, d_s, rw_, st));
-        HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        CO_HIPCHK(norm2<double>(r64_, n, ncol, d_s, rw_, st));
+        CO_HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+        CO_HIPCHK(co_await sync(st));
         bool all = true;
         worst = 0.0;
         for (int c = 0; c < ncol; ++c) {
@@ -903,16 +956,16 @@ int Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, do
         if (outer >= prm.max_outer || total_it >= prm.max_iters) { status = DWF_NOT_CONVERGED; break; }
         // inner right-hand side D_PV^dagger r (with the PV polynomial D_PV^dagger p(X) r)
         if (prm.pv_poly_order > 0) {
-            HIPCHK(pv_poly<double>(r64_, y64_, z64_, ncol, st));
-            HIPCHK(fine_dw<double>(L.U64, y64_, t64_, nullptr, L.Lx, L.Ly, L.Ls, ncol, 1.0, M5, true, nullptr, 1, st));
+            CO_HIPCHK(pv_poly<double>(r64_, y64_, z64_, ncol, st));
+            CO_HIPCHK(fine_dw<double>(L.U64, y64_, t64_, nullptr, L.Lx, L.Ly, L.Ls, ncol, 1.0, M5, true, nullptr, 1, st));
             cnt_.fine_applies += 1 + 2 * prm.pv_poly_order;
         } else {
-            HIPCHK(fine_dw<double>(L.U64, r64_, t64_, nullptr, L.Lx, L.Ly, L.Ls, ncol, 1.0, M5, true, nullptr, 1, st));
+            CO_HIPCHK(fine_dw<double>(L.U64, r64_, t64_, nullptr, L.Lx, L.Ly, L.Ls, ncol, 1.0, M5, true, nullptr, 1, st));
             cnt_.fine_applies += 1;
         }
-        HIPCHK(norm2<double>(t64_, n, ncol, d_s, rw_, st));
-        HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        CO_HIPCHK(norm2<double>(t64_, n, ncol, d_s, rw_, st));
+        CO_HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+        CO_HIPCHK(co_await sync(st));
         std::vector<double> itol(ncol);
         for (int c = 0; c < ncol; ++c) {
             const double ra = std::sqrt(h_scal_[c]);
@@ -923,23 +976,23 @@ int Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, do
         int it = 0, e;
         const int maxit = prm.max_iters - total_it;
         if (L.vec_prec == P_F32) {
-            HIPCHK((vconvert<double, float>(t64_, C<float>(w.rhs), nt, st)));
-            e = fgcr<float>(0, C<float>(w.rhs), C<float>(w.x), ncol, itol.data(), maxit,
+            CO_HIPCHK((vconvert<double, float>(t64_, C<float>(w.rhs), nt, st)));
+            e = co_await fgcr<float>(0, C<float>(w.rhs), C<float>(w.x), ncol, itol.data(), maxit,
                             prm.outer_restart, &it, st);
             if (e < 0) { status = e; break; }
-            HIPCHK((vadd<float, double>(C<float>(w.x), x, nt, st)));
+            CO_HIPCHK((vadd<float, double>(C<float>(w.x), x, nt, st)));
         } else {
-            HIPCHK((vconvert<double, double>(t64_, C<double>(w.rhs), nt, st)));
-            e = fgcr<double>(0, C<double>(w.rhs), C<double>(w.x), ncol, itol.data(), maxit,
+            CO_HIPCHK((vconvert<double, double>(t64_, C<double>(w.rhs), nt, st)));
+            e = co_await fgcr<double>(0, C<double>(w.rhs), C<double>(w.x), ncol, itol.data(), maxit,
                              prm.outer_restart, &it, st);
             if (e < 0) { status = e; break; }
-            HIPCHK((vadd<double, double>(C<double>(w.x), x, nt, st)));
+            CO_HIPCHK((vadd<double, double>(C<double>(w.x), x, nt, st)));
         }
         total_it += it;
         ++outer;
         if (it == 0) { status = DWF_NOT_CONVERGED; break; }
     }
-    HIPCHK(hipStreamSynchronize(st));
+    CO_HIPCHK(co_await sync(st));
     if (stats) {
         stats->status = status;
         stats->outer_steps = outer;
@@ -951,7 +1004,7 @@ int Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, do
         }
         stats->true_rel_residual = worst;
     }
-    return status;
+    co_return status;
 }
 
 // ------------------------------------------------------------ diagnostics
@@ -1025,7 +1078,7 @@ int Hierarchy::level_op(int level, int op, const cpx<double>* in, cpx<double>* o
                 return DWF_OK;
             case MG_OP_KCYCLE: {
                 HIPCHK(to_prec<T>(in, bin, nl, st));
-                int e = kcycle<T>(level, xi, xo, ncol, st);
+                int e = Hierarchy::run(kcycle<T>(level, xi, xo, ncol, st));
                 if (e < 0) return e;
                 HIPCHK(from_prec<T>(bout, out, nl, st));
                 return DWF_OK;
@@ -1077,6 +1130,13 @@ int Hierarchy::time_op(int level, int op, const cpx<double>* in, int ncol, int i
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return status;
+}
+
+int Hierarchy::coarse_config(int level, int ncol, bool dagger, int* tw, int* tpb) const {
+    if (level < 1 || level >= (int)levels.size() || ncol < 1) return DWF_EINVAL;
+    const Level& L = levels[level];
+    CoarseGeom g{L.Lx, L.Ly, L.Ls, L.n};
+    return coarse_mfma_config(L.link_prec, L.vec_prec, g, ncol, dagger, tw, tpb) ? DWF_OK : DWF_EUNSUPPORTED;
 }
 
 int Hierarchy::update_links(const cpx<double>* U, hipStream_t st) {

@@ -6,12 +6,14 @@
 #include <algorithm>
 #include <cstdint>
 #include <map>
+#include <set>
 #include <tuple>
 #include <utility>
 #include <vector>
 
 #include "../../include/dwfmg.h"
 #include "kernels.hpp"
+#include "task.hpp"
 
 namespace dwf {
 
@@ -116,10 +118,21 @@ public:
     // solves ncol right-hand sides, in groups of at most max_ncol
     int solve(const cpx<double>* b, cpx<double>* x, int ncol, double tol, int flags, dwf_solve_stats* stats,
               hipStream_t st);
+    // the same solve as a coroutine (the batched driver runs several at once)
+    Task solve_task(const cpx<double>* b, cpx<double>* x, int ncol, double tol, int flags, dwf_solve_stats* stats,
+                    hipStream_t st);
     int max_ncol() const { return max_ncol_; }
+
+    // Batched driving from one host thread.  In batch mode a read-back point of
+    // the solve records an event on the context's stream and suspends the solve
+    // unless the event has completed; poll() resumes the suspended solve once
+    // its event has completed (or failed) and says whether it did.
+    void set_batch(bool on) { batch_ = on; }
+    bool poll();
     int level_op(int level, int op, const cpx<double>* in, cpx<double>* out, int ncol, double mass,
                  hipStream_t st);
     int export_level(int level, cpx<double>* V, cpx<double>* kernel, hipStream_t st);
+    int coarse_config(int level, int ncol, bool dagger, int* tw, int* tpb) const;
     int time_op(int level, int op, const cpx<double>* in, int ncol, int iters, double* avg_ms, hipStream_t st);
     int update_links(const cpx<double>* U, hipStream_t st);
     hipStream_t stream() const { return st_; }
@@ -164,8 +177,43 @@ private:
         int* info = nullptr;
     } dtmp_{};
     int plan(int Lx, int Ly, int Ls, int max_ncol);
-    int solve_group(const cpx<double>* b, cpx<double>* x, int ncol, double tol, int flags, dwf_solve_stats* stats,
-                    hipStream_t st);
+    std::set<int> coarse_tuned_;   // column counts whose coarse launch configurations were timed
+    Task solve_group(const cpx<double>* b, cpx<double>* x, int ncol, double tol, int flags, dwf_solve_stats* stats,
+                     hipStream_t st);
+    // read-back point: the host needs the stream's work done (scalars copied
+    // to the pinned mirrors).  Outside batch mode: hipStreamSynchronize.
+    bool batch_ = false;
+    hipEvent_t wait_ev_ = nullptr;
+    std::coroutine_handle<> wait_h_{};
+    hipError_t* wait_slot_ = nullptr;
+    struct StreamWait {
+        Hierarchy* h;
+        hipStream_t st;
+        hipError_t err = hipSuccess;
+        bool await_ready() {
+            if (!h->batch_) {
+                err = hipStreamSynchronize(st);
+                return true;
+            }
+            err = hipEventRecord(h->wait_ev_, st);
+            if (err != hipSuccess) return true;
+            const hipError_t q = hipEventQuery(h->wait_ev_);
+            if (q == hipErrorNotReady) return false;
+            err = q;
+            return true;
+        }
+        void await_suspend(std::coroutine_handle<> c) {
+            h->wait_h_ = c;
+            h->wait_slot_ = &err;
+        }
+        hipError_t await_resume() const { return err; }
+    };
+    StreamWait sync(hipStream_t st) { return StreamWait{this, st}; }
+    // runs a task to completion outside batch mode (it never suspends there)
+    static int run(Task t) {
+        t.start();
+        return t.done() ? t.result() : DWF_EHIP;
+    }
     SolveCounters cnt_{};
     // solves run on a stream of the context, so that fixed launch sequences
     // (a chunk of coarsest CGNR iterations, a GCR smoother) can be captured
@@ -218,15 +266,15 @@ private:
     template <typename T> hipError_t restrict_to(int l, const cpx<T>* r, void* rc_next, int ncol, hipStream_t st);
     template <typename T> hipError_t prolong_from(int l, const void* ec_next, cpx<T>* e, int ncol, hipStream_t st);
 
-    // solvers
-    template <typename T> int kcycle(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t st);
+    // solvers (coroutines: they contain read-back points)
+    template <typename T> Task kcycle(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t st);
     template <typename T> int smooth(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t st);
-    template <typename T> int coarse_solve(int l, const void* rhs, void* x, int ncol, hipStream_t st);
-    template <typename T> int cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st);
-    template <typename T> int fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* rel_tol,
-                                   int maxit, int restart, int* iters_out, hipStream_t st);
-    template <typename T> int gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol, int maxit,
-                                        int restart, int* iters_out, hipStream_t st);
+    template <typename T> Task coarse_solve(int l, const void* rhs, void* x, int ncol, hipStream_t st);
+    template <typename T> Task cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st);
+    template <typename T> Task fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* rel_tol,
+                                    int maxit, int restart, int* iters_out, hipStream_t st);
+    template <typename T> Task gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double tol, int maxit,
+                                         int restart, int* iters_out, hipStream_t st);
     int null_vectors(int l, const cpx<double>* start, cpx<double>* v, hipStream_t st);
 };
 

@@ -92,6 +92,7 @@ def lib() -> ctypes.CDLL:
                                      ctypes.POINTER(i), d, i, ctypes.POINTER(CStats), vp]
         L.mg_update_links.argtypes = [vp, vp, vp]
         L.mg_level_info.argtypes = [vp, i] + [ctypes.POINTER(i)] * 5
+        L.mg_coarse_config.argtypes = [vp, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]
         L.mg_deflation_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(d), vp]
         L.dwf_krylov_solve.argtypes = [vp, vp, vp, i, i, i, d, d, i, i, d, i, ctypes.POINTER(CStats), vp]
         L.mg_destroy.argtypes = [vp]
@@ -102,7 +103,7 @@ def lib() -> ctypes.CDLL:
                      "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
                      "dwf_pack", "dwf_unpack", "dwf_force", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
                      "mg_time_op", "dwf_norm2", "dwf_copy_bandwidth", "mg_update_links", "mg_solve_batch",
-                     "mg_level_info", "mg_deflation_info", "mg_destroy", "dwf_release_scratch",
+                     "mg_level_info", "mg_coarse_config", "mg_deflation_info", "mg_destroy", "dwf_release_scratch",
                      "dwf_krylov_solve"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -570,6 +571,13 @@ class MG:
         _check(lib().mg_level_info(self._h, level, *[ctypes.byref(v) for v in vals]), "mg_level_info")
         Lx, Ly, Ls, n, nvec = (v.value for v in vals)
         return dict(Lx=Lx, Ly=Ly, Ls=Ls, n=n, nvec=nvec)
+
+    def coarse_config(self, level: int = 1, ncol: int = 1, dagger: bool = False):
+        """(tile width, tiles per workgroup) of the matrix-core coarse stencil on `level`."""
+        tw, tpb = ctypes.c_int(), ctypes.c_int()
+        _check(lib().mg_coarse_config(self._h, int(level), int(ncol), 1 if dagger else 0, ctypes.byref(tw),
+                                      ctypes.byref(tpb)), "mg_coarse_config")
+        return tw.value, tpb.value
 
     def deflation_info(self):
         """Coarsest-level deflation space: dict(nev, iters, worst_residual, lambdas) with
