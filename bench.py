@@ -50,7 +50,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_params(dwfmg, wl, mixed, nev=0, **eig):
+def make_params(dwfmg, wl, mixed, nev=0, m_setup=None, setup_iters=None, **eig):
     n = len(wl["nvec"])
     if mixed:
         link = [dwfmg.P_BF16] * n
@@ -60,8 +60,13 @@ def make_params(dwfmg, wl, mixed, nev=0, **eig):
         link = [dwfmg.P_F64] * n
         vec = [dwfmg.P_F64] * n
         fine = dwfmg.P_F64
+    extra = {}
+    if m_setup is not None:
+        extra["m_setup"] = m_setup
+    if setup_iters is not None:
+        extra["setup_iters"] = setup_iters
     return dwfmg.MGParams(nvec=list(wl["nvec"]), block=list(wl["block"]), Ls_coarse=list(wl["Ls_coarse"]),
-                          link_prec=link, vec_prec=vec, fine_prec=fine, coarsest_nev=nev, **eig)
+                          link_prec=link, vec_prec=vec, fine_prec=fine, coarsest_nev=nev, **extra, **eig)
 
 
 def null_starts(inputs, wl, torch):
@@ -348,6 +353,8 @@ def main():
     ap.add_argument("--eig-degree", type=int, default=None, help="Chebyshev degree of the Lanczos acceleration")
     ap.add_argument("--eig-maxit", type=int, default=None)
     ap.add_argument("--eig-tol", type=float, default=None)
+    ap.add_argument("--m-setup", type=float, default=None, help="mass of the setup relaxation's Wilson kernel")
+    ap.add_argument("--setup-iters", type=int, default=None, help="CG iterations per null vector (max)")
     ap.add_argument("--nvec", type=int, nargs="+", default=None, help="override the workload's null vectors per level")
     ap.add_argument("--ls-coarse", type=int, nargs="+", default=None, help="override the coarse Ls per level")
     ap.add_argument("--quick", action="store_true", help="only the headline solve and its roofline")
@@ -390,6 +397,10 @@ def main():
         return d
 
     head = coarsest(args.coarsest, args.coarsest_tol)
+    if args.m_setup is not None:
+        head["m_setup"] = args.m_setup
+    if args.setup_iters is not None:
+        head["setup_iters"] = args.setup_iters
     for k, v in (("eig_degree", args.eig_degree), ("eig_maxit", args.eig_maxit), ("eig_tol", args.eig_tol)):
         if v is not None:
             head[k] = v
@@ -581,7 +592,8 @@ def main():
                    "mg": {"nvec": wl["nvec"], "block": wl["block"], "Ls_coarse": wl["Ls_coarse"],
                           "coarsest_solver": args.coarsest, "coarsest_tol": head["coarsest_tol"],
                           "coarsest_restart": args.coarsest_restart if args.coarsest == "gcr" else None,
-                          "coarsest_nev": args.nev},
+                          "coarsest_nev": args.nev, "m_setup": head.get("m_setup", 0.0),
+                          "setup_iters": head.get("setup_iters", 250)},
                    "precision": "fine FP32, coarse links BF16 (FP32 arithmetic), coarse vectors FP64, "
                                 "outer defect correction FP64"},
         "roofline": {"bound": "hbm", "kernel": "coarse_mfma_kernel (coarse D_DW apply, level 1)",

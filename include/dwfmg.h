@@ -235,9 +235,11 @@ typedef struct {
     double inner_tol;                     /* relative tolerance of one inner solve      */
     int    max_iters;                     /* cap on fine GCR iterations per solve       */
     int    max_outer;                     /* cap on defect-correction steps             */
-    int    coarsest_nev;                  /* deflate the coarsest CGNR with this many
-                                             lowest eigenvectors of A^dag A (0: off;
-                                             needs FP64 coarsest vectors)               */
+    int    coarsest_nev;                  /* deflate the coarsest solve (CGNR or GCR)
+                                             with this many lowest eigenvectors of
+                                             A^dag A: every call starts from
+                                             V Lambda^-1 V^dag A^dag b (0: off; needs
+                                             FP64 coarsest vectors)                     */
     int    eig_degree;                    /* degree of the Chebyshev polynomial that
                                              accelerates the Lanczos eigensolve
                                              (0: chosen from the spectral bounds)       */

@@ -347,7 +347,6 @@ int check_mg_args(int Lx, int Ly, int Ls, double m_f, double M5, const dwf_mg_pa
     if (p->coarsest_solver != DWF_COARSEST_CGNR && p->coarsest_solver != DWF_COARSEST_GCR) return DWF_EINVAL;
     if (p->coarsest_solver == DWF_COARSEST_GCR && (p->coarsest_restart < 1 || p->coarsest_restart > 16))
         return DWF_EINVAL;
-    if (p->coarsest_solver == DWF_COARSEST_GCR && p->coarsest_nev > 0) return DWF_EUNSUPPORTED;
     if (p->transfer != DWF_TRANSFER_WALL && p->transfer != DWF_TRANSFER_BULK && p->transfer != DWF_TRANSFER_SLICE1)
         return DWF_EINVAL;
     if (p->pv_poly_order < 0 || p->pv_poly_order > DWF_PV_POLY_MAX) return DWF_EINVAL;

@@ -398,6 +398,21 @@ Task Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double to
     CO_HIPCHK((vconvert<T, T>(b, P, nt, st)));   // the first search direction (later cycles: by the residual pass)
     CO_HIPCHK(norm2<T>(b, n, ncol, g.rr, rw_, st));
     CO_HIPCHK(gcr_dev_init(ncol, g, st));
+    if constexpr (std::is_same<T, double>::value) {
+        if (def_nev_ > 0 && l == (int)levels.size() - 1) {
+            // deflated start x0 = V Lambda^{-1} V^dag A^dag b (V: lowest eigenvectors of
+            // A^dag A, the right singular vectors of A): the minimiser of |b - A x| over
+            // span(V); the tolerance stays relative to |b|.  W_0 is scratch here (the
+            // first iteration writes it).
+            cpx<T>* z = W;
+            CO_HIPCHK(apply_Adag<T>(l, b, z, t, ncol, st));
+            if (int e = deflate_guess(l, z, x, ncol, st)) co_return e;
+            CO_HIPCHK(apply_A<T>(l, x, z, t, ncol, st));
+            CO_HIPCHK(vsub<T>(b, z, r, nt, st));
+            CO_HIPCHK((vconvert<T, T>(r, P, nt, st)));
+            CO_HIPCHK(norm2<T>(r, n, ncol, g.rr, rw_, st));
+        }
+    }
     // one restart cycle: kmax fused iterations (inner products, then one pass that orthogonalises
     // the new direction and updates the residual; the stop flags alternate between two buffers so
     // that no kernel writes the flags it reads), the solution update, and the restart
