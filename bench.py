@@ -367,6 +367,9 @@ def main():
                          "next to a plain 256 MiB copy, for rocprofv3 --pmc runs; prints no benchmark line")
     args = ap.parse_args()
 
+    if args.counters:
+        # the counter runs time one fixed launch configuration: no tuning dispatches
+        os.environ["DWF_AUTOTUNE"] = "0"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the library has no "
               f"multi-GPU path)", file=sys.stderr)
