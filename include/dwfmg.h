@@ -205,6 +205,11 @@ int dwf_force(const void* U, const void* X, const void* Y, double* F, int Lx, in
  * plus write).  Synchronises `stream`. */
 int dwf_copy_bandwidth(const void* src, void* dst, size_t bytes, int iters, double* gb_per_s, void* stream);
 
+/* Compact U(1) links from their angles (the differentiation form's variables):
+ * U_mu(x) = exp(i theta_mu(x)); theta [2][Ly][Lx] double, U [2][Ly][Lx]
+ * complex128 (device).  Asynchronous on `stream`. */
+int dwf_links_from_theta(const double* theta, void* U, int Lx, int Ly, void* stream);
+
 /* out[c] = |x_c|^2 (FP64 accumulation, deterministic order) for ncol columns
  * of n complex128 each; out is a device array of ncol doubles. */
 int dwf_norm2(const void* x, size_t n, int ncol, double* out, void* stream);

@@ -20,7 +20,7 @@ class DWFAction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, theta: torch.Tensor, phi: torch.Tensor, mg: "dwfmg.MG", tol: float = 1e-12):
-        U = torch.polar(torch.ones_like(theta), theta).contiguous()
+        U = dwfmg.dwf_links_from_theta(theta.detach().contiguous())
         mg.update_links(U)
         x, st = mg.solve(dwfmg.dwf_gamma5R(phi), tol)
         Y = dwfmg.dwf_gamma5R(x)

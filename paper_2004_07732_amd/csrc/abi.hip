@@ -270,6 +270,11 @@ int dwf_force(const void* U, const void* X, const void* Y, double* F, int Lx, in
                             S(stream)));
 }
 
+int dwf_links_from_theta(const double* theta, void* U, int Lx, int Ly, void* stream) {
+    if (!theta || !U || !dims_ok(Lx, Ly, 1, 1)) return DWF_EINVAL;
+    return hip_status(links_from_theta(theta, (cpx<double>*)U, 2LL * Lx * Ly, S(stream)));
+}
+
 int dwf_krylov_solve(const void* U, const void* b, void* x, int Lx, int Ly, int Ls, double m_f, double M5,
                      int method, int ell, double tol, int maxit, dwf_solve_stats* stats, void* stream) {
     if (!U || !b || !x || !dims_ok(Lx, Ly, Ls, 1) || Ls < 2) return DWF_EINVAL;

@@ -237,6 +237,8 @@ hipError_t gauge_transform(const cpx<double>* U, const cpx<double>* g, const cpx
                            hipStream_t st);
 hipError_t force(const cpx<double>* U, const cpx<double>* X, const cpx<double>* Y, double* F,
                  int Lx, int Ly, int Ls, int ncol, hipStream_t st);
+// U = exp(i theta) for n angles
+hipError_t links_from_theta(const double* theta, cpx<double>* U, long long n, hipStream_t st);
 // scalar finiteness check: flag[0] = 1 if any entry of x is not finite
 template <typename T>
 hipError_t check_finite(const cpx<T>* x, size_t n, int* flag, hipStream_t st);

@@ -107,6 +107,20 @@ __global__ void k_force(const cpx<double>* U, const spinor<double>* X, const spi
     F[t] = -2.0 * a.im;
 }
 
+// U_mu(x) = exp(i theta_mu(x)) = cos theta + i sin theta (the compact U(1) links)
+__global__ void k_links_from_theta(const double* theta, cpx<double>* U, long long n) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double sv, cv;
+    sincos(theta[t], &sv, &cv);
+    U[t] = {cv, sv};
+}
+
+hipError_t links_from_theta(const double* theta, cpx<double>* U, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_links_from_theta, dim3(grid_for(n)), dim3(kBlock), 0, st, theta, U, n);
+    return hipGetLastError();
+}
+
 hipError_t force(const cpx<double>* U, const cpx<double>* X, const cpx<double>* Y, double* F,
                  int Lx, int Ly, int Ls, int ncol, hipStream_t st) {
     const int V = Lx * Ly;

@@ -76,6 +76,7 @@ def lib() -> ctypes.CDLL:
         L.dwf_pack.argtypes = [vp, vp, sz, vp]
         L.dwf_unpack.argtypes = [vp, vp, sz, vp]
         L.dwf_force.argtypes = [vp, vp, vp, vp, i, i, i, i, vp]
+        L.dwf_links_from_theta.argtypes = [vp, vp, i, i, vp]
         L.dwf_mg_default_params.argtypes = [ctypes.POINTER(CParams), i]
         L.dwf_mg_default_params.restype = None
         L.mg_workspace_bytes.argtypes = [i, i, i, i, ctypes.POINTER(CParams)]
@@ -101,7 +102,7 @@ def lib() -> ctypes.CDLL:
         L.dwf_strerror.restype = ctypes.c_char_p
         for name in ("dwf_apply", "dwf_pv_apply", "dwf_pv_apply_noalloc", "dwf_fine_config", "dwf_pv_poly_apply", "dwf_pv_poly_chebyshev",
                      "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
-                     "dwf_pack", "dwf_unpack", "dwf_force", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
+                     "dwf_pack", "dwf_unpack", "dwf_force", "dwf_links_from_theta", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
                      "mg_time_op", "dwf_norm2", "dwf_copy_bandwidth", "mg_update_links", "mg_solve_batch",
                      "mg_level_info", "mg_coarse_config", "mg_deflation_info", "mg_destroy", "dwf_release_scratch",
                      "dwf_krylov_solve"):
@@ -425,6 +426,17 @@ def dwf_force(U, X, Y, stream=None):
     F = torch.empty(U.shape, dtype=torch.float64, device=U.device)
     _check(lib().dwf_force(_ptr(U), _ptr(X), _ptr(Y), _ptr(F), Lx, Ly, Ls, nrhs, _stream(stream)), "dwf_force")
     return F
+
+
+def dwf_links_from_theta(theta, stream=None):
+    """U = exp(i theta) for theta [2, Ly, Lx] float64; returns a complex128 tensor."""
+    _need(theta, "theta", torch.float64)
+    if theta.dim() != 3 or theta.shape[0] != 2:
+        raise ValueError("theta must be [2, Ly, Lx]")
+    U = torch.empty(theta.shape, dtype=torch.complex128, device=theta.device)
+    _check(lib().dwf_links_from_theta(_ptr(theta), _ptr(U), theta.shape[2], theta.shape[1], _stream(stream)),
+           "dwf_links_from_theta")
+    return U
 
 
 def dwf_norm2(x, stream=None):

@@ -63,7 +63,7 @@ def test_differentiation_form_full_size():
     mg = dwfmg.MG(T(g.U), Ls, m, M5, params, starts)
     th = T(g.theta).requires_grad_(True)
     tol = 1e-10
-    U = torch.polar(torch.ones_like(th.detach()), th.detach())
+    U = dwfmg.dwf_links_from_theta(th.detach())
     # forward pieces, as the autograd function runs them
     Y = dwfmg.dwf_gamma5R(mg.solve(dwfmg.dwf_gamma5R(T(phi)), tol)[0])
     X = mg.solve(Y, tol)[0]

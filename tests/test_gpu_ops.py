@@ -208,3 +208,12 @@ def test_argument_errors_on_device():
     assert e.value.code == dwfmg.DWF_EINVAL
     with pytest.raises(ValueError):
         dwfmg.dwf_apply(U, psi.to(torch.complex64), 0.1, -1.0)
+
+
+def test_links_from_theta():
+    """U = exp(i theta) on the device against numpy's cos / sin of the same angles
+    (the generator's links), to a couple of ulp."""
+    theta = inputs.metropolis_u1(32, 16, 6.0, 20, 19).theta
+    U = dwfmg.dwf_links_from_theta(torch.from_numpy(theta).to(DEV)).cpu().numpy()
+    want = inputs.links_from_theta(theta)
+    assert np.max(np.abs(U - want)) < 4e-16
