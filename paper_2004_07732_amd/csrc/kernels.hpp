@@ -239,6 +239,17 @@ hipError_t force(const cpx<double>* U, const cpx<double>* X, const cpx<double>* 
                  int Lx, int Ly, int Ls, int ncol, hipStream_t st);
 // U = exp(i theta) for n angles
 hipError_t links_from_theta(const double* theta, cpx<double>* U, long long n, hipStream_t st);
+// copy up to kPublishItems blocks of 32-bit words from device memory to host-coherent
+// memory (device views), then store `value` to *seq (release, system scope)
+constexpr int kPublishItems = 3;
+struct PublishArgs {
+    const uint32_t* src[kPublishItems];
+    uint32_t* dst[kPublishItems];
+    int words[kPublishItems];
+    unsigned* seq;
+    unsigned value;
+};
+hipError_t publish_to_host(const PublishArgs& a, hipStream_t st);
 // scalar finiteness check: flag[0] = 1 if any entry of x is not finite
 template <typename T>
 hipError_t check_finite(const cpx<T>* x, size_t n, int* flag, hipStream_t st);

@@ -66,6 +66,7 @@ Hierarchy::~Hierarchy() {
     if (h_scal_) (void)hipHostFree(h_scal_);
     if (h_int_) (void)hipHostFree(h_int_);
     if (h_cg_) (void)hipHostFree(h_cg_);
+    if (h_seq_) (void)hipHostFree(h_seq_);
     if (ev_in_) (void)hipEventDestroy(ev_in_);
     if (wait_ev_) (void)hipEventDestroy(wait_ev_);
     if (st_) (void)hipStreamDestroy(st_);
@@ -78,14 +79,55 @@ std::recursive_mutex& runtime_mutex() {
 
 bool Hierarchy::poll() {
     if (!wait_h_) return false;
-    const hipError_t q = hipEventQuery(wait_ev_);
-    if (q == hipErrorNotReady) return false;
-    if (wait_slot_) *wait_slot_ = q;
+    hipError_t res = hipSuccess;
+    if (!(wait_seq_ && seq_arrived(wait_seq_))) {
+        const hipError_t q = hipEventQuery(wait_ev_);
+        if (q == hipErrorNotReady) return false;
+        // the stream has finished: a published number is visible by now unless it failed
+        res = q;
+        if (res == hipSuccess && wait_seq_ && !seq_arrived(wait_seq_)) res = hipErrorUnknown;
+    }
+    if (wait_slot_) *wait_slot_ = res;
     std::coroutine_handle<> h = wait_h_;
     wait_h_ = nullptr;
     wait_slot_ = nullptr;
+    wait_seq_ = 0;
     h.resume();
     return true;
+}
+
+hipError_t Hierarchy::publish(hipStream_t st, std::initializer_list<HostCopy> items, unsigned* value) {
+    PublishArgs a{};
+    int k = 0;
+    for (const HostCopy& c : items) {
+        if (k == kPublishItems || c.bytes % 4 != 0 || c.bytes / 4 > (size_t)INT32_MAX) return hipErrorInvalidValue;
+        char* dst = nullptr;
+        for (const HostView& v : views_)
+            if (v.host && (char*)c.host >= v.host && (char*)c.host + c.bytes <= v.host + v.bytes)
+                dst = v.dev + ((char*)c.host - v.host);
+        if (!dst) return hipErrorInvalidValue;
+        a.src[k] = reinterpret_cast<const uint32_t*>(c.dev);
+        a.dst[k] = reinterpret_cast<uint32_t*>(dst);
+        a.words[k] = (int)(c.bytes / 4);
+        ++k;
+    }
+    if (++pub_ == 0) ++pub_;   // 0 is the word's initial value
+    a.seq = reinterpret_cast<unsigned*>(views_[3].dev);
+    a.value = pub_;
+    *value = pub_;
+    return publish_to_host(a, st);
+}
+
+hipError_t Hierarchy::wait_published(unsigned v, hipStream_t st) const {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spin = 1;; ++spin) {
+        if (seq_arrived(v)) return hipSuccess;
+        if ((spin & 1023u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(kSpinMs)) break;
+    }
+    // long GPU work (or a failure): block in the runtime instead of spinning
+    const hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    return seq_arrived(v) ? hipSuccess : hipErrorUnknown;
 }
 
 void Hierarchy::clear_graphs() {
@@ -352,8 +394,7 @@ Task Hierarchy::cgnr(int l, const cpx<T>* b, cpx<T>* x, int ncol, hipStream_t st
         } else {
             if (int e = chunk(kCgChunk)) co_return e;
         }
-        CO_HIPCHK(hipMemcpyAsync(h_cg_, s, sizeof(CgScal) * ncol, hipMemcpyDeviceToHost, st));
-        CO_HIPCHK(co_await sync(st));
+        CO_HIPCHK(co_await read_back(st, {{h_cg_, s, sizeof(CgScal) * ncol}}));
         bool all = true;
         for (int c = 0; c < ncol; ++c)
             if (!h_cg_[c].done) all = false;
@@ -439,16 +480,13 @@ Task Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double to
         } else if (int e = cycle()) {
             co_return e;
         }
-        CO_HIPCHK(hipMemcpyAsync(h_int_, g.stop, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
-        CO_HIPCHK(co_await sync(st));
+        CO_HIPCHK(co_await read_back(st, {{h_int_, g.stop, sizeof(int) * ncol}}));
         bool all = true;
         for (int cc = 0; cc < ncol; ++cc)
             if (h_int_[cc] == 0) all = false;
         if (all) break;
     }
-    CO_HIPCHK(hipMemcpyAsync(h_int_, g.stop, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
-    CO_HIPCHK(hipMemcpyAsync(h_int_ + ncol, g.it, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
-    CO_HIPCHK(co_await sync(st));
+    CO_HIPCHK(co_await read_back(st, {{h_int_, g.stop, sizeof(int) * ncol}, {h_int_ + ncol, g.it, sizeof(int) * ncol}}));
     int it = 0, status = DWF_OK;
     for (int cc = 0; cc < ncol; ++cc) {
         it = std::max(it, h_int_[ncol + cc]);
@@ -549,8 +587,7 @@ Task Hierarchy::fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* 
     CO_HIPCHK(vzero<T>(x, nt, st));
     CO_HIPCHK(vconvert<T, T>(b, r, nt, st));
     CO_HIPCHK(norm2<T>(b, n, ncol, g.rr, rw_, st));
-    CO_HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-    CO_HIPCHK(co_await sync(st));
+    CO_HIPCHK(co_await read_back(st, {{h_scal_, g.rr, sizeof(double) * ncol}}));
     std::vector<double> bb(h_scal_, h_scal_ + ncol), rr(bb);
     std::vector<int> stop(ncol, 0);
     int it = 0, k = 0, status = DWF_OK;
@@ -586,8 +623,7 @@ Task Hierarchy::fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* 
         CO_HIPCHK(gcr_rupdate<T>(Wk, r, nullptr, k, n, ncol, true, g, rw_, st));
         ++k;
         ++it;
-        CO_HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-        CO_HIPCHK(co_await sync(st));
+        CO_HIPCHK(co_await read_back(st, {{h_scal_, g.rr, sizeof(double) * ncol}}));
         for (int c = 0; c < ncol; ++c) if (!stop[c]) rr[c] = h_scal_[c];
         bool conv = true;
         for (int c = 0; c < ncol; ++c)
@@ -599,8 +635,7 @@ Task Hierarchy::fgcr(int l, const cpx<T>* b, cpx<T>* x, int ncol, const double* 
                 CO_HIPCHK(apply_A<T>(l, x, t2, t, ncol, st));
                 CO_HIPCHK(vsub<T>(b, t2, r, nt, st));
                 CO_HIPCHK(norm2<T>(r, n, ncol, g.rr, rw_, st));
-                CO_HIPCHK(hipMemcpyAsync(h_scal_, g.rr, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-                CO_HIPCHK(co_await sync(st));
+                CO_HIPCHK(co_await read_back(st, {{h_scal_, g.rr, sizeof(double) * ncol}}));
                 for (int c = 0; c < ncol; ++c) if (!stop[c]) rr[c] = h_scal_[c];
             }
         }
@@ -644,8 +679,9 @@ int Hierarchy::null_vectors(int l, const cpx<double>* start, cpx<double>* v, hip
             HIPCHK(cg_beta<double>(r, n, nv, s, maxit, rw_, st));
             HIPCHK(cg_update_p<double>(p, r, n, nv, s, st));
         }
-        HIPCHK(hipMemcpyAsync(h_cg_, s, sizeof(CgScal) * nv, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        unsigned v = 0;
+        HIPCHK(publish(st, {{h_cg_, s, sizeof(CgScal) * nv}}, &v));
+        HIPCHK(wait_published(v, st));
         bool all = true;
         for (int c = 0; c < nv; ++c) if (!h_cg_[c].done) all = false;
         if (all) break;
@@ -817,9 +853,20 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
         if (!ev_in_) HIPCHK(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
         if (!wait_ev_) HIPCHK(hipEventCreateWithFlags(&wait_ev_, hipEventDisableTiming));
         const int hc = std::max(rw_.max_cols, 64);
-        HIPCHK(hipHostMalloc((void**)&h_scal_, sizeof(double) * 4 * hc, hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&h_int_, sizeof(int) * 4 * hc, hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&h_cg_, sizeof(CgScal) * hc, hipHostMallocDefault));
+        // host-coherent: the publishing kernel stores into them directly
+        HIPCHK(hipHostMalloc((void**)&h_scal_, sizeof(double) * 4 * hc, hipHostMallocCoherent));
+        HIPCHK(hipHostMalloc((void**)&h_int_, sizeof(int) * 4 * hc, hipHostMallocCoherent));
+        HIPCHK(hipHostMalloc((void**)&h_cg_, sizeof(CgScal) * hc, hipHostMallocCoherent));
+        HIPCHK(hipHostMalloc((void**)&h_seq_, 64, hipHostMallocCoherent));
+        *h_seq_ = 0;
+        pub_ = 0;
+        void* hp[4] = {h_scal_, h_int_, h_cg_, h_seq_};
+        const size_t hb[4] = {sizeof(double) * 4 * hc, sizeof(int) * 4 * hc, sizeof(CgScal) * hc, 64};
+        for (int i = 0; i < 4; ++i) {
+            void* d = nullptr;
+            HIPCHK(hipHostGetDevicePointer(&d, hp[i], 0));
+            views_[i] = HostView{(char*)hp[i], (char*)d, hb[i]};
+        }
     }
     const char* ng = std::getenv("DWF_NO_GRAPHS");
     use_graphs_ = !(ng && ng[0] == '1');
@@ -940,8 +987,7 @@ Task Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, d
     }
     double* d_s = work_[0].gcr.rr;   // scratch for column norms between inner solves
     CO_HIPCHK(norm2<double>(b, n, ncol, d_s, rw_, st));
-    CO_HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-    CO_HIPCHK(co_await sync(st));
+    CO_HIPCHK(co_await read_back(st, {{h_scal_, d_s, sizeof(double) * ncol}}));
     std::vector<double> bb(h_scal_, h_scal_ + ncol);
     for (int c = 0; c < ncol; ++c)
         if (!std::isfinite(bb[c])) co_return DWF_ENAN;
@@ -955,8 +1001,7 @@ Task Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, d
         CO_HIPCHK(fine_dw<double>(L.U64, x, r64_, b, L.Lx, L.Ly, L.Ls, ncol, m, M5, false, nullptr, 1, st));
         cnt_.fine_applies += 1;
         CO_HIPCHK(norm2<double>(r64_, n, ncol, d_s, rw_, st));
-        CO_HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-        CO_HIPCHK(co_await sync(st));
+        CO_HIPCHK(co_await read_back(st, {{h_scal_, d_s, sizeof(double) * ncol}}));
         bool all = true;
         worst = 0.0;
         for (int c = 0; c < ncol; ++c) {
@@ -979,8 +1024,7 @@ Task Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, d
             cnt_.fine_applies += 1;
         }
         CO_HIPCHK(norm2<double>(t64_, n, ncol, d_s, rw_, st));
-        CO_HIPCHK(hipMemcpyAsync(h_scal_, d_s, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
-        CO_HIPCHK(co_await sync(st));
+        CO_HIPCHK(co_await read_back(st, {{h_scal_, d_s, sizeof(double) * ncol}}));
         std::vector<double> itol(ncol);
         for (int c = 0; c < ncol; ++c) {
             const double ra = std::sqrt(h_scal_[c]);

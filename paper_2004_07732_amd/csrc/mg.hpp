@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <initializer_list>
 #include <map>
 #include <set>
 #include <tuple>
@@ -148,10 +149,15 @@ private:
     std::vector<std::pair<void*, size_t>> zero_at_setup_;   // flags that start at zero
     std::vector<LevelWork> work_;
     RedWork rw_{};
-    // pinned host mirrors for scalar read-back
+    // pinned, host-coherent mirrors for scalar read-back, and the sequence word the
+    // publishing kernel stores last (host pointers; the device views are looked up)
     double* h_scal_ = nullptr;
     int* h_int_ = nullptr;
     CgScal* h_cg_ = nullptr;
+    unsigned* h_seq_ = nullptr;
+    struct HostView { char* host = nullptr; char* dev = nullptr; size_t bytes = 0; };
+    HostView views_[4];
+    unsigned pub_ = 0;            // last sequence number published
     int* d_flag_ = nullptr;
     cpx<double>* r64_ = nullptr;
     cpx<double>* t64_ = nullptr;
@@ -186,6 +192,44 @@ private:
     hipEvent_t wait_ev_ = nullptr;
     std::coroutine_handle<> wait_h_{};
     hipError_t* wait_slot_ = nullptr;
+    unsigned wait_seq_ = 0;       // batch mode: the sequence number a suspended read waits for
+    // Scalar read-back: a one-wavefront kernel stores the device words into the host
+    // mirrors and then a new sequence number (publish_to_host); the host spins on the
+    // number for up to kSpinMs (a stream synchronisation after that).  About 8 us
+    // from the end of the GPU work to the next launch, against about 25 us for a
+    // device-to-host copy followed by hipStreamSynchronize.
+    struct HostCopy { void* host; const void* dev; size_t bytes; };
+    static constexpr int kSpinMs = 20;
+    hipError_t publish(hipStream_t st, std::initializer_list<HostCopy> items, unsigned* value);
+    bool seq_arrived(unsigned v) const { return __atomic_load_n(h_seq_, __ATOMIC_ACQUIRE) == v; }
+    hipError_t wait_published(unsigned v, hipStream_t st) const;
+    struct HostRead {
+        Hierarchy* h;
+        hipStream_t st;
+        unsigned v;
+        hipError_t err;
+        bool await_ready() {
+            if (err != hipSuccess) return true;
+            if (!h->batch_) {
+                err = h->wait_published(v, st);
+                return true;
+            }
+            if (h->seq_arrived(v)) return true;
+            err = hipEventRecord(h->wait_ev_, st);   // lets poll() tell a finished stream from a slow one
+            return err != hipSuccess;
+        }
+        void await_suspend(std::coroutine_handle<> c) {
+            h->wait_h_ = c;
+            h->wait_slot_ = &err;
+            h->wait_seq_ = v;
+        }
+        hipError_t await_resume() const { return err; }
+    };
+    HostRead read_back(hipStream_t st, std::initializer_list<HostCopy> items) {
+        unsigned v = 0;
+        const hipError_t e = publish(st, items, &v);
+        return HostRead{this, st, v, e};
+    }
     struct StreamWait {
         Hierarchy* h;
         hipStream_t st;

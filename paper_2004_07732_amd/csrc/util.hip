@@ -121,6 +121,26 @@ hipError_t links_from_theta(const double* theta, cpx<double>* U, long long n, hi
     return hipGetLastError();
 }
 
+// Scalar read-back without a copy engine or a stream synchronisation: one
+// wavefront copies the listed device words into host-coherent memory and then
+// stores the sequence number with release ordering at system scope, so that a
+// host that reads the number also reads the words.
+__global__ void __launch_bounds__(64) k_publish(PublishArgs a) {
+#pragma unroll
+    for (int k = 0; k < kPublishItems; ++k)
+        for (int i = threadIdx.x; i < a.words[k]; i += 64) a.dst[k][i] = a.src[k][i];
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(a.seq, a.value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t publish_to_host(const PublishArgs& a, hipStream_t st) {
+    if (!a.seq) return hipErrorInvalidValue;
+    for (int k = 0; k < kPublishItems; ++k)
+        if (a.words[k] < 0 || (a.words[k] > 0 && (!a.src[k] || !a.dst[k]))) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t force(const cpx<double>* U, const cpx<double>* X, const cpx<double>* Y, double* F,
                  int Lx, int Ly, int Ls, int ncol, hipStream_t st) {
     const int V = Lx * Ly;
