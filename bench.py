@@ -355,6 +355,10 @@ def main():
     ap.add_argument("--eig-tol", type=float, default=None)
     ap.add_argument("--m-setup", type=float, default=None, help="mass of the setup relaxation's Wilson kernel")
     ap.add_argument("--setup-iters", type=int, default=None, help="CG iterations per null vector (max)")
+    ap.add_argument("--smooth-iters", type=int, default=20,
+                    help="post-smoothing GCR steps per K-cycle (default 20; the paper's parameter table has 8)")
+    ap.add_argument("--smooth-restart", type=int, default=5,
+                    help="restart length of the post-smoothing GCR (default 5; 0: none, the paper's smoother)")
     ap.add_argument("--nvec", type=int, nargs="+", default=None, help="override the workload's null vectors per level")
     ap.add_argument("--ls-coarse", type=int, nargs="+", default=None, help="override the coarse Ls per level")
     ap.add_argument("--quick", action="store_true", help="only the headline solve and its roofline")
@@ -396,7 +400,7 @@ def main():
     def coarsest(kind, tol=None):
         d = {"coarsest_solver": dwfmg.COARSEST_GCR if kind == "gcr" else dwfmg.COARSEST_CGNR,
              "coarsest_restart": args.coarsest_restart}
-        d["coarsest_tol"] = tol if tol is not None else (0.25 if kind == "gcr" else 0.05)
+        d["coarsest_tol"] = tol if tol is not None else (0.5 if kind == "gcr" else 0.05)
         return d
 
     head = coarsest(args.coarsest, args.coarsest_tol)
@@ -404,6 +408,8 @@ def main():
         head["m_setup"] = args.m_setup
     if args.setup_iters is not None:
         head["setup_iters"] = args.setup_iters
+    head["smooth_iters"] = args.smooth_iters
+    head["smooth_restart"] = args.smooth_restart
     for k, v in (("eig_degree", args.eig_degree), ("eig_maxit", args.eig_maxit), ("eig_tol", args.eig_tol)):
         if v is not None:
             head[k] = v
@@ -519,15 +525,18 @@ def main():
             mgv = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wlv, True, **kw), null_starts(inputs, wlv, torch))
             _, tv, stv, _ = timed(mgv, b, ROW_SAMPLES, 1)
             rows[name] = {"solves_per_s": 1.0 / tv, "samples": ROW_SAMPLES,
-                          "mg": {"nvec": wlv["nvec"], "block": wlv["block"], "Ls_coarse": wlv["Ls_coarse"]},
+                          "mg": {"nvec": wlv["nvec"], "block": wlv["block"], "Ls_coarse": wlv["Ls_coarse"],
+                                 "smooth_iters": kw.get("smooth_iters", 8), "smooth_restart": kw.get("smooth_restart", 0)},
                           "coarsest": {k: v for k, v in kw.items() if k.startswith("coarsest")}, **stats_dict(stv)}
             if kw.get("pv_poly") is not None:
                 rows[name]["pv_poly"] = list(kw["pv_poly"])
             log(f"[bench] {name}: {tv * 1e3:.1f} ms/solve, fine applies {stv.fine_applies}")
             mgv.close()
         wl4 = dict(wl, Ls_coarse=[4] * len(wl["nvec"]))
-        # the paper's parameter table throughout: coarse Ls 4 and coarsest CGNR to 0.05
+        # the paper's parameter table throughout: coarse Ls 4, coarsest CGNR to 0.05, 8 post-smoothing steps
         variant("paper_table_cgnr_Ls4", wl4, **coarsest("cgnr"))
+        # the headline hierarchy with the paper's smoother (8 steps, one GCR cycle) and coarsest GCR(6) to 0.25
+        variant("smoother8_gcr025", wl, **coarsest("gcr", 0.25))
         # coarse Ls 4 with the headline's coarsest GCR
         variant("gcr_Ls4", wl4, **head)
         # three-level hierarchy (4x4 / 8 vectors, then 2x2 / 12 vectors), headline coarsest settings
@@ -596,7 +605,8 @@ def main():
                           "coarsest_solver": args.coarsest, "coarsest_tol": head["coarsest_tol"],
                           "coarsest_restart": args.coarsest_restart if args.coarsest == "gcr" else None,
                           "coarsest_nev": args.nev, "m_setup": head.get("m_setup", 0.0),
-                          "setup_iters": head.get("setup_iters", 250)},
+                          "setup_iters": head.get("setup_iters", 250), "smooth_iters": head.get("smooth_iters", 8),
+                          "smooth_restart": head.get("smooth_restart", 0)},
                    "precision": "fine FP32, coarse links BF16 (FP32 arithmetic), coarse vectors FP64, "
                                 "outer defect correction FP64"},
         "roofline": {"bound": "hbm", "kernel": "coarse_mfma_kernel (coarse D_DW apply, level 1)",

@@ -231,7 +231,13 @@ typedef struct {
     int    setup_iters;                   /* CG iterations per null vector (max)        */
     double setup_tol;                     /* |B v| <= setup_tol |B v0|                  */
     int    outer_restart;                 /* fine flexible GCR restart length           */
-    int    smooth_iters;                  /* post-smoothing GCR steps (all levels)      */
+    int    smooth_iters;                  /* post-smoothing GCR steps (all levels),
+                                             0..16, or up to 64 with a restart          */
+    int    smooth_restart;                /* restart length of the post-smoothing GCR,
+                                             0..16 (0: no restart, all smooth_iters
+                                             steps in one cycle, the paper's smoother;
+                                             each cycle continues from the residual of
+                                             the previous one)                          */
     int    inter_maxit;                   /* intermediate GCR max iterations            */
     double inter_tol;                     /* intermediate GCR relative tolerance        */
     int    inter_restart;

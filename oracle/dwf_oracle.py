@@ -761,6 +761,7 @@ class MGParams:
     m_setup: float = 0.0           # READING: mass of the setup Wilson kernel
     outer_restart: int = 16
     smooth_iters: int = 8          # post-smoothing GCR steps (pre-smoothing 0)
+    smooth_restart: int = 0        # restart length of the smoothing GCR (0: one cycle of smooth_iters)
     inter_maxit: int = 16
     inter_tol: float = 0.25
     inter_restart: int = 16
@@ -874,8 +875,8 @@ class MG:
         if self.params.smooth_iters == 0:
             return z0
         rs = r - self.A(l, z0)
-        zs, _ = gcr(lambda v: self.A(l, v), rs, 0.0, self.params.smooth_iters,
-                    self.params.smooth_iters)
+        ks = self.params.smooth_restart or self.params.smooth_iters
+        zs, _ = gcr(lambda v: self.A(l, v), rs, 0.0, self.params.smooth_iters, ks)
         return z0 + zs
 
     def solve(self, b, tol, maxit=10000):

@@ -304,6 +304,7 @@ void dwf_mg_default_params(dwf_mg_params* p, int nlevels) {
     p->setup_tol = 1e-4;
     p->outer_restart = 16;
     p->smooth_iters = 8;
+    p->smooth_restart = 0;
     p->inter_maxit = 16;
     p->inter_tol = 0.25;
     p->inter_restart = 16;
@@ -343,7 +344,10 @@ int check_mg_args(int Lx, int Ly, int Ls, double m_f, double M5, const dwf_mg_pa
     if (!dims_ok(Lx, Ly, Ls, 1) || Ls < 2 || !std::isfinite(m_f) || !std::isfinite(M5)) return DWF_EINVAL;
     if (max_nrhs < 1 || max_nrhs > 4096) return DWF_EINVAL;
     if (p->nlevels < 1 || p->nlevels > DWF_MAX_LEVELS) return DWF_EINVAL;
-    if (p->outer_restart < 1 || p->outer_restart > 16 || p->smooth_iters < 0 || p->smooth_iters > 16) return DWF_EINVAL;
+    if (p->outer_restart < 1 || p->outer_restart > 16 || p->smooth_iters < 0) return DWF_EINVAL;
+    // one smoothing cycle is at most 16 steps; with a restart, up to 64 steps in all
+    if (p->smooth_restart < 0 || p->smooth_restart > 16) return DWF_EINVAL;
+    if (p->smooth_iters > (p->smooth_restart > 0 ? 64 : 16)) return DWF_EINVAL;
     if (p->nlevels > 1 && (p->inter_restart < 1 || p->inter_restart > 16)) return DWF_EINVAL;
     if (!valid_prec(p->fine_prec, false)) return DWF_EINVAL;
     if (p->coarsest_nev < 0 || (p->coarsest_nev > 0 && (p->eig_maxit < 1 || p->eig_degree < 0 || !(p->eig_tol > 0.0))))

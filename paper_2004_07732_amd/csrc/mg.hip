@@ -289,6 +289,7 @@ int Hierarchy::alloc_level_work(int l, int ncol) {
     const bool coarsest_gcr = coarsest && prm.coarsest_solver == DWF_COARSEST_GCR;
     w.kmax = (l == 0) ? prm.outer_restart : (coarsest ? (coarsest_gcr ? prm.coarsest_restart : 0) : prm.inter_restart);
     w.ksmooth = coarsest ? 0 : prm.smooth_iters;
+    w.kscycle = (prm.smooth_restart > 0 && prm.smooth_restart < w.ksmooth) ? prm.smooth_restart : w.ksmooth;
     auto A = [&](size_t bytes) { return dalloc(bytes); };
     w.r = A(vb); w.x = A(vb); w.tmp = A(vb); w.tmp2 = A(vb); w.rhs = A(vb);
     if (!w.r || !w.x || !w.tmp || !w.tmp2 || !w.rhs) return DWF_EINVAL;
@@ -302,8 +303,8 @@ int Hierarchy::alloc_level_work(int l, int ncol) {
         if (!w.P || !w.W) return DWF_EINVAL;
     }
     if (w.ksmooth > 0) {
-        w.Ps = A(vb * (w.ksmooth + 1));
-        w.Ws = A(vb * w.ksmooth);
+        w.Ps = A(vb * (w.kscycle + 1));
+        w.Ws = A(vb * w.kscycle);
         w.rs = A(vb);
         w.zt = A(vb);
         if (!w.Ps || !w.Ws || !w.rs || !w.zt) return DWF_EINVAL;
@@ -337,7 +338,7 @@ int Hierarchy::alloc_level_work(int l, int ncol) {
         return DWF_OK;
     };
     if (w.kmax > 0 && mk_gcr(w.gcr, w.kmax) != DWF_OK) return DWF_EINVAL;
-    if (w.ksmooth > 0 && mk_gcr(w.gsm, w.ksmooth) != DWF_OK) return DWF_EINVAL;
+    if (w.ksmooth > 0 && mk_gcr(w.gsm, w.kscycle) != DWF_OK) return DWF_EINVAL;
     return DWF_OK;
 }
 
@@ -511,7 +512,11 @@ int Hierarchy::smooth(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t s
     cpx<T>* Az = C<T>(w.tmp2);
     // the steps are the fused GCR iteration of the coarsest solve (inner products in
     // one pass, orthogonalisation and residual update in a second) with a stopping
-    // threshold that is never met, so that all ns steps are taken
+    // threshold that is never met, so that all ns steps are taken.  With a restart
+    // length ks < ns the steps run in cycles of ks (the orthogonalisation cost of a
+    // step grows with its index in the cycle); each cycle adds its correction to z and
+    // the next starts from the recursive residual.
+    const int ks = w.kscycle;
     GcrDev& g = w.gsm;
     auto body = [&]() -> int {
         HIPCHK(apply_A<T>(l, z, Az, t, ncol, st));
@@ -519,16 +524,25 @@ int Hierarchy::smooth(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t s
         HIPCHK(vconvert<T, T>(rs, Ps, nt, st));
         HIPCHK(norm2<T>(rs, n, ncol, g.rr, rw_, st));
         HIPCHK(gcr_dev_init(ncol, g, st));
-        for (int j = 0; j < ns; ++j) {
-            cpx<T>* Pj = Ps + (size_t)j * nt;
-            cpx<T>* Wj = Ws + (size_t)j * nt;
-            const int* s_in = (j % 2 == 0) ? g.stop : g.stop2;
-            int* s_out = (j % 2 == 0) ? g.stop2 : g.stop;
-            HIPCHK(apply_A<T>(l, Pj, Wj, t, ncol, st));
-            HIPCHK(gcr_fused_step<T>(Ws, nt, j, Wj, rs, (j + 1 < ns) ? Ps + (size_t)(j + 1) * nt : nullptr, n, ncol,
-                                     -1.0, s_in, s_out, g, rw_, st));
+        for (int c0 = 0; c0 < ns; c0 += ks) {
+            const int kc = std::min(ks, ns - c0);
+            for (int j = 0; j < kc; ++j) {
+                cpx<T>* Pj = Ps + (size_t)j * nt;
+                cpx<T>* Wj = Ws + (size_t)j * nt;
+                const int* s_in = (j % 2 == 0) ? g.stop : g.stop2;
+                int* s_out = (j % 2 == 0) ? g.stop2 : g.stop;
+                HIPCHK(apply_A<T>(l, Pj, Wj, t, ncol, st));
+                HIPCHK(gcr_fused_step<T>(Ws, nt, j, Wj, rs, (j + 1 < kc) ? Ps + (size_t)(j + 1) * nt : nullptr, n,
+                                         ncol, -1.0, s_in, s_out, g, rw_, st));
+            }
+            if (c0 + kc < ns) {
+                // z += this cycle's correction, P_0 = the residual, the last step's flags to g.stop
+                HIPCHK(gcr_solve_xupdate_restart<T>(Ps, nt, kc, z, n, ncol, rs, (kc % 2 == 0) ? g.stop : g.stop2,
+                                                    g, st));
+            } else {
+                HIPCHK((gcr_solve_xupdate<T, T>(Ps, nt, kc, z, n, ncol, true, g, st)));
+            }
         }
-        HIPCHK((gcr_solve_xupdate<T, T>(Ps, nt, ns, z, n, ncol, true, w.gsm, st)));
         return DWF_OK;
     };
     if (use_graphs_ && st == st_) {

@@ -45,7 +45,8 @@ struct Level {
 struct LevelWork {
     int ncol = 0;
     int kmax = 0;                 // flexible GCR restart length (0: none)
-    int ksmooth = 0;
+    int ksmooth = 0;              // post-smoothing steps
+    int kscycle = 0;              // steps per smoothing cycle (the GCR restart length)
     void* P = nullptr;            // [kmax] directions
     void* W = nullptr;            // [kmax] A directions
     void* r = nullptr;
@@ -53,8 +54,8 @@ struct LevelWork {
     void* tmp = nullptr;
     void* tmp2 = nullptr;
     void* rhs = nullptr;
-    void* Ps = nullptr;           // [ksmooth+1] smoother directions
-    void* Ws = nullptr;           // [ksmooth]
+    void* Ps = nullptr;           // [kscycle+1] smoother directions
+    void* Ws = nullptr;           // [kscycle]
     void* rs = nullptr;
     void* zt = nullptr;           // K-cycle output scratch
     void* py = nullptr;           // fine level with the PV polynomial: p(X) w and X's intermediate

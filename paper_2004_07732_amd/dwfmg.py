@@ -138,6 +138,7 @@ class CParams(ctypes.Structure):
         ("setup_tol", ctypes.c_double),
         ("outer_restart", ctypes.c_int),
         ("smooth_iters", ctypes.c_int),
+        ("smooth_restart", ctypes.c_int),
         ("inter_maxit", ctypes.c_int),
         ("inter_tol", ctypes.c_double),
         ("inter_restart", ctypes.c_int),
@@ -185,6 +186,7 @@ class MGParams:
     setup_tol: float = 1e-4
     outer_restart: int = 16
     smooth_iters: int = 8
+    smooth_restart: int = 0        # restart length of the post-smoothing GCR (0: none)
     inter_maxit: int = 16
     inter_tol: float = 0.25
     inter_restart: int = 16
@@ -217,7 +219,7 @@ class MGParams:
             c.Ls_coarse[l] = self.Ls_coarse[l]
             c.link_prec[l] = self.link_prec[l]
             c.vec_prec[l] = self.vec_prec[l]
-        for name in ("fine_prec", "m_setup", "setup_iters", "setup_tol", "outer_restart", "smooth_iters",
+        for name in ("fine_prec", "m_setup", "setup_iters", "setup_tol", "outer_restart", "smooth_iters", "smooth_restart",
                      "inter_maxit", "inter_tol", "inter_restart", "coarsest_maxit", "coarsest_tol", "inner_tol",
                      "max_iters", "max_outer", "coarsest_nev", "eig_degree", "eig_maxit", "eig_tol",
                      "coarsest_solver", "coarsest_restart", "transfer"):

@@ -143,6 +143,26 @@ def test_workspace_bytes_on_the_host(libdwf):
     assert dwfmg.workspace_bytes(L, L, 1, p, 1) == 0
 
 
+def test_smoother_restart_parameters_on_the_host(libdwf):
+    """Post-smoothing steps: at most 16 in one GCR cycle; with a restart length of
+    1..16, up to 64 steps, and the smoother's direction buffers hold one cycle
+    (24 steps in cycles of 6 need less memory than 16 steps in one cycle)."""
+    from paper_2004_07732_amd import dwfmg
+    L, Ls = 64, 8
+    ok = lambda **kw: dwfmg.workspace_bytes(L, L, Ls, _headline_params(dwfmg, **kw), 1)
+    assert ok(smooth_iters=16) > 0
+    assert ok(smooth_iters=17) == 0
+    assert ok(smooth_iters=24, smooth_restart=6) > 0
+    assert ok(smooth_iters=64, smooth_restart=16) > 0
+    assert ok(smooth_iters=65, smooth_restart=16) == 0
+    assert ok(smooth_iters=16, smooth_restart=17) == 0
+    assert ok(smooth_iters=16, smooth_restart=-1) == 0
+    fine_vec = L * L * Ls * 2 * 8     # one FP32 fine vector
+    assert ok(smooth_iters=16) - ok(smooth_iters=24, smooth_restart=6) >= 2 * 10 * fine_vec
+    # a restart at least as long as the steps is no restart
+    assert ok(smooth_iters=8, smooth_restart=8) == ok(smooth_iters=8) == ok(smooth_iters=8, smooth_restart=12)
+
+
 def _span(src, header):
     """(start, end) of the brace-matched definition whose header matches `header`."""
     m = re.search(header, src, flags=re.M)

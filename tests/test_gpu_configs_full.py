@@ -111,13 +111,13 @@ def test_headline_configuration(nrhs):
     """The benchmark's own configuration at full size: 256^2 x Ls 16, beta 6,
     m_f 0.01, 2 levels (4x4 aggregates, 16 null vectors, coarse Ls 2), FP32 fine
     level, BF16 matrix-core coarse links, FP64 coarse vectors, coarsest GCR(6) to
-    0.25, FP64 defect correction to 1e-10; the oracle recomputes the residual of
-    every right-hand side."""
+    0.5, 20 post-smoothing GCR steps in cycles of 5, FP64 defect correction to
+    1e-10; the oracle recomputes the residual of every right-hand side."""
     L, Ls, m, M5 = 256, 16, 0.01, -1.0
     g, b, starts = headline_inputs(nrhs)
     p = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[dwfmg.P_F64],
                        fine_prec=dwfmg.P_F32, coarsest_solver=dwfmg.COARSEST_GCR, coarsest_restart=6,
-                       coarsest_tol=0.25)
+                       coarsest_tol=0.5, smooth_iters=20, smooth_restart=5)
     mg = dwfmg.MG(torch.from_numpy(g.U).cuda(), Ls, m, M5, p, starts, max_nrhs=nrhs)
     x, st = mg.solve(b, 1e-10)
     say(f"[headline] nrhs {nrhs}: {st.solve_ms:.0f} ms, fine iters {st.fine_iters}, residual {st.true_rel_residual:.2e}")

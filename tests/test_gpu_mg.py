@@ -154,6 +154,24 @@ def test_kcycle_matches_oracle(levels):
     assert err < 1e-8
 
 
+@pytest.mark.parametrize("restart", [3, 4])
+def test_kcycle_restarted_smoother_matches_oracle(restart):
+    """Eight post-smoothing GCR steps in cycles of 3 (3, 3, 2) or 4 (4, 4): the GPU
+    continues each cycle from the recursive residual, the oracle from the true one;
+    the two agree to rounding."""
+    U, mg, omg = build_pair(16, 4, 0.05, -1.0, LEVELS_2, 352, smooth_restart=restart)
+    omg.params.smooth_restart = restart
+    r = inputs.gaussian_field((1, 4, 16, 16, 2), 353)
+    got = mg.level_op(0, dwfmg.MG_OP_KCYCLE, T(r), 1).cpu().numpy()
+    want = omg.kcycle(0, r[0])
+    err = rel(got[0], want)
+    print(f"K-cycle (smoother restart {restart}) GPU vs oracle relative difference: {err:.2e}")
+    assert err < 1e-8
+    # and the restart changes the result (the cycles are not one GCR(8))
+    omg.params.smooth_restart = 0
+    assert rel(omg.kcycle(0, r[0]), want) > 1e-6
+
+
 def test_setup_relaxation_parity():
     """With the default 250-iteration setup the GPU and oracle null vectors come
     from the same CG on the same starts."""

@@ -249,6 +249,35 @@ def test_smoothed_kcycle_is_coarse_correction_plus_minimal_residual_steps():
     assert kcycle_error() < 1e-9
 
 
+@pytest.mark.parametrize("restart", [3, 4])
+def test_restarted_smoother_is_a_sequence_of_minimal_residual_cycles(restart):
+    """With a smoother restart length k, eight steps are cycles of k (the last one
+    shorter): each cycle adds the minimiser of the residual over the Krylov space of
+    the residual it starts from (dense least squares, as above).  The same
+    hierarchy without the restart gives a different result."""
+    mg, shape = _small_hierarchy(8)
+    mg.params.smooth_restart = restart
+    r = cgauss(shape, 93)
+    got = mg.kcycle(0, r).reshape(-1)
+    A0 = O.assemble(lambda v: mg.A(0, v), shape)
+    Ac = O.assemble(lambda v: mg.A(1, v), (2, 2, 2, 4))
+    rc = mg.restrict(0, r)
+    ec = np.linalg.solve(Ac, rc.reshape(-1)).reshape(rc.shape)
+    z = mg.prolong(0, ec).reshape(-1)
+    rs = r.reshape(-1) - A0 @ z
+    done = 0
+    while done < 8:
+        k = min(restart, 8 - done)
+        Q = krylov_basis(A0, rs, k)
+        c, *_ = np.linalg.lstsq(A0 @ Q, rs, rcond=None)
+        z = z + Q @ c
+        rs = rs - A0 @ (Q @ c)
+        done += k
+    assert np.linalg.norm(got - z) / np.linalg.norm(z) < 1e-9
+    mg.params.smooth_restart = 0
+    assert np.linalg.norm(mg.kcycle(0, r).reshape(-1) - z) / np.linalg.norm(z) > 1e-6
+
+
 class _MGSmoothSign(O.MG):
     def kcycle(self, l, r):
         e = self.coarse_solve(l + 1, self.restrict(l, r))
