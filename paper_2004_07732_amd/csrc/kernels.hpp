@@ -240,14 +240,16 @@ hipError_t force(const cpx<double>* U, const cpx<double>* X, const cpx<double>* 
 // U = exp(i theta) for n angles
 hipError_t links_from_theta(const double* theta, cpx<double>* U, long long n, hipStream_t st);
 // copy up to kPublishItems blocks of 32-bit words from device memory to host-coherent
-// memory (device views), then store `value` to *seq (release, system scope)
+// memory (device views), then store the next sequence number to *seq (release, system
+// scope).  The number is one more than the device counter *ctr, which the kernel
+// advances, so that a launch captured in a graph publishes a new number on every replay.
 constexpr int kPublishItems = 3;
 struct PublishArgs {
     const uint32_t* src[kPublishItems];
     uint32_t* dst[kPublishItems];
     int words[kPublishItems];
     unsigned* seq;
-    unsigned value;
+    unsigned* ctr;
 };
 hipError_t publish_to_host(const PublishArgs& a, hipStream_t st);
 // scalar finiteness check: flag[0] = 1 if any entry of x is not finite

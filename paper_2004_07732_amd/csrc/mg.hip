@@ -111,10 +111,11 @@ hipError_t Hierarchy::publish(hipStream_t st, std::initializer_list<HostCopy> it
         a.words[k] = (int)(c.bytes / 4);
         ++k;
     }
-    if (++pub_ == 0) ++pub_;   // 0 is the word's initial value
     a.seq = reinterpret_cast<unsigned*>(views_[3].dev);
-    a.value = pub_;
-    *value = pub_;
+    a.ctr = d_pub_ctr_;
+    // the kernel publishes one more than its counter; outside a capture the host's count
+    // advances with it (a captured launch advances it at every replay: see the caller)
+    if (!capturing_) *value = ++pub_;
     return publish_to_host(a, st);
 }
 
@@ -472,6 +473,9 @@ Task Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double to
         // solution update, and the next cycle continues from the recursive residual (its
         // norm and the stop flags are those of the last fused step)
         HIPCHK(gcr_solve_xupdate_restart<T>(P, nt, kmax, x, n, ncol, r, (kmax % 2 == 0) ? g.stop : g.stop2, g, st));
+        // the cycle ends by publishing the stop flags to the host (part of the graph)
+        unsigned v = 0;
+        HIPCHK(publish(st, {{h_int_, g.stop, sizeof(int) * ncol}}, &v));
         return DWF_OK;
     };
     const int max_cycles = std::max(1, (maxit + kmax - 1) / kmax);
@@ -481,7 +485,9 @@ Task Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double to
         } else if (int e = cycle()) {
             co_return e;
         }
-        CO_HIPCHK(co_await read_back(st, {{h_int_, g.stop, sizeof(int) * ncol}}));
+        // a replayed cycle publishes without the host's count seeing the launch
+        if (use_graphs_ && st == st_) ++pub_;
+        CO_HIPCHK(co_await wait_for(st, pub_));
         bool all = true;
         for (int cc = 0; cc < ncol; ++cc)
             if (h_int_[cc] == 0) all = false;
@@ -764,6 +770,8 @@ int Hierarchy::plan(int Lx, int Ly, int Ls, int max_ncol) {
     rw_.max_cols = std::max({max_ncol, 64, dnk});
     rw_.partial = (double*)T(sizeof(double) * (size_t)rw_.max_cols * rw_.max_q * rw_.nblk);
     d_flag_ = (int*)T(sizeof(int) * 4);
+    d_pub_ctr_ = (unsigned*)T(sizeof(unsigned) * 4);
+    if (d_pub_ctr_) zero_at_setup_.emplace_back(d_pub_ctr_, sizeof(unsigned) * 4);
     const size_t nf = F.vec_elems() * max_ncol;
     r64_ = (cpx<double>*)T(zb * nf);
     t64_ = (cpx<double>*)T(zb * nf);
@@ -872,8 +880,6 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
         HIPCHK(hipHostMalloc((void**)&h_int_, sizeof(int) * 4 * hc, hipHostMallocCoherent));
         HIPCHK(hipHostMalloc((void**)&h_cg_, sizeof(CgScal) * hc, hipHostMallocCoherent));
         HIPCHK(hipHostMalloc((void**)&h_seq_, 64, hipHostMallocCoherent));
-        *h_seq_ = 0;
-        pub_ = 0;
         void* hp[4] = {h_scal_, h_int_, h_cg_, h_seq_};
         const size_t hb[4] = {sizeof(double) * 4 * hc, sizeof(int) * 4 * hc, sizeof(CgScal) * hc, 64};
         for (int i = 0; i < 4; ++i) {
@@ -885,6 +891,9 @@ int Hierarchy::setup(const cpx<double>* U, int Lx, int Ly, int Ls, double m_, do
     const char* ng = std::getenv("DWF_NO_GRAPHS");
     use_graphs_ = !(ng && ng[0] == '1');
     for (auto& z : zero_at_setup_) HIPCHK(hipMemsetAsync(z.first, 0, z.second, st));
+    // published numbers restart with the device counter
+    *h_seq_ = 0;
+    pub_ = 0;
     Level& f = levels[0];
     HIPCHK(hipMemcpyAsync(f.U64, U, sizeof(cpx<double>) * 2 * f.nsites, hipMemcpyDeviceToDevice, st));
     HIPCHK((vconvert<double, float>(f.U64, f.U32, 2 * (size_t)f.nsites, st)));

@@ -158,7 +158,8 @@ private:
     unsigned* h_seq_ = nullptr;
     struct HostView { char* host = nullptr; char* dev = nullptr; size_t bytes = 0; };
     HostView views_[4];
-    unsigned pub_ = 0;            // last sequence number published
+    unsigned pub_ = 0;            // sequence number of the last publishing launch enqueued
+    unsigned* d_pub_ctr_ = nullptr;   // its device counterpart, advanced by the kernel
     int* d_flag_ = nullptr;
     cpx<double>* r64_ = nullptr;
     cpx<double>* t64_ = nullptr;
@@ -231,6 +232,8 @@ private:
         const hipError_t e = publish(st, items, &v);
         return HostRead{this, st, v, e};
     }
+    // wait for a number whose publishing launch is already enqueued (inside a graph)
+    HostRead wait_for(hipStream_t st, unsigned v) { return HostRead{this, st, v, hipSuccess}; }
     struct StreamWait {
         Hierarchy* h;
         hipStream_t st;

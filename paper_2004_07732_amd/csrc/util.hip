@@ -130,11 +130,15 @@ __global__ void __launch_bounds__(64) k_publish(PublishArgs a) {
     for (int k = 0; k < kPublishItems; ++k)
         for (int i = threadIdx.x; i < a.words[k]; i += 64) a.dst[k][i] = a.src[k][i];
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(a.seq, a.value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (threadIdx.x == 0) {
+        const unsigned v = *a.ctr + 1u;
+        *a.ctr = v;
+        __hip_atomic_store(a.seq, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 hipError_t publish_to_host(const PublishArgs& a, hipStream_t st) {
-    if (!a.seq) return hipErrorInvalidValue;
+    if (!a.seq || !a.ctr) return hipErrorInvalidValue;
     for (int k = 0; k < kPublishItems; ++k)
         if (a.words[k] < 0 || (a.words[k] > 0 && (!a.src[k] || !a.dst[k]))) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, a);
