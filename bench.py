@@ -239,16 +239,40 @@ def coarse_mfma_per_launch(nsites, n, Ls_c, ncol, tw=None):
     return nsites * (n // 16) * ntile * 2 * (5 * n // 16)
 
 
-def solve_model_bytes(fine_applies, coarse_iters, k, L, Ls, coarse_launch_bytes, coarse_vec_bytes):
+def smoother_model_passes(ns, ks):
+    """Fine-vector passes of one post-smoothing call: the initial residual (subtract:
+    3, copy: 2, norm: 1), then per step j of a cycle of kc steps the multi-dot (j + 2)
+    and the fused update (j + 2 read; w and r written, and the next direction except
+    after the cycle's last step), and per cycle the solution update (kc + 2), with the
+    restart copy (2 more) on every cycle but the last."""
+    if ns <= 0:
+        return 0
+    ks = ks if 0 < ks < ns else ns
+    passes, done = 6, 0
+    while done < ns:
+        kc = min(ks, ns - done)
+        passes += kc * kc + 6 * kc - 1 + kc + 2
+        done += kc
+        if done < ns:
+            passes += 2
+    return passes
+
+
+def solve_model_bytes(fine_applies, coarse_iters, k, L, Ls, coarse_launch_bytes, coarse_vec_bytes,
+                      kcycles=0, smooth_iters=0, smooth_restart=0):
     """HBM bytes of one solve by a model (a lower bound): the fine FP32 stencils
     (vector read and written, links once per apply), two coarse stencils per
-    coarsest iteration (A-hat = D_PV-hat^dag D_DW-hat), and the coarsest GCR(k)
-    vector algebra: at direction j the multi-dot reads j + 2 vectors and the fused
-    update reads j + 2 and writes 3; each cycle's solution update and restart move
-    k + 4.  The fine-level vector algebra is not counted."""
+    coarsest iteration (A-hat = D_PV-hat^dag D_DW-hat), the coarsest GCR(k)
+    vector algebra (at direction j the multi-dot reads j + 2 vectors and the fused
+    update reads j + 2 and writes 3, 2 after the cycle's last direction; each
+    cycle's solution update and restart move k + 4) and, for `kcycles` K-cycles,
+    the post-smoother's FP32 vector algebra (smoother_model_passes).  The outer
+    flexible GCR's vector algebra is not counted."""
     fine_apply = 2 * Ls * L * L * 2 * 8 + 2 * L * L * 8
+    fine_vec = Ls * L * L * 2 * 8
     return (fine_applies * fine_apply + 2 * coarse_iters * coarse_launch_bytes
-            + coarse_iters * (k * k + 7 * k + 4) / k * coarse_vec_bytes)
+            + coarse_iters * (k * k + 7 * k + 3) / k * coarse_vec_bytes
+            + kcycles * smoother_model_passes(smooth_iters, smooth_restart) * fine_vec)
 
 
 def timed(mg, b, steps, warmup, tol=1e-10):
@@ -497,8 +521,9 @@ def main():
                    "algorithmic_TFLOP_s": useful_tf, "peak_bf16_TFLOP_s": PEAK_BF16_TFLOPS,
                    "frac_issued": issued_tf / PEAK_BF16_TFLOPS, "frac_algorithmic": useful_tf / PEAK_BF16_TFLOPS}
     solve_bytes = (solve_model_bytes(stats.fine_applies, stats.level_iters[0], args.coarsest_restart, L, Ls,
-                                     coarse_bytes, nsites * Lsc * n * vec_bytes)
-                   if args.coarsest == "gcr" else None)
+                                     coarse_bytes, nsites * Lsc * n * vec_bytes, kcycles=stats.level_calls[0],
+                                     smooth_iters=args.smooth_iters, smooth_restart=args.smooth_restart)
+                   if args.coarsest == "gcr" and len(wl["nvec"]) == 1 else None)
     solve_roofline = None
     if solve_bytes is not None:
         gbs = solve_bytes / t_step / 1e9

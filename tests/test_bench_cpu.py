@@ -47,8 +47,26 @@ def test_whole_solve_byte_model_worked_example():
     # 2 x 65536 x 8 B of links = 34 603 008 B
     fine = 34_603_008
     coarse_vec = 4096 * 2 * 32 * 16
-    # GCR(6): per cycle sum_{j<6} (2j + 7) = 72 vector passes, plus 6 + 4 for the
-    # solution update and restart: 82 passes per 6 iterations
+    # GCR(6): per cycle sum_{j<6} (2j + 7) = 72 vector passes less the direction copy
+    # after the last one, plus 6 + 4 for the solution update and restart: 81 passes
+    # per 6 iterations
     got = bench.solve_model_bytes(10, 12, 6, 256, 16, 58_720_256, coarse_vec)
-    want = 10 * fine + 2 * 12 * 58_720_256 + 12 * 82 / 6 * coarse_vec
+    want = 10 * fine + 2 * 12 * 58_720_256 + 12 * 81 / 6 * coarse_vec
     assert abs(got - want) <= 1e-6 * want
+
+
+def test_smoother_byte_model_worked_example():
+    # 20 steps in cycles of 5: 6 passes for the initial residual; per cycle
+    # sum_{j<5} (2j + 7) = 55 passes less the last direction copy, and a solution
+    # update of 7, with a restart copy of 2 on the first three cycles:
+    # 6 + 4 * 61 + 3 * 2 = 256
+    assert bench.smoother_model_passes(20, 5) == 256
+    # the paper's 8 steps in one cycle: 6 + (64 + 48 - 1) + 10 = 127
+    assert bench.smoother_model_passes(8, 0) == 127 == bench.smoother_model_passes(8, 8)
+    assert bench.smoother_model_passes(0, 5) == 0
+    fine_vec = 16 * 256 * 256 * 2 * 8
+    base = bench.solve_model_bytes(10, 12, 6, 256, 16, 58_720_256, 4096 * 2 * 32 * 16)
+    got = bench.solve_model_bytes(10, 12, 6, 256, 16, 58_720_256, 4096 * 2 * 32 * 16, kcycles=3, smooth_iters=20,
+                                  smooth_restart=5)
+    assert got - base == 3 * 256 * fine_vec
+
