@@ -658,9 +658,12 @@ __global__ void k_gcr_solve(int k, int ncol, GcrDev g) {
     gcr_back_substitute(k, g.wr + 2 * b, g.nn + b, g.D + b * g.kmax * 2, (size_t)g.kmax, g.gam + 2 * b);
 }
 
-template <typename T, typename Tx>
-__global__ void k_gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int accumulate, GcrDev g,
+// (the direction count K is a template argument, as in the fused GCR kernels: with a
+// run-time count every direction's load sat behind its own branch and waited there)
+template <typename T, typename Tx, int K>
+__global__ void k_gcr_xupdate(const cpx<T>* P, size_t pstride, cpx<Tx>* x, size_t n, int accumulate, GcrDev g,
                               int solve, const cpx<T>* rsrc, cpx<T>* p0dst, const int* stop_src, int ncol) {
+    constexpr int k = K;
     const int col = blockIdx.y;
     const size_t o = (size_t)col * n;
     const double* gam = g.gam + 2 * (size_t)col * g.kmax;
@@ -689,21 +692,20 @@ __global__ void k_gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x
         __syncthreads();
         gam = sgam;
     }
-    cpx<double> c[16];
+    cpx<double> c[K > 0 ? K : 1];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) c[i] = (i < k) ? cpx<double>{gam[2 * i], gam[2 * i + 1]} : cpx<double>{0.0, 0.0};
+    for (int i = 0; i < K; ++i) c[i] = cpx<double>{gam[2 * i], gam[2 * i + 1]};
     if (stop_src && stop_src != g.stop && blockIdx.x == 0 && blockIdx.y == 0)
         for (int cc = threadIdx.x; cc < ncol; cc += blockDim.x) g.stop[cc] = stop_src[cc];
     GRID_STRIDE(e, n) {
         cpx<double> acc = {0.0, 0.0};
         if (accumulate) acc = {(double)x[o + e].re, (double)x[o + e].im};
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (i < k) {
-                const cpx<double> p = up(P[(size_t)i * pstride + o + e]);
-                acc.re += c[i].re * p.re - c[i].im * p.im;
-                acc.im += c[i].re * p.im + c[i].im * p.re;
-            }
+        for (int i = 0; i < K; ++i) {
+            const cpx<double> p = up(P[(size_t)i * pstride + o + e]);
+            acc.re += c[i].re * p.re - c[i].im * p.im;
+            acc.im += c[i].re * p.im + c[i].im * p.re;
+        }
         x[o + e] = {(Tx)acc.re, (Tx)acc.im};
         // restart: the residual becomes the first direction (after P_0 was read above)
         if (p0dst) p0dst[o + e] = rsrc[o + e];
@@ -777,11 +779,19 @@ hipError_t gcr_solve(int k, int ncol, const GcrDev& g, hipStream_t st) {
     return hipGetLastError();
 }
 template <typename T, typename Tx>
+void launch_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int ncol, bool accumulate,
+                    const GcrDev& g, int solve, const cpx<T>* rsrc, cpx<T>* p0dst, const int* stop_src,
+                    hipStream_t st) {
+    with_j(k, [&](auto kc) {
+        hipLaunchKernelGGL((k_gcr_xupdate<T, Tx, decltype(kc)::value>), ew_grid(n, ncol), dim3(kBlock), 0, st, P,
+                           pstride, x, n, accumulate ? 1 : 0, g, solve, rsrc, p0dst, stop_src, ncol);
+    }, std::make_integer_sequence<int, 17>{});
+}
+template <typename T, typename Tx>
 hipError_t gcr_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x, size_t n, int ncol,
                        bool accumulate, const GcrDev& g, hipStream_t st) {
-    if (k > 16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_gcr_xupdate<T, Tx>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, pstride, k, x, n,
-                       accumulate ? 1 : 0, g, 0, (const cpx<T>*)nullptr, (cpx<T>*)nullptr, (const int*)nullptr, 0);
+    if (k < 0 || k > 16) return hipErrorInvalidValue;
+    launch_xupdate<T, Tx>(P, pstride, k, x, n, ncol, accumulate, g, 0, nullptr, nullptr, nullptr, st);
     return hipGetLastError();
 }
 template <typename T, typename Tx>
@@ -794,8 +804,7 @@ hipError_t gcr_solve_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<Tx>* x,
         if (hipError_t e = gcr_solve(k, ncol, g, st)) return e;
         return gcr_xupdate<T, Tx>(P, pstride, k, x, n, ncol, accumulate, g, st);
     }
-    hipLaunchKernelGGL((k_gcr_xupdate<T, Tx>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, pstride, k, x, n,
-                       accumulate ? 1 : 0, g, 1, (const cpx<T>*)nullptr, (cpx<T>*)nullptr, (const int*)nullptr, 0);
+    launch_xupdate<T, Tx>(P, pstride, k, x, n, ncol, accumulate, g, 1, nullptr, nullptr, nullptr, st);
     return hipGetLastError();
 }
 template <typename T>
@@ -806,8 +815,7 @@ hipError_t gcr_solve_xupdate_restart(cpx<T>* P, size_t pstride, int k, cpx<T>* x
         if (hipError_t e = gcr_solve_xupdate<T, T>(P, pstride, k, x, n, ncol, true, g, st)) return e;
         return gcr_restart<T>(r, P, n, ncol, stop_src, g, st);
     }
-    hipLaunchKernelGGL((k_gcr_xupdate<T, T>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, pstride, k, x, n, 1, g, 1, r, P,
-                       stop_src, ncol);
+    launch_xupdate<T, T>(P, pstride, k, x, n, ncol, true, g, 1, r, P, stop_src, st);
     return hipGetLastError();
 }
 
