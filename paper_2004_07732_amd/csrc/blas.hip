@@ -402,6 +402,13 @@ hipError_t cg_update_p(cpx<T>* p, const cpx<T>* z, size_t n, int ncol, const CgS
 // ------------------------------------------------------------ GCR
 namespace {
 __device__ __forceinline__ cpx<double> ld2(const double* p) { return {p[0], p[1]}; }
+// entries per thread whose loads the fused GCR kernels issue together (bounded by
+// the registers of U (j + 2) loaded vectors)
+template <typename T>
+constexpr int gcr_unroll(int j) {
+    return sizeof(T) == 4 ? (j <= 6 ? 4 : 2) : (j <= 6 ? 2 : 1);
+}
+
 __device__ __forceinline__ cpx<double> cdiv_real(cpx<double> a, double d) {
     return d > 0.0 ? cpx<double>{a.re / d, a.im / d} : cpx<double>{0.0, 0.0};
 }
@@ -526,20 +533,43 @@ k_gcr_dots(const cpx<T>* W, size_t wstride, const cpx<T>* w, const cpx<T>* r, si
     double v[35];
 #pragma unroll
     for (int q = 0; q < 35; ++q) v[q] = 0.0;
-    if (!stopped) GRID_STRIDE(e, n) {
-        const cpx<double> we = up(w[o + e]), re = up(r[o + e]);
+    // the entries of a thread are added in grid-stride order; U of them are loaded
+    // together, so that a thread keeps U (j + 2) loads in flight (same sums, same order)
+    constexpr int U = gcr_unroll<T>(j);
+    auto add = [&](const cpx<T>& wt, const cpx<T>& rt, const cpx<T>* Wt) {
+        const cpx<double> we = up(wt), re = up(rt);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if (i < j) {
-                const cpx<double> p = cjmul(up(W[(size_t)i * wstride + o + e]), we);
-                v[3 + 2 * i] += p.re;
-                v[4 + 2 * i] += p.im;
-            }
+        for (int i = 0; i < j; ++i) {
+            const cpx<double> p = cjmul(up(Wt[i]), we);
+            v[3 + 2 * i] += p.re;
+            v[4 + 2 * i] += p.im;
         }
         v[0] += we.re * we.re + we.im * we.im;
         const cpx<double> p = cjmul(we, re);
         v[1] += p.re;
         v[2] += p.im;
+    };
+    if (!stopped) {
+        const size_t stride = (size_t)gridDim.x * blockDim.x;
+        size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+        for (; e + (U - 1) * stride < n; e += U * stride) {
+            cpx<T> wv[U], rv[U], Wv[U][j > 0 ? j : 1];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                wv[u] = w[o + e + u * stride];
+                rv[u] = r[o + e + u * stride];
+#pragma unroll
+                for (int i = 0; i < j; ++i) Wv[u][i] = W[(size_t)i * wstride + o + e + u * stride];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) add(wv[u], rv[u], Wv[u]);
+        }
+        for (; e < n; e += stride) {
+            cpx<T> Wt[j > 0 ? j : 1];
+#pragma unroll
+            for (int i = 0; i < j; ++i) Wt[i] = W[(size_t)i * wstride + o + e];
+            add(w[o + e], r[o + e], Wt);
+        }
     }
     write_partials<35>(v, 2 * j + 3, rw, col, sh, tot);
 }
@@ -575,21 +605,39 @@ k_gcr_fused_update(const cpx<T>* W, size_t wstride, cpx<T>* w, cpx<T>* r, cpx<T>
 #pragma unroll
         for (int i = 0; i < 16; ++i) cc[i] = {(T)c[i].re, (T)c[i].im};
         const cpx<T> at = {(T)a.re, (T)a.im};
-        GRID_STRIDE(e, n) {
-            cpx<T> we = w[o + e];
+        // one entry: w' = w - sum c_i W_i, r -= a w', copy = r (U entries' loads issued together)
+        auto step = [&](size_t i0, cpx<T> we, cpx<T> re, const cpx<T>* Wt) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (i < j) {
-                    const cpx<T> Wi = W[(size_t)i * wstride + o + e];
-                    we.re -= cc[i].re * Wi.re - cc[i].im * Wi.im;
-                    we.im -= cc[i].re * Wi.im + cc[i].im * Wi.re;
-                }
-            w[o + e] = we;
-            cpx<T> re = r[o + e];
+            for (int i = 0; i < j; ++i) {
+                we.re -= cc[i].re * Wt[i].re - cc[i].im * Wt[i].im;
+                we.im -= cc[i].re * Wt[i].im + cc[i].im * Wt[i].re;
+            }
+            w[i0] = we;
             re.re -= at.re * we.re - at.im * we.im;
             re.im -= at.re * we.im + at.im * we.re;
-            r[o + e] = re;
-            if (copy) copy[o + e] = re;
+            r[i0] = re;
+            if (copy) copy[i0] = re;
+        };
+        constexpr int U = gcr_unroll<T>(j);
+        const size_t stride = (size_t)gridDim.x * blockDim.x;
+        size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+        for (; e + (U - 1) * stride < n; e += U * stride) {
+            cpx<T> wv[U], rv[U], Wv[U][j > 0 ? j : 1];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                wv[u] = w[o + e + u * stride];
+                rv[u] = r[o + e + u * stride];
+#pragma unroll
+                for (int i = 0; i < j; ++i) Wv[u][i] = W[(size_t)i * wstride + o + e + u * stride];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) step(o + e + u * stride, wv[u], rv[u], Wv[u]);
+        }
+        for (; e < n; e += stride) {
+            cpx<T> Wt[j > 0 ? j : 1];
+#pragma unroll
+            for (int i = 0; i < j; ++i) Wt[i] = W[(size_t)i * wstride + o + e];
+            step(o + e, w[o + e], r[o + e], Wt);
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
