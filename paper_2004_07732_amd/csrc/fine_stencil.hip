@@ -34,6 +34,8 @@
 #include <string>
 #include <vector>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace dwf {
@@ -101,24 +103,38 @@ __device__ __forceinline__ spinor<R> unpack4(const typename vec4_of<R>::type& v)
     return r;
 }
 
-// write-once output: nontemporal stores keep it from displacing the input
-// slices that neighbouring workgroups are still reading from L2
-__device__ __forceinline__ void store_stream(spinor<float>* p, const spinor<float>& v) {
+// Output stores.  A large write-once output goes out with nontemporal stores, which
+// keep it from displacing the input slices that neighbouring workgroups are still
+// reading from L2; an output that fits the Infinity Cache with room to spare (the
+// solver's vectors, read again by the next launch) is stored normally so that it
+// stays there (kStreamStoreBytes, decided per launch).
+constexpr double kStreamStoreBytes = 64.0 * 1024 * 1024;
+template <bool NT>
+__device__ __forceinline__ void store_out(spinor<float>* p, const spinor<float>& v) {
     typedef float f32x4 __attribute__((ext_vector_type(4)));
-    __builtin_nontemporal_store(f32x4{v.c0.re, v.c0.im, v.c1.re, v.c1.im}, reinterpret_cast<f32x4*>(p));
+    const f32x4 x = {v.c0.re, v.c0.im, v.c1.re, v.c1.im};
+    if constexpr (NT) __builtin_nontemporal_store(x, reinterpret_cast<f32x4*>(p));
+    else *reinterpret_cast<f32x4*>(p) = x;
 }
-__device__ __forceinline__ void store_stream(spinor<double>* p, const spinor<double>& v) {
+template <bool NT>
+__device__ __forceinline__ void store_out(spinor<double>* p, const spinor<double>& v) {
     typedef double f64x2 __attribute__((ext_vector_type(2)));
     f64x2* q = reinterpret_cast<f64x2*>(p);
-    __builtin_nontemporal_store(f64x2{v.c0.re, v.c0.im}, q);
-    __builtin_nontemporal_store(f64x2{v.c1.re, v.c1.im}, q + 1);
+    const f64x2 x0 = {v.c0.re, v.c0.im}, x1 = {v.c1.re, v.c1.im};
+    if constexpr (NT) {
+        __builtin_nontemporal_store(x0, q);
+        __builtin_nontemporal_store(x1, q + 1);
+    } else {
+        q[0] = x0;
+        q[1] = x1;
+    }
 }
 
 // out = D psi  (RESID: out = b - D psi).  DW selects the domain-wall operator
 // (diagonal D_W(M5)+1 plus the fifth-dimension hop); otherwise a stack of
 // independent 2-d Wilson fields D_W(M).  `diag` = d + M5 + 1 or d + M,
 // `mwrap` = -m (the corner blocks of eq. DWoperator).
-template <typename R, bool DAG, bool DW, bool RESID>
+template <typename R, bool DAG, bool DW, bool RESID, bool NT>
 __global__ void __launch_bounds__(kBlock)
 fine_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in,
             spinor<R>* __restrict__ out, const spinor<R>* __restrict__ b,
@@ -187,7 +203,7 @@ fine_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in,
             res.c0 = bb.c0 - res.c0;
             res.c1 = bb.c1 - res.c1;
         }
-        store_stream(out + o, res);
+        store_out<NT>(out + o, res);
         if (DW) { prv = cur; cur = nxt; }
     }
 }
@@ -200,7 +216,7 @@ fine_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in,
 // barrier, read the four neighbours, evaluate, store.  The buffer written at
 // slice s was last read at slice s-2, before the barrier of slice s-1, so one
 // barrier per slice suffices.  Requires Lx % TX == 0 and Ly % TY == 0.
-template <typename R, bool DAG, bool RESID, int TX, int TY>
+template <typename R, bool DAG, bool RESID, int TX, int TY, bool NT>
 __global__ void __launch_bounds__(TX * TY)
 fine_tile_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in, spinor<R>* __restrict__ out,
                  const spinor<R>* __restrict__ b, const int* __restrict__ skip, int skip_stride, int Lx, int Ly,
@@ -276,7 +292,7 @@ fine_tile_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in,
             res.c0 = bb.c0 - res.c0;
             res.c1 = bb.c1 - res.c1;
         }
-        store_stream(out + o, res);
+        store_out<NT>(out + o, res);
         prv = cur;
         cur = nxt;
         nxt = unpack4<R>(nn);
@@ -436,17 +452,26 @@ static hipError_t launch_tile(const cpx<R>* U, const spinor<R>* si, spinor<R>* s
                               int Ly, int Ls, int ncol, R diag, R mwrap, bool dagger, const int* skip,
                               int skip_stride, int cs, hipStream_t st) {
     if (Lx % TX || Ly % TY) return hipErrorInvalidValue;
+    const int nt = (double)Lx * Ly * Ls * ncol * sizeof(spinor<R>) >= kStreamStoreBytes ? 1 : 0;
     const int nchunk = (Ls + cs - 1) / cs;
     const int ntile = (Lx / TX) * (Ly / TY);
     const long long nblocks = (long long)ntile * nchunk * ncol;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
     dim3 grid((unsigned)nblocks), block(TX * TY);
+    auto go = [&](auto dag, auto resid, auto ntc) {
+        hipLaunchKernelGGL((fine_tile_kernel<R, decltype(dag)::value, decltype(resid)::value, TX, TY,
+                                             decltype(ntc)::value>),
+                           grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, ntile, diag,
+                           mwrap);
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
     if (sb) {
-        if (dagger) hipLaunchKernelGGL((fine_tile_kernel<R, true, true, TX, TY>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, ntile, diag, mwrap);
-        else        hipLaunchKernelGGL((fine_tile_kernel<R, false, true, TX, TY>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, ntile, diag, mwrap);
+        if (dagger) { if (nt) go(T_{}, T_{}, T_{}); else go(T_{}, T_{}, F_{}); }
+        else        { if (nt) go(F_{}, T_{}, T_{}); else go(F_{}, T_{}, F_{}); }
     } else {
-        if (dagger) hipLaunchKernelGGL((fine_tile_kernel<R, true, false, TX, TY>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, ntile, diag, mwrap);
-        else        hipLaunchKernelGGL((fine_tile_kernel<R, false, false, TX, TY>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, ntile, diag, mwrap);
+        if (dagger) { if (nt) go(T_{}, F_{}, T_{}); else go(T_{}, F_{}, F_{}); }
+        else        { if (nt) go(F_{}, F_{}, T_{}); else go(F_{}, F_{}, F_{}); }
     }
     return hipGetLastError();
 }
@@ -472,13 +497,21 @@ static hipError_t launch_fine(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, co
     const int nsb = (Lx * Ly + kBlock - 1) / kBlock;
     const long long nblocks = (long long)nsb * nchunk * ncol;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int nt = (double)Lx * Ly * Ls * ncol * sizeof(spinor<R>) >= kStreamStoreBytes ? 1 : 0;
     dim3 grid((unsigned)nblocks), block(kBlock);
+    auto go = [&](auto dag, auto resid, auto ntc) {
+        hipLaunchKernelGGL((fine_kernel<R, decltype(dag)::value, true, decltype(resid)::value, decltype(ntc)::value>),
+                           grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, nsb, diag,
+                           mwrap);
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
     if (b) {
-        if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, true, true>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
-        else        hipLaunchKernelGGL((fine_kernel<R, false, true, true>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
+        if (dagger) { if (nt) go(T_{}, T_{}, T_{}); else go(T_{}, T_{}, F_{}); }
+        else        { if (nt) go(F_{}, T_{}, T_{}); else go(F_{}, T_{}, F_{}); }
     } else {
-        if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, true, false>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
-        else        hipLaunchKernelGGL((fine_kernel<R, false, true, false>), grid, block, 0, st, U, si, so, sb, skip, skip_stride, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
+        if (dagger) { if (nt) go(T_{}, F_{}, T_{}); else go(T_{}, F_{}, F_{}); }
+        else        { if (nt) go(F_{}, F_{}, T_{}); else go(F_{}, F_{}, F_{}); }
     }
     return hipGetLastError();
 }
@@ -495,9 +528,14 @@ hipError_t wilson2d(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int 
     auto* si = reinterpret_cast<const spinor<R>*>(in);
     auto* so = reinterpret_cast<spinor<R>*>(out);
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int nt = (double)Lx * Ly * ncol * sizeof(spinor<R>) >= kStreamStoreBytes ? 1 : 0;
     dim3 grid((unsigned)nblocks), block(kBlock);
-    if (dagger) hipLaunchKernelGGL((fine_kernel<R, true, false, false>), grid, block, 0, st, U, si, so, nullptr, nullptr, 1, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
-    else        hipLaunchKernelGGL((fine_kernel<R, false, false, false>), grid, block, 0, st, U, si, so, nullptr, nullptr, 1, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
+    auto go = [&](auto dag, auto ntc) {
+        hipLaunchKernelGGL((fine_kernel<R, decltype(dag)::value, false, false, decltype(ntc)::value>), grid, block, 0,
+                           st, U, si, so, nullptr, nullptr, 1, Lx, Ly, Ls, nchunk, cs, nsb, diag, mwrap);
+    };
+    if (dagger) { if (nt) go(std::true_type{}, std::true_type{}); else go(std::true_type{}, std::false_type{}); }
+    else        { if (nt) go(std::false_type{}, std::true_type{}); else go(std::false_type{}, std::false_type{}); }
     return hipGetLastError();
 }
 
