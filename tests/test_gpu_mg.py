@@ -278,6 +278,33 @@ def test_batched_multi_lattice_solve_fp16():
         assert res <= 1e-10 and st.status == 0
 
 
+def test_fp16_coarse_links_with_scaled_sources():
+    """FP16 matrix-core coarse links under sources scaled far outside the FP16 range
+    (largest finite 65504, smallest normal 6e-5): each staged coarse vector tile is
+    brought near 1 by a power of two, so a source scaled by 2^20 or 2^-20 runs the
+    same iterations on scaled numbers (the solution scaled exactly, bit for bit), and
+    sources scaled by 1e6 and 1e-6 converge with the same iteration counts to 1e-10."""
+    L, Ls, m, M5 = 32, 8, 0.01, -1.0
+    g = inputs.metropolis_u1(L, L, 6.0, 60, 40001)
+    starts = [T(inputs.gaussian_field((16, L, L, 2), 40002))]
+    params = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_F16],
+                            vec_prec=[dwfmg.P_F64], fine_prec=dwfmg.P_F32, coarsest_solver=dwfmg.COARSEST_GCR,
+                            coarsest_restart=6, coarsest_tol=0.5, smooth_iters=20, smooth_restart=5)
+    mg = dwfmg.MG(T(g.U), Ls, m, M5, params, starts, max_nrhs=1)
+    b = inputs.gaussian_field((1, Ls, L, L, 2), 40003)
+    x1, s1 = mg.solve(T(b), 1e-10)
+    assert s1.status == 0 and oracle_residual(g.U, x1.cpu().numpy(), b, m, M5) <= 1e-10
+    for scale in (2.0 ** 20, 2.0 ** -20):
+        xs, ss = mg.solve(T(b * scale), 1e-10)
+        assert ss.status == 0
+        assert torch.equal(xs, x1 * scale), scale
+        assert (ss.fine_iters, ss.level_iters) == (s1.fine_iters, s1.level_iters)
+    for scale in (1e6, 1e-6):
+        xs, ss = mg.solve(T(b * scale), 1e-10)
+        assert ss.status == 0 and oracle_residual(g.U, xs.cpu().numpy(), b * scale, m, M5) <= 1e-10
+        assert abs(ss.fine_iters - s1.fine_iters) <= 1, (scale, ss.fine_iters, s1.fine_iters)
+
+
 # ----------------------------------------------------------------------------- solves
 def oracle_residual(U, x, b, m, M5):
     return max(np.linalg.norm(b[i] - O.dwf(U, x[i], m, M5)) / np.linalg.norm(b[i]) for i in range(b.shape[0]))
