@@ -282,6 +282,18 @@ typedef struct {
                                              D_PV^dag p(.) r all use it; coarse levels
                                              are unchanged                              */
     double pv_poly[DWF_PV_POLY_MAX + 1];  /* c_0..c_K (see dwf_pv_poly_chebyshev)     */
+    double stagnation_ratio;              /* an outer defect-correction step stagnates
+                                             when the worst relative residual is above
+                                             this times its value after the previous
+                                             step (default 0.9; 0 disables): the solve
+                                             then promotes every 16-bit coarse kernel to
+                                             its FP64 Galerkin links and continues, or
+                                             with none left stops (DWF_NOT_CONVERGED).
+                                             The last steps of a solve legitimately
+                                             gain only about 2x (the inner tolerance
+                                             then asks for just enough to reach the
+                                             target), so values near 0.5 stop solves
+                                             that would converge                       */
 } dwf_mg_params;
 
 typedef struct {
@@ -293,6 +305,9 @@ typedef struct {
     long long level_calls[DWF_MAX_LEVELS];/* solves on each coarse level                */
     double    true_rel_residual;          /* max over rhs of |b - D_DW x| / |b| (FP64)  */
     double    solve_ms;                   /* wall time of the solve                     */
+    int       escalations;                /* stagnations answered by promoting the
+                                             16-bit coarse links to FP64 (the hierarchy
+                                             keeps them for later solves)               */
 } dwf_solve_stats;
 
 void dwf_mg_default_params(dwf_mg_params* p, int nlevels);

@@ -321,6 +321,7 @@ void dwf_mg_default_params(dwf_mg_params* p, int nlevels) {
     p->coarsest_restart = 16;
     p->transfer = DWF_TRANSFER_WALL;
     p->pv_poly_order = 0;
+    p->stagnation_ratio = 0.9;
     for (int k = 0; k <= DWF_PV_POLY_MAX; ++k) p->pv_poly[k] = (k == 0) ? 1.0 : 0.0;
 }
 
@@ -359,6 +360,7 @@ int check_mg_args(int Lx, int Ly, int Ls, double m_f, double M5, const dwf_mg_pa
     if (p->transfer != DWF_TRANSFER_WALL && p->transfer != DWF_TRANSFER_BULK && p->transfer != DWF_TRANSFER_SLICE1)
         return DWF_EINVAL;
     if (p->pv_poly_order < 0 || p->pv_poly_order > DWF_PV_POLY_MAX) return DWF_EINVAL;
+    if (!(p->stagnation_ratio >= 0.0) || !(p->stagnation_ratio < 1.0)) return DWF_EINVAL;
     for (int k = 0; k <= p->pv_poly_order; ++k)
         if (!std::isfinite(p->pv_poly[k])) return DWF_EINVAL;
     if (p->transfer == DWF_TRANSFER_BULK)

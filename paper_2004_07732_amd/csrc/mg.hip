@@ -29,6 +29,11 @@ static void report_hip(hipError_t e, int line) {
     static const bool on = std::getenv("DWF_VERBOSE") != nullptr;
     if (on) std::fprintf(stderr, "[dwfmg] HIP error '%s' at mg.hip:%d\n", hipGetErrorString(e), line);
 }
+// with DWF_VERBOSE set, the outer defect correction reports its residual per step
+static bool verbose_solve() {
+    static const bool on = std::getenv("DWF_VERBOSE") != nullptr;
+    return on;
+}
 #define HIPCHK(...)                                 \
     do {                                            \
         hipError_t e_ = (__VA_ARGS__);              \
@@ -955,6 +960,7 @@ Task Hierarchy::solve_task(const cpx<double>* b, cpx<double>* x, int ncol, doubl
             tot.level_calls[l] += g.level_calls[l];
         }
         tot.true_rel_residual = std::max(tot.true_rel_residual, g.true_rel_residual);
+        tot.escalations += g.escalations;
         if (e < 0) break;
     }
     // the caller's stream continues after the solve
@@ -1017,8 +1023,8 @@ Task Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, d
     CO_HIPCHK(vzero<double>(x, nt, st));
     const double floor_tol = (L.vec_prec == P_F32) ? 1e-5 : 1e-13;
     const double inner_floor = prm.inner_tol > 0 ? prm.inner_tol : floor_tol;
-    int status = DWF_NOT_CONVERGED, outer = 0, total_it = 0;
-    double worst = 0.0;
+    int status = DWF_NOT_CONVERGED, outer = 0, total_it = 0, escalations = 0;
+    double worst = 0.0, prev_worst = 0.0;
     std::vector<double> rel(ncol, 1.0);
     while (true) {
         CO_HIPCHK(fine_dw<double>(L.U64, x, r64_, b, L.Lx, L.Ly, L.Ls, ncol, m, M5, false, nullptr, 1, st));
@@ -1034,9 +1040,28 @@ Task Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, d
             worst = std::max(worst, rel[c]);
             if (rel[c] > tol) all = false;
         }
+        if (verbose_solve())
+            std::fprintf(stderr, "[dwfmg] outer step %d: worst relative residual %.3e after %d fine iterations\n",
+                         outer, worst, total_it);
         if (status == DWF_ENAN) break;
         if (all) { status = DWF_OK; break; }
         if (outer >= prm.max_outer || total_it >= prm.max_iters) { status = DWF_NOT_CONVERGED; break; }
+        // stagnation: the last outer step did not cut the worst residual by the ratio.  A
+        // 16-bit coarse kernel is then the suspect: promote it to its FP64 links and go on;
+        // with nothing left to promote, stop.  Near the target a step only asks the inner
+        // solve for the missing factor (itol below), so a ratio around 0.5 there is normal
+        // progress and the default threshold sits well above it.
+        if (outer > 0 && prm.stagnation_ratio > 0.0 && worst > prm.stagnation_ratio * prev_worst) {
+            if (promote_coarse_links()) {
+                ++escalations;
+                if (verbose_solve()) std::fprintf(stderr, "[dwfmg] stagnation: coarse links promoted to FP64\n");
+            } else {
+                if (verbose_solve()) std::fprintf(stderr, "[dwfmg] stagnation with FP64 coarse links: stop\n");
+                status = DWF_NOT_CONVERGED;
+                break;
+            }
+        }
+        prev_worst = worst;
         // inner right-hand side D_PV^dagger r (with the PV polynomial D_PV^dagger p(X) r)
         if (prm.pv_poly_order > 0) {
             CO_HIPCHK(pv_poly<double>(r64_, y64_, z64_, ncol, st));
@@ -1072,7 +1097,11 @@ Task Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, d
         }
         total_it += it;
         ++outer;
-        if (it == 0) { status = DWF_NOT_CONVERGED; break; }
+        if (it == 0) {
+            if (verbose_solve()) std::fprintf(stderr, "[dwfmg] inner solve made no iteration: stop\n");
+            status = DWF_NOT_CONVERGED;
+            break;
+        }
     }
     CO_HIPCHK(co_await sync(st));
     if (stats) {
@@ -1085,8 +1114,26 @@ Task Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, d
             stats->level_calls[l] = cnt_.level_calls[l];
         }
         stats->true_rel_residual = worst;
+        stats->escalations = escalations;
     }
     co_return status;
+}
+
+// Stagnation response: every coarse level whose kernel is stored in 16 bits (BF16 or
+// FP16 matrix-core fragments) switches to the FP64 links it was built from (kept since
+// setup) and the VALU coarse kernel.  The captured graphs hold the old launches and are
+// dropped (the stream is idle here: the caller has just read a residual back).
+bool Hierarchy::promote_coarse_links() {
+    bool any = false;
+    for (int l = 1; l < (int)levels.size(); ++l) {
+        Level& c = levels[l];
+        if (c.link_prec != P_BF16 && c.link_prec != P_F16) continue;
+        c.link_prec = P_F64;
+        c.links = c.links64;
+        any = true;
+    }
+    if (any) clear_graphs();
+    return any;
 }
 
 // ------------------------------------------------------------ diagnostics

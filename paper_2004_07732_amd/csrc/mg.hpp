@@ -274,6 +274,7 @@ private:
     std::map<GraphKey, hipGraphExec_t> graphs_;
     template <class F> int run_graph(const GraphKey& key, hipStream_t st, F&& enqueue);
     void clear_graphs();
+    bool promote_coarse_links();
 
 public:
     // coarsest-level deflation (lowest eigenpairs of A^dag A on the coarsest level)

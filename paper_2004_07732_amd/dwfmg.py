@@ -156,6 +156,7 @@ class CParams(ctypes.Structure):
         ("transfer", ctypes.c_int),
         ("pv_poly_order", ctypes.c_int),
         ("pv_poly", ctypes.c_double * (PV_POLY_MAX + 1)),
+        ("stagnation_ratio", ctypes.c_double),
     ]
 
 
@@ -169,6 +170,7 @@ class CStats(ctypes.Structure):
         ("level_calls", ctypes.c_longlong * MAX_LEVELS),
         ("true_rel_residual", ctypes.c_double),
         ("solve_ms", ctypes.c_double),
+        ("escalations", ctypes.c_int),
     ]
 
 
@@ -204,6 +206,7 @@ class MGParams:
     transfer: int = 0              # TRANSFER_WALL (the paper's method), TRANSFER_BULK (Sec. 4.1) or
                                    # TRANSFER_SLICE1 (the literal-slice reading, a test toggle)
     pv_poly: Optional[List[float]] = None   # c_0..c_K of the PV polynomial on the fine level (None: A itself)
+    stagnation_ratio: float = 0.9  # outer step stagnates above this residual ratio: promote 16-bit coarse links
 
     @property
     def nlevels(self) -> int:
@@ -222,7 +225,7 @@ class MGParams:
         for name in ("fine_prec", "m_setup", "setup_iters", "setup_tol", "outer_restart", "smooth_iters", "smooth_restart",
                      "inter_maxit", "inter_tol", "inter_restart", "coarsest_maxit", "coarsest_tol", "inner_tol",
                      "max_iters", "max_outer", "coarsest_nev", "eig_degree", "eig_maxit", "eig_tol",
-                     "coarsest_solver", "coarsest_restart", "transfer"):
+                     "coarsest_solver", "coarsest_restart", "transfer", "stagnation_ratio"):
             setattr(c, name, getattr(self, name))
         if self.pv_poly is not None:
             coef = [float(v) for v in self.pv_poly]
@@ -244,6 +247,7 @@ class SolveStats:
     level_calls: List[int]
     true_rel_residual: float
     solve_ms: float
+    escalations: int = 0
 
 
 def _stream(stream=None) -> ctypes.c_void_p:
@@ -468,7 +472,7 @@ def release_scratch():
 # ----------------------------------------------------------------------------- multigrid
 def _stats(st: "CStats") -> "SolveStats":
     return SolveStats(st.status, st.outer_steps, st.fine_iters, st.fine_applies, list(st.level_iters),
-                      list(st.level_calls), st.true_rel_residual, st.solve_ms)
+                      list(st.level_calls), st.true_rel_residual, st.solve_ms, st.escalations)
 
 
 def dwf_krylov_solve(U, b, m_f, M5, method=KRYLOV_BICGSTAB, ell=6, tol=1e-10, maxit=1_000_000, x=None,
@@ -569,8 +573,7 @@ class MG:
         st = CStats()
         code = lib().mg_solve(self._h, _ptr(b), _ptr(x), bb.shape[0], float(tol), DWF_PV_SOURCE if pv_source else 0,
                               ctypes.byref(st), _stream(stream))
-        stats = SolveStats(st.status, st.outer_steps, st.fine_iters, st.fine_applies, list(st.level_iters),
-                           list(st.level_calls), st.true_rel_residual, st.solve_ms)
+        stats = _stats(st)
         if check:
             _check(code, "mg_solve")
         return x, stats

@@ -146,7 +146,8 @@ def test_workspace_bytes_on_the_host(libdwf):
 def test_smoother_restart_parameters_on_the_host(libdwf):
     """Post-smoothing steps: at most 16 in one GCR cycle; with a restart length of
     1..16, up to 64 steps, and the smoother's direction buffers hold one cycle
-    (24 steps in cycles of 6 need less memory than 16 steps in one cycle)."""
+    (24 steps in cycles of 6 need less memory than 16 steps in one cycle).  The
+    stagnation ratio lies in [0, 1)."""
     from paper_2004_07732_amd import dwfmg
     L, Ls = 64, 8
     ok = lambda **kw: dwfmg.workspace_bytes(L, L, Ls, _headline_params(dwfmg, **kw), 1)
@@ -159,6 +160,9 @@ def test_smoother_restart_parameters_on_the_host(libdwf):
     assert ok(smooth_iters=16, smooth_restart=-1) == 0
     fine_vec = L * L * Ls * 2 * 8     # one FP32 fine vector
     assert ok(smooth_iters=16) - ok(smooth_iters=24, smooth_restart=6) >= 2 * 10 * fine_vec
+    # the stagnation ratio: 0 (off) up to below 1
+    assert ok(stagnation_ratio=0.0) > 0 and ok(stagnation_ratio=0.9) > 0
+    assert ok(stagnation_ratio=1.0) == 0 and ok(stagnation_ratio=-0.5) == 0
     # a restart at least as long as the steps is no restart
     assert ok(smooth_iters=8, smooth_restart=8) == ok(smooth_iters=8) == ok(smooth_iters=8, smooth_restart=12)
 

@@ -459,6 +459,38 @@ def test_singular_free_field_does_not_hang():
     assert st.fine_iters <= 40
 
 
+def test_stagnation_promotes_16bit_coarse_links():
+    """Stagnation detection with the ratio forced to 1e-30 (every outer step counts as
+    stagnating).  The first solve promotes the BF16 matrix-core coarse kernel to its
+    FP64 Galerkin links after one outer step and still meets its tolerance (the oracle
+    recomputes the residual); the hierarchy keeps the FP64 links, so the second solve has
+    nothing left to promote and stops at its first stagnation with DWF_NOT_CONVERGED.
+    The default ratio (0.9) does not fire on this converging solve."""
+    L, Ls, m, M5 = 32, 8, 0.01, -1.0
+    g = inputs.metropolis_u1(L, L, 6.0, 60, 41001)
+    starts = [T(inputs.gaussian_field((16, L, L, 2), 41002))]
+    b = inputs.gaussian_field((1, Ls, L, L, 2), 41003)
+    kw = dict(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[dwfmg.P_F64],
+              fine_prec=dwfmg.P_F32, coarsest_solver=dwfmg.COARSEST_GCR, coarsest_restart=6, coarsest_tol=0.5)
+    mg0 = dwfmg.MG(T(g.U), Ls, m, M5, dwfmg.MGParams(**kw), starts)
+    x0, s0 = mg0.solve(T(b), 1e-8)
+    assert s0.status == 0 and s0.escalations == 0 and s0.outer_steps >= 2
+    mg0.close()
+    mg = dwfmg.MG(T(g.U), Ls, m, M5, dwfmg.MGParams(stagnation_ratio=1e-30, **kw), starts)
+    assert mg.coarse_config(1, 1) is not None          # the matrix-core kernel before the promotion
+    x1, s1 = mg.solve(T(b), 1e-8)
+    assert s1.status == 0 and s1.escalations == 1
+    assert oracle_residual(g.U, x1.cpu().numpy(), b, m, M5) <= 1e-8
+    with pytest.raises(dwfmg.DwfError) as e:           # no matrix-core launch left on level 1
+        mg.coarse_config(1, 1)
+    assert e.value.code == dwfmg.DWF_EUNSUPPORTED
+    x2, s2 = mg.solve(T(b), 1e-8, check=False)
+    assert s2.status == dwfmg.DWF_NOT_CONVERGED and s2.escalations == 0 and s2.outer_steps == 1
+    for bad in (-0.1, 1.0, float("nan")):
+        with pytest.raises(dwfmg.DwfError):
+            dwfmg.MG(T(g.U), Ls, m, M5, dwfmg.MGParams(stagnation_ratio=bad, **kw), starts)
+
+
 def test_setup_argument_errors():
     L = 8
     U = T(np.ones((2, L, L), dtype=np.complex128))
