@@ -639,6 +639,12 @@ k_gcr_fused_update(const cpx<T>* W, size_t wstride, cpx<T>* w, cpx<T>* r, cpx<T>
             for (int i = 0; i < j; ++i) Wt[i] = W[(size_t)i * wstride + o + e];
             step(o + e, w[o + e], r[o + e], Wt);
         }
+    } else if (copy) {
+        // a column that stopped earlier in the cycle: its later directions are zero.  The
+        // solution update weights them by zero coefficients, which must not meet whatever
+        // the unwritten buffer holds (a non-finite word would turn 0 x into NaN), and a
+        // zero direction keeps the stencil of that column finite for its tile neighbours.
+        GRID_STRIDE(e, n) copy[o + e] = cpx<T>{(T)0, (T)0};
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const size_t s = kb + j;

@@ -167,7 +167,8 @@ hipError_t gcr_dev_init(int ncol, const GcrDev& g, hipStream_t st);
 //           a = <w, r>/|w'|^2 (r is orthogonal to every W_i, so <w', r> = <w, r>), then in one pass
 //           w' = w - sum c_i W_i, r -= a w', copy = r; block 0 stores nn_j, wr_j, D[j][.], the new
 //           |r|^2 = |r|^2 - |<w, r>|^2/|w'|^2 and the stop flag into `stop_out` (while `stop_in`
-//           is only read).
+//           is only read).  A column already stopped only sets copy = 0, so that every
+//           direction a later solution update reads was written in this cycle.
 template <typename T>
 hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx<T>* r, cpx<T>* copy, size_t n,
                           int ncol, double tol2, const int* stop_in, int* stop_out, const GcrDev& g,

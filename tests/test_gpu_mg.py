@@ -491,6 +491,48 @@ def test_stagnation_promotes_16bit_coarse_links():
             dwfmg.MG(T(g.U), Ls, m, M5, dwfmg.MGParams(stagnation_ratio=bad, **kw), starts)
 
 
+@pytest.mark.parametrize("case", ["bf16_f32coarsest_gcr", "bf16_f64coarsest_gcr", "f16_f32coarsest_cgnr",
+                                  "three_level_gcr"])
+def test_solves_never_read_unwritten_workspace(case):
+    """A hierarchy built in a caller's workspace whose bytes are all 0xFF (a NaN in FP32 and
+    FP64) solves two right-hand sides to the same bits as one built in a zeroed workspace: no
+    kernel reads memory that the setup or the solve did not write first.  The coarsest GCR
+    stops columns within a restart cycle; the directions after the stop are zero, never
+    stale memory (FP32 coarsest vectors in a reused buffer once turned the K-cycle into NaN)."""
+    L, Ls, m, M5 = 32, 8, 0.01, -1.0
+    g = inputs.metropolis_u1(L, L, 6.0, 60, 42001)
+    b = T(inputs.gaussian_field((2, Ls, L, L, 2), 42003))
+    G, C = dwfmg.COARSEST_GCR, dwfmg.COARSEST_CGNR
+    if case == "three_level_gcr":
+        kw = dict(nvec=[8, 12], block=[(4, 4), (2, 2)], Ls_coarse=[2, 2], link_prec=[dwfmg.P_BF16] * 2,
+                  vec_prec=[dwfmg.P_F32, dwfmg.P_F32], coarsest_solver=G)
+        starts = [T(inputs.gaussian_field((8, L, L, 2), 42002)),
+                  T(inputs.gaussian_field((12, L // 4, L // 4, 16), 42004))]
+    else:
+        lp = dwfmg.P_F16 if case.startswith("f16") else dwfmg.P_BF16
+        vp = dwfmg.P_F32 if "f32coarsest" in case else dwfmg.P_F64
+        kw = dict(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[lp], vec_prec=[vp],
+                  coarsest_solver=C if case.endswith("cgnr") else G)
+        starts = [T(inputs.gaussian_field((16, L, L, 2), 42002))]
+    p = dwfmg.MGParams(fine_prec=dwfmg.P_F32, coarsest_restart=6, coarsest_tol=0.5, smooth_iters=20, smooth_restart=5,
+                       **kw)
+    need = dwfmg.workspace_bytes(L, L, Ls, p, max_nrhs=2)
+    out = {}
+    for fill in (0, 255):
+        ws = torch.full((need,), fill, dtype=torch.uint8, device=DEV)
+        torch.cuda.synchronize()
+        mg = dwfmg.MG(T(g.U), Ls, m, M5, p, starts, max_nrhs=2, workspace=ws)
+        x, st = mg.solve(b, 1e-10)
+        kc = mg.level_op(0, dwfmg.MG_OP_KCYCLE, b, 2)
+        out[fill] = (x.cpu().numpy(), kc.cpu().numpy(), st)
+        mg.close()
+    (x0, k0, s0), (x1, k1, s1) = out[0], out[255]
+    assert np.isfinite(x1).all() and np.isfinite(k1).all()
+    assert np.array_equal(x0, x1) and np.array_equal(k0, k1)
+    assert (s0.fine_iters, s0.level_iters, s0.outer_steps) == (s1.fine_iters, s1.level_iters, s1.outer_steps)
+    assert oracle_residual(g.U, x1, b.cpu().numpy(), m, M5) <= 1e-10
+
+
 def test_setup_argument_errors():
     L = 8
     U = T(np.ones((2, L, L), dtype=np.complex128))
