@@ -5,8 +5,8 @@ Metric: MG-preconditioned domain-wall solves per second to a true FP64
 relative residual of 1e-10 on a 256^2 x Ls 16 lattice (beta 6, m_f 0.01,
 M5 = -1) with the 2-level hierarchy (4x4 aggregates, 16 null vectors, coarse
 Ls 2), mixed precision (FP32 fine level, BF16 coarse links on the matrix
-cores, FP64 outer defect correction and FP64 coarse Krylov vectors).  The
-coarsest level runs restarted GCR(6) on hat-A to 0.25 by default.  Rows beside
+cores, FP32 coarse Krylov vectors, FP64 outer defect correction).  The
+coarsest level runs restarted GCR(6) on hat-A to 0.5 by default.  Rows beside
 the headline: the paper's parameter table throughout (coarse Ls 4, coarsest
 CGNR to 0.05), coarse Ls 4 with GCR, three levels, 8 null vectors.
 
@@ -54,7 +54,8 @@ def make_params(dwfmg, wl, mixed, nev=0, m_setup=None, setup_iters=None, **eig):
     n = len(wl["nvec"])
     if mixed:
         link = [dwfmg.P_BF16] * n
-        vec = [dwfmg.P_F32] * (n - 1) + [dwfmg.P_F64]
+        # FP32 Krylov vectors on every coarse level (the deflated coarsest solve keeps FP64)
+        vec = [dwfmg.P_F32] * (n - 1) + [dwfmg.P_F64 if nev > 0 else dwfmg.P_F32]
         fine = dwfmg.P_F32
     else:
         link = [dwfmg.P_F64] * n
@@ -505,7 +506,7 @@ def main():
     t_coarse_ms = sorted(mg.time_op(1, dwfmg.MG_OP_DW, xin, 1, iters=200) for _ in range(5))[2]
     n, nsites, Lsc = c["n"], c["Lx"] * c["Ly"], c["Ls"]
     link_bytes = 4  # bfloat16 complex
-    vec_bytes = 16 if make_params(dwfmg, wl, True).vec_prec[0] == dwfmg.P_F64 else 8
+    vec_bytes = 16 if make_params(dwfmg, wl, True, args.nev).vec_prec[0] == dwfmg.P_F64 else 8
     coarse_bytes = coarse_stencil_bytes(nsites, n, Lsc, 1, link_bytes, vec_bytes)
     stored_bytes = coarse_stencil_bytes(nsites, n, Lsc, 1, link_bytes, vec_bytes, link_blocks=3)
     achieved = coarse_bytes / (t_coarse_ms * 1e-3) / 1e9
@@ -632,7 +633,7 @@ def main():
                           "coarsest_nev": args.nev, "m_setup": head.get("m_setup", 0.0),
                           "setup_iters": head.get("setup_iters", 250), "smooth_iters": head.get("smooth_iters", 8),
                           "smooth_restart": head.get("smooth_restart", 0)},
-                   "precision": "fine FP32, coarse links BF16 (FP32 arithmetic), coarse vectors FP64, "
+                   "precision": "fine FP32, coarse links BF16 (FP32 arithmetic), coarse vectors FP32, "
                                 "outer defect correction FP64"},
         "roofline": {"bound": "hbm", "kernel": "coarse_mfma_kernel (coarse D_DW apply, level 1)",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,

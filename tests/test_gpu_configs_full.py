@@ -110,12 +110,12 @@ def headline_inputs(nrhs):
 def test_headline_configuration(nrhs):
     """The benchmark's own configuration at full size: 256^2 x Ls 16, beta 6,
     m_f 0.01, 2 levels (4x4 aggregates, 16 null vectors, coarse Ls 2), FP32 fine
-    level, BF16 matrix-core coarse links, FP64 coarse vectors, coarsest GCR(6) to
+    level, BF16 matrix-core coarse links, FP32 coarse vectors, coarsest GCR(6) to
     0.5, 20 post-smoothing GCR steps in cycles of 5, FP64 defect correction to
     1e-10; the oracle recomputes the residual of every right-hand side."""
     L, Ls, m, M5 = 256, 16, 0.01, -1.0
     g, b, starts = headline_inputs(nrhs)
-    p = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[dwfmg.P_F64],
+    p = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[dwfmg.P_F32],
                        fine_prec=dwfmg.P_F32, coarsest_solver=dwfmg.COARSEST_GCR, coarsest_restart=6,
                        coarsest_tol=0.5, smooth_iters=20, smooth_restart=5)
     mg = dwfmg.MG(torch.from_numpy(g.U).cuda(), Ls, m, M5, p, starts, max_nrhs=nrhs)
@@ -139,18 +139,19 @@ def bf16_round(a):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("ncol", [1, 16])
-def test_headline_coarse_stencil_full_size(ncol):
+@pytest.mark.parametrize("ncol,vec", [(1, "f32"), (16, "f32"), (1, "f64"), (16, "f64")])
+def test_headline_coarse_stencil_full_size(ncol, vec):
     """The coarse operator of the headline hierarchy at its full size (64^2
     coarse sites x coarse Ls 2, 32 dof per site, BF16 links on the matrix cores,
-    FP64 vectors), element by element against the oracle's coarse operator
+    FP32 or FP64 vectors), element by element against the oracle's coarse operator
     built by the oracle from the same gauge field and null-vector starts (no
     relaxation, so both sides build the same prolongator) and rounded to BF16.
-    ncol = 1 is the launch the benchmark's roofline line times."""
+    ncol = 1 with FP32 vectors is the launch the benchmark's roofline line times."""
     L, Ls, m, M5, nv = 256, 16, 0.01, -1.0, 16
     g = inputs.metropolis_u1(L, L, 6.0, 200, inputs.gauge_seed(4, L))
     start = inputs.gaussian_field((nv, L, L, 2), inputs.null_start_seed(6, 0))
-    p = dwfmg.MGParams(nvec=[nv], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[dwfmg.P_F64],
+    vp = dwfmg.P_F32 if vec == "f32" else dwfmg.P_F64
+    p = dwfmg.MGParams(nvec=[nv], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[vp],
                        fine_prec=dwfmg.P_F32, setup_iters=0)
     mg = dwfmg.MG(torch.from_numpy(g.U).cuda(), Ls, m, M5, p, [torch.from_numpy(start).cuda()], max_nrhs=ncol)
     op = O.MGParams(levels=[O.LevelParams(nvec=nv, block=(4, 4), Ls=2, setup_iters=0)])
@@ -159,13 +160,16 @@ def test_headline_coarse_stencil_full_size(ncol):
     Sb = O.Stencil(diag=bf16_round(S.diag.real) + 1j * bf16_round(S.diag.imag),
                    hop=bf16_round(S.hop.real) + 1j * bf16_round(S.hop.imag), chir=S.chir)
     x = inputs.gaussian_field((ncol, 2, L // 4, L // 4, 2 * nv), 7_100_000 + ncol)
+    if vec == "f32":   # the FP32 vector the kernel reads (and the oracle applies to)
+        x = x.astype(np.complex64).astype(np.complex128)
     for code, dag in ((dwfmg.MG_OP_DW, False), (dwfmg.MG_OP_DW_DAG, True)):
         got = mg.level_op(1, code, torch.from_numpy(x).cuda(), ncol).cpu().numpy()
         want = O.stencil_dwf(Sb, x, m, M5, dagger=dag)
         err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
         emax = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
-        say(f"[coarse full] ncol {ncol} dagger {dag}: rel 2-norm {err:.2e}, max elementwise {emax:.2e}")
-        # the FP64 vector enters the matrix cores as two BF16 parts, which carry 16
+        say(f"[coarse full] ncol {ncol} {vec} dagger {dag}: rel 2-norm {err:.2e}, max elementwise {emax:.2e}")
+        # the vector enters the matrix cores as two BF16 parts, which carry 16
         # significant bits: |x - hi - lo| <= 2^-16 |x| per entry; FP32 accumulation
-        # adds ~1e-7.  Bars: 2^-16 on the 2-norm, 4 x 2^-16 on the largest entry.
+        # (and an FP32 output) add ~1e-7.  Bars: 2^-16 on the 2-norm, 4 x 2^-16 on
+        # the largest entry.
         assert err < 2.0 ** -16 and emax < 4 * 2.0 ** -16
