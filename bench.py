@@ -362,6 +362,35 @@ def stencil_rows(dwfmg, inputs, torch, m, M5):
     return rows
 
 
+def fine_a_rows(dwfmg, inputs, torch, mg, L, Ls):
+    """Level-0 A = D_PV^dag D_DW of the headline hierarchy (FP32) for 1 and 16 columns:
+    HIP-event time per application (median of three runs of 100) with the two stencil
+    launches pinned and with each fused tile shape at each chunk length the timed choice
+    considers; algorithmic bytes of A as one operator (psi read once, out written once, the
+    links once)."""
+    out = {}
+    for ncol in (1, 16):
+        x = torch.from_numpy(inputs.gaussian_field((ncol, Ls, L, L, 2), 9_000_000 + ncol)).cuda()
+        def t_of(shape, chunk):
+            dwfmg.dwf_fine_a_config(shape, chunk)
+            return sorted(mg.time_op(0, dwfmg.MG_OP_A, x, ncol, iters=100) for _ in range(3))[1] * 1e3
+        try:
+            two = t_of(dwfmg.FINE_A_TWO, 1)
+            fused = min((t_of(sh, c), sh, c) for sh in (dwfmg.FINE_A_16x16, dwfmg.FINE_A_32x8, dwfmg.FINE_A_16x8)
+                        for c in sorted({Ls, (Ls + 1) // 2, (Ls + 3) // 4, 4, 2}))
+        finally:
+            dwfmg.dwf_fine_a_config(dwfmg.FINE_A_AUTO)
+        nbytes = ncol * Ls * L * L * 32 + 2 * L * L * 8
+        out[f"{ncol}rhs"] = {"shape": f"{L}^2 x {Ls} x {ncol} rhs", "dtype": "complex64", "bytes": nbytes,
+                            "two_launch_us": two, "fused_us": fused[0], "fused_tile": ["16x16", "32x8", "16x8"][fused[1] - 1],
+                            "fused_chunk": fused[2], "two_launch_GB_s": nbytes / (two * 1e-6) / 1e9,
+                            "fused_GB_s": nbytes / (fused[0] * 1e-6) / 1e9,
+                            "chosen": "fused" if fused[0] * 1.03 < two else "two launches"}
+        log(f"[bench] fine A {ncol} rhs: two launches {two:.1f} us, fused {fused[0]:.1f} us "
+            f"({out[f'{ncol}rhs']['fused_tile']}, chunk {fused[2]})")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -544,6 +573,11 @@ def main():
         log(f"[bench] 16 rhs: {t16 * 1e3:.1f} ms per batch, {16.0 / t16:.3f} solves/s, "
             f"residual {st16.true_rel_residual:.2e}")
         del b16
+    # the solver's fine A = D_PV^dag D_DW: two stencil launches against the fused launch (the
+    # timed choice's best fused configuration), 1 and 16 columns, FP32
+    fine_a = {}
+    if not args.quick:
+        fine_a = fine_a_rows(dwfmg, inputs, torch, mg, L, Ls)
     mg.close()
 
     if not args.quick:
@@ -648,6 +682,7 @@ def main():
         "mixed_vs_fp64": (mixed_sps / fp64["solves_per_s"]) if fp64 else None,
         "rows": rows,
         "fine_stencil": stencil,
+        "fine_a": fine_a,
         "setup_s": setup_s,
         "solve": stats_dict(stats),
     }

@@ -112,6 +112,32 @@ int dwf_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls,
 #define DWF_FINE_TILE_128x4   3
 int dwf_fine_config(int shape, int chunk);
 
+/* Launch configuration of the fine-level operator A = D_PV^dagger D_DW(m) (eq.
+ * NormalExp) inside the multigrid solver (mg_solve, mg_level_op MG_OP_A on level
+ * 0; not the polynomial-corrected form).  DWF_FINE_A_TWO applies the two stencils
+ * (each with its dwf_fine_config choice) through an intermediate field; the fused
+ * shapes apply both in one launch over LDS tiles of the given size, evaluating the
+ * intermediate on every tile and its one-site ring and never storing it (the
+ * lattice must divide into the tiles; FP64 fields only with DWF_FINE_A_16x8, whose
+ * LDS fits).  Both forms evaluate every site with the same arithmetic, to rounding
+ * (FMA contraction may differ between the kernels).  By default (DWF_FINE_A_AUTO)
+ * the library times the candidates once per lattice shape, column count and
+ * precision and keeps the fused launch only when it is more than 3% faster.
+ * dwf_fine_a_config pins a choice for later calls (chunk = output slices per
+ * workgroup, 1..4095, capped at Ls; ignored for DWF_FINE_A_TWO and
+ * DWF_FINE_A_AUTO); a pinned fused shape that does not fit a lattice falls back to
+ * the automatic choice there.  Returns DWF_EINVAL for an unknown shape or a chunk
+ * out of range.  dwf_fine_a_chosen reports the automatic choice made for a shape
+ * (prec: 0 FP64, DWF_PREC_F32 FP32): DWF_OK with *shape and *chunk, or
+ * DWF_EINVAL if none was made yet. */
+#define DWF_FINE_A_AUTO   -1
+#define DWF_FINE_A_TWO     0   /* two stencil launches through an intermediate field  */
+#define DWF_FINE_A_16x16   1   /* one fused launch, LDS tiles of 16 x 16 sites        */
+#define DWF_FINE_A_32x8    2
+#define DWF_FINE_A_16x8    3
+int dwf_fine_a_config(int shape, int chunk);
+int dwf_fine_a_chosen(int prec, int Lx, int Ly, int Ls, int nrhs, int* shape, int* chunk);
+
 /* Pauli-Villars forms (Sec. 2.2, eq. NormalExp): see the DWF_PV* modes.  The
  * product modes use a library-owned intermediate field (allocated on first use
  * and kept until dwf_release_scratch; a call on one stream waits, on the

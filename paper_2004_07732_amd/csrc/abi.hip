@@ -196,6 +196,14 @@ int dwf_pv_poly_chebyshev(int order, double lam_min, double lam_max, double* c) 
 
 int dwf_fine_config(int shape, int chunk) { return set_fine_config(shape, chunk) ? DWF_OK : DWF_EINVAL; }
 
+int dwf_fine_a_config(int shape, int chunk) { return set_fine_a_config(shape, chunk) ? DWF_OK : DWF_EINVAL; }
+
+int dwf_fine_a_chosen(int prec, int Lx, int Ly, int Ls, int nrhs, int* shape, int* chunk) {
+    if (!shape || !chunk || (prec != 0 && prec != DWF_PREC_F32)) return DWF_EINVAL;
+    const int bytes = prec == DWF_PREC_F32 ? (int)sizeof(float) : (int)sizeof(double);
+    return fine_a_chosen(bytes, Lx, Ly, Ls, nrhs, shape, chunk) ? DWF_OK : DWF_EINVAL;
+}
+
 int dwf_pv_apply(const void* U, const void* psi, void* out, int Lx, int Ly, int Ls, int nrhs, double m_f,
                  double M5, int mode, int flags, void* stream) {
     if (!U || !psi || !out || psi == out || !dims_ok(Lx, Ly, Ls, nrhs)) return DWF_EINVAL;

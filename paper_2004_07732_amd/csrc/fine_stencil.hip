@@ -516,6 +516,325 @@ static hipError_t launch_fine(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, co
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ fused A = D_PV^dag D_DW(m)
+// One launch for both stencils of the fine A (eq. NormalExp): the intermediate
+// t = D_DW(m) psi never goes to memory.  A workgroup owns a TX x TY tile of one column
+// and a chunk [s0, s1) of output slices and walks k = s0-1 .. s1:
+//  - t_k is evaluated on the tile and its one-site ring (each ring site again, from the
+//    LDS box of psi_k with a two-site margin and the boxes of psi_{k-1}, psi_{k+1}) into an
+//    LDS tile, so that D_PV^dag finds all four neighbours of every tile site;
+//  - out_{k-1} = D_PV^dag t follows from the tile of t_{k-1} and, at the thread's own site,
+//    t_{k-2} (lower chirality, from below) and t_k (upper chirality, from above);
+//  - psi_{k+2}'s box is loaded while t_k is evaluated and written to LDS after it.
+// Four psi boxes and two t tiles rotate, so one barrier per slice suffices: the psi box
+// written at step k was last read at step k-1, the t tile written at step k was last read
+// at step k-1, both before step k-1's barrier.  Every site evaluates the same expressions
+// as the two separate stencil kernels (dw_site), in the same order.
+// Requires Lx % TX == 0 and Ly % TY == 0.
+template <typename R, int TX, int TY, bool NTS>
+__global__ void __launch_bounds__(TX * TY)
+fine_a_kernel(const cpx<R>* __restrict__ U, const spinor<R>* __restrict__ in, spinor<R>* __restrict__ out,
+              const int* __restrict__ skip, int skip_stride, int Lx, int Ly, int Ls, int nchunk, int cs, int ntile,
+              R diag, R mdw, R mpv) {
+    constexpr int NTH = TX * TY;
+    constexpr int BX = TX + 4, BY = TY + 4;                            // psi box: two-site margin
+    constexpr int EX = TX + 2, EY = TY + 2;                            // t tile: one-site margin
+    constexpr int NBOX = (TX + 2) * (TY + 2) + 2 * TX + 2 * TY;        // psi sites read per slice
+    constexpr int NRING = 2 * TX + 2 * TY;                             // ring sites of t
+    static_assert(NBOX <= 2 * NTH && NRING <= NTH, "two box sites and one ring site per thread at most");
+    __shared__ __attribute__((aligned(16))) spinor<R> pb[4][BY][BX];
+    __shared__ __attribute__((aligned(16))) spinor<R> tb[2][EY][EX];
+    typedef typename vec4_of<R>::type vec4;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int chunk = (int)(lb % (unsigned)nchunk);
+    const unsigned tt = lb / (unsigned)nchunk;
+    const int tl = (int)(tt % (unsigned)ntile);
+    const int col = (int)(tt / (unsigned)ntile);
+    if (skip && skip[(size_t)col * skip_stride]) return;   // the same for the whole workgroup
+    const int V = Lx * Ly;
+    const int ntx = Lx / TX;
+    const int x0 = (tl % ntx) * TX, y0 = (tl / ntx) * TY;
+    const int tid = (int)threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    auto wx = [&](int x) { return x < 0 ? x + Lx : (x >= Lx ? x - Lx : x); };   // |offset| <= 2 < Lx
+    auto wy = [&](int y) { return y < 0 ? y + Ly : (y >= Ly ? y - Ly : y); };
+    const R half = R(0.5);
+    // links of a site: U/2 forward, U/2 of the backward neighbour
+    auto links = [&](int gx, int gy, cpx<R>& h0, cpx<R>& h0m, cpx<R>& h1, cpx<R>& h1m) {
+        const int site = gy * Lx + gx;
+        h0 = half * U[site];
+        h0m = half * U[gy * Lx + wx(gx - 1)];
+        h1 = half * U[V + site];
+        h1m = half * U[V + wy(gy - 1) * Lx + gx];
+    };
+    const int x = x0 + lx, y = y0 + ly;
+    const int site = y * Lx + x;
+    cpx<R> hu0, hu0m, hu1, hu1m;
+    links(x, y, hu0, hu0m, hu1, hu1m);
+    // this thread's ring site of t (threads tid < NRING): row below, row above, left
+    // column, right column, in tile-local coordinates
+    const bool has_ring = tid < NRING;
+    int rpx = 0, rpy = 0;
+    {
+        const int r = has_ring ? tid : 0;
+        if (r < TX) { rpx = r; rpy = -1; }
+        else if (r < 2 * TX) { rpx = r - TX; rpy = TY; }
+        else if (r < 2 * TX + TY) { rpx = -1; rpy = r - 2 * TX; }
+        else { rpx = TX; rpy = r - 2 * TX - TY; }
+    }
+    cpx<R> ru0 = {}, ru0m = {}, ru1 = {}, ru1m = {};
+    if (has_ring) links(wx(x0 + rpx), wy(y0 + rpy), ru0, ru0m, ru1, ru1m);
+    // this thread's (at most two) psi box sites: the (TX+2) x (TY+2) box, then the four
+    // arms of the two-site margin (left, right, below, above)
+    int gs[2] = {-1, -1}, ls[2] = {0, 0};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int i = tid + e * NTH;
+        if (i < NBOX) {
+            int px, py;
+            if (i < (TX + 2) * (TY + 2)) { px = i % (TX + 2) - 1; py = i / (TX + 2) - 1; }
+            else {
+                const int j = i - (TX + 2) * (TY + 2);
+                if (j < TY) { px = -2; py = j; }
+                else if (j < 2 * TY) { px = TX + 1; py = j - TY; }
+                else if (j < 2 * TY + TX) { px = j - 2 * TY; py = -2; }
+                else { px = j - 2 * TY - TX; py = TY + 1; }
+            }
+            gs[e] = wy(y0 + py) * Lx + wx(x0 + px);
+            ls[e] = (py + 2) * BX + (px + 2);
+        }
+    }
+    const size_t colbase = (size_t)col * Ls * V;
+    const spinor<R>* src = in + colbase;
+    const int s0 = chunk * cs;
+    const int s1 = min(s0 + cs, Ls);
+    auto slice = [&](int k) { k %= Ls; return k < 0 ? k + Ls : k; };   // walk index -> slice
+    auto buf = [&](int k) -> spinor<R>(*)[BX] { return pb[(k + 8) & 3]; };   // k >= -2
+    auto load_box = [&](int k, vec4 (&a)[2]) {
+        const spinor<R>* sl = src + (size_t)slice(k) * V;
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+            if (gs[e] >= 0) a[e] = load4(sl + gs[e]);
+    };
+    auto put_box = [&](int k, const vec4 (&a)[2]) {
+        spinor<R>* b = &buf(k)[0][0];
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+            if (gs[e] >= 0) *reinterpret_cast<vec4*>(b + ls[e]) = a[e];
+    };
+    // t_k at tile-local (px, py): D_DW(m) from the psi boxes (corner blocks -m at the wrap)
+    auto t_at = [&](int k, int px, int py, cpx<R> h0, cpx<R> h0m, cpx<R> h1, cpx<R> h1m) {
+        const spinor<R>(*c)[BX] = buf(k);
+        const spinor<R>(*pv)[BX] = buf(k - 1);
+        const spinor<R>(*nx)[BX] = buf(k + 1);
+        const int bx = px + 2, by = py + 2;
+        spinor<R> prv = pv[by][bx], nxt = nx[by][bx];
+        const int sk = slice(k);
+        if (sk == 0) { prv.c0 = mdw * prv.c0; prv.c1 = mdw * prv.c1; }
+        if (sk == Ls - 1) { nxt.c0 = mdw * nxt.c0; nxt.c1 = mdw * nxt.c1; }
+        return dw_site<R, false>(c[by][bx + 1], c[by][bx - 1], c[by + 1][bx], c[by - 1][bx], c[by][bx], prv, nxt,
+                                 h0, h0m, h1, h1m, diag);
+    };
+    {   // the boxes of psi_{s0-2}, psi_{s0-1}, psi_{s0}
+        vec4 a[3][2] = {};
+        load_box(s0 - 2, a[0]);
+        load_box(s0 - 1, a[1]);
+        load_box(s0, a[2]);
+        put_box(s0 - 2, a[0]);
+        put_box(s0 - 1, a[1]);
+        put_box(s0, a[2]);
+    }
+    __syncthreads();
+    spinor<R> tp = {}, tc = {}, tn = {};   // t at the own site, walk k-2, k-1, k
+    for (int k = s0 - 1; k <= s1; ++k) {   // (the same bounds for the whole workgroup)
+        vec4 a[2] = {};
+        const bool pre = k + 2 <= s1 + 1;
+        if (pre) load_box(k + 2, a);
+        tn = t_at(k, lx, ly, hu0, hu0m, hu1, hu1m);
+        spinor<R>(*tw)[EX] = tb[k & 1];
+        tw[ly + 1][lx + 1] = tn;
+        if (has_ring && k >= s0 && k < s1) tw[rpy + 1][rpx + 1] = t_at(k, rpx, rpy, ru0, ru0m, ru1, ru1m);
+        if (k - 1 >= s0) {   // out_{k-1} = D_PV^dag t (corner blocks -1 at the wrap)
+            const int so = k - 1;
+            const spinor<R>(*q)[EX] = tb[so & 1];
+            spinor<R> prv = tp, nxt = tn;
+            if (so == 0) { prv.c0 = mpv * prv.c0; prv.c1 = mpv * prv.c1; }
+            if (so == Ls - 1) { nxt.c0 = mpv * nxt.c0; nxt.c1 = mpv * nxt.c1; }
+            const spinor<R> res = dw_site<R, true>(q[ly + 1][lx + 2], q[ly + 1][lx], q[ly + 2][lx + 1], q[ly][lx + 1],
+                                                   tc, prv, nxt, hu0, hu0m, hu1, hu1m, diag);
+            store_out<NTS>(out + colbase + (size_t)so * V + site, res);
+        }
+        if (pre) put_box(k + 2, a);
+        tp = tc;
+        tc = tn;
+        __syncthreads();
+    }
+}
+
+// Launch configuration of the fine A: 0 = the two stencil launches (each with its own
+// configuration), else fused tile shape * kCfgStride + slice chunk
+struct ATileShape { int tx, ty; };
+static constexpr ATileShape kATiles[] = {{16, 16}, {32, 8}, {16, 8}};
+static constexpr int kNumATiles = (int)(sizeof(kATiles) / sizeof(kATiles[0]));
+
+// the fused kernel's LDS (four psi boxes, two t tiles) must fit one workgroup's 64 KB
+template <typename R>
+static constexpr bool a_tile_lds_ok(int tx, int ty) {
+    return (4 * (tx + 4) * (ty + 4) + 2 * (tx + 2) * (ty + 2)) * (int)sizeof(spinor<R>) <= 64 * 1024;
+}
+template <typename R>
+static bool a_tile_fits(int shape, int Lx, int Ly) {
+    if (shape < 1 || shape > kNumATiles) return false;
+    const ATileShape t = kATiles[shape - 1];
+    return Lx % t.tx == 0 && Ly % t.ty == 0 && a_tile_lds_ok<R>(t.tx, t.ty);
+}
+
+template <typename R, int TX, int TY>
+static hipError_t launch_a_tile(const cpx<R>* U, const spinor<R>* si, spinor<R>* so, int Lx, int Ly, int Ls,
+                                int ncol, R diag, R mdw, R mpv, const int* skip, int skip_stride, int cs,
+                                hipStream_t st) {
+    if constexpr (!a_tile_lds_ok<R>(TX, TY)) {
+        return hipErrorInvalidValue;
+    } else {
+        if (Lx % TX || Ly % TY || Ls < 2) return hipErrorInvalidValue;
+        const int nt = (double)Lx * Ly * Ls * ncol * sizeof(spinor<R>) >= kStreamStoreBytes ? 1 : 0;
+        const int nchunk = (Ls + cs - 1) / cs;
+        const int ntile = (Lx / TX) * (Ly / TY);
+        const long long nblocks = (long long)ntile * nchunk * ncol;
+        if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+        dim3 grid((unsigned)nblocks), block(TX * TY);
+        if (nt)
+            hipLaunchKernelGGL((fine_a_kernel<R, TX, TY, true>), grid, block, 0, st, U, si, so, skip, skip_stride,
+                               Lx, Ly, Ls, nchunk, cs, ntile, diag, mdw, mpv);
+        else
+            hipLaunchKernelGGL((fine_a_kernel<R, TX, TY, false>), grid, block, 0, st, U, si, so, skip, skip_stride,
+                               Lx, Ly, Ls, nchunk, cs, ntile, diag, mdw, mpv);
+        return hipGetLastError();
+    }
+}
+
+template <typename R>
+static hipError_t launch_a(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, cpx<R>* tmp, int Lx, int Ly, int Ls,
+                           int ncol, double m, double M5, const int* skip, int skip_stride, int cfg, hipStream_t st,
+                           bool may_time) {
+    const int shape = cfg / kCfgStride, cs = cfg % kCfgStride;
+    if (shape == 0) {
+        hipError_t e = fine_dw_impl<R>(U, in, tmp, nullptr, Lx, Ly, Ls, ncol, m, M5, false, skip, skip_stride, st,
+                                       may_time);
+        if (e != hipSuccess) return e;
+        return fine_dw_impl<R>(U, tmp, out, nullptr, Lx, Ly, Ls, ncol, 1.0, M5, true, skip, skip_stride, st,
+                               may_time);
+    }
+    if (cs < 1 || !a_tile_fits<R>(shape, Lx, Ly)) return hipErrorInvalidValue;
+    const R diag = R(2.0 + M5 + 1.0), mdw = R(-m), mpv = R(-1.0);
+    auto* si = reinterpret_cast<const spinor<R>*>(in);
+    auto* so = reinterpret_cast<spinor<R>*>(out);
+    static_assert(kNumATiles == 3, "one case per fused tile shape");
+    switch (shape) {
+        case 1: return launch_a_tile<R, kATiles[0].tx, kATiles[0].ty>(U, si, so, Lx, Ly, Ls, ncol, diag, mdw, mpv, skip, skip_stride, cs, st);
+        case 2: return launch_a_tile<R, kATiles[1].tx, kATiles[1].ty>(U, si, so, Lx, Ly, Ls, ncol, diag, mdw, mpv, skip, skip_stride, cs, st);
+        case 3: return launch_a_tile<R, kATiles[2].tx, kATiles[2].ty>(U, si, so, Lx, Ly, Ls, ncol, diag, mdw, mpv, skip, skip_stride, cs, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// pinned configuration of the fine A (shape * kCfgStride + chunk), or -1 (timed choice)
+static std::atomic<int> g_a_pin{-1};
+
+bool set_fine_a_config(int shape, int chunk) {
+    if (shape == -1) { g_a_pin.store(-1); return true; }
+    if (shape < 0 || shape > kNumATiles || (shape > 0 && (chunk < 1 || chunk >= kCfgStride))) return false;
+    g_a_pin.store(shape * kCfgStride + (shape > 0 ? chunk : 0));
+    return true;
+}
+
+// the fine A's configuration, timed once per lattice shape, column count and precision
+// (two launches or one fused launch per tile shape and chunk); the two launches stay
+// unless a fused configuration is faster by more than 3%
+static std::mutex g_a_mu;
+static std::map<std::string, int> g_a_cache;
+
+template <typename R>
+static int tuned_a_cfg(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, cpx<R>* tmp, int Lx, int Ly, int Ls,
+                       int ncol, double m, double M5, hipStream_t st, bool may_time) {
+    std::mutex& mu = g_a_mu;
+    std::map<std::string, int>& cache = g_a_cache;
+    const int heuristic = 0;
+    const char* en = std::getenv("DWF_AUTOTUNE");
+    if (en && en[0] == '0') return heuristic;
+    char keyb[128];
+    std::snprintf(keyb, sizeof keyb, "fine_a/%zu/%d/%d/%d/%d", sizeof(R), Lx, Ly, Ls, ncol);
+    const std::string key(keyb);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (!may_time || hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        return it != cache.end() ? it->second : heuristic;
+    }
+    std::lock_guard<std::recursive_mutex> rlk(runtime_mutex());
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    std::vector<int> cand = {0};
+    for (int shape = 1; shape <= kNumATiles; ++shape) {
+        if (!a_tile_fits<R>(shape, Lx, Ly) || Ls < 2) continue;
+        std::vector<int> chunks;
+        for (int c : {Ls, (Ls + 1) / 2, (Ls + 3) / 4, 4, 2})
+            if (c >= 1 && c <= Ls && std::find(chunks.begin(), chunks.end(), c) == chunks.end()) chunks.push_back(c);
+        for (int c : chunks) cand.push_back(shape * kCfgStride + c);
+    }
+    int best = heuristic;
+    if (cand.size() > 1) {
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return heuristic;
+        if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return heuristic; }
+        float best_t = 1e30f, heur_t = 1e30f;
+        for (int c : cand) {
+            if (launch_a<R>(U, in, out, tmp, Lx, Ly, Ls, ncol, m, M5, nullptr, 1, c, st, true) != hipSuccess) continue;
+            float tc = 1e30f;
+            for (int trial = 0; trial < 3; ++trial) {
+                (void)hipEventRecord(e0, st);
+                for (int r = 0; r < 10; ++r)
+                    (void)launch_a<R>(U, in, out, tmp, Lx, Ly, Ls, ncol, m, M5, nullptr, 1, c, st, true);
+                (void)hipEventRecord(e1, st);
+                (void)hipEventSynchronize(e1);
+                float t = 0.f;
+                if (hipEventElapsedTime(&t, e0, e1) == hipSuccess && t < tc) tc = t;
+            }
+            if (c == heuristic) heur_t = tc;
+            if (tc < best_t) { best_t = tc; best = c; }
+        }
+        if (heur_t < 1e30f && heur_t <= 1.03f * best_t) best = heuristic;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    cache[key] = best;
+    return best;
+}
+
+template <typename R>
+hipError_t fine_a(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, cpx<R>* tmp, int Lx, int Ly, int Ls, int ncol,
+                  double m, double M5, const int* skip, int skip_stride, hipStream_t st) {
+    const int pin = g_a_pin.load(std::memory_order_relaxed);
+    int cfg;
+    if (pin >= 0 && (pin / kCfgStride == 0 || (a_tile_fits<R>(pin / kCfgStride, Lx, Ly) && Ls >= 2)))
+        cfg = pin / kCfgStride == 0 ? 0 : (pin / kCfgStride) * kCfgStride + std::min(pin % kCfgStride, Ls);
+    else
+        cfg = tuned_a_cfg<R>(U, in, out, tmp, Lx, Ly, Ls, ncol, m, M5, st, true);
+    return launch_a<R>(U, in, out, tmp, Lx, Ly, Ls, ncol, m, M5, skip, skip_stride, cfg, st, true);
+}
+
+bool fine_a_chosen(int prec_bytes, int Lx, int Ly, int Ls, int ncol, int* shape, int* chunk) {
+    char keyb[128];
+    std::snprintf(keyb, sizeof keyb, "fine_a/%d/%d/%d/%d/%d", prec_bytes, Lx, Ly, Ls, ncol);
+    std::lock_guard<std::mutex> lk(g_a_mu);
+    auto it = g_a_cache.find(keyb);
+    if (it == g_a_cache.end()) return false;
+    *shape = it->second / kCfgStride;
+    *chunk = it->second % kCfgStride;
+    return true;
+}
+
 template <typename R>
 hipError_t wilson2d(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int Ly, int ncol,
                     double M, bool dagger, hipStream_t st) {
@@ -543,6 +862,8 @@ template hipError_t fine_dw<float>(const cpx<float>*, const cpx<float>*, cpx<flo
 template hipError_t fine_dw<double>(const cpx<double>*, const cpx<double>*, cpx<double>*, const cpx<double>*, int, int, int, int, double, double, bool, const int*, int, hipStream_t);
 template hipError_t fine_dw_untimed<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, int, int, int, int, double, double, bool, hipStream_t);
 template hipError_t fine_dw_untimed<double>(const cpx<double>*, const cpx<double>*, cpx<double>*, int, int, int, int, double, double, bool, hipStream_t);
+template hipError_t fine_a<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, cpx<float>*, int, int, int, int, double, double, const int*, int, hipStream_t);
+template hipError_t fine_a<double>(const cpx<double>*, const cpx<double>*, cpx<double>*, cpx<double>*, int, int, int, int, double, double, const int*, int, hipStream_t);
 template hipError_t wilson2d<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, int, int, int, double, bool, hipStream_t);
 template hipError_t wilson2d<double>(const cpx<double>*, const cpx<double>*, cpx<double>*, int, int, int, double, bool, hipStream_t);
 

@@ -49,6 +49,17 @@ hipError_t fine_dw_untimed(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int L
 // pin the fine stencil's launch configuration (shape -1: automatic choice);
 // returns false for an unknown shape or chunk
 bool set_fine_config(int shape, int chunk);
+// out = D_PV^dag D_DW(m) in on the fine level (the operator A of eq. NormalExp): two
+// stencil launches through tmp, or one fused launch that keeps the intermediate in LDS
+// (tmp then untouched), whichever the timed choice or the pin selects
+template <typename R>
+hipError_t fine_a(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, cpx<R>* tmp, int Lx, int Ly, int Ls, int ncol,
+                  double m, double M5, const int* skip, int skip_stride, hipStream_t st);
+// pin the fine A's configuration: shape -1 timed choice, 0 two launches, k >= 1 fused tile
+// shape k with the given slice chunk; false for an unknown shape or chunk
+bool set_fine_a_config(int shape, int chunk);
+// the timed choice for a shape (false if none was made yet)
+bool fine_a_chosen(int prec_bytes, int Lx, int Ly, int Ls, int ncol, int* shape, int* chunk);
 template <typename R>
 hipError_t wilson2d(const cpx<R>* U, const cpx<R>* in, cpx<R>* out, int Lx, int Ly, int ncol,
                     double M, bool dagger, hipStream_t st);

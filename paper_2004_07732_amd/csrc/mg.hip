@@ -204,6 +204,13 @@ hipError_t Hierarchy::pv_poly(const cpx<T>* w, cpx<T>* y, cpx<T>* z, int ncol, h
 template <typename T>
 hipError_t Hierarchy::apply_A(int l, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp, int ncol, hipStream_t st,
                               const int* skip) {
+    if (l == 0 && prm.pv_poly_order == 0) {
+        if (!capturing_) cnt_.fine_applies += a_cost(0);
+        const Level& L = levels[0];
+        const cpx<T>* U;
+        if constexpr (std::is_same<T, float>::value) U = L.U32; else U = L.U64;
+        return fine_a<T>(U, in, out, tmp, L.Lx, L.Ly, L.Ls, ncol, m, M5, skip, skip ? kSkipStride : 1, st);
+    }
     hipError_t e = apply_dw<T>(l, in, tmp, m, false, ncol, st, skip);
     if (e != hipSuccess) return e;
     if (l == 0 && !capturing_) cnt_.fine_applies += a_cost(0);

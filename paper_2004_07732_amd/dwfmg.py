@@ -42,6 +42,7 @@ KRYLOV_CGNR, KRYLOV_BICGSTAB = 0, 1
 TRANSFER_WALL, TRANSFER_BULK, TRANSFER_SLICE1 = 0, 1, 2
 PV_POLY_MAX = 3
 FINE_AUTO, FINE_ROW, FINE_TILE_64x8, FINE_TILE_32x16, FINE_TILE_128x4 = -1, 0, 1, 2, 3
+FINE_A_AUTO, FINE_A_TWO, FINE_A_16x16, FINE_A_32x8, FINE_A_16x8 = -1, 0, 1, 2, 3
 
 
 class DwfError(RuntimeError):
@@ -68,6 +69,8 @@ def lib() -> ctypes.CDLL:
         L.dwf_pv_apply_noalloc_max_bytes.argtypes = []
         L.dwf_pv_apply_noalloc_max_bytes.restype = sz
         L.dwf_fine_config.argtypes = [i, i]
+        L.dwf_fine_a_config.argtypes = [i, i]
+        L.dwf_fine_a_chosen.argtypes = [i, i, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]
         L.dwf_pv_poly_apply.argtypes = [vp, vp, vp, i, i, i, i, d, d, ctypes.POINTER(d), i, i, vp]
         L.dwf_pv_poly_chebyshev.argtypes = [i, d, d, ctypes.POINTER(d)]
         L.dwf_wilson_apply.argtypes = [vp, vp, vp, i, i, i, d, i, vp]
@@ -100,7 +103,8 @@ def lib() -> ctypes.CDLL:
         L.dwf_release_scratch.argtypes = []
         L.dwf_strerror.argtypes = [i]
         L.dwf_strerror.restype = ctypes.c_char_p
-        for name in ("dwf_apply", "dwf_pv_apply", "dwf_pv_apply_noalloc", "dwf_fine_config", "dwf_pv_poly_apply", "dwf_pv_poly_chebyshev",
+        for name in ("dwf_apply", "dwf_pv_apply", "dwf_pv_apply_noalloc", "dwf_fine_config", "dwf_fine_a_config",
+                     "dwf_fine_a_chosen", "dwf_pv_poly_apply", "dwf_pv_poly_chebyshev",
                      "dwf_wilson_apply", "dwf_gamma5R", "dwf_gauge_transform",
                      "dwf_pack", "dwf_unpack", "dwf_force", "dwf_links_from_theta", "mg_setup", "mg_solve", "mg_level_op", "mg_export",
                      "mg_time_op", "dwf_norm2", "dwf_copy_bandwidth", "mg_update_links", "mg_solve_batch",
@@ -328,6 +332,21 @@ def dwf_fine_config(shape, chunk=1):
     """Pin the fine stencil's launch configuration for the process (FINE_ROW or a
     FINE_TILE_* shape, `chunk` slices per thread); FINE_AUTO restores the tuned choice."""
     _check(lib().dwf_fine_config(int(shape), int(chunk)), "dwf_fine_config")
+
+
+def dwf_fine_a_config(shape, chunk=1):
+    """Pin the launch configuration of the solver's fine A = D_PV^dag D_DW: FINE_A_TWO
+    (two stencil launches) or a fused FINE_A_* tile shape with `chunk` output slices per
+    workgroup; FINE_A_AUTO restores the timed choice."""
+    _check(lib().dwf_fine_a_config(int(shape), int(chunk)), "dwf_fine_a_config")
+
+
+def dwf_fine_a_chosen(Lx, Ly, Ls, nrhs, f32=True):
+    """(shape, chunk) the timed choice picked for the fine A at this shape, or None."""
+    sh, ch = ctypes.c_int(), ctypes.c_int()
+    code = lib().dwf_fine_a_chosen(DWF_PREC_F32 if f32 else 0, int(Lx), int(Ly), int(Ls), int(nrhs),
+                                   ctypes.byref(sh), ctypes.byref(ch))
+    return (sh.value, ch.value) if code == DWF_OK else None
 
 
 def dwf_pv_apply(U, psi, m_f, M5, mode=DWF_PVDAG_DW, out=None, stream=None):
