@@ -415,6 +415,10 @@ def main():
                     help="restart length of the post-smoothing GCR (default 5; 0: none, the paper's smoother)")
     ap.add_argument("--nvec", type=int, nargs="+", default=None, help="override the workload's null vectors per level")
     ap.add_argument("--ls-coarse", type=int, nargs="+", default=None, help="override the coarse Ls per level")
+    ap.add_argument("--fine-a", choices=["auto", "two", "fused"], default="auto",
+                    help="the solver's fine A: timed choice (default), the two stencil launches, or the fused launch "
+                         "(16x16 tiles, chunk Ls); a profiler's per-launch overhead can tip the timed choice, so "
+                         "profiled runs pin the choice the unprofiled benchmark makes")
     ap.add_argument("--quick", action="store_true", help="only the headline solve and its roofline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -439,6 +443,10 @@ def main():
     from paper_2004_07732_amd import dwfmg, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.fine_a == "two":
+        dwfmg.dwf_fine_a_config(dwfmg.FINE_A_TWO)
+    elif args.fine_a == "fused":
+        dwfmg.dwf_fine_a_config(dwfmg.FINE_A_16x16, 4096 - 1)
     wl = dict(WORKLOADS[args.workload])
     if args.nvec:
         wl["nvec"] = list(args.nvec)
