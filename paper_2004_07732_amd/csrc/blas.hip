@@ -668,6 +668,163 @@ k_gcr_fused_update(const cpx<T>* W, size_t wstride, cpx<T>* w, cpx<T>* r, cpx<T>
     }
 }
 
+// ---- Gram-form GCR step (the smoother's cycles).  With w_i = A p_i kept as computed
+// (not orthogonalised) and r0 the cycle's starting residual, step j's minimal residual over
+// span(p_0..p_j) is r_{j+1} = r0 - sum_{i<=j} y_i w_i with G y = b, G_il = <w_i, w_l>,
+// b_i = <w_i, r0> (the normal equations of the same least-squares problem GCR solves by
+// orthogonalising).  The multi-dot of step j gives G's new row and b_j.  Its finaliser is
+// one workgroup per column: wave q adds the partials of quantity q, then one thread solves
+// the (j+1)-square system by Cholesky in FP64 registers (a pivot that is not positive drops
+// that direction: its y is zero) and stores G's row, b_j, y and the stop flag.  The
+// streaming kernel then writes out = r_{j+1} (the next direction, or r0 itself in place at
+// the end of the cycle); no orthogonalised direction and no running residual is written.
+template <int j>
+__global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw, int nb, const int* stop_in,
+                                                                     int* stop_out, GcrDev g) {
+    constexpr int m = j + 1;
+    constexpr int NQ = 2 * j + 3;
+    static_assert(64 * NQ <= 1024, "one wave per inner product in one workgroup");
+    __shared__ double tq[NQ];
+    const int col = blockIdx.x;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;   // one wave per quantity
+    const bool stopped = stop_in[col] != 0;
+    if (!stopped && q < NQ) {
+        const double* part = rw.partial + (size_t)col * rw.max_q * rw.nblk + (size_t)q * rw.nblk;
+        double sq = 0.0;
+#pragma unroll 8
+        for (int b = lane; b < nb; b += 64) sq += part[b];
+        sq = wave_sum(sq);
+        if (lane == 0) tq[q] = sq;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const size_t kb = (size_t)col * g.kmax;
+    if (stopped) {
+        for (int l = 0; l < j; ++l) {
+            g.D[((kb + j) * g.kmax + l) * 2] = 0.0;
+            g.D[((kb + j) * g.kmax + l) * 2 + 1] = 0.0;
+        }
+        g.nn[kb + j] = 0.0;
+        g.wr[2 * (kb + j)] = 0.0;
+        g.wr[2 * (kb + j) + 1] = 0.0;
+        for (int i = 0; i < m; ++i) { g.gam[2 * (kb + i)] = 0.0; g.gam[2 * (kb + i) + 1] = 0.0; }
+        stop_out[col] = stop_in[col];
+        return;
+    }
+    // G (lower triangle: G_il = conj <w_l, w_i>, l < i) and b
+    cpx<double> G[m][m], b[m];
+#pragma unroll
+    for (int i = 0; i < j; ++i) {
+#pragma unroll
+        for (int l = 0; l < i; ++l)
+            G[i][l] = {g.D[((kb + i) * g.kmax + l) * 2], -g.D[((kb + i) * g.kmax + l) * 2 + 1]};
+        G[i][i] = {g.nn[kb + i], 0.0};
+        b[i] = {g.wr[2 * (kb + i)], g.wr[2 * (kb + i) + 1]};
+    }
+#pragma unroll
+    for (int l = 0; l < j; ++l) G[j][l] = {tq[3 + 2 * l], -tq[4 + 2 * l]};
+    G[j][j] = {tq[0], 0.0};
+    b[j] = {tq[1], tq[2]};
+    // Cholesky G = L L^H in place (lower triangle), inv[i] = 1 / L_ii or 0 for a dropped direction
+    double inv[m];
+#pragma unroll
+    for (int i = 0; i < m; ++i) {
+#pragma unroll
+        for (int l = 0; l <= i; ++l) {
+            cpx<double> acc = G[i][l];
+#pragma unroll
+            for (int qq = 0; qq < l; ++qq) {   // - L_iq conj(L_lq)
+                acc.re -= G[i][qq].re * G[l][qq].re + G[i][qq].im * G[l][qq].im;
+                acc.im -= G[i][qq].im * G[l][qq].re - G[i][qq].re * G[l][qq].im;
+            }
+            if (l == i) {
+                const bool ok = acc.re > 0.0 && finite(acc.re);
+                inv[i] = ok ? 1.0 / sqrt(acc.re) : 0.0;
+                G[i][i] = {ok ? sqrt(acc.re) : 0.0, 0.0};
+            } else {
+                G[i][l] = {acc.re * inv[l], acc.im * inv[l]};
+            }
+        }
+    }
+    cpx<double> u[m], y[m];
+#pragma unroll
+    for (int i = 0; i < m; ++i) {   // L u = b
+        cpx<double> acc = b[i];
+#pragma unroll
+        for (int qq = 0; qq < i; ++qq) {
+            acc.re -= G[i][qq].re * u[qq].re - G[i][qq].im * u[qq].im;
+            acc.im -= G[i][qq].re * u[qq].im + G[i][qq].im * u[qq].re;
+        }
+        u[i] = {acc.re * inv[i], acc.im * inv[i]};
+    }
+#pragma unroll
+    for (int i = m - 1; i >= 0; --i) {   // L^H y = u, (L^H)_iq = conj(L_qi)
+        cpx<double> acc = u[i];
+#pragma unroll
+        for (int qq = i + 1; qq < m; ++qq) {
+            acc.re -= G[qq][i].re * y[qq].re + G[qq][i].im * y[qq].im;
+            acc.im -= G[qq][i].re * y[qq].im - G[qq][i].im * y[qq].re;
+        }
+        y[i] = {acc.re * inv[i], acc.im * inv[i]};
+    }
+#pragma unroll
+    for (int l = 0; l < j; ++l) {
+        g.D[((kb + j) * g.kmax + l) * 2] = tq[3 + 2 * l];
+        g.D[((kb + j) * g.kmax + l) * 2 + 1] = tq[4 + 2 * l];
+    }
+    g.nn[kb + j] = tq[0];
+    g.wr[2 * (kb + j)] = tq[1];
+    g.wr[2 * (kb + j) + 1] = tq[2];
+#pragma unroll
+    for (int i = 0; i < m; ++i) { g.gam[2 * (kb + i)] = y[i].re; g.gam[2 * (kb + i) + 1] = y[i].im; }
+    stop_out[col] = (finite(tq[0]) && finite(tq[1]) && finite(tq[2])) ? 0 : 2;
+}
+
+template <typename T, int j>
+__global__ void __launch_bounds__(kBlock)
+k_gcr_gram_step(const cpx<T>* W, size_t wstride, const cpx<T>* r0, cpx<T>* out, size_t n, const int* stop_in,
+                GcrDev g) {
+    constexpr int m = j + 1;
+    const int col = blockIdx.y;
+    const size_t o = (size_t)col * n;
+    if (stop_in[col] != 0) {   // (block-uniform) a stopped column's later directions are zero; r0 is kept
+        if (out != r0) GRID_STRIDE(e, n) out[o + e] = cpx<T>{(T)0, (T)0};
+        return;
+    }
+    const double* gam = g.gam + 2 * (size_t)col * g.kmax;
+    cpx<T> c[m];
+#pragma unroll
+    for (int i = 0; i < m; ++i) c[i] = {(T)gam[2 * i], (T)gam[2 * i + 1]};
+    constexpr int U = gcr_unroll<T>(j);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    auto step = [&](size_t i0, cpx<T> re, const cpx<T>* Wt) {
+#pragma unroll
+        for (int i = 0; i < m; ++i) {
+            re.re -= c[i].re * Wt[i].re - c[i].im * Wt[i].im;
+            re.im -= c[i].re * Wt[i].im + c[i].im * Wt[i].re;
+        }
+        out[i0] = re;
+    };
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; e + (U - 1) * stride < n; e += U * stride) {
+        cpx<T> rv[U], Wv[U][m];
+#pragma unroll
+        for (int u2 = 0; u2 < U; ++u2) {
+            rv[u2] = r0[o + e + u2 * stride];
+#pragma unroll
+            for (int i = 0; i < m; ++i) Wv[u2][i] = W[(size_t)i * wstride + o + e + u2 * stride];
+        }
+#pragma unroll
+        for (int u2 = 0; u2 < U; ++u2) step(o + e + u2 * stride, rv[u2], Wv[u2]);
+    }
+    for (; e < n; e += stride) {
+        cpx<T> Wt[m];
+#pragma unroll
+        for (int i = 0; i < m; ++i) Wt[i] = W[(size_t)i * wstride + o + e];
+        step(o + e, r0[o + e], Wt);
+    }
+}
+
 // restart of the device-driven GCR on the recursive residual: the next first
 // direction is r, and the stop flags of the last step move to g.stop
 template <typename T>
@@ -818,6 +975,30 @@ hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx
     return hipGetLastError();
 }
 template <typename T>
+hipError_t gcr_gram_step(const cpx<T>* W, size_t wstride, int j, const cpx<T>* r0, cpx<T>* out, size_t n, int ncol,
+                         const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw, hipStream_t st) {
+    if (j < 0 || j >= kGramMax || 2 * j + 3 > kGcrTot || 2 * j + 3 > rw.max_q || j >= g.kmax) return hipErrorInvalidValue;
+    const dim3 grid = red_grid(n, ncol, rw);
+    auto launch = [&](auto jc) {
+        constexpr int J = decltype(jc)::value;
+        hipLaunchKernelGGL((k_gcr_dots<T, J>), grid, dim3(kBlock), 0, st, W, wstride, W + (size_t)J * wstride, r0, n,
+                           stop_in, rw);
+        hipLaunchKernelGGL(k_fin_gram<J>, dim3(ncol), dim3(64 * (2 * J + 3)), 0, st, rw, (int)grid.x, stop_in, stop_out,
+                           g);
+        hipLaunchKernelGGL((k_gcr_gram_step<T, J>), ew_grid(n, ncol), dim3(kBlock), 0, st, W, wstride, r0, out, n,
+                           stop_in, g);
+    };
+    with_j(j, launch, std::make_integer_sequence<int, kGramMax>{});
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t gcr_gam_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<T>* x, size_t n, int ncol, const cpx<T>* r,
+                           cpx<T>* p0, const int* stop_src, const GcrDev& g, hipStream_t st) {
+    if (k < 1 || k > 16) return hipErrorInvalidValue;
+    launch_xupdate<T, T>(P, pstride, k, x, n, ncol, true, g, 0, r, p0, stop_src, st);
+    return hipGetLastError();
+}
+template <typename T>
 hipError_t gcr_restart(const cpx<T>* r, cpx<T>* P0, size_t n, int ncol, const int* stop_src, const GcrDev& g,
                        hipStream_t st) {
     hipLaunchKernelGGL(k_gcr_restart<T>, ew_grid(n * ncol, 1), dim3(kBlock), 0, st, r, P0, n * ncol, stop_src, g.stop,
@@ -922,6 +1103,10 @@ template hipError_t gcr_xupdate<double, double>(const cpx<double>*, size_t, int,
 template hipError_t gcr_xupdate<float, double>(const cpx<float>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
 template hipError_t gcr_solve_xupdate<float, float>(const cpx<float>*, size_t, int, cpx<float>*, size_t, int, bool, const GcrDev&, hipStream_t);
 template hipError_t gcr_solve_xupdate<double, double>(const cpx<double>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
+template hipError_t gcr_gram_step<float>(const cpx<float>*, size_t, int, const cpx<float>*, cpx<float>*, size_t, int, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
+template hipError_t gcr_gram_step<double>(const cpx<double>*, size_t, int, const cpx<double>*, cpx<double>*, size_t, int, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
+template hipError_t gcr_gam_xupdate<float>(const cpx<float>*, size_t, int, cpx<float>*, size_t, int, const cpx<float>*, cpx<float>*, const int*, const GcrDev&, hipStream_t);
+template hipError_t gcr_gam_xupdate<double>(const cpx<double>*, size_t, int, cpx<double>*, size_t, int, const cpx<double>*, cpx<double>*, const int*, const GcrDev&, hipStream_t);
 template hipError_t gcr_solve_xupdate_restart<float>(cpx<float>*, size_t, int, cpx<float>*, size_t, int, const cpx<float>*, const int*, const GcrDev&, hipStream_t);
 template hipError_t gcr_solve_xupdate_restart<double>(cpx<double>*, size_t, int, cpx<double>*, size_t, int, const cpx<double>*, const int*, const GcrDev&, hipStream_t);
 

@@ -184,6 +184,20 @@ template <typename T>
 hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx<T>* r, cpx<T>* copy, size_t n,
                           int ncol, double tol2, const int* stop_in, int* stop_out, const GcrDev& g,
                           const RedWork& rw, hipStream_t st);
+// Gram-form GCR step j (the smoother's restart cycles, j < kGramMax), three launches: the
+// multi-dot of w_j = W_j against W_0..W_{j-1} and r0, its finaliser, and one pass that
+// solves G y = b (G_il = <W_i, W_l>, b_i = <W_i, r0>, i, l <= j) in every block and writes
+// out = r0 - sum_{i<=j} y_i W_i (out may be r0).  Keeps G's rows in g.D / g.nn, b in g.wr
+// and y in g.gam; a not-finite inner product sets stop flag 2 in stop_out.
+constexpr int kGramMax = 7;   // (the finaliser runs one wave per inner product: 2 j + 3 <= 16 waves)
+template <typename T>
+hipError_t gcr_gram_step(const cpx<T>* W, size_t wstride, int j, const cpx<T>* r0, cpx<T>* out, size_t n, int ncol,
+                         const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw, hipStream_t st);
+// x += sum_{i<k} g.gam[i] P_i with g.gam as stored (no substitution); with p0 != null also
+// P_0 = r (the next cycle's first direction) and the stop flags of stop_src into g.stop
+template <typename T>
+hipError_t gcr_gam_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<T>* x, size_t n, int ncol, const cpx<T>* r,
+                           cpx<T>* p0, const int* stop_src, const GcrDev& g, hipStream_t st);
 // next restart cycle on the recursive residual: P0 = r, and the stop flags of the
 // cycle's last step (stop_src) become g.stop
 template <typename T>
