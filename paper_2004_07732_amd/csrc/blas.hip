@@ -678,6 +678,7 @@ k_gcr_fused_update(const cpx<T>* W, size_t wstride, cpx<T>* w, cpx<T>* r, cpx<T>
 // that direction: its y is zero) and stores G's row, b_j, y and the stop flag.  The
 // streaming kernel then writes out = r_{j+1} (the next direction, or r0 itself in place at
 // the end of the cycle); no orthogonalised direction and no running residual is written.
+constexpr int kGramPartials = 1024;
 template <int j>
 __global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw, int nb, const int* stop_in,
                                                                      int* stop_out, GcrDev g) {
@@ -978,7 +979,9 @@ template <typename T>
 hipError_t gcr_gram_step(const cpx<T>* W, size_t wstride, int j, const cpx<T>* r0, cpx<T>* out, size_t n, int ncol,
                          const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw, hipStream_t st) {
     if (j < 0 || j >= kGramMax || 2 * j + 3 > kGcrTot || 2 * j + 3 > rw.max_q || j >= g.kmax) return hipErrorInvalidValue;
-    const dim3 grid = red_grid(n, ncol, rw);
+    // at most kGramPartials multi-dot blocks: the finaliser's waves each add that many partials
+    dim3 grid = red_grid(n, ncol, rw);
+    grid.x = std::min(grid.x, (unsigned)kGramPartials);
     auto launch = [&](auto jc) {
         constexpr int J = decltype(jc)::value;
         hipLaunchKernelGGL((k_gcr_dots<T, J>), grid, dim3(kBlock), 0, st, W, wstride, W + (size_t)J * wstride, r0, n,
