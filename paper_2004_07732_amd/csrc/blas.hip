@@ -826,6 +826,40 @@ k_gcr_gram_step(const cpx<T>* W, size_t wstride, const cpx<T>* r0, cpx<T>* out, 
     }
 }
 
+// The last Gram-form step of a cycle together with the cycle's solution update: with
+// P_0 = r0 (the cycle's starting residual, the first direction), x += sum_{i<K} y_i P_i and
+// P_0 = r0 - sum_{i<K} y_i W_i (the next cycle's starting residual) in one pass, element
+// by element in place.
+template <typename T, int K>
+__global__ void __launch_bounds__(kBlock)
+k_gcr_gram_last(cpx<T>* P, const cpx<T>* W, size_t stride_v, cpx<T>* x, size_t n, const int* stop_src, GcrDev g,
+                int ncol) {
+    const int col = blockIdx.y;
+    const size_t o = (size_t)col * n;
+    if (stop_src != g.stop && blockIdx.x == 0 && blockIdx.y == 0)
+        for (int cc = threadIdx.x; cc < ncol; cc += blockDim.x) g.stop[cc] = stop_src[cc];
+    const double* gam = g.gam + 2 * (size_t)col * g.kmax;
+    cpx<double> c[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) c[i] = {gam[2 * i], gam[2 * i + 1]};
+    GRID_STRIDE(e, n) {
+        cpx<double> acc = {(double)x[o + e].re, (double)x[o + e].im};
+        cpx<T> rn = P[o + e];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const cpx<double> p = up(P[(size_t)i * stride_v + o + e]);
+            acc.re += c[i].re * p.re - c[i].im * p.im;
+            acc.im += c[i].re * p.im + c[i].im * p.re;
+            const cpx<T> wv = W[(size_t)i * stride_v + o + e];
+            const cpx<T> ci = {(T)c[i].re, (T)c[i].im};
+            rn.re -= ci.re * wv.re - ci.im * wv.im;
+            rn.im -= ci.re * wv.im + ci.im * wv.re;
+        }
+        x[o + e] = {(T)acc.re, (T)acc.im};
+        P[o + e] = rn;
+    }
+}
+
 // restart of the device-driven GCR on the recursive residual: the next first
 // direction is r, and the stop flags of the last step move to g.stop
 template <typename T>
@@ -995,10 +1029,22 @@ hipError_t gcr_gram_step(const cpx<T>* W, size_t wstride, int j, const cpx<T>* r
     return hipGetLastError();
 }
 template <typename T>
-hipError_t gcr_gam_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<T>* x, size_t n, int ncol, const cpx<T>* r,
-                           cpx<T>* p0, const int* stop_src, const GcrDev& g, hipStream_t st) {
-    if (k < 1 || k > 16) return hipErrorInvalidValue;
-    launch_xupdate<T, T>(P, pstride, k, x, n, ncol, true, g, 0, r, p0, stop_src, st);
+hipError_t gcr_gram_last(cpx<T>* P, const cpx<T>* W, size_t stride_v, int k, cpx<T>* x, size_t n, int ncol,
+                         const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw, hipStream_t st) {
+    const int j = k - 1;
+    if (j < 0 || j >= kGramMax || 2 * j + 3 > kGcrTot || 2 * j + 3 > rw.max_q || j >= g.kmax) return hipErrorInvalidValue;
+    dim3 grid = red_grid(n, ncol, rw);
+    grid.x = std::min(grid.x, (unsigned)kGramPartials);
+    auto launch = [&](auto jc) {
+        constexpr int J = decltype(jc)::value;
+        hipLaunchKernelGGL((k_gcr_dots<T, J>), grid, dim3(kBlock), 0, st, W, stride_v, W + (size_t)J * stride_v, P, n,
+                           stop_in, rw);
+        hipLaunchKernelGGL(k_fin_gram<J>, dim3(ncol), dim3(64 * (2 * J + 3)), 0, st, rw, (int)grid.x, stop_in, stop_out,
+                           g);
+        hipLaunchKernelGGL((k_gcr_gram_last<T, J + 1>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, W, stride_v, x, n,
+                           stop_out, g, ncol);
+    };
+    with_j(j, launch, std::make_integer_sequence<int, kGramMax>{});
     return hipGetLastError();
 }
 template <typename T>
@@ -1108,8 +1154,8 @@ template hipError_t gcr_solve_xupdate<float, float>(const cpx<float>*, size_t, i
 template hipError_t gcr_solve_xupdate<double, double>(const cpx<double>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
 template hipError_t gcr_gram_step<float>(const cpx<float>*, size_t, int, const cpx<float>*, cpx<float>*, size_t, int, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
 template hipError_t gcr_gram_step<double>(const cpx<double>*, size_t, int, const cpx<double>*, cpx<double>*, size_t, int, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
-template hipError_t gcr_gam_xupdate<float>(const cpx<float>*, size_t, int, cpx<float>*, size_t, int, const cpx<float>*, cpx<float>*, const int*, const GcrDev&, hipStream_t);
-template hipError_t gcr_gam_xupdate<double>(const cpx<double>*, size_t, int, cpx<double>*, size_t, int, const cpx<double>*, cpx<double>*, const int*, const GcrDev&, hipStream_t);
+template hipError_t gcr_gram_last<float>(cpx<float>*, const cpx<float>*, size_t, int, cpx<float>*, size_t, int, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
+template hipError_t gcr_gram_last<double>(cpx<double>*, const cpx<double>*, size_t, int, cpx<double>*, size_t, int, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
 template hipError_t gcr_solve_xupdate_restart<float>(cpx<float>*, size_t, int, cpx<float>*, size_t, int, const cpx<float>*, const int*, const GcrDev&, hipStream_t);
 template hipError_t gcr_solve_xupdate_restart<double>(cpx<double>*, size_t, int, cpx<double>*, size_t, int, const cpx<double>*, const int*, const GcrDev&, hipStream_t);
 

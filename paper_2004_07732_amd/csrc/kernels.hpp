@@ -193,11 +193,13 @@ constexpr int kGramMax = 7;   // (the finaliser runs one wave per inner product:
 template <typename T>
 hipError_t gcr_gram_step(const cpx<T>* W, size_t wstride, int j, const cpx<T>* r0, cpx<T>* out, size_t n, int ncol,
                          const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw, hipStream_t st);
-// x += sum_{i<k} g.gam[i] P_i with g.gam as stored (no substitution); with p0 != null also
-// P_0 = r (the next cycle's first direction) and the stop flags of stop_src into g.stop
+// The last Gram-form step (j = k - 1) of a cycle whose starting residual is P_0, fused with
+// the cycle's solution update: multi-dot and finaliser as in gcr_gram_step, then one pass
+// x += sum_{i<k} y_i P_i, P_0 = P_0 - sum_{i<k} y_i W_i (the next cycle's residual and first
+// direction); the stop flags of stop_out become g.stop.
 template <typename T>
-hipError_t gcr_gam_xupdate(const cpx<T>* P, size_t pstride, int k, cpx<T>* x, size_t n, int ncol, const cpx<T>* r,
-                           cpx<T>* p0, const int* stop_src, const GcrDev& g, hipStream_t st);
+hipError_t gcr_gram_last(cpx<T>* P, const cpx<T>* W, size_t stride_v, int k, cpx<T>* x, size_t n, int ncol,
+                         const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw, hipStream_t st);
 // next restart cycle on the recursive residual: P0 = r, and the stop flags of the
 // cycle's last step (stop_src) become g.stop
 template <typename T>

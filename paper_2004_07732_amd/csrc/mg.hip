@@ -539,40 +539,46 @@ int Hierarchy::smooth(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t s
     // the next starts from the recursive residual.
     const int ks = w.kscycle;
     GcrDev& g = w.gsm;
+    // Short cycles take the Gram form (the directions' inner products and the cycle's starting
+    // residual give each step's minimal residual; no orthogonalised direction and no running
+    // residual is stored: two vector passes fewer per step, and the starting residual is the
+    // first direction P_0 itself); long ones keep the orthogonalising form, whose accuracy does
+    // not depend on the Gram matrix's condition (the square of the directions').
+    const bool gram = ks <= kGramSteps;
     auto body = [&]() -> int {
         HIPCHK(apply_A<T>(l, z, Az, t, ncol, st));
-        HIPCHK(vsub<T>(r, Az, rs, nt, st));
-        HIPCHK(vconvert<T, T>(rs, Ps, nt, st));
-        HIPCHK(norm2<T>(rs, n, ncol, g.rr, rw_, st));
+        if (gram) {
+            HIPCHK(vsub<T>(r, Az, Ps, nt, st));
+            HIPCHK(norm2<T>(Ps, n, ncol, g.rr, rw_, st));
+        } else {
+            HIPCHK(vsub<T>(r, Az, rs, nt, st));
+            HIPCHK(vconvert<T, T>(rs, Ps, nt, st));
+            HIPCHK(norm2<T>(rs, n, ncol, g.rr, rw_, st));
+        }
         HIPCHK(gcr_dev_init(ncol, g, st));
         for (int c0 = 0; c0 < ns; c0 += ks) {
             const int kc = std::min(ks, ns - c0);
-            // Short cycles take the Gram form (the directions' inner products and the cycle's
-            // starting residual give each step's minimal residual; no orthogonalised direction
-            // and no running residual is stored: two vector passes fewer per step); long ones
-            // keep the orthogonalising form, whose accuracy does not depend on the Gram matrix's
-            // condition (the square of the directions').
-            const bool gram = ks <= kGramSteps;
             for (int j = 0; j < kc; ++j) {
                 cpx<T>* Pj = Ps + (size_t)j * nt;
                 cpx<T>* Wj = Ws + (size_t)j * nt;
                 const int* s_in = (j % 2 == 0) ? g.stop : g.stop2;
                 int* s_out = (j % 2 == 0) ? g.stop2 : g.stop;
                 HIPCHK(apply_A<T>(l, Pj, Wj, t, ncol, st));
-                if (gram) {
-                    // the next direction r_{j+1}, or at the cycle's end the residual in place
-                    HIPCHK(gcr_gram_step<T>(Ws, nt, j, rs, (j + 1 < kc) ? Ps + (size_t)(j + 1) * nt : rs, n, ncol,
-                                            s_in, s_out, g, rw_, st));
+                if (gram && j + 1 < kc) {
+                    // the next direction r_{j+1} = P_0 - sum y_i W_i
+                    HIPCHK(gcr_gram_step<T>(Ws, nt, j, Ps, Ps + (size_t)(j + 1) * nt, n, ncol, s_in, s_out, g, rw_,
+                                            st));
+                } else if (gram) {
+                    // z += this cycle's correction, P_0 = the next cycle's starting residual
+                    HIPCHK(gcr_gram_last<T>(Ps, Ws, nt, kc, z, n, ncol, s_in, s_out, g, rw_, st));
                 } else {
                     HIPCHK(gcr_fused_step<T>(Ws, nt, j, Wj, rs, (j + 1 < kc) ? Ps + (size_t)(j + 1) * nt : nullptr,
                                              n, ncol, -1.0, s_in, s_out, g, rw_, st));
                 }
             }
             const int* s_last = (kc % 2 == 0) ? g.stop : g.stop2;
-            if (gram) {
-                // z += this cycle's correction (the last step's y), P_0 = the residual for the next cycle
-                HIPCHK(gcr_gam_xupdate<T>(Ps, nt, kc, z, n, ncol, rs, (c0 + kc < ns) ? Ps : nullptr, s_last, g, st));
-            } else if (c0 + kc < ns) {
+            if (gram) continue;   // (the last Gram step did the solution update)
+            if (c0 + kc < ns) {
                 // z += this cycle's correction, P_0 = the residual, the last step's flags to g.stop
                 HIPCHK(gcr_solve_xupdate_restart<T>(Ps, nt, kc, z, n, ncol, rs, s_last, g, st));
             } else {
