@@ -244,22 +244,29 @@ GRAM_STEPS = 6   # longest smoother cycle the library runs in the Gram form
 
 
 def smoother_model_passes(ns, ks):
-    """Fine-vector passes of one post-smoothing call: the initial residual (subtract:
-    3, copy: 2, norm: 1), then per step j of a cycle of kc steps the multi-dot (j + 2)
-    and either, in cycles of at most GRAM_STEPS steps (the Gram form), the next
-    direction (j + 2 read, 1 written), or else the fused update (j + 2 read; w and r
-    written, and the next direction except after the cycle's last step); per cycle the
-    solution update (kc + 2), with the restart copy (2 more) on every cycle but the last."""
+    """Fine-vector passes of one post-smoothing call.
+    Gram form (cycles of at most GRAM_STEPS steps): the initial residual straight into the
+    first direction (subtract: 3, norm: 1); per step j < kc - 1 of a cycle the multi-dot
+    (j + 2) and the next direction (j + 2 read, 1 written); the cycle's last step the
+    multi-dot (kc + 1) and the pass that updates z and the starting residual (2 kc + 1
+    read, 2 written): kc^2 + 5 kc + 1 per cycle.
+    Orthogonalising form: the initial residual (subtract: 3, copy: 2, norm: 1); per step
+    the multi-dot (j + 2) and the fused update (j + 2 read; w and r written, and the next
+    direction except after the cycle's last step); per cycle the solution update
+    (kc + 2), with the restart copy (2 more) on every cycle but the last."""
     if ns <= 0:
         return 0
     ks = ks if 0 < ks < ns else ns
     gram = ks <= GRAM_STEPS
-    passes, done = 6, 0
+    passes, done = (4 if gram else 6), 0
     while done < ns:
         kc = min(ks, ns - done)
-        passes += (kc * kc + 4 * kc if gram else kc * kc + 6 * kc - 1) + kc + 2
+        if gram:
+            passes += kc * kc + 5 * kc + 1
+        else:
+            passes += kc * kc + 6 * kc - 1 + kc + 2
         done += kc
-        if done < ns:
+        if done < ns and not gram:
             passes += 2
     return passes
 
