@@ -681,7 +681,7 @@ k_gcr_fused_update(const cpx<T>* W, size_t wstride, cpx<T>* w, cpx<T>* r, cpx<T>
 constexpr int kGramPartials = 1024;
 template <int j>
 __global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw, int nb, const int* stop_in,
-                                                                     int* stop_out, GcrDev g) {
+                                                                     int* stop_out, GcrDev g, double tol2, int last) {
     constexpr int m = j + 1;
     constexpr int NQ = 2 * j + 3;
     static_assert(64 * NQ <= 1024, "one wave per inner product in one workgroup");
@@ -708,7 +708,10 @@ __global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw
         g.nn[kb + j] = 0.0;
         g.wr[2 * (kb + j)] = 0.0;
         g.wr[2 * (kb + j) + 1] = 0.0;
-        for (int i = 0; i < m; ++i) { g.gam[2 * (kb + i)] = 0.0; g.gam[2 * (kb + i) + 1] = 0.0; }
+        // the coefficients of the step the column stopped at stay (a stopped step's own is
+        // zero), so that the cycle's solution update adds that step's minimal residual correction
+        g.gam[2 * (kb + j)] = 0.0;
+        g.gam[2 * (kb + j) + 1] = 0.0;
         stop_out[col] = stop_in[col];
         return;
     }
@@ -776,9 +779,22 @@ __global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw
     g.nn[kb + j] = tq[0];
     g.wr[2 * (kb + j)] = tq[1];
     g.wr[2 * (kb + j) + 1] = tq[2];
+    // |r_{j+1}|^2 = |r0|^2 - Re <b, y> (the minimal residual), the cycle's |r0|^2 in g.rr
+    double by = 0.0;
 #pragma unroll
-    for (int i = 0; i < m; ++i) { g.gam[2 * (kb + i)] = y[i].re; g.gam[2 * (kb + i) + 1] = y[i].im; }
-    stop_out[col] = (finite(tq[0]) && finite(tq[1]) && finite(tq[2])) ? 0 : 2;
+    for (int i = 0; i < m; ++i) {
+        g.gam[2 * (kb + i)] = y[i].re;
+        g.gam[2 * (kb + i) + 1] = y[i].im;
+        by += b[i].re * y[i].re + b[i].im * y[i].im;
+    }
+    double rr = g.rr[col] - by;
+    if (rr < 0.0) rr = 0.0;
+    if (last) g.rr[col] = rr;
+    g.it[col] += 1;
+    int f = 0;
+    if (!(finite(tq[0]) && finite(tq[1]) && finite(tq[2]) && finite(rr))) f = 2;
+    else if (rr <= tol2 * g.bb[col]) f = 1;
+    stop_out[col] = f;
 }
 
 template <typename T, int j>
@@ -1011,7 +1027,8 @@ hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx
 }
 template <typename T>
 hipError_t gcr_gram_step(const cpx<T>* W, size_t wstride, int j, const cpx<T>* r0, cpx<T>* out, size_t n, int ncol,
-                         const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw, hipStream_t st) {
+                         double tol2, const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw,
+                         hipStream_t st) {
     if (j < 0 || j >= kGramMax || 2 * j + 3 > kGcrTot || 2 * j + 3 > rw.max_q || j >= g.kmax) return hipErrorInvalidValue;
     // at most kGramPartials multi-dot blocks: the finaliser's waves each add that many partials
     dim3 grid = red_grid(n, ncol, rw);
@@ -1021,7 +1038,7 @@ hipError_t gcr_gram_step(const cpx<T>* W, size_t wstride, int j, const cpx<T>* r
         hipLaunchKernelGGL((k_gcr_dots<T, J>), grid, dim3(kBlock), 0, st, W, wstride, W + (size_t)J * wstride, r0, n,
                            stop_in, rw);
         hipLaunchKernelGGL(k_fin_gram<J>, dim3(ncol), dim3(64 * (2 * J + 3)), 0, st, rw, (int)grid.x, stop_in, stop_out,
-                           g);
+                           g, tol2, 0);
         hipLaunchKernelGGL((k_gcr_gram_step<T, J>), ew_grid(n, ncol), dim3(kBlock), 0, st, W, wstride, r0, out, n,
                            stop_in, g);
     };
@@ -1030,7 +1047,8 @@ hipError_t gcr_gram_step(const cpx<T>* W, size_t wstride, int j, const cpx<T>* r
 }
 template <typename T>
 hipError_t gcr_gram_last(cpx<T>* P, const cpx<T>* W, size_t stride_v, int k, cpx<T>* x, size_t n, int ncol,
-                         const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw, hipStream_t st) {
+                         double tol2, const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw,
+                         hipStream_t st) {
     const int j = k - 1;
     if (j < 0 || j >= kGramMax || 2 * j + 3 > kGcrTot || 2 * j + 3 > rw.max_q || j >= g.kmax) return hipErrorInvalidValue;
     dim3 grid = red_grid(n, ncol, rw);
@@ -1040,7 +1058,7 @@ hipError_t gcr_gram_last(cpx<T>* P, const cpx<T>* W, size_t stride_v, int k, cpx
         hipLaunchKernelGGL((k_gcr_dots<T, J>), grid, dim3(kBlock), 0, st, W, stride_v, W + (size_t)J * stride_v, P, n,
                            stop_in, rw);
         hipLaunchKernelGGL(k_fin_gram<J>, dim3(ncol), dim3(64 * (2 * J + 3)), 0, st, rw, (int)grid.x, stop_in, stop_out,
-                           g);
+                           g, tol2, 1);
         hipLaunchKernelGGL((k_gcr_gram_last<T, J + 1>), ew_grid(n, ncol), dim3(kBlock), 0, st, P, W, stride_v, x, n,
                            stop_out, g, ncol);
     };
@@ -1152,10 +1170,10 @@ template hipError_t gcr_xupdate<double, double>(const cpx<double>*, size_t, int,
 template hipError_t gcr_xupdate<float, double>(const cpx<float>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
 template hipError_t gcr_solve_xupdate<float, float>(const cpx<float>*, size_t, int, cpx<float>*, size_t, int, bool, const GcrDev&, hipStream_t);
 template hipError_t gcr_solve_xupdate<double, double>(const cpx<double>*, size_t, int, cpx<double>*, size_t, int, bool, const GcrDev&, hipStream_t);
-template hipError_t gcr_gram_step<float>(const cpx<float>*, size_t, int, const cpx<float>*, cpx<float>*, size_t, int, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
-template hipError_t gcr_gram_step<double>(const cpx<double>*, size_t, int, const cpx<double>*, cpx<double>*, size_t, int, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
-template hipError_t gcr_gram_last<float>(cpx<float>*, const cpx<float>*, size_t, int, cpx<float>*, size_t, int, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
-template hipError_t gcr_gram_last<double>(cpx<double>*, const cpx<double>*, size_t, int, cpx<double>*, size_t, int, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
+template hipError_t gcr_gram_step<float>(const cpx<float>*, size_t, int, const cpx<float>*, cpx<float>*, size_t, int, double, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
+template hipError_t gcr_gram_step<double>(const cpx<double>*, size_t, int, const cpx<double>*, cpx<double>*, size_t, int, double, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
+template hipError_t gcr_gram_last<float>(cpx<float>*, const cpx<float>*, size_t, int, cpx<float>*, size_t, int, double, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
+template hipError_t gcr_gram_last<double>(cpx<double>*, const cpx<double>*, size_t, int, cpx<double>*, size_t, int, double, const int*, int*, const GcrDev&, const RedWork&, hipStream_t);
 template hipError_t gcr_solve_xupdate_restart<float>(cpx<float>*, size_t, int, cpx<float>*, size_t, int, const cpx<float>*, const int*, const GcrDev&, hipStream_t);
 template hipError_t gcr_solve_xupdate_restart<double>(cpx<double>*, size_t, int, cpx<double>*, size_t, int, const cpx<double>*, const int*, const GcrDev&, hipStream_t);
 

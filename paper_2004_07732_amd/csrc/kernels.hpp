@@ -184,22 +184,26 @@ template <typename T>
 hipError_t gcr_fused_step(const cpx<T>* W, size_t wstride, int j, cpx<T>* w, cpx<T>* r, cpx<T>* copy, size_t n,
                           int ncol, double tol2, const int* stop_in, int* stop_out, const GcrDev& g,
                           const RedWork& rw, hipStream_t st);
-// Gram-form GCR step j (the smoother's restart cycles, j < kGramMax), three launches: the
-// multi-dot of w_j = W_j against W_0..W_{j-1} and r0, its finaliser, and one pass that
-// solves G y = b (G_il = <W_i, W_l>, b_i = <W_i, r0>, i, l <= j) in every block and writes
-// out = r0 - sum_{i<=j} y_i W_i (out may be r0).  Keeps G's rows in g.D / g.nn, b in g.wr
-// and y in g.gam; a not-finite inner product sets stop flag 2 in stop_out.
+// Gram-form GCR step j (restart cycles of at most kGramMax steps), three launches: the
+// multi-dot of w_j = W_j against W_0..W_{j-1} and r0, a finaliser that solves
+// G y = b (G_il = <W_i, W_l>, b_i = <W_i, r0>, i, l <= j) once per column, and one pass
+// out = r0 - sum_{i<=j} y_i W_i.  Keeps G's rows in g.D / g.nn, b in g.wr and y in g.gam; the
+// new residual norm |r0|^2 - Re <b, y> (g.rr holds the cycle's |r0|^2) decides the stop flag
+// in stop_out (1 at or below tol2 |b|^2, 2 if not finite); a stopped column's directions are
+// zero and its coefficients stay those of the step it stopped at.
 constexpr int kGramMax = 7;   // (the finaliser runs one wave per inner product: 2 j + 3 <= 16 waves)
 template <typename T>
 hipError_t gcr_gram_step(const cpx<T>* W, size_t wstride, int j, const cpx<T>* r0, cpx<T>* out, size_t n, int ncol,
-                         const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw, hipStream_t st);
+                         double tol2, const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw,
+                         hipStream_t st);
 // The last Gram-form step (j = k - 1) of a cycle whose starting residual is P_0, fused with
-// the cycle's solution update: multi-dot and finaliser as in gcr_gram_step, then one pass
-// x += sum_{i<k} y_i P_i, P_0 = P_0 - sum_{i<k} y_i W_i (the next cycle's residual and first
-// direction); the stop flags of stop_out become g.stop.
+// the cycle's solution update: multi-dot and finaliser as in gcr_gram_step (g.rr becomes the
+// next cycle's |r0|^2), then one pass x += sum_{i<k} y_i P_i, P_0 = P_0 - sum_{i<k} y_i W_i (the
+// next cycle's residual and first direction); the stop flags of stop_out become g.stop.
 template <typename T>
 hipError_t gcr_gram_last(cpx<T>* P, const cpx<T>* W, size_t stride_v, int k, cpx<T>* x, size_t n, int ncol,
-                         const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw, hipStream_t st);
+                         double tol2, const int* stop_in, int* stop_out, const GcrDev& g, const RedWork& rw,
+                         hipStream_t st);
 // next restart cycle on the recursive residual: P0 = r, and the stop flags of the
 // cycle's last step (stop_src) become g.stop
 template <typename T>

@@ -473,7 +473,9 @@ Task Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double to
     }
     // one restart cycle: kmax fused iterations (inner products, then one pass that orthogonalises
     // the new direction and updates the residual; the stop flags alternate between two buffers so
-    // that no kernel writes the flags it reads), the solution update, and the restart
+    // that no kernel writes the flags it reads), the solution update, and the restart.  Cycles
+    // of at most kGramSteps take the Gram form instead (the smoother's), with the residual in P_0.
+    const bool gram = kmax <= kGramSteps;
     auto cycle = [&]() -> int {
         for (int k = 0; k < kmax; ++k) {
             cpx<T>* Pk = P + (size_t)k * nt;
@@ -481,13 +483,24 @@ Task Hierarchy::gcr_plain(int l, const cpx<T>* b, cpx<T>* x, int ncol, double to
             const int* s_in = (k % 2 == 0) ? g.stop : g.stop2;
             int* s_out = (k % 2 == 0) ? g.stop2 : g.stop;
             HIPCHK(apply_A<T>(l, Pk, Wk, t, ncol, st));
-            // the updated residual is the next search direction
-            HIPCHK(gcr_fused_step<T>(W, nt, k, Wk, r, k + 1 < kmax ? P + (size_t)(k + 1) * nt : nullptr, n, ncol,
-                                     tol2, s_in, s_out, g, rw_, st));
+            if (gram && k + 1 < kmax) {
+                // the next direction: the minimal residual so far, from P_0 (the cycle's residual)
+                HIPCHK(gcr_gram_step<T>(W, nt, k, P, P + (size_t)(k + 1) * nt, n, ncol, tol2, s_in, s_out, g, rw_,
+                                        st));
+            } else if (gram) {
+                // and the solution update, P_0 = the next cycle's residual
+                HIPCHK(gcr_gram_last<T>(P, W, nt, kmax, x, n, ncol, tol2, s_in, s_out, g, rw_, st));
+            } else {
+                // the updated residual is the next search direction
+                HIPCHK(gcr_fused_step<T>(W, nt, k, Wk, r, k + 1 < kmax ? P + (size_t)(k + 1) * nt : nullptr, n,
+                                         ncol, tol2, s_in, s_out, g, rw_, st));
+            }
         }
         // solution update, and the next cycle continues from the recursive residual (its
         // norm and the stop flags are those of the last fused step)
-        HIPCHK(gcr_solve_xupdate_restart<T>(P, nt, kmax, x, n, ncol, r, (kmax % 2 == 0) ? g.stop : g.stop2, g, st));
+        if (!gram)
+            HIPCHK(gcr_solve_xupdate_restart<T>(P, nt, kmax, x, n, ncol, r, (kmax % 2 == 0) ? g.stop : g.stop2, g,
+                                                st));
         // the cycle ends by publishing the stop flags to the host (part of the graph)
         unsigned v = 0;
         HIPCHK(publish(st, {{h_int_, g.stop, sizeof(int) * ncol}}, &v));
@@ -566,11 +579,11 @@ int Hierarchy::smooth(int l, const cpx<T>* r, cpx<T>* z, int ncol, hipStream_t s
                 HIPCHK(apply_A<T>(l, Pj, Wj, t, ncol, st));
                 if (gram && j + 1 < kc) {
                     // the next direction r_{j+1} = P_0 - sum y_i W_i
-                    HIPCHK(gcr_gram_step<T>(Ws, nt, j, Ps, Ps + (size_t)(j + 1) * nt, n, ncol, s_in, s_out, g, rw_,
-                                            st));
+                    HIPCHK(gcr_gram_step<T>(Ws, nt, j, Ps, Ps + (size_t)(j + 1) * nt, n, ncol, -1.0, s_in, s_out, g,
+                                            rw_, st));
                 } else if (gram) {
                     // z += this cycle's correction, P_0 = the next cycle's starting residual
-                    HIPCHK(gcr_gram_last<T>(Ps, Ws, nt, kc, z, n, ncol, s_in, s_out, g, rw_, st));
+                    HIPCHK(gcr_gram_last<T>(Ps, Ws, nt, kc, z, n, ncol, -1.0, s_in, s_out, g, rw_, st));
                 } else {
                     HIPCHK(gcr_fused_step<T>(Ws, nt, j, Wj, rs, (j + 1 < kc) ? Ps + (size_t)(j + 1) * nt : nullptr,
                                              n, ncol, -1.0, s_in, s_out, g, rw_, st));
