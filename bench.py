@@ -276,15 +276,20 @@ def solve_model_bytes(fine_applies, coarse_iters, k, L, Ls, coarse_launch_bytes,
     """HBM bytes of one solve by a model (a lower bound): the fine FP32 stencils
     (vector read and written, links once per apply), two coarse stencils per
     coarsest iteration (A-hat = D_PV-hat^dag D_DW-hat), the coarsest GCR(k)
-    vector algebra (at direction j the multi-dot reads j + 2 vectors and the fused
-    update reads j + 2 and writes 3, 2 after the cycle's last direction; each
-    cycle's solution update and restart move k + 4) and, for `kcycles` K-cycles,
-    the post-smoother's FP32 vector algebra (smoother_model_passes).  The outer
-    flexible GCR's vector algebra is not counted."""
+    vector algebra per restart cycle of k iterations and, for `kcycles` K-cycles,
+    the post-smoother's FP32 vector algebra (smoother_model_passes).  The coarsest
+    cycle: in the Gram form (k <= GRAM_STEPS) the multi-dot (j + 2) and the next
+    direction (j + 3) at each step but the last, whose multi-dot (k + 1) is followed
+    by the pass that updates x and the starting residual (2 k + 3): k^2 + 5 k + 1
+    passes; in the orthogonalising form the multi-dot (j + 2) and the fused update
+    (j + 2 read, 3 written, 2 after the last direction), then the solution update
+    and restart (k + 4): k^2 + 7 k + 3.  The outer flexible GCR's vector algebra is
+    not counted."""
     fine_apply = 2 * Ls * L * L * 2 * 8 + 2 * L * L * 8
     fine_vec = Ls * L * L * 2 * 8
+    cycle = k * k + 5 * k + 1 if k <= GRAM_STEPS else k * k + 7 * k + 3
     return (fine_applies * fine_apply + 2 * coarse_iters * coarse_launch_bytes
-            + coarse_iters * (k * k + 7 * k + 3) / k * coarse_vec_bytes
+            + coarse_iters * cycle / k * coarse_vec_bytes
             + kcycles * smoother_model_passes(smooth_iters, smooth_restart) * fine_vec)
 
 

@@ -47,11 +47,17 @@ def test_whole_solve_byte_model_worked_example():
     # 2 x 65536 x 8 B of links = 34 603 008 B
     fine = 34_603_008
     coarse_vec = 4096 * 2 * 32 * 16
-    # GCR(6): per cycle sum_{j<6} (2j + 7) = 72 vector passes less the direction copy
-    # after the last one, plus 6 + 4 for the solution update and restart: 81 passes
-    # per 6 iterations
+    # GCR(6), Gram form: per cycle sum_{j<5} (2j + 5) = 45 passes, the last step's
+    # multi-dot (7) and its update of x and the residual (13 read, 2 written): 67
+    # passes per 6 iterations
     got = bench.solve_model_bytes(10, 12, 6, 256, 16, 58_720_256, coarse_vec)
-    want = 10 * fine + 2 * 12 * 58_720_256 + 12 * 81 / 6 * coarse_vec
+    want = 10 * fine + 2 * 12 * 58_720_256 + 12 * 67 / 6 * coarse_vec
+    assert abs(got - want) <= 1e-6 * want
+    # GCR(8), orthogonalising form: per cycle sum_{j<8} (2j + 7) = 112 vector passes less
+    # the direction copy after the last one, plus 8 + 4 for the solution update and
+    # restart: 123 passes per 8 iterations
+    got = bench.solve_model_bytes(10, 16, 8, 256, 16, 58_720_256, coarse_vec)
+    want = 10 * fine + 2 * 16 * 58_720_256 + 16 * 123 / 8 * coarse_vec
     assert abs(got - want) <= 1e-6 * want
 
 
