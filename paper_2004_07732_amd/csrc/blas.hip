@@ -668,17 +668,19 @@ k_gcr_fused_update(const cpx<T>* W, size_t wstride, cpx<T>* w, cpx<T>* r, cpx<T>
     }
 }
 
-// ---- Gram-form GCR step (the smoother's cycles).  With w_i = A p_i kept as computed
-// (not orthogonalised) and r0 the cycle's starting residual, step j's minimal residual over
-// span(p_0..p_j) is r_{j+1} = r0 - sum_{i<=j} y_i w_i with G y = b, G_il = <w_i, w_l>,
-// b_i = <w_i, r0> (the normal equations of the same least-squares problem GCR solves by
-// orthogonalising).  The multi-dot of step j gives G's new row and b_j.  Its finaliser is
-// one workgroup per column: wave q adds the partials of quantity q, then one thread solves
-// the (j+1)-square system by Cholesky in FP64 registers (a pivot that is not positive drops
-// that direction: its y is zero) and stores G's row, b_j, y and the stop flag.  The
-// streaming kernel then writes out = r_{j+1} (the next direction, or r0 itself in place at
-// the end of the cycle); no orthogonalised direction and no running residual is written.
-constexpr int kGramPartials = 1024;
+// ---- Gram-form GCR step (short restart cycles: the smoother's and the coarsest solve's).
+// With w_i = A p_i kept as computed (not orthogonalised) and r0 the cycle's starting
+// residual, step j's minimal residual over span(p_0..p_j) is r_{j+1} = r0 - sum_{i<=j} y_i w_i
+// with G y = b, G_il = <w_i, w_l>, b_i = <w_i, r0> (the normal equations of the same
+// least-squares problem GCR solves by orthogonalising).  The multi-dot of step j gives G's
+// new row and b_j.  Its finaliser is one workgroup per column: wave q adds the partials of
+// quantity q, then one thread solves the (j+1)-square system by Cholesky in FP64 registers
+// (a pivot that is not positive drops that direction: its y is zero) and stores G's row,
+// b_j, y, the new residual norm and the stop flag.  A streaming pass then writes
+// r_{j+1}, the next direction (k_gcr_gram_step), or at the cycle's last step adds the
+// correction to x and leaves r_{j+1} in P_0 (k_gcr_gram_last); no orthogonalised direction
+// and no running residual is written.
+constexpr int kGramPartials = 1024;   // multi-dot blocks per column (partials per finaliser wave)
 template <int j>
 __global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw, int nb, const int* stop_in,
                                                                      int* stop_out, GcrDev g, double tol2, int last) {
