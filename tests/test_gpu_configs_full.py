@@ -110,12 +110,12 @@ def headline_inputs(nrhs):
 def test_headline_configuration(nrhs):
     """The benchmark's own configuration at full size: 256^2 x Ls 16, beta 6,
     m_f 0.01, 2 levels (4x4 aggregates, 16 null vectors, coarse Ls 2), FP32 fine
-    level, BF16 matrix-core coarse links, FP32 coarse vectors, coarsest GCR(6) to
+    level, BF16 matrix-core coarse links, FP64 coarsest vectors, coarsest GCR(6) to
     0.5, 20 post-smoothing GCR steps in cycles of 5, FP64 defect correction to
     1e-10; the oracle recomputes the residual of every right-hand side."""
     L, Ls, m, M5 = 256, 16, 0.01, -1.0
     g, b, starts = headline_inputs(nrhs)
-    p = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[dwfmg.P_F32],
+    p = dwfmg.MGParams(nvec=[16], block=[(4, 4)], Ls_coarse=[2], link_prec=[dwfmg.P_BF16], vec_prec=[dwfmg.P_F64],
                        fine_prec=dwfmg.P_F32, coarsest_solver=dwfmg.COARSEST_GCR, coarsest_restart=6,
                        coarsest_tol=0.5, smooth_iters=20, smooth_restart=5)
     mg = dwfmg.MG(torch.from_numpy(g.U).cuda(), Ls, m, M5, p, starts, max_nrhs=nrhs)
@@ -146,7 +146,7 @@ def test_headline_coarse_stencil_full_size(ncol, vec):
     FP32 or FP64 vectors), element by element against the oracle's coarse operator
     built by the oracle from the same gauge field and null-vector starts (no
     relaxation, so both sides build the same prolongator) and rounded to BF16.
-    ncol = 1 with FP32 vectors is the launch the benchmark's roofline line times."""
+    ncol = 1 with FP64 vectors is the launch the benchmark's roofline line times."""
     L, Ls, m, M5, nv = 256, 16, 0.01, -1.0, 16
     g = inputs.metropolis_u1(L, L, 6.0, 200, inputs.gauge_seed(4, L))
     start = inputs.gaussian_field((nv, L, L, 2), inputs.null_start_seed(6, 0))
