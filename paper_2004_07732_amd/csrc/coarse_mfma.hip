@@ -55,6 +55,8 @@
 #include <string>
 #include <vector>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace dwf {
@@ -103,9 +105,9 @@ __device__ __forceinline__ void load4(const cpx<T>* p, float (&re)[4], float (&i
 
 }  // namespace
 
-template <bool F16, typename T, int N, bool DAG, int TW>
+template <bool F16, typename TI, typename TO, int N, bool DAG, int TW>
 __global__ void __launch_bounds__(256)
-coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<TI>* __restrict__ in, cpx<TO>* __restrict__ out,
                    const int* __restrict__ skip, int sks, int Lx, int Ly, int Ls, int nsites, int ncol,
                    float cdiag, float mwrap, int tpb) {
     using HF = Half<F16>;
@@ -244,7 +246,7 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         // e = (d * TW + c8) * N + k.  The loads do not depend on the column flags
         // (columns past the end read column 0), so all of them are in flight
         // together; dead columns are zeroed afterwards.
-        cpx<T> v[PER];
+        cpx<TI> v[PER];
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int e = min(tid_in_site + p * MT * 64, SLAB - 1);   // (past the end: a repeat, not stored)
@@ -265,8 +267,8 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
 #pragma unroll
             for (int e = 0; e < 4; ++e) { cr[e] = ci[e] = hr[e] = hi[e] = 0.f; }
             if ((q & 7) < TW) {
-                load4<T>(in + ((uint32_t)cl * nsites + nb[0]) * N + i0, cr, ci);
-                load4<T>(in + ((uint32_t)(rhs * Ls + so) * nsites + nb[0]) * N + i0, hr, hi);
+                load4<TI>(in + ((uint32_t)cl * nsites + nb[0]) * N + i0, cr, ci);
+                load4<TI>(in + ((uint32_t)(rhs * Ls + so) * nsites + nb[0]) * N + i0, hr, hi);
             }
         };
         if (TW < 8) {
@@ -378,16 +380,16 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
         for (int e = 0; e < 4; ++e) p[e] = __shfl_xor(acc[e], 8, 64);
         const bool wr = valid_site && !imag_col && col_ok(cbase + (q & 7));
         if (wr) {
-            cpx<T>* dst = out + ((uint32_t)cl * nsites + site) * N + i0;
+            cpx<TO>* dst = out + ((uint32_t)cl * nsites + site) * N + i0;
             const float u = unscale * osg;
             if (TW == 8) {   // several tiles: the site-local terms are loaded here, by the writing lanes
                 load_local();
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    dst[e] = {(T)(acc[e] * u + cdiag * cr[e] + f * hr[e]), (T)(p[e] * u + cdiag * ci[e] + f * hi[e])};
+                    dst[e] = {(TO)(acc[e] * u + cdiag * cr[e] + f * hr[e]), (TO)(p[e] * u + cdiag * ci[e] + f * hi[e])};
             } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) dst[e] = {(T)(acc[e] * u), (T)(p[e] * u)};
+                for (int e = 0; e < 4; ++e) dst[e] = {(TO)(acc[e] * u), (TO)(p[e] * u)};
             }
         }
         __syncthreads();   // sB and smax are rewritten for the next column tile
@@ -396,8 +398,8 @@ coarse_mfma_kernel(const u32x4* __restrict__ links, const cpx<T>* __restrict__ i
 
 namespace {
 
-template <bool F16, typename T, int N>
-hipError_t launch_n(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol, double m,
+template <bool F16, typename TI, typename TO, int N>
+hipError_t launch_n(const void* links, const cpx<TI>* in, cpx<TO>* out, const CoarseGeom& g, int ncol, double m,
                     double M5, bool dagger, const int* skip, int sks, int tw, int tpb, hipStream_t st) {
     constexpr int MT = N / 16;
     constexpr int SPB = 1;
@@ -411,15 +413,15 @@ hipError_t launch_n(const void* links, const cpx<T>* in, cpx<T>* out, const Coar
     const u32x4* lk = reinterpret_cast<const u32x4*>(links);
     const float cd = (float)(M5 + 1.0), mw = (float)(-m);
     // the kernel indexes the vectors and links with 32-bit offsets
-    const double vec_bytes = (double)g.Ls * ncol * nsites * N * sizeof(cpx<T>);
+    const double vec_bytes = (double)g.Ls * ncol * nsites * N * std::max(sizeof(cpx<TI>), sizeof(cpx<TO>));
     const double link_bytes = (double)nsites * 3 * N * N * 4;
     if (vec_bytes >= 4294967296.0 || link_bytes >= 4294967296.0) return hipErrorInvalidValue;
 #define DWF_COARSE_LAUNCH(TWV)                                                                                        \
     do {                                                                                                              \
-        if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, true, TWV>), grid, block, 0, st, lk, in, out,   \
-                                       skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw, tpb);                       \
-        else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, T, N, false, TWV>), grid, block, 0, st, lk, in, out,  \
-                                       skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw, tpb);                       \
+        if (dagger) hipLaunchKernelGGL((coarse_mfma_kernel<F16, TI, TO, N, true, TWV>), grid, block, 0, st, lk, in,  \
+                                       out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw, tpb);                  \
+        else        hipLaunchKernelGGL((coarse_mfma_kernel<F16, TI, TO, N, false, TWV>), grid, block, 0, st, lk, in, \
+                                       out, skip, sks, g.Lx, g.Ly, g.Ls, nsites, ncol, cd, mw, tpb);                  \
     } while (0)
     if (tw == 2) DWF_COARSE_LAUNCH(2);        // one tile of 2 columns (one rhs on 2 coarse slices)
     else if (tw == 4) DWF_COARSE_LAUNCH(4);   // one tile of 4 columns
@@ -428,14 +430,14 @@ hipError_t launch_n(const void* links, const cpx<T>* in, cpx<T>* out, const Coar
     return hipGetLastError();
 }
 
-template <bool F16, typename T>
-hipError_t launch_p(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol, double m,
+template <bool F16, typename TI, typename TO>
+hipError_t launch_p(const void* links, const cpx<TI>* in, cpx<TO>* out, const CoarseGeom& g, int ncol, double m,
                     double M5, bool dagger, const int* skip, int sks, int tw, int tpb, hipStream_t st) {
     switch (g.n) {
-        case 16: return launch_n<F16, T, 16>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
-        case 32: return launch_n<F16, T, 32>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
-        case 48: return launch_n<F16, T, 48>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
-        case 64: return launch_n<F16, T, 64>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
+        case 16: return launch_n<F16, TI, TO, 16>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
+        case 32: return launch_n<F16, TI, TO, 32>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
+        case 48: return launch_n<F16, TI, TO, 48>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
+        case 64: return launch_n<F16, TI, TO, 64>(links, in, out, g, ncol, m, M5, dagger, skip, sks, tw, tpb, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -463,14 +465,20 @@ std::string tune_key(bool f16, size_t tsz, const CoarseGeom& g, int ncol, bool d
     return k;
 }
 
-template <bool F16, typename T>
-int choose_cfg(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g, int ncol, double m, double M5,
+// (key: the vector size, or input size * 100 + output size when the two differ)
+template <typename TI, typename TO>
+constexpr size_t vec_key() {
+    return std::is_same<TI, TO>::value ? sizeof(TI) : sizeof(TI) * 100 + sizeof(TO);
+}
+
+template <bool F16, typename TI, typename TO>
+int choose_cfg(const void* links, const cpx<TI>* in, cpx<TO>* out, const CoarseGeom& g, int ncol, double m, double M5,
                bool dagger, hipStream_t st) {
     const int C = g.Ls * ncol;
     const int heur = heuristic_cfg(C);
     const char* en = std::getenv("DWF_AUTOTUNE");
     if (en && en[0] == '0') return heur;
-    const std::string key = tune_key(F16, sizeof(T), g, ncol, dagger);
+    const std::string key = tune_key(F16, vec_key<TI, TO>(), g, ncol, dagger);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -497,13 +505,13 @@ int choose_cfg(const void* links, const cpx<T>* in, cpx<T>* out, const CoarseGeo
         float best_t = 1e30f, heur_t = 1e30f;
         for (int c : cand) {
             const int tw = c / kTpbStride, tpb = c % kTpbStride;
-            if (launch_p<F16, T>(links, in, out, g, ncol, m, M5, dagger, nullptr, 1, tw, tpb, st) != hipSuccess)
+            if (launch_p<F16, TI, TO>(links, in, out, g, ncol, m, M5, dagger, nullptr, 1, tw, tpb, st) != hipSuccess)
                 continue;
             float tc = 1e30f;
             for (int trial = 0; trial < 3; ++trial) {
                 (void)hipEventRecord(e0, st);
                 for (int r = 0; r < 10; ++r)
-                    (void)launch_p<F16, T>(links, in, out, g, ncol, m, M5, dagger, nullptr, 1, tw, tpb, st);
+                    (void)launch_p<F16, TI, TO>(links, in, out, g, ncol, m, M5, dagger, nullptr, 1, tw, tpb, st);
                 (void)hipEventRecord(e1, st);
                 (void)hipEventSynchronize(e1);
                 float t = 0.f;
@@ -526,15 +534,23 @@ bool coarse_mfma_supported(int n, int link_prec) {
     return (link_prec == P_BF16 || link_prec == P_F16) && (n % 16) == 0 && n <= 64;
 }
 
+template <typename TI, typename TO>
+hipError_t coarse_apply_mfma_io(const void* links, int link_prec, const cpx<TI>* in, cpx<TO>* out, const CoarseGeom& g,
+                                int ncol, double m, double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
+    if (link_prec == P_F16) {
+        const int c = choose_cfg<true, TI, TO>(links, in, out, g, ncol, m, M5, dagger, st);
+        return launch_p<true, TI, TO>(links, in, out, g, ncol, m, M5, dagger, skip, sks, c / kTpbStride,
+                                      c % kTpbStride, st);
+    }
+    const int c = choose_cfg<false, TI, TO>(links, in, out, g, ncol, m, M5, dagger, st);
+    return launch_p<false, TI, TO>(links, in, out, g, ncol, m, M5, dagger, skip, sks, c / kTpbStride, c % kTpbStride,
+                                   st);
+}
+
 template <typename T>
 hipError_t coarse_apply_mfma(const void* links, int link_prec, const cpx<T>* in, cpx<T>* out, const CoarseGeom& g,
                              int ncol, double m, double M5, bool dagger, const int* skip, int sks, hipStream_t st) {
-    if (link_prec == P_F16) {
-        const int c = choose_cfg<true, T>(links, in, out, g, ncol, m, M5, dagger, st);
-        return launch_p<true, T>(links, in, out, g, ncol, m, M5, dagger, skip, sks, c / kTpbStride, c % kTpbStride, st);
-    }
-    const int c = choose_cfg<false, T>(links, in, out, g, ncol, m, M5, dagger, st);
-    return launch_p<false, T>(links, in, out, g, ncol, m, M5, dagger, skip, sks, c / kTpbStride, c % kTpbStride, st);
+    return coarse_apply_mfma_io<T, T>(links, link_prec, in, out, g, ncol, m, M5, dagger, skip, sks, st);
 }
 
 bool coarse_mfma_config(int link_prec, int vec_prec, const CoarseGeom& g, int ncol, bool dagger, int* tw, int* tpb) {
@@ -594,6 +610,8 @@ hipError_t convert_links_fragment16(const cpx<double>* in, void* out, int link_p
 }
 
 template hipError_t coarse_apply_mfma<float>(const void*, int, const cpx<float>*, cpx<float>*, const CoarseGeom&, int, double, double, bool, const int*, int, hipStream_t);
+template hipError_t coarse_apply_mfma_io<double, float>(const void*, int, const cpx<double>*, cpx<float>*, const CoarseGeom&, int, double, double, bool, const int*, int, hipStream_t);
+template hipError_t coarse_apply_mfma_io<float, double>(const void*, int, const cpx<float>*, cpx<double>*, const CoarseGeom&, int, double, double, bool, const int*, int, hipStream_t);
 template hipError_t coarse_apply_mfma<double>(const void*, int, const cpx<double>*, cpx<double>*, const CoarseGeom&, int, double, double, bool, const int*, int, hipStream_t);
 
 }  // namespace dwf

@@ -97,6 +97,12 @@ hipError_t convert_links_fragment16(const cpx<double>* in, void* out, int link_p
 // launch configuration the matrix-core path uses for this shape (the tuned one
 // once a call has timed it, else the heuristic): tile width and tiles per workgroup
 bool coarse_mfma_config(int link_prec, int vec_prec, const CoarseGeom& g, int ncol, bool dagger, int* tw, int* tpb);
+// the matrix-core stencil with input and output vectors of different precisions (the
+// intermediate of the coarsest A: FP64 in, FP32 out, then FP32 in, FP64 out; the kernel's
+// accumulation is FP32, so an FP32 intermediate holds exactly what an FP64 one would)
+template <typename TI, typename TO>
+hipError_t coarse_apply_mfma_io(const void* links, int link_prec, const cpx<TI>* in, cpx<TO>* out, const CoarseGeom& g,
+                                int ncol, double m, double M5, bool dagger, const int* skip, int sks, hipStream_t st);
 // complex 16-bit entries of that storage: the site term and the two forward hops
 // (the backward hops are the sigma_3-adjoints of the neighbours' forward hops)
 size_t links_fragment16_entries(int nsites, int n);

@@ -214,6 +214,22 @@ hipError_t Hierarchy::apply_A(int l, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp,
         if constexpr (std::is_same<T, float>::value) U = L.U32; else U = L.U64;
         return fine_a<T>(U, in, out, tmp, L.Lx, L.Ly, L.Ls, ncol, m, M5, skip, skip ? kSkipStride : 1, st);
     }
+    if constexpr (std::is_same<T, double>::value) {
+        const Level& L = levels[l];
+        if (!L.fine && L.Ls <= kMaxCoarseLs && coarse_mfma_supported(L.n, L.link_prec)) {
+            // FP64 coarse vectors on the matrix cores: the stencil accumulates in FP32, so
+            // its output holds FP32 values, and the intermediate D_DW in is kept in FP32
+            // (half its bytes) without changing any bit of A in
+            const CoarseGeom g{L.Lx, L.Ly, L.Ls, L.n};
+            const int stride = skip ? kSkipStride : 1;
+            cpx<float>* t = reinterpret_cast<cpx<float>*>(tmp);
+            hipError_t e = coarse_apply_mfma_io<double, float>(L.links, L.link_prec, in, t, g, ncol, m, M5, false,
+                                                               skip, stride, st);
+            if (e != hipSuccess) return e;
+            return coarse_apply_mfma_io<float, double>(L.links, L.link_prec, t, out, g, ncol, 1.0, M5, true, skip,
+                                                       stride, st);
+        }
+    }
     hipError_t e = apply_dw<T>(l, in, tmp, m, false, ncol, st, skip);
     if (e != hipSuccess) return e;
     if (l == 0 && !capturing_) cnt_.fine_applies += a_cost(0);
@@ -1055,6 +1071,10 @@ Task Hierarchy::solve_group(const cpx<double>* b_in, cpx<double>* x, int ncol, d
                                                st));
                 }
             }
+            // and the FP64 levels' A with its FP32 intermediate
+            if (Lc.vec_prec != P_F32)
+                CO_HIPCHK(apply_A<double>(l, C<double>(work_[l].rhs), C<double>(work_[l].tmp2), C<double>(work_[l].tmp),
+                                          ncol, st));
         }
         coarse_tuned_.insert(ncol);
     }
