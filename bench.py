@@ -227,6 +227,14 @@ def coarse_stencil_bytes(nsites, n, Ls_c, ncol, link_bytes, vec_bytes, link_bloc
     return nsites * (link_blocks * n * n * link_bytes + 2 * Ls_c * ncol * n * vec_bytes)
 
 
+def coarse_a_bytes(launch_bytes, nsites, n, Ls_c, ncol, vec_bytes):
+    """Algorithmic bytes of one coarse A-hat = D_PV-hat^dag D_DW-hat: two stencil
+    launches of `launch_bytes` each, less what the narrower intermediate saves: with
+    FP64 vectors (16 B complex) the D_DW-hat output is written and read back as FP32
+    (8 B complex), which the stencil's FP32 accumulation makes exact."""
+    return 2 * launch_bytes - 2 * nsites * Ls_c * ncol * n * (vec_bytes - 8)
+
+
 def coarse_mfma_per_launch(nsites, n, Ls_c, ncol, tw=None):
     """Matrix-core products (16x16x32, BF16) one coarse launch issues.  A wave owns
     16 output rows of one site and a tile of up to TW (slice, column) pairs (TW = 2,
@@ -272,11 +280,11 @@ def smoother_model_passes(ns, ks):
     return passes
 
 
-def solve_model_bytes(fine_applies, coarse_iters, k, L, Ls, coarse_launch_bytes, coarse_vec_bytes,
+def solve_model_bytes(fine_applies, coarse_iters, k, L, Ls, coarse_a, coarse_vec_bytes,
                       kcycles=0, smooth_iters=0, smooth_restart=0):
     """HBM bytes of one solve by a model (a lower bound): the fine FP32 stencils
-    (vector read and written, links once per apply), two coarse stencils per
-    coarsest iteration (A-hat = D_PV-hat^dag D_DW-hat), the coarsest GCR(k)
+    (vector read and written, links once per apply), one coarse A-hat per coarsest
+    iteration (`coarse_a` bytes, coarse_a_bytes), the coarsest GCR(k)
     vector algebra per restart cycle of k iterations and, for `kcycles` K-cycles,
     the post-smoother's FP32 vector algebra (smoother_model_passes).  The coarsest
     cycle: in the Gram form (k <= GRAM_STEPS) the multi-dot (j + 2) and the next
@@ -289,7 +297,7 @@ def solve_model_bytes(fine_applies, coarse_iters, k, L, Ls, coarse_launch_bytes,
     fine_apply = 2 * Ls * L * L * 2 * 8 + 2 * L * L * 8
     fine_vec = Ls * L * L * 2 * 8
     cycle = k * k + 5 * k + 1 if k <= GRAM_STEPS else k * k + 7 * k + 3
-    return (fine_applies * fine_apply + 2 * coarse_iters * coarse_launch_bytes
+    return (fine_applies * fine_apply + coarse_iters * coarse_a
             + coarse_iters * cycle / k * coarse_vec_bytes
             + kcycles * smoother_model_passes(smooth_iters, smooth_restart) * fine_vec)
 
@@ -577,7 +585,8 @@ def main():
                    "algorithmic_TFLOP_s": useful_tf, "peak_bf16_TFLOP_s": PEAK_BF16_TFLOPS,
                    "frac_issued": issued_tf / PEAK_BF16_TFLOPS, "frac_algorithmic": useful_tf / PEAK_BF16_TFLOPS}
     solve_bytes = (solve_model_bytes(stats.fine_applies, stats.level_iters[0], args.coarsest_restart, L, Ls,
-                                     coarse_bytes, nsites * Lsc * n * vec_bytes, kcycles=stats.level_calls[0],
+                                     coarse_a_bytes(coarse_bytes, nsites, n, Lsc, 1, vec_bytes),
+                                     nsites * Lsc * n * vec_bytes, kcycles=stats.level_calls[0],
                                      smooth_iters=args.smooth_iters, smooth_restart=args.smooth_restart)
                    if args.coarsest == "gcr" and len(wl["nvec"]) == 1 else None)
     solve_roofline = None

@@ -42,6 +42,16 @@ def test_coarse_matrix_core_count_worked_example():
     assert bench.coarse_mfma_per_launch(64, 16, 9, 1) == 64 * 1 * 2 * 2 * 5
 
 
+def test_coarse_a_bytes_worked_example():
+    # two launches on the 3 stored blocks: 2 x 12 288 B of links per site; vectors
+    # FP64 in (16 B), FP32 intermediate out and in (8 B each), FP64 out (16 B) on
+    # 2 slices x 32 components: 2 x 32 x 48 = 3 072 B per site
+    assert bench.coarse_a_bytes(58_720_256, 4096, 32, 2, 1, 16) == 4096 * (24576 + 3072) == 113_246_208
+    # FP32 vectors: the intermediate is FP32 already, two whole launches
+    f32_launch = bench.coarse_stencil_bytes(4096, 32, 2, 1, 4, 8, link_blocks=3)
+    assert bench.coarse_a_bytes(f32_launch, 4096, 32, 2, 1, 8) == 2 * f32_launch
+
+
 def test_whole_solve_byte_model_worked_example():
     # one fine FP32 apply at 256^2 x 16: 2 x 16 x 65536 x 2 x 8 B of vectors plus
     # 2 x 65536 x 8 B of links = 34 603 008 B
@@ -49,15 +59,15 @@ def test_whole_solve_byte_model_worked_example():
     coarse_vec = 4096 * 2 * 32 * 16
     # GCR(6), Gram form: per cycle sum_{j<5} (2j + 5) = 45 passes, the last step's
     # multi-dot (7) and its update of x and the residual (13 read, 2 written): 67
-    # passes per 6 iterations
-    got = bench.solve_model_bytes(10, 12, 6, 256, 16, 58_720_256, coarse_vec)
-    want = 10 * fine + 2 * 12 * 58_720_256 + 12 * 67 / 6 * coarse_vec
+    # passes per 6 iterations; one coarse A per iteration
+    got = bench.solve_model_bytes(10, 12, 6, 256, 16, 113_246_208, coarse_vec)
+    want = 10 * fine + 12 * 113_246_208 + 12 * 67 / 6 * coarse_vec
     assert abs(got - want) <= 1e-6 * want
     # GCR(8), orthogonalising form: per cycle sum_{j<8} (2j + 7) = 112 vector passes less
     # the direction copy after the last one, plus 8 + 4 for the solution update and
     # restart: 123 passes per 8 iterations
-    got = bench.solve_model_bytes(10, 16, 8, 256, 16, 58_720_256, coarse_vec)
-    want = 10 * fine + 2 * 16 * 58_720_256 + 16 * 123 / 8 * coarse_vec
+    got = bench.solve_model_bytes(10, 16, 8, 256, 16, 113_246_208, coarse_vec)
+    want = 10 * fine + 16 * 113_246_208 + 16 * 123 / 8 * coarse_vec
     assert abs(got - want) <= 1e-6 * want
 
 
@@ -75,8 +85,8 @@ def test_smoother_byte_model_worked_example():
     assert bench.smoother_model_passes(8, 0) == 127 == bench.smoother_model_passes(8, 8)
     assert bench.smoother_model_passes(0, 5) == 0
     fine_vec = 16 * 256 * 256 * 2 * 8
-    base = bench.solve_model_bytes(10, 12, 6, 256, 16, 58_720_256, 4096 * 2 * 32 * 16)
-    got = bench.solve_model_bytes(10, 12, 6, 256, 16, 58_720_256, 4096 * 2 * 32 * 16, kcycles=3, smooth_iters=20,
+    base = bench.solve_model_bytes(10, 12, 6, 256, 16, 113_246_208, 4096 * 2 * 32 * 16)
+    got = bench.solve_model_bytes(10, 12, 6, 256, 16, 113_246_208, 4096 * 2 * 32 * 16, kcycles=3, smooth_iters=20,
                                   smooth_restart=5)
     assert got - base == 3 * 208 * fine_vec
 
