@@ -471,7 +471,9 @@ int mg_deflation_info(const dwf_mg* mg, int* nev, int* iters, double* worst_resi
  * workgroup processes.  The library times the candidates at the first solve
  * with ncol columns (DWF_AUTOTUNE=0: the heuristic, the narrowest tile that holds
  * every column and all tiles in one workgroup); before that this reports the
- * heuristic.  The choice never changes a result.  DWF_EUNSUPPORTED for a level
+ * heuristic.  Widths 2 and 4 add the site-local terms before the hops, width 8
+ * after them, so a different width can change results by FP32 rounding (far below
+ * the BF16/FP16 split's 2^-16 relative).  DWF_EUNSUPPORTED for a level
  * without the matrix-core path. */
 int mg_coarse_config(const dwf_mg* mg, int level, int ncol, int dagger, int* tile_width, int* tiles_per_block);
 

@@ -687,11 +687,30 @@ __global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw
     constexpr int m = j + 1;
     constexpr int NQ = 2 * j + 3;
     static_assert(64 * NQ <= 1024, "one wave per inner product in one workgroup");
+    // G's rows and b of the cycle's earlier steps, one value per thread: D's j x j block
+    // (only the lower triangle is used), |w_i|^2, <w_i, r0>
+    constexpr int ND = 2 * j * j;
+    constexpr int NOLD = ND + 3 * j;
+    static_assert(NOLD <= 64 * NQ, "one earlier value per thread");
     __shared__ double tq[NQ];
+    __shared__ double old[NOLD > 0 ? NOLD : 1];
     const int col = blockIdx.x;
-    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;   // one wave per quantity
-    const bool stopped = stop_in[col] != 0;
-    if (!stopped && q < NQ) {
+    const int t = threadIdx.x;
+    const int lane = t & 63, q = t >> 6;   // one wave per quantity
+    const size_t kb = (size_t)col * g.kmax;
+    // every load is issued before the first wait: the stop flag, the partials (added
+    // whether or not the column has stopped: a stopped column's sums go unused) and the
+    // earlier rows
+    const int sflag = stop_in[col];
+    const double rr0 = g.rr[col];
+    const int it0 = g.it[col];
+    double ov = 0.0;
+    if (t < NOLD) {   // (the address by selects: one load, no branches between the loads)
+        const double* src = t < ND ? g.D + ((kb + t / (2 * j)) * g.kmax + (t % (2 * j)) / 2) * 2 + (t & 1)
+                                   : (t < ND + j ? g.nn + kb + (t - ND) : g.wr + 2 * kb + (t - ND - j));
+        ov = *src;
+    }
+    {
         const double* part = rw.partial + (size_t)col * rw.max_q * rw.nblk + (size_t)q * rw.nblk;
         double sq = 0.0;
 #pragma unroll 8
@@ -699,10 +718,10 @@ __global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw
         sq = wave_sum(sq);
         if (lane == 0) tq[q] = sq;
     }
+    if (t < NOLD) old[t] = ov;
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    const size_t kb = (size_t)col * g.kmax;
-    if (stopped) {
+    if (t != 0) return;
+    if (sflag != 0) {
         for (int l = 0; l < j; ++l) {
             g.D[((kb + j) * g.kmax + l) * 2] = 0.0;
             g.D[((kb + j) * g.kmax + l) * 2 + 1] = 0.0;
@@ -714,7 +733,7 @@ __global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw
         // zero), so that the cycle's solution update adds that step's minimal residual correction
         g.gam[2 * (kb + j)] = 0.0;
         g.gam[2 * (kb + j) + 1] = 0.0;
-        stop_out[col] = stop_in[col];
+        stop_out[col] = sflag;
         return;
     }
     // G (lower triangle: G_il = conj <w_l, w_i>, l < i) and b
@@ -722,10 +741,9 @@ __global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw
 #pragma unroll
     for (int i = 0; i < j; ++i) {
 #pragma unroll
-        for (int l = 0; l < i; ++l)
-            G[i][l] = {g.D[((kb + i) * g.kmax + l) * 2], -g.D[((kb + i) * g.kmax + l) * 2 + 1]};
-        G[i][i] = {g.nn[kb + i], 0.0};
-        b[i] = {g.wr[2 * (kb + i)], g.wr[2 * (kb + i) + 1]};
+        for (int l = 0; l < i; ++l) G[i][l] = {old[i * 2 * j + 2 * l], -old[i * 2 * j + 2 * l + 1]};
+        G[i][i] = {old[ND + i], 0.0};
+        b[i] = {old[ND + j + 2 * i], old[ND + j + 2 * i + 1]};
     }
 #pragma unroll
     for (int l = 0; l < j; ++l) G[j][l] = {tq[3 + 2 * l], -tq[4 + 2 * l]};
@@ -789,10 +807,10 @@ __global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw
         g.gam[2 * (kb + i) + 1] = y[i].im;
         by += b[i].re * y[i].re + b[i].im * y[i].im;
     }
-    double rr = g.rr[col] - by;
+    double rr = rr0 - by;
     if (rr < 0.0) rr = 0.0;
     if (last) g.rr[col] = rr;
-    g.it[col] += 1;
+    g.it[col] = it0 + 1;
     int f = 0;
     if (!(finite(tq[0]) && finite(tq[1]) && finite(tq[2]) && finite(rr))) f = 2;
     else if (rr <= tol2 * g.bb[col]) f = 1;
@@ -806,14 +824,23 @@ k_gcr_gram_step(const cpx<T>* W, size_t wstride, const cpx<T>* r0, cpx<T>* out, 
     constexpr int m = j + 1;
     const int col = blockIdx.y;
     const size_t o = (size_t)col * n;
-    if (stop_in[col] != 0) {   // (block-uniform) a stopped column's later directions are zero; r0 is kept
+    // the coefficients are loaded with the stop flag, one wait for both (the empty asm
+    // statements take them before the branch; the compiler would otherwise move the
+    // coefficient loads below it, a second round trip)
+    const double* gam = g.gam + 2 * (size_t)col * g.kmax;
+    double gv[2 * m];
+#pragma unroll
+    for (int i = 0; i < 2 * m; ++i) gv[i] = gam[i];
+    const int sflag = stop_in[col];
+#pragma unroll
+    for (int i = 0; i < 2 * m; ++i) asm volatile("" ::"s"(gv[i]));
+    cpx<T> c[m];
+#pragma unroll
+    for (int i = 0; i < m; ++i) c[i] = {(T)gv[2 * i], (T)gv[2 * i + 1]};
+    if (sflag != 0) {   // (block-uniform) a stopped column's later directions are zero; r0 is kept
         if (out != r0) GRID_STRIDE(e, n) out[o + e] = cpx<T>{(T)0, (T)0};
         return;
     }
-    const double* gam = g.gam + 2 * (size_t)col * g.kmax;
-    cpx<T> c[m];
-#pragma unroll
-    for (int i = 0; i < m; ++i) c[i] = {(T)gam[2 * i], (T)gam[2 * i + 1]};
     constexpr int U = gcr_unroll<T>(j);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     auto step = [&](size_t i0, cpx<T> re, const cpx<T>* Wt) {

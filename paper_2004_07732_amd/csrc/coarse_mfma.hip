@@ -446,8 +446,9 @@ hipError_t launch_p(const void* links, const cpx<TI>* in, cpx<TO>* out, const Co
 // candidates once per coarse shape, column count, precisions and adjoint flag,
 // as the fine stencil's is (DWF_AUTOTUNE=0 keeps the heuristic).  The heuristic:
 // the narrowest tile that holds every column, all tiles in one workgroup.
-// Every configuration evaluates each output with the same arithmetic in the same
-// order, so the choice never changes a result.
+// Tile widths 2 and 4 start the accumulator with the site-local terms, width 8 adds
+// them after the hops, so the two can differ by FP32 rounding (far below the split
+// vector's 2^-16); configurations of one width agree bit for bit.
 constexpr int kTpbStride = 1024;
 inline int pack_cfg(int tw, int tpb) { return tw * kTpbStride + tpb; }
 inline int heuristic_cfg(int C) {

@@ -544,3 +544,42 @@ def test_setup_argument_errors():
     too_many = dwfmg.MGParams(nvec=[40], block=[(4, 4)], Ls_coarse=[2])
     with pytest.raises(dwfmg.DwfError):
         dwfmg.MG(U, 4, 0.1, -1.0, too_many, [T(inputs.gaussian_field((40, L, L, 2), 6))])
+
+
+@pytest.mark.parametrize("nvec,block,Lsc,ncol,link", [(16, (4, 4), 2, 1, "bf16"), (16, (4, 4), 2, 2, "bf16"),
+                                                        (16, (4, 4), 3, 3, "bf16"), (8, (4, 4), 2, 5, "bf16"),
+                                                        (24, (8, 4), 2, 1, "f16")])
+def test_coarse_A_with_fp32_intermediate_is_bit_exact(nvec, block, Lsc, ncol, link, monkeypatch):
+    """On FP64 coarse vectors with matrix-core links, A = D_PV^dag D_DW keeps its
+    intermediate D_DW v in FP32.  The stencil accumulates in FP32 and takes its input
+    as FP32, so an FP64 intermediate would hold the same FP32 values and feed the
+    second stencil the same input: A must equal D_DW(m) followed by D_PV^dag, each
+    applied with FP64 vectors in and out, bit for bit (one, two and several column
+    tiles; 16, 32 and 48 coarse components).  The launch configurations are the
+    heuristic's on both sides (the timed choice is made per input and output type, and
+    tile width 8 adds the site-local terms in another order than widths 2 and 4)."""
+    monkeypatch.setenv("DWF_AUTOTUNE", "0")
+    L, Ls, m, M5 = 32, 4, 0.03, -1.0
+    g = inputs.metropolis_u1(L, L, 6.0, 30, 42001)
+    starts = [T(inputs.gaussian_field((nvec, L, L, 2), 42002))]
+    lp = dwfmg.P_BF16 if link == "bf16" else dwfmg.P_F16
+    p = dwfmg.MGParams(nvec=[nvec], block=[block], Ls_coarse=[Lsc], link_prec=[lp], vec_prec=[dwfmg.P_F64],
+                       fine_prec=dwfmg.P_F32, setup_iters=0)
+    mg = dwfmg.MG(T(g.U), Ls, m, M5, p, starts, max_nrhs=ncol)
+    assert mg.coarse_config(1, ncol) is not None      # the matrix-core kernel runs on level 1
+    info = mg.info(1)
+    x = T(inputs.gaussian_field((ncol, info["Ls"], info["Ly"], info["Lx"], info["n"]), 42003 + ncol))
+    a = mg.level_op(1, dwfmg.MG_OP_A, x, ncol).cpu().numpy()
+    t = mg.level_op(1, dwfmg.MG_OP_DW, x, ncol)
+    # the FP64 intermediate holds FP32 values
+    tn = t.cpu().numpy()
+    assert np.array_equal(tn, tn.astype(np.complex64).astype(np.complex128))
+    two = mg.level_op(1, dwfmg.MG_OP_PV_DAG, t, ncol).cpu().numpy()
+    assert np.array_equal(a, two)
+    assert np.linalg.norm(a) > 0
+    # with the timed configurations the two sides may take different tile widths:
+    # equal to FP32 rounding
+    monkeypatch.setenv("DWF_AUTOTUNE", "1")
+    at = mg.level_op(1, dwfmg.MG_OP_A, x, ncol).cpu().numpy()
+    assert rel(at, two) < 1e-6
+    mg.close()
