@@ -576,6 +576,17 @@ def main():
     traffic = stored_traffic(os.path.join(ROOT, "paper_2004_07732_amd", "csrc", "coarse_mfma.hip"), stored_bytes)
     log(f"[bench] coarse stencil {t_coarse_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic (5 link blocks), "
         f"{stored_bytes / (t_coarse_ms * 1e-3) / 1e9:.0f} GB/s on the 3 stored blocks")
+    # the coarse A = D_PV-hat^dag D_DW-hat as the solve applies it (with FP64 vectors its
+    # intermediate in FP32): median of five runs of 200 applications
+    t_a_ms = sorted(mg.time_op(1, dwfmg.MG_OP_A, xin, 1, iters=200) for _ in range(5))[2]
+    a_bytes = coarse_a_bytes(coarse_bytes, nsites, n, Lsc, 1, vec_bytes)
+    a_stored = coarse_a_bytes(stored_bytes, nsites, n, Lsc, 1, vec_bytes)
+    coarse_a = {"us_per_application": t_a_ms * 1e3, "launches": 2, "algorithmic_bytes": a_bytes,
+                "GB_s": a_bytes / (t_a_ms * 1e-3) / 1e9, "frac": a_bytes / (t_a_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                "stored_bytes": a_stored,
+                "frac_stored_bytes": a_stored / (t_a_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    log(f"[bench] coarse A {t_a_ms * 1e3:.1f} us per application (two launches), "
+        f"{coarse_a['GB_s']:.0f} GB/s algorithmic = {coarse_a['frac']:.3f}")
     tw, tpb = mg.coarse_config(1, 1)
     mfma_per_launch = coarse_mfma_per_launch(nsites, n, Lsc, 1, tw)
     issued_tf = mfma_per_launch * 16 * 16 * 32 * 2 / (t_coarse_ms * 1e-3) / 1e12
@@ -715,6 +726,7 @@ def main():
                      "frac_counter_bytes": (traffic / (t_coarse_ms * 1e-3) / 1e9 / PEAK_HBM_GBS) if traffic else None},
         "cpu_baseline": cpu,
         "coarse_mfma": coarse_mfma,
+        "coarse_A": coarse_a,
         "solve_roofline": solve_roofline,
         "fp64": fp64,
         "mixed_vs_fp64": (mixed_sps / fp64["solves_per_s"]) if fp64 else None,
