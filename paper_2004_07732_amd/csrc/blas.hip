@@ -527,7 +527,13 @@ k_gcr_dots(const cpx<T>* W, size_t wstride, const cpx<T>* w, const cpx<T>* r, si
     SHARED_RED;
     const int col = blockIdx.y;
     const size_t o = (size_t)col * n;
-    const bool stopped = stop[col] != 0;
+    // the vectors are read whatever the stop flag says, so that no load waits for it;
+    // a stopped column's sums (possibly of unwritten directions) are replaced by zeros.
+    // The flag is read by a vector load (an offset the compiler cannot see is zero), which
+    // completes in order with the vectors' loads instead of holding them back.
+    int zoff;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zoff));
+    const int sflag = stop[col + zoff];
     // layout (static indices, so the accumulators stay in registers):
     // [|w|^2, Re <w, r>, Im <w, r>, Re <W_0, w>, Im <W_0, w>, ...]
     double v[35];
@@ -549,7 +555,7 @@ k_gcr_dots(const cpx<T>* W, size_t wstride, const cpx<T>* w, const cpx<T>* r, si
         v[1] += p.re;
         v[2] += p.im;
     };
-    if (!stopped) {
+    {
         const size_t stride = (size_t)gridDim.x * blockDim.x;
         size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
         for (; e + (U - 1) * stride < n; e += U * stride) {
@@ -571,6 +577,8 @@ k_gcr_dots(const cpx<T>* W, size_t wstride, const cpx<T>* w, const cpx<T>* r, si
             add(w[o + e], r[o + e], Wt);
         }
     }
+#pragma unroll
+    for (int q = 0; q < 35; ++q) v[q] = sflag != 0 ? 0.0 : v[q];
     write_partials<35>(v, 2 * j + 3, rw, col, sh, tot);
 }
 
