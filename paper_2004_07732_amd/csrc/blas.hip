@@ -708,10 +708,14 @@ __global__ void __launch_bounds__(64 * (2 * kGramMax + 1)) k_fin_gram(RedWork rw
     const size_t kb = (size_t)col * g.kmax;
     // every load is issued before the first wait: the stop flag, the partials (added
     // whether or not the column has stopped: a stopped column's sums go unused) and the
-    // earlier rows
-    const int sflag = stop_in[col];
-    const double rr0 = g.rr[col];
-    const int it0 = g.it[col];
+    // earlier rows.  The flag and the column's scalars are read by vector loads (an offset
+    // the compiler cannot see is zero), which complete in order with the partials' loads
+    // instead of holding them back in a wait shared with the kernel arguments.
+    int zoff;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zoff));
+    const int sflag = stop_in[col + zoff];
+    const double rr0 = g.rr[col + zoff];
+    const int it0 = g.it[col + zoff];
     double ov = 0.0;
     if (t < NOLD) {   // (the address by selects: one load, no branches between the loads)
         const double* src = t < ND ? g.D + ((kb + t / (2 * j)) * g.kmax + (t % (2 * j)) / 2) * 2 + (t & 1)
