@@ -219,7 +219,8 @@ hipError_t Hierarchy::apply_A(int l, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp,
         if (!L.fine && L.Ls <= kMaxCoarseLs && coarse_mfma_supported(L.n, L.link_prec)) {
             // FP64 coarse vectors on the matrix cores: the stencil accumulates in FP32, so
             // its output holds FP32 values, and the intermediate D_DW in is kept in FP32
-            // (half its bytes) without changing any bit of A in
+            // (half its bytes); under the same launch configurations A in is the same, bit
+            // for bit, as with an FP64 intermediate
             const CoarseGeom g{L.Lx, L.Ly, L.Ls, L.n};
             const int stride = skip ? kSkipStride : 1;
             cpx<float>* t = reinterpret_cast<cpx<float>*>(tmp);
