@@ -449,10 +449,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stencil", action="store_true", help="skip the fine-stencil bandwidth rows")
-    ap.add_argument("--counters", nargs="?", const="coarse", choices=["coarse", "fine"], default=None,
-                    help="only run one kernel (21 launches: the dominant coarse stencil, or with 'fine' the "
-                         "fine stencil at 512^2 x 32 x 4 rhs FP32 in a fixed launch configuration) "
-                         "next to a plain 256 MiB copy, for rocprofv3 --pmc runs; prints no benchmark line")
+    ap.add_argument("--counters", nargs="?", const="coarse", choices=["coarse", "coarse16", "fine"], default=None,
+                    help="only run one kernel (21 launches: the dominant coarse stencil; with 'coarse16' the "
+                         "same stencil on 16 right-hand sides; with 'fine' the fine stencil at 512^2 x 32 x 4 rhs "
+                         "FP32 in a fixed launch configuration) next to a plain 256 MiB copy, for rocprofv3 --pmc "
+                         "runs; prints no benchmark line")
     args = ap.parse_args()
 
     if args.counters:
@@ -525,16 +526,19 @@ def main():
         return
 
     if args.counters:
-        mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True, **head), starts)
+        nc = 16 if args.counters == "coarse16" else 1
+        mg = dwfmg.MG(U, Ls, m, M5, make_params(dwfmg, wl, True, **head), starts, max_nrhs=nc)
         c = mg.info(1)
-        xin = torch.from_numpy(inputs.gaussian_field((1, c["Ls"], c["Ly"], c["Lx"], c["n"]), 5)).cuda()
-        mg.time_op(1, dwfmg.MG_OP_DW, xin, 1, iters=20)
+        xin = torch.from_numpy(inputs.gaussian_field((nc, c["Ls"], c["Ly"], c["Lx"], c["n"]), 5)).cuda()
+        mg.time_op(1, dwfmg.MG_OP_DW, xin, nc, iters=20)
         a = torch.ones(256 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
         bcopy = torch.empty_like(a)
         for _ in range(5):
             bcopy.copy_(a)
         torch.cuda.synchronize()
-        log("[bench] counters run done: 21 coarse launches, 5 copies of 256 MiB")
+        tw, tpb = mg.coarse_config(1, nc)
+        log(f"[bench] counters run done: 21 coarse launches on {nc} rhs (tile width {tw}, {tpb} tiles per "
+            f"workgroup), 5 copies of 256 MiB")
         return
 
     # ---------------------------------------------------------------- headline: mixed precision, 1 rhs
