@@ -140,13 +140,17 @@ def bf16_round(a):
 
 
 @pytest.mark.parametrize("ncol,vec", [(1, "f32"), (16, "f32"), (1, "f64"), (16, "f64")])
-def test_headline_coarse_stencil_full_size(ncol, vec):
+def test_headline_coarse_stencil_full_size(ncol, vec, monkeypatch):
     """The coarse operator of the headline hierarchy at its full size (64^2
     coarse sites x coarse Ls 2, 32 dof per site, BF16 links on the matrix cores,
     FP32 or FP64 vectors), element by element against the oracle's coarse operator
     built by the oracle from the same gauge field and null-vector starts (no
     relaxation, so both sides build the same prolongator) and rounded to BF16.
-    ncol = 1 with FP64 vectors is the launch the benchmark's roofline line times."""
+    ncol = 1 with FP64 vectors is the launch the benchmark's roofline line times.
+    With FP64 vectors also the coarse A = D_PV^dag D_DW as the solve applies it
+    (its intermediate in FP32): bit for bit against D_DW then D_PV^dag on FP64
+    vectors under the same launch configurations, and against the oracle's A on
+    the rounded links."""
     L, Ls, m, M5, nv = 256, 16, 0.01, -1.0, 16
     g = inputs.metropolis_u1(L, L, 6.0, 200, inputs.gauge_seed(4, L))
     start = inputs.gaussian_field((nv, L, L, 2), inputs.null_start_seed(6, 0))
@@ -173,3 +177,17 @@ def test_headline_coarse_stencil_full_size(ncol, vec):
         # (and an FP32 output) add ~1e-7.  Bars: 2^-16 on the 2-norm, 4 x 2^-16 on
         # the largest entry.
         assert err < 2.0 ** -16 and emax < 4 * 2.0 ** -16
+    if vec == "f64":
+        monkeypatch.setenv("DWF_AUTOTUNE", "0")   # the same (heuristic) configurations on both sides
+        xd = torch.from_numpy(x).cuda()
+        a = mg.level_op(1, dwfmg.MG_OP_A, xd, ncol).cpu().numpy()
+        t = mg.level_op(1, dwfmg.MG_OP_DW, xd, ncol)
+        two = mg.level_op(1, dwfmg.MG_OP_PV_DAG, t, ncol).cpu().numpy()
+        assert np.array_equal(a, two)
+        want = O.stencil_dwf(Sb, O.stencil_dwf(Sb, x, m, M5), 1.0, M5, dagger=True)
+        err = float(np.linalg.norm(a - want) / np.linalg.norm(want))
+        emax = float(np.max(np.abs(a - want)) / np.max(np.abs(want)))
+        say(f"[coarse full] ncol {ncol} A with FP32 intermediate: bit-identical to the two FP64 stencils; "
+            f"against the oracle rel 2-norm {err:.2e}, max elementwise {emax:.2e}")
+        # two applications, each splitting its input into BF16 parts: twice the bars
+        assert err < 2 * 2.0 ** -16 and emax < 8 * 2.0 ** -16
